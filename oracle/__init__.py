@@ -1,0 +1,212 @@
+"""FP64 CPU oracle of the discretised elastic 2->2 collision operator.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark load it; the product library never does.  It is a thin ctypes
+wrapper over ``kxg_oracle.c`` (plain C loops, FP64), which shares no code with
+the GPU library.  ``build()`` compiles it with gcc.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "kxg_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+GL, EXACT = 0, 1          # angular quadrature: Gauss-Legendre in mu, closed form
+LIN, LOG = 0, 1           # interpolation of f at the fourth momentum
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-shared", "-fPIC", "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        L.or_angular_gl.restype = ctypes.c_double
+        L.or_angular_exact.restype = ctypes.c_double
+        L.or_weight.restype = ctypes.c_double
+        L.or_drift.restype = ctypes.c_double
+        L.or_heun.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], (a.dtype, a.flags)
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_threads(n: int) -> None:
+    os.environ["OMP_NUM_THREADS"] = str(n)
+
+
+class Grid:
+    """Grid quantities p, dp, E, K, h of the oracle (App. B)."""
+
+    def __init__(self, p, mass: float = 1.0, dp: Optional[np.ndarray] = None):
+        self.p = _f64(p)
+        self.n = len(self.p)
+        self.mass = float(mass)
+        self.dp_override = None if dp is None else _f64(dp)
+        n = self.n
+        self.dp, self.E, self.K, self.h = (np.empty(n) for _ in range(4))
+        lib().or_grid(ctypes.c_int(n), _p(self.p), ctypes.c_double(self.mass),
+                      _p(self.dp_override), _p(self.dp), _p(self.E), _p(self.K),
+                      _p(self.h))
+
+
+def gauss_legendre(n: int) -> Tuple[np.ndarray, np.ndarray]:
+    x, w = np.empty(n), np.empty(n)
+    lib().or_gauss_legendre(ctypes.c_int(n), _p(x), _p(w))
+    return x, w
+
+
+def angular_gl(pi, pn, pm, mass=1.0, nmu=18) -> float:
+    x, w = gauss_legendre(nmu)
+    K = lambda q: q * q / (np.sqrt(q * q + mass * mass) + mass)
+    return lib().or_angular_gl(ctypes.c_double(pi), ctypes.c_double(pn),
+                               ctypes.c_double(pm), ctypes.c_double(K(pi)),
+                               ctypes.c_double(K(pn)), ctypes.c_double(K(pm)),
+                               ctypes.c_int(nmu), _p(x), _p(w))
+
+
+def angular_exact(p1, p2, p3, p4) -> float:
+    return lib().or_angular_exact(*(ctypes.c_double(v) for v in (p1, p2, p3, p4)))
+
+
+class Operator:
+    """Precomputed A[i,n,m], R[i,j] of the oracle (linear interpolation)."""
+
+    def __init__(self, p, mass=1.0, gdof=1.0, m2=1.0, quad=GL, nmu=18,
+                 dp: Optional[np.ndarray] = None, keep_bracket: bool = False):
+        self.grid = Grid(p, mass, dp)
+        n = self.grid.n
+        self.n, self.mass, self.gdof, self.m2 = n, float(mass), float(gdof), float(m2)
+        self.quad, self.nmu = int(quad), int(nmu)
+        self.A = np.empty((n, n, n))
+        self.R = np.empty((n, n))
+        self.jl = np.empty((n, n, n), dtype=np.int32) if keep_bracket else None
+        self.wr = np.empty((n, n, n)) if keep_bracket else None
+        lib().or_kernel_build(
+            ctypes.c_int(n), _p(self.grid.p), _p(self.grid.dp_override),
+            ctypes.c_double(self.mass), ctypes.c_double(self.gdof),
+            ctypes.c_double(self.m2), ctypes.c_int(self.quad), ctypes.c_int(self.nmu),
+            _p(self.A), _p(self.R),
+            None if self.jl is None else self.jl.ctypes.data_as(_ip),
+            _p(self.wr))
+
+    # -- the operator --------------------------------------------------------
+    def collision(self, f, project: bool = False):
+        """Returns (C, gain, loss) for f of shape [N] or [B, N]."""
+        f = _f64(f)
+        one = f.ndim == 1
+        fb = f.reshape(1, -1) if one else f
+        nb = fb.shape[0]
+        g, l, c = np.empty_like(fb), np.empty_like(fb), np.empty_like(fb)
+        lib().or_collision_ar(ctypes.c_int(self.n), ctypes.c_int(nb), _p(self.A),
+                              _p(self.R), _p(fb), _p(g), _p(l), _p(c))
+        if project:
+            c = np.stack([self.project(fb[b], c[b])[0] for b in range(nb)])
+        if one:
+            return c[0], g[0], l[0]
+        return c, g, l
+
+    def project(self, f, craw, eps_supp: float = 1e-12):
+        f, craw = _f64(f), _f64(craw)
+        out = np.empty(self.n)
+        diag = np.empty(8)
+        lib().or_project(ctypes.c_int(self.n), _p(self.grid.h), _p(self.grid.E),
+                         _p(f), _p(craw), ctypes.c_double(eps_supp), _p(out), _p(diag))
+        return out, diag
+
+    def moments(self, f):
+        out = np.empty(3)
+        lib().or_moments(ctypes.c_int(self.n), _p(self.grid.h), _p(self.grid.E),
+                         _p(_f64(f)), _p(out))
+        return out
+
+    def rk4(self, f0, lam: float, dt: float, nsteps: int, project: bool = True,
+            traj: bool = False):
+        f = _f64(f0).copy()
+        tr = np.empty((nsteps, self.n)) if traj else None
+        lib().or_rk4(ctypes.c_int(self.n), _p(self.A), _p(self.R), _p(self.grid.h),
+                     _p(self.grid.E), _p(f), ctypes.c_double(lam), ctypes.c_double(dt),
+                     ctypes.c_int(nsteps), ctypes.c_int(int(project)), _p(tr))
+        return (f, tr) if traj else f
+
+    def heun(self, x0, lam: float, Hi: float, u_end: float, dt0: float,
+             expansion: bool = True, project: bool = True, rtol: float = 1e-6,
+             atol: Optional[float] = None, safety: float = 0.9, fmin: float = 0.2,
+             fmax: float = 5.0, max_steps: int = 10000, replay_dt=None, u0: float = 0.0):
+        """Adaptive (or replayed) Heun in u.  Returns dict with the final state,
+        accepted (u, dt), outflow and rejection count."""
+        x = _f64(x0).copy()
+        if atol is None:
+            atol = 1e-12 * float(np.max(np.abs(x)))
+        nrep = 0 if replay_dt is None else len(replay_dt)
+        cap = max(nrep, max_steps)
+        acc_u, acc_dt = np.empty(cap), np.empty(cap)
+        rd = None if replay_dt is None else _f64(replay_dt)
+        outflow = ctypes.c_double(0.0)
+        nrej = ctypes.c_int(0)
+        nacc = lib().or_heun(
+            ctypes.c_int(self.n), _p(self.A), _p(self.R), _p(self.grid.p),
+            _p(self.grid.dp_override), ctypes.c_double(self.mass), _p(x),
+            ctypes.c_int(int(expansion)), ctypes.c_int(int(project)),
+            ctypes.c_double(lam), ctypes.c_double(Hi), ctypes.c_double(u0),
+            ctypes.c_double(u_end), ctypes.c_double(dt0), ctypes.c_double(rtol),
+            ctypes.c_double(atol), ctypes.c_double(safety), ctypes.c_double(fmin),
+            ctypes.c_double(fmax), ctypes.c_int(max_steps), ctypes.c_int(nrep), _p(rd),
+            _p(acc_u), _p(acc_dt), ctypes.byref(outflow), ctypes.byref(nrej))
+        return {"x": x, "u": acc_u[:nacc], "dt": acc_dt[:nacc],
+                "outflow": outflow.value, "rejected": nrej.value}
+
+    def gamma0(self, f) -> float:
+        """Largest loss rate max_i sum_j R_ij f_j (the initial scattering rate)."""
+        return float(np.max(self.R @ _f64(f)))
+
+
+def direct(p, f, mass=1.0, gdof=1.0, m2=1.0, quad=GL, nmu=18, interp=LIN,
+           dp: Optional[np.ndarray] = None):
+    """Direct per-(i,n,m) evaluation of eq. app_dense_collision."""
+    p, f = _f64(p), _f64(f)
+    n = len(p)
+    g, l, c = np.empty(n), np.empty(n), np.empty(n)
+    lib().or_collision_direct(ctypes.c_int(n), _p(p), _p(None if dp is None else _f64(dp)),
+                              ctypes.c_double(mass), ctypes.c_double(gdof),
+                              ctypes.c_double(m2), ctypes.c_int(quad), ctypes.c_int(nmu),
+                              ctypes.c_int(interp), _p(f), _p(g), _p(l), _p(c))
+    return c, g, l
+
+
+def drift(p, dp, g):
+    out = np.empty(len(p))
+    o = lib().or_drift(ctypes.c_int(len(p)), _p(_f64(p)), _p(_f64(dp)), _p(_f64(g)), _p(out))
+    return out, o

@@ -1,0 +1,582 @@
+/*
+ * kxg_oracle.c -- plain, slow FP64 CPU oracle for the discretised, isotropic,
+ * elastic 2->2 self-collision operator of arXiv 2607.00755 ("KineticXGPU").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this file; only the test suite, the smoke check and the CPU
+ * baseline of the benchmark load it (through oracle/__init__.py).  It shares
+ * no source with the GPU library.
+ *
+ * Every routine follows the paper's own steps and notation, in FP64, with
+ * plain loops.  Readings of points the paper leaves open (weights, the
+ * Jacobian of the reduced kernel, linear vs. log interpolation, the drift
+ * discretisation) are stated at the routine that takes them.
+ *
+ * Parity pins: every routine here is pinned by the CPU tests against the
+ * paper's printed numbers, closed forms, invariants or brute force (see the
+ * test files named in each comment).  Nothing here is "parity unpinned".
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Grid (App. B, "physical momenta p_i, energies E_i, widths Delta p_i,      */
+/* moment weights h_i = p_i^2 Delta p_i").                                   */
+/* Reading of the unspecified widths: grid points are quadrature nodes,      */
+/* endpoints included; Delta p_i = p_i * (trapezoid width in ln p), i.e.     */
+/* p_i (ln p_{i+1} - ln p_{i-1})/2 inside and one-sided halves at the ends.  */
+/* A caller may override the widths.                                         */
+/* Kinetic energy K_i = E_i - m is formed as p^2/(E+m) so that the           */
+/* energy-conservation cut can be decided without cancellation.              */
+/* ------------------------------------------------------------------------ */
+void or_grid(int n, const double *p, double mass, const double *dp_override,
+             double *dp, double *E, double *K, double *h)
+{
+    for (int i = 0; i < n; ++i) {
+        E[i] = sqrt(p[i] * p[i] + mass * mass);
+        K[i] = (p[i] * p[i]) / (E[i] + mass);
+    }
+    for (int i = 0; i < n; ++i) {
+        if (dp_override) {
+            dp[i] = dp_override[i];
+        } else {
+            double lo = (i > 0) ? log(p[i - 1]) : log(p[i]);
+            double hi = (i < n - 1) ? log(p[i + 1]) : log(p[i]);
+            dp[i] = p[i] * (hi - lo) / 2.0;
+        }
+        h[i] = p[i] * p[i] * dp[i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gauss-Legendre nodes and weights on [-1,1] (App. B: "the remaining mu    */
+/* integral is evaluated with Gauss-Legendre quadrature").  Newton's method */
+/* on the Legendre polynomial P_n, three-term recurrence.  Nodes ascending. */
+/* ------------------------------------------------------------------------ */
+void or_gauss_legendre(int n, double *x, double *w)
+{
+    for (int k = 0; k < n; ++k) {
+        /* k-th root counted from +1 downwards */
+        double z = cos(M_PI * (k + 0.75) / (n + 0.5));
+        double pn = 0.0, pnm1 = 0.0, dpn = 1.0;
+        for (int it = 0; it < 200; ++it) {
+            double a = 1.0, b = 0.0;            /* P_j, P_{j-1} */
+            for (int j = 1; j <= n; ++j) {
+                double c = b;
+                b = a;
+                a = ((2.0 * j - 1.0) * z * b - (j - 1.0) * c) / j;
+            }
+            pn = a;
+            pnm1 = b;
+            dpn = n * (z * pn - pnm1) / (z * z - 1.0);
+            double dz = pn / dpn;
+            z -= dz;
+            if (fabs(dz) <= 1e-16 * fabs(z) + 1e-300)
+                break;
+        }
+        {
+            double a = 1.0, b = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                double c = b;
+                b = a;
+                a = ((2.0 * j - 1.0) * z * b - (j - 1.0) * c) / j;
+            }
+            dpn = n * (z * a - b) / (z * z - 1.0);
+        }
+        x[n - 1 - k] = z;
+        w[n - 1 - k] = 2.0 / ((1.0 - z * z) * dpn * dpn);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Angular factor Phi_inm = int dmu dnu / (sqrt(1-mu^2) sqrt(1-nu^2)        */
+/*                                        sqrt(1-cos^2 phi))               */
+/* by the paper's route (App. B, eqs. app_cosphi, app_measure_rewrite,      */
+/* app_I_mu, app_F_1d): for each Gauss-Legendre node mu, the coefficients   */
+/* A0, A1, K^2, the quadratic a nu^2 + b nu + c, its discriminant, roots    */
+/* clipped to [-1,1] and the analytic nu integral I(mu) via arcsin; then    */
+/* Phi = p_n p_m sum_q w_q I(mu_q).                                         */
+/* A0 is written as (K_n-K_i)(K_m-K_i) - p_i^2 + p_i p_n mu, which equals   */
+/* m^2 + E_n E_m - E_n E_i - E_m E_i + p_i p_n mu exactly.                  */
+/* ------------------------------------------------------------------------ */
+double or_angular_gl(double pi, double pn, double pm, double Ki, double Kn,
+                     double Km, int nmu, const double *xmu, const double *wmu)
+{
+    double a0c = (Kn - Ki) * (Km - Ki) - pi * pi;
+    double sum = 0.0;
+    for (int q = 0; q < nmu; ++q) {
+        double mu = xmu[q];
+        double A0 = a0c + pi * pn * mu;
+        double A1 = pi * pm - pn * pm * mu;
+        double K2 = pn * pn * pm * pm * (1.0 - mu * mu);
+        double a = -(K2 + A1 * A1);
+        double b = -2.0 * A0 * A1;
+        double c = K2 - A0 * A0;
+        double disc = b * b - 4.0 * a * c;
+        if (!(disc > 0.0) || !(a < 0.0))
+            continue;                        /* no allowed nu interval */
+        double sd = sqrt(disc);
+        double r1 = (-b + sd) / (2.0 * a);
+        double r2 = (-b - sd) / (2.0 * a);
+        double lo = r1 < r2 ? r1 : r2;
+        double hi = r1 < r2 ? r2 : r1;
+        if (lo < -1.0) lo = -1.0;
+        if (hi > 1.0) hi = 1.0;
+        if (!(lo < hi))
+            continue;                        /* interval misses [-1,1] */
+        double s_lo = (2.0 * a * lo + b) / sd;
+        double s_hi = (2.0 * a * hi + b) / sd;
+        if (s_lo > 1.0) s_lo = 1.0;
+        if (s_lo < -1.0) s_lo = -1.0;
+        if (s_hi > 1.0) s_hi = 1.0;
+        if (s_hi < -1.0) s_hi = -1.0;
+        double I = (asin(s_lo) - asin(s_hi)) / sqrt(-a);
+        sum += wmu[q] * I;
+    }
+    return pn * pm * sum;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Closed form of the same angular factor for a constant matrix element,    */
+/* used as an independent pin of the Gauss-Legendre route:                  */
+/*   Phi = pi * S(p1,p2,p3,p4) / (2 p1),                                    */
+/* S = |p1-p2-p3-p4| + |p1-p2+p3+p4| + |p1+p2-p3+p4| + |p1+p2+p3-p4|        */
+/*   - |p1-p2-p3+p4| - |p1-p2+p3-p4| - |p1+p2-p3-p4| - (p1+p2+p3+p4),       */
+/* with p1 = p_i, p2 = p_j~ (the fourth momentum), p3 = p_n, p4 = p_m.      */
+/* It follows from writing the momentum delta function of eq. C22_general   */
+/* as a Fourier integral and doing the three solid-angle integrals.         */
+/* ------------------------------------------------------------------------ */
+double or_angular_exact(double p1, double p2, double p3, double p4)
+{
+    double s = fabs(p1 - p2 - p3 - p4) + fabs(p1 - p2 + p3 + p4)
+             + fabs(p1 + p2 - p3 + p4) + fabs(p1 + p2 + p3 - p4)
+             - fabs(p1 - p2 - p3 + p4) - fabs(p1 - p2 + p3 - p4)
+             - fabs(p1 + p2 - p3 - p4) - (p1 + p2 + p3 + p4);
+    return M_PI * s / (2.0 * p1);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One kernel entry (i,n,m): the fourth momentum from energy conservation   */
+/* (eq. app_fourth_momentum, in kinetic energy K = E - m), the kinematic    */
+/* cuts (E_j~ >= m and q_min <= q_j~ <= q_max, App. B), the discrete weight  */
+/* (eq. discrete_weight) and the energy-linear interpolation bracket        */
+/* (eq. app_interp_weights).                                                */
+/*                                                                          */
+/* Reading of the reduced kernel: the reduction of eq. C22_general carries  */
+/* the phase-space factors 1/(2E_3) 1/(2E_4) of the two integrated legs, so */
+/*   F_inm = |M|^2/(4 (2 pi)^4) * (p_n p_m/(E_n E_m)) * Phi_inm,             */
+/* which is the printed eq. app_F_1d times p_n p_m/(E_n E_m).  The MC pin   */
+/* of the full 9-D definition decides between the two (tests).              */
+/*                                                                          */
+/* Cuts in K: keep iff K_0 <= K~ <= K_{N-1} (equivalent to E~ >= m and the  */
+/* grid range cut on a grid with p_0 > 0).  Bracket: jL = the largest       */
+/* j <= N-2 with K_j <= K~, omega_R = (K~ - K_jL)/(K_jL+1 - K_jL), which is */
+/* the paper's energy-linear weight since E - K is constant.                */
+/* Returns W (0 when cut) and writes jL, omega_R.                           */
+/* ------------------------------------------------------------------------ */
+double or_weight(int n, const double *p, const double *dp, const double *E,
+                 const double *K, double mass, double gdof, double m2,
+                 int quad, int nmu, const double *xmu, const double *wmu,
+                 int i, int a, int b, int *jl_out, double *wr_out)
+{
+    double kt = (K[a] + K[b]) - K[i];
+    *jl_out = -1;
+    *wr_out = 0.0;
+    if (!(kt >= K[0] && kt <= K[n - 1]))
+        return 0.0;
+    int jl = 0;
+    for (int j = 0; j <= n - 2; ++j)
+        if (K[j] <= kt)
+            jl = j;
+    double wr = (kt - K[jl]) / (K[jl + 1] - K[jl]);
+    double phi;
+    if (quad == 1) {
+        double pt = sqrt(kt * (kt + 2.0 * mass));
+        phi = or_angular_exact(p[i], pt, p[a], p[b]);
+    } else {
+        phi = or_angular_gl(p[i], p[a], p[b], K[i], K[a], K[b], nmu, xmu, wmu);
+    }
+    double F = m2 / (4.0 * pow(2.0 * M_PI, 4.0)) * (p[a] * p[b] / (E[a] * E[b])) * phi;
+    double W = dp[a] * dp[b] * F / (2.0 * E[i] * gdof);
+    *jl_out = jl;
+    *wr_out = wr;
+    return W;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kernel tensors of the linear-interpolation form of eq. app_dense_collision:
+ *   A[i][n][m] = W_inm (0 if cut),
+ *   R[i][j]    = sum_{n,m} W_inm (omega_L delta_{j,jL} + omega_R delta_{j,jL+1}),
+ * so that C_i = sum_{n,m} A_inm f_n f_m - f_i sum_j R_ij f_j.
+ * Optionally the per-entry bracket (jL, omega_R) for the direct evaluation.
+ * quad: 0 = Gauss-Legendre in mu with analytic nu (the paper's), 1 = closed form.
+ * ------------------------------------------------------------------------ */
+void or_kernel_build(int n, const double *p, const double *dp_override,
+                     double mass, double gdof, double m2, int quad, int nmu,
+                     double *A, double *R, int *jl_all, double *wr_all)
+{
+    double *dp = malloc(sizeof(double) * n), *E = malloc(sizeof(double) * n);
+    double *K = malloc(sizeof(double) * n), *h = malloc(sizeof(double) * n);
+    double *xmu = malloc(sizeof(double) * (nmu > 0 ? nmu : 1));
+    double *wmu = malloc(sizeof(double) * (nmu > 0 ? nmu : 1));
+    or_grid(n, p, mass, dp_override, dp, E, K, h);
+    if (nmu > 0)
+        or_gauss_legendre(nmu, xmu, wmu);
+    memset(R, 0, sizeof(double) * (size_t)n * n);
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < n; ++a) {
+            for (int b = 0; b < n; ++b) {
+                int jl;
+                double wr;
+                double W = or_weight(n, p, dp, E, K, mass, gdof, m2, quad, nmu,
+                                     xmu, wmu, i, a, b, &jl, &wr);
+                size_t idx = ((size_t)i * n + a) * n + b;
+                A[idx] = W;
+                if (jl_all) jl_all[idx] = jl;
+                if (wr_all) wr_all[idx] = wr;
+                if (jl >= 0) {
+                    R[(size_t)i * n + jl] += W * (1.0 - wr);
+                    R[(size_t)i * n + jl + 1] += W * wr;
+                }
+            }
+        }
+    }
+    free(dp); free(E); free(K); free(h); free(xmu); free(wmu);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Direct evaluation of eq. app_dense_collision: for every (i,n,m) recompute */
+/* W_inm, the fourth momentum and the interpolated f_j~, then sum           */
+/* W [f_n f_m - f_i f_j~].  interp = 0: energy-linear interpolation of f    */
+/* (the form that the precomputed A/R tensors represent); interp = 1: the   */
+/* paper's log interpolation (eq. app_log_interp) with an absolute floor    */
+/* of 1e-300 under the logarithm.  Outputs gain, loss and C = gain - loss.  */
+/* ------------------------------------------------------------------------ */
+void or_collision_direct(int n, const double *p, const double *dp_override,
+                         double mass, double gdof, double m2, int quad, int nmu,
+                         int interp, const double *f, double *gain,
+                         double *loss, double *C)
+{
+    const double floor_ = 1e-300;
+    double *dp = malloc(sizeof(double) * n), *E = malloc(sizeof(double) * n);
+    double *K = malloc(sizeof(double) * n), *h = malloc(sizeof(double) * n);
+    double *xmu = malloc(sizeof(double) * (nmu > 0 ? nmu : 1));
+    double *wmu = malloc(sizeof(double) * (nmu > 0 ? nmu : 1));
+    or_grid(n, p, mass, dp_override, dp, E, K, h);
+    if (nmu > 0)
+        or_gauss_legendre(nmu, xmu, wmu);
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < n; ++i) {
+        double g = 0.0, l = 0.0;
+        for (int a = 0; a < n; ++a) {
+            for (int b = 0; b < n; ++b) {
+                int jl;
+                double wr;
+                double W = or_weight(n, p, dp, E, K, mass, gdof, m2, quad, nmu,
+                                     xmu, wmu, i, a, b, &jl, &wr);
+                if (jl < 0)
+                    continue;
+                double ft;
+                if (interp == 0) {
+                    ft = (1.0 - wr) * f[jl] + wr * f[jl + 1];
+                } else {
+                    double fl = f[jl] > floor_ ? f[jl] : floor_;
+                    double fr = f[jl + 1] > floor_ ? f[jl + 1] : floor_;
+                    ft = exp((1.0 - wr) * log(fl) + wr * log(fr));
+                }
+                g += W * f[a] * f[b];
+                l += W * f[i] * ft;
+            }
+        }
+        gain[i] = g;
+        loss[i] = l;
+        C[i] = g - l;
+    }
+    free(dp); free(E); free(K); free(h); free(xmu); free(wmu);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same operator from the precomputed tensors (linear interpolation):   */
+/* gain_i = sum_{n,m} A_inm f_n f_m, loss_i = f_i sum_j R_ij f_j.           */
+/* f holds nb distributions of length n, row-major.                         */
+/* ------------------------------------------------------------------------ */
+void or_collision_ar(int n, int nb, const double *A, const double *R,
+                     const double *f, double *gain, double *loss, double *C)
+{
+    for (int bb = 0; bb < nb; ++bb) {
+        const double *fb = f + (size_t)bb * n;
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; ++i) {
+            double g = 0.0;
+            for (int a = 0; a < n; ++a) {
+                const double *row = A + ((size_t)i * n + a) * n;
+                double s = 0.0;
+                for (int b = 0; b < n; ++b)
+                    s += row[b] * fb[b];
+                g += fb[a] * s;
+            }
+            double r = 0.0;
+            for (int j = 0; j < n; ++j)
+                r += R[(size_t)i * n + j] * fb[j];
+            double l = fb[i] * r;
+            if (gain) gain[(size_t)bb * n + i] = g;
+            if (loss) loss[(size_t)bb * n + i] = l;
+            C[(size_t)bb * n + i] = g - l;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Two-moment projection (App. C, eqs. app_self_projection and              */
+/* app_projection_system): support weights xi_i = |f_i|/f_max above        */
+/* eps_supp, the 2x2 system in (alpha, beta) with A00, A01, A11 and the raw */
+/* residuals R0, R1, and C_proj = C_raw - xi (alpha + beta E).              */
+/* Diagnostics (eqs. app_epsilon_definition, app_projection_relative_       */
+/* correction): diag = {alpha, beta, eps_N_raw, eps_E_raw, eps_N_proj,      */
+/* eps_E_proj, R_N, R_E}.  One distribution.                                */
+/* ------------------------------------------------------------------------ */
+void or_project(int n, const double *h, const double *E, const double *f,
+                const double *craw, double eps_supp, double *cproj,
+                double *diag)
+{
+    double fmax = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (fabs(f[i]) > fmax)
+            fmax = fabs(f[i]);
+    double A00 = 0, A01 = 0, A11 = 0, R0 = 0, R1 = 0;
+    double *xi = malloc(sizeof(double) * n);
+    for (int i = 0; i < n; ++i) {
+        double r = fmax > 0.0 ? fabs(f[i]) / fmax : 0.0;
+        xi[i] = r > eps_supp ? r : 0.0;
+        A00 += h[i] * xi[i];
+        A01 += h[i] * E[i] * xi[i];
+        A11 += h[i] * E[i] * E[i] * xi[i];
+        R0 += h[i] * craw[i];
+        R1 += h[i] * E[i] * craw[i];
+    }
+    double det = A00 * A11 - A01 * A01;
+    double alpha = 0.0, beta = 0.0;
+    if (det != 0.0) {
+        alpha = (R0 * A11 - R1 * A01) / det;
+        beta = (R1 * A00 - R0 * A01) / det;
+    }
+    double nr = 0, dr = 0, ner = 0, der = 0, np_ = 0, nep = 0, cn = 0, ce = 0;
+    for (int i = 0; i < n; ++i) {
+        cproj[i] = craw[i] - xi[i] * (alpha + beta * E[i]);
+        nr += h[i] * craw[i];
+        dr += h[i] * fabs(craw[i]);
+        ner += h[i] * E[i] * craw[i];
+        der += h[i] * E[i] * fabs(craw[i]);
+        np_ += h[i] * cproj[i];
+        nep += h[i] * E[i] * cproj[i];
+        cn += h[i] * fabs(cproj[i] - craw[i]);
+        ce += h[i] * E[i] * fabs(cproj[i] - craw[i]);
+    }
+    double dp_ = 0, dep = 0;
+    for (int i = 0; i < n; ++i) {
+        dp_ += h[i] * fabs(cproj[i]);
+        dep += h[i] * E[i] * fabs(cproj[i]);
+    }
+    if (diag) {
+        diag[0] = alpha;
+        diag[1] = beta;
+        diag[2] = dr > 0 ? nr / dr : 0.0;
+        diag[3] = der > 0 ? ner / der : 0.0;
+        diag[4] = dp_ > 0 ? np_ / dp_ : 0.0;
+        diag[5] = dep > 0 ? nep / dep : 0.0;
+        diag[6] = dr > 0 ? cn / dr : 0.0;
+        diag[7] = der > 0 ? ce / der : 0.0;
+    }
+    free(xi);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discrete moments (App. B): number sum h f, energy sum h E f, and the     */
+/* Boltzmann entropy S = -sum h f (ln f - 1) over bins with f > 0.          */
+/* ------------------------------------------------------------------------ */
+void or_moments(int n, const double *h, const double *E, const double *f,
+                double *out3)
+{
+    double N = 0, En = 0, S = 0;
+    for (int i = 0; i < n; ++i) {
+        N += h[i] * f[i];
+        En += h[i] * E[i] * f[i];
+        if (f[i] > 0.0)
+            S -= h[i] * f[i] * (log(f[i]) - 1.0);
+    }
+    out3[0] = N;
+    out3[1] = En;
+    out3[2] = S;
+}
+
+/* Right-hand side lambda * C[f] of df/dt = lambda C (projected or raw). */
+static void rhs_static(int n, const double *A, const double *R, const double *h,
+                       const double *E, const double *f, double lambda,
+                       int project, double *out, double *tmp)
+{
+    or_collision_ar(n, 1, A, R, f, NULL, NULL, tmp);
+    if (project)
+        or_project(n, h, E, f, tmp, 1e-12, out, NULL);
+    else
+        memcpy(out, tmp, sizeof(double) * n);
+    for (int i = 0; i < n; ++i)
+        out[i] *= lambda;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fixed-step classical RK4 (Sec. 4.2) on df/dt = lambda C_proj[f] without  */
+/* expansion; f is advanced in place by nsteps steps of size dt.  If traj   */
+/* is given, it receives f after every step ((nsteps) x n).                 */
+/* ------------------------------------------------------------------------ */
+void or_rk4(int n, const double *A, const double *R, const double *h,
+            const double *E, double *f, double lambda, double dt, int nsteps,
+            int project, double *traj)
+{
+    double *k1 = malloc(sizeof(double) * n), *k2 = malloc(sizeof(double) * n);
+    double *k3 = malloc(sizeof(double) * n), *k4 = malloc(sizeof(double) * n);
+    double *y = malloc(sizeof(double) * n), *tmp = malloc(sizeof(double) * n);
+    for (int s = 0; s < nsteps; ++s) {
+        rhs_static(n, A, R, h, E, f, lambda, project, k1, tmp);
+        for (int i = 0; i < n; ++i) y[i] = f[i] + 0.5 * dt * k1[i];
+        rhs_static(n, A, R, h, E, y, lambda, project, k2, tmp);
+        for (int i = 0; i < n; ++i) y[i] = f[i] + 0.5 * dt * k2[i];
+        rhs_static(n, A, R, h, E, y, lambda, project, k3, tmp);
+        for (int i = 0; i < n; ++i) y[i] = f[i] + dt * k3[i];
+        rhs_static(n, A, R, h, E, y, lambda, project, k4, tmp);
+        for (int i = 0; i < n; ++i)
+            f[i] += dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+        if (traj)
+            memcpy(traj + (size_t)s * n, f, sizeof(double) * n);
+    }
+    free(k1); free(k2); free(k3); free(k4); free(y); free(tmp);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hubble drift of the fBE (eq. fbe) on a fixed physical grid.  In          */
+/* u = ln a the redshift term is d_u f = d_{ln p} f; it is discretised in   */
+/* conservative upwind form on g_i = a^3 p_i^3 f_i (comoving number per     */
+/* unit ln p), with cell sizes V_i = Delta p_i / p_i (the same measure as   */
+/* the moment weights h_i, so that drift and collisions conserve the same   */
+/* sum_i V_i g_i):                                                          */
+/*   V_i dg_i/du = g_{i+1} - g_i  (i < N-1),   V_{N-1} dg/du = -g_{N-1},    */
+/* nothing enters through p_max, and g_0 per unit u leaves through p_min.   */
+/* Writes dg/du into out; returns the outflow rate g_0.                     */
+/* ------------------------------------------------------------------------ */
+double or_drift(int n, const double *p, const double *dp, const double *g,
+                double *out)
+{
+    for (int i = 0; i < n; ++i) {
+        double V = dp[i] / p[i];
+        double next = (i + 1 < n) ? g[i + 1] : 0.0;
+        out[i] = (next - g[i]) / V;
+    }
+    return g[0];
+}
+
+/* Right-hand side in u = ln a (eq. numerical_evolution_loga) for the state
+ * x: with expansion, x = g = a^3 p^3 f and
+ *   dg/du = drift + a^3 p^3 lambda C[f] / H(u),  H = H_i e^{-2u} (radiation),
+ * without expansion x = f and dx/du = lambda C[f] / H_i (u is then t H_i). */
+static double rhs_u(int n, const double *A, const double *R, const double *p,
+                    const double *dp, const double *h, const double *E,
+                    const double *x, double u, double lambda, double Hi,
+                    int expansion, int project, double *out, double *f,
+                    double *c, double *tmp)
+{
+    if (!expansion) {
+        rhs_static(n, A, R, h, E, x, lambda / Hi, project, out, tmp);
+        return 0.0;
+    }
+    double a3 = exp(3.0 * u);
+    for (int i = 0; i < n; ++i)
+        f[i] = x[i] / (a3 * p[i] * p[i] * p[i]);
+    rhs_static(n, A, R, h, E, f, lambda, project, c, tmp);
+    double outflow = or_drift(n, p, dp, x, out);
+    double H = Hi * exp(-2.0 * u);
+    for (int i = 0; i < n; ++i)
+        out[i] += a3 * p[i] * p[i] * p[i] * c[i] / H;
+    return outflow;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive Heun in u (Sec. 4.2): Euler predictor x* = x + dt k1, trapezoid */
+/* corrector x_new = x + dt (k1 + k2)/2 with k2 = rhs(u+dt, x*), and the    */
+/* predictor-corrector difference as the local error estimate:             */
+/*   err = max_i |x_new - x*| / (atol + rtol max(|x_i|, |x_new_i|)),        */
+/* accept iff err <= 1; next dt = dt * clamp(safety err^{-1/2}, fmin, fmax). */
+/* The step is clipped to end exactly at u_end.  Two operator calls per     */
+/* attempted step.  With nreplay > 0 the steps are not adapted: dt_k is     */
+/* taken from replay_dt and always accepted.  Records accepted (u_k, dt_k). */
+/* Returns the number of accepted steps; *outflow accumulates the drift     */
+/* outflow (trapezoid in u, consistent with the Heun update).              */
+/* ------------------------------------------------------------------------ */
+int or_heun(int n, const double *A, const double *R, const double *p,
+            const double *dp_override, double mass, double *x, int expansion,
+            int project, double lambda, double Hi, double u0, double u_end,
+            double dt0, double rtol, double atol, double safety, double fmin,
+            double fmax, int max_steps, int nreplay, const double *replay_dt,
+            double *acc_u, double *acc_dt, double *outflow, int *nrejected)
+{
+    double *dp = malloc(sizeof(double) * n), *E = malloc(sizeof(double) * n);
+    double *K = malloc(sizeof(double) * n), *h = malloc(sizeof(double) * n);
+    double *k1 = malloc(sizeof(double) * n), *k2 = malloc(sizeof(double) * n);
+    double *xs = malloc(sizeof(double) * n), *xn = malloc(sizeof(double) * n);
+    double *f = malloc(sizeof(double) * n), *c = malloc(sizeof(double) * n);
+    double *tmp = malloc(sizeof(double) * n);
+    or_grid(n, p, mass, dp_override, dp, E, K, h);
+    double u = u0, dt = dt0;
+    int acc = 0, rej = 0;
+    double out = 0.0;
+    int limit = nreplay > 0 ? nreplay : max_steps;
+    while (acc < limit) {
+        if (nreplay > 0) {
+            dt = replay_dt[acc];
+        } else {
+            if (!(u < u_end))
+                break;
+            if (u + dt > u_end)
+                dt = u_end - u;
+        }
+        double o1 = rhs_u(n, A, R, p, dp, h, E, x, u, lambda, Hi, expansion,
+                          project, k1, f, c, tmp);
+        for (int i = 0; i < n; ++i)
+            xs[i] = x[i] + dt * k1[i];
+        double o2 = rhs_u(n, A, R, p, dp, h, E, xs, u + dt, lambda, Hi,
+                          expansion, project, k2, f, c, tmp);
+        double err = 0.0;
+        for (int i = 0; i < n; ++i) {
+            xn[i] = x[i] + 0.5 * dt * (k1[i] + k2[i]);
+            double sc = atol + rtol * (fabs(x[i]) > fabs(xn[i]) ? fabs(x[i]) : fabs(xn[i]));
+            double e = fabs(xn[i] - xs[i]) / sc;
+            if (e > err)
+                err = e;
+        }
+        if (nreplay > 0 || err <= 1.0) {
+            if (acc_u) acc_u[acc] = u;
+            if (acc_dt) acc_dt[acc] = dt;
+            out += 0.5 * dt * (o1 + o2);
+            u += dt;
+            memcpy(x, xn, sizeof(double) * n);
+            ++acc;
+        } else {
+            ++rej;
+        }
+        if (nreplay == 0) {
+            double fac = err > 0.0 ? safety / sqrt(err) : fmax;
+            if (fac < fmin) fac = fmin;
+            if (fac > fmax) fac = fmax;
+            dt *= fac;
+        }
+    }
+    if (outflow) *outflow = out;
+    if (nrejected) *nrejected = rej;
+    free(dp); free(E); free(K); free(h); free(k1); free(k2); free(xs);
+    free(xn); free(f); free(c); free(tmp);
+    return acc;
+}
