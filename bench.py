@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark of the collision-operator hot path on one MI355X.
+
+Step = one RK4 step of the batched FP32 workload (N = 256 log grid on
+p/m in [1e-3, 20], B = 512 seeded bimodal distributions, lambda log-uniform in
+[1e-3, 1e3]): four evaluations of C[f] (MFMA GEMM gain + FP64 loss,
+projection) and the FP64 state update, all on the device.  value = C[f]
+evaluations per second (4 B / step time), inputs resident in HBM.
+
+Also reported: the plain FP64 single-distribution path at N = 256 (B = 1,
+one HBM stream over the dense tensor) and the ratio, the 16-bit split path at
+B = 4096, the roofline of the dominant kernel (GEMM duration from HIP events
+on its own stream over the timed region) and the FP64 CPU oracle timed on the
+host cores on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "C[f] evals/s at N=256 batched vs plain FP64; p50/p99 solve latency"
+PEAK = {"f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "f64": 78.6}   # TFLOP/s dense
+HBM_PEAK = 8000.0                                                    # GB/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    return ap.parse_args()
+
+
+def packed_k(n):
+    nb = (n + 15) // 16
+    return nb * (nb + 1) // 2 * 256
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU "
+              "layout is a design note, not an implementation.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2607_00755_amd import inputs, kxg
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    # ---------------- batched FP32 RK4 (the timed step) ----------------
+    w = inputs.batched_fp32_n256(512)
+    n, B = w.n, w.batch
+    p = w.grid()
+    f0 = torch.tensor(w.f0(), device=dev)
+    t0 = time.time()
+    ker = kxg.Kernel(p, precs=(kxg.F64, kxg.F32), b_cap=B)
+    log("kernel build N=%d: %.3f s" % (n, time.time() - t0))
+    st = kxg.Stepper(ker, kind=kxg.RK4, prec=kxg.F32, b_cap=B)
+    for b, s in enumerate(w.solves):
+        st.set(b, f0[b], lam=s.lam, t_end=1e30, h_i=1.0)
+    st.advance(args.warmup)
+    torch.cuda.synchronize()
+    kxg.profile_begin(4 * args.steps + 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.advance(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gemm_ms, gemm_n = kxg.profile_end()
+    ms_step = 1e3 * wall / args.steps
+    value = 4 * B / (wall / args.steps)
+    q = st.query()
+    bad = sum(1 for x in q[:B] if x["status"] < 0)
+    log("batched f32 RK4: %.3f ms/step, %.3e C-evals/s, %d failed slots" % (ms_step, value, bad))
+    gemm_avg_ms = gemm_ms / max(gemm_n, 1)
+    flops_exec = 2.0 * B * n * packed_k(n)
+    flops_dense = 2.0 * B * n * n * n
+    achieved = flops_exec / (gemm_avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["f32"],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4), "traffic": None,
+                "kernel": "k_gemm_f32<4>", "avg_launch_us": round(gemm_avg_ms * 1e3, 2),
+                "launches": gemm_n, "flops_per_launch": flops_exec,
+                "dense_equiv_flops_per_launch": flops_dense}
+
+    extras = {}
+    # ---------------- plain FP64 single distribution ----------------
+    f1 = f0[:1].contiguous()
+    C1 = torch.empty_like(f1)
+    d1 = torch.empty((1, kxg.NDIAG), dtype=torch.float64, device=dev)
+    for _ in range(5):
+        ker.eval(f1, prec=kxg.F64, out=C1, diag=d1)
+    torch.cuda.synchronize()
+    reps = 200
+    kxg.profile_begin(reps + 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ker.eval(f1, prec=kxg.F64, out=C1, diag=d1)
+    torch.cuda.synchronize()
+    plain_wall = (time.perf_counter() - t0) / reps
+    s_ms, s_n = kxg.profile_end()
+    stream_us = 1e3 * s_ms / max(s_n, 1)
+    plain = 1.0 / plain_wall
+    bytes_stream = 8.0 * n ** 3
+    extras["plain_fp64"] = {"evals_per_s": round(plain, 1), "us_per_eval": round(1e6 * plain_wall, 2),
+                            "stream_kernel_us": round(stream_us, 2),
+                            "stream_GBps": round(bytes_stream / (stream_us * 1e-6) / 1e9, 1),
+                            "hbm_frac": round(bytes_stream / (stream_us * 1e-6) / 1e9 / HBM_PEAK, 4)}
+    extras["batched_vs_plain_fp64"] = round(value / plain, 1)
+    log("plain fp64 N=256: %.1f us/eval (stream kernel %.1f us, %.0f GB/s)" %
+        (1e6 * plain_wall, stream_us, bytes_stream / (stream_us * 1e-6) / 1e9))
+
+    if not args.no_extras:
+        # ---------------- 16-bit split at B = 4096 ----------------
+        w4 = inputs.mixed_n256(4096)
+        f4 = torch.tensor(w4.f0(), device=dev)
+        k4 = kxg.Kernel(p, precs=(kxg.BF16X3, kxg.F16X3), b_cap=4096)
+        C4 = torch.empty_like(f4)
+        d4 = torch.empty((4096, kxg.NDIAG), dtype=torch.float64, device=dev)
+        for prec, name in ((kxg.BF16X3, "bf16x3"), (kxg.F16X3, "f16x3")):
+            for _ in range(3):
+                k4.eval(f4, prec=prec, out=C4, diag=d4)
+            torch.cuda.synchronize()
+            reps4 = 20
+            kxg.profile_begin(reps4 + 2)
+            t0 = time.perf_counter()
+            for _ in range(reps4):
+                k4.eval(f4, prec=prec, out=C4, diag=d4)
+            torch.cuda.synchronize()
+            wl = (time.perf_counter() - t0) / reps4
+            g_ms, g_n = kxg.profile_end()
+            g_us = 1e3 * g_ms / max(g_n, 1)
+            fl = 3 * 2.0 * 4096 * n * packed_k(n)
+            extras[name + "_b4096"] = {
+                "evals_per_s": round(4096 / wl, 1), "ms_per_call": round(1e3 * wl, 3),
+                "gemm_us": round(g_us, 1), "mfma_tflops": round(fl / (g_us * 1e-6) / 1e12, 1),
+                "mfma_frac": round(fl / (g_us * 1e-6) / 1e12 / PEAK["bf16"], 4)}
+            log("%s B=4096: %.3f ms/call, gemm %.1f us" % (name, 1e3 * wl, g_us))
+        del k4
+
+    # ---------------- CPU oracle baseline ----------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        op = oracle.Operator(p)
+        fb = w.f0()[0]
+        op.collision(fb, project=True)
+        cnt, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            op.collision(fb, project=True)
+            cnt += 1
+        el = time.perf_counter() - t0
+        cpu = {"value": round(cnt / el, 2), "unit": "C-evals/s", "cores": threads, "kind": "oracle",
+               "sample": "%d evaluations of one N=256 distribution (FP64 A/R contraction + "
+                         "projection) in %.1f s" % (cnt, el)}
+        log("cpu oracle: %.2f C-evals/s on %d threads" % (cnt / el, threads))
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "C-evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": w.name + " RK4 step (4 evals, projected, FP64 state)",
+                      "n_grid": n, "batch": B, "p_range": [w.pmin, w.pmax], "n_mu": 18,
+                      "parallelism": "1 GPU"},
+           "roofline": roofline, "cpu_baseline": cpu}
+    out.update(extras)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

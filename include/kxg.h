@@ -1,0 +1,257 @@
+/*
+ * kxg.h -- C ABI of libkxg: the discretised, isotropic, elastic 2->2
+ * self-collision operator of arXiv 2607.00755 on one MI355X (gfx950).
+ *
+ * The library evaluates, for a batch of distributions f_b on a fixed
+ * momentum grid,
+ *
+ *     C_i[f] = sum_{n,m} A[i,n,m] f_n f_m  -  f_i sum_j R[i,j] f_j
+ *
+ * (gain minus loss, Sec. 4.1 eq. discrete_collision_operator with the
+ * energy-linear interpolation weights of App. B eq. app_interp_weights
+ * applied to f), optionally followed by the two-moment conservation
+ * projection of App. C (eqs. app_self_projection, app_projection_system),
+ * and integrates df/dt = lambda C[f] (fixed RK4) or the expanding-universe
+ * equation of Sec. 4.2 (eq. numerical_evolution_loga, adaptive Heun in
+ * u = ln a, with the Hubble drift of eq. fbe) on the device.
+ *
+ * Conventions for every entry point:
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory on the current device; "stream" is a hipStream_t passed as void*
+ *    (NULL = the default stream).
+ *  - Distributions and results are FP64, row-major [B][n] (distribution b
+ *    at offset b*n), whatever precision the contraction runs in.
+ *  - Caller-owned buffers stay caller-owned; handles own everything they
+ *    allocate and release it in the matching *_free call.
+ *  - Entry points return a kxg_status and never throw; on error nothing has
+ *    been enqueued and kxg_last_error() gives a message (thread-local).
+ *  - Work is enqueued asynchronously on the stream; device faults surface as
+ *    KXG_EHIP on a later call that synchronises.
+ */
+#ifndef KXG_H
+#define KXG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KXG_OK = 0,
+    KXG_EINVAL = 1,        /* bad argument (message says which) */
+    KXG_ENOMEM = 2,        /* device or host allocation failed */
+    KXG_EHIP = 3,          /* a HIP runtime call failed */
+    KXG_EUNSUPPORTED = 4,  /* precision not built into this kernel handle */
+    KXG_ESTEP = 5,         /* step size underflow in the adaptive stepper */
+    KXG_ENUMERIC = 6       /* non-finite values met */
+} kxg_status;
+
+/* Precision of the contraction sum_{n,m} A f f (the loss term, the
+ * projection and all state updates are FP64 in every case). */
+typedef enum {
+    KXG_F64 = 0,     /* FP64 stream over the dense kernel tensor          */
+    KXG_F32 = 1,     /* FP32: stream for B <= 4, MFMA GEMM above          */
+    KXG_BF16X3 = 2,  /* BF16 MFMA, hi+lo split of A and of f_n f_m,
+                        3 products, FP32 accumulation                     */
+    KXG_F16X3 = 3    /* FP16 MFMA, hi+lo split with power-of-two scaling  */
+} kxg_prec;
+#define KXG_PREC_BIT(p) (1u << (p))
+
+/* Angular integral of the reduced kernel (App. B). */
+typedef enum {
+    KXG_QUAD_GL = 0,    /* Gauss-Legendre in mu, analytic nu (eq. app_I_mu) */
+    KXG_QUAD_EXACT = 1  /* closed form of the same double integral          */
+} kxg_quad;
+
+/* Momentum grid and model (Sec. 4.1 and App. B).  All host memory, read
+ * only during kxg_kernel_build. */
+typedef struct {
+    int32_t n;          /* grid points, 4 <= n <= 1024                        */
+    const double *p;    /* [n] physical momenta, > 0, strictly increasing     */
+    const double *dp;   /* [n] widths Delta p_i, or NULL for the trapezoid in
+                           ln p (interior p_i (ln p_{i+1} - ln p_{i-1})/2,
+                           half that at the two ends)                          */
+    double mass;        /* particle mass m > 0                                 */
+    double g_dof;       /* internal degrees of freedom g_chi > 0               */
+    double m2;          /* constant |M|^2 > 0 (contact interaction)            */
+    int32_t n_mu;       /* Gauss-Legendre nodes in mu (the paper uses 18)      */
+    int32_t quad;       /* kxg_quad                                            */
+} kxg_grid;
+
+typedef struct kxg_kernel kxg_kernel;
+
+/* Build the kernel tensors of a grid (App. B eqs. app_fourth_momentum to
+ * app_interp_weights, Sec. 4.1 eq. discrete_weight): on the device, for every
+ * (i,n,m) the fourth momentum from energy conservation, the kinematic cuts,
+ * the angular integral and the weight W_inm = A[i,n,m]; then R[i,j] from the
+ * interpolation bracket of the fourth momentum.  The FP64 tensors are always
+ * built; prec_mask (bits KXG_PREC_BIT(p)) selects the extra device copies.
+ * b_cap is the largest batch any later kxg_eval on this handle will pass
+ * (sizes its workspace).  Blocks until the build has finished.
+ * Errors: KXG_EINVAL (grid fields out of range, p not increasing, b_cap < 1),
+ * KXG_ENOMEM, KXG_EHIP. */
+kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask,
+                            int32_t b_cap, void *stream, kxg_kernel **out);
+
+/* Release a kernel handle and all its device memory (NULL is a no-op). */
+void kxg_kernel_free(kxg_kernel *k);
+
+/* Grid size n of a handle. */
+int32_t kxg_kernel_n(const kxg_kernel *k);
+
+/* Device bytes held for precision prec (the tensors an evaluation at that
+ * precision reads), or for all of the handle if prec < 0.  Used for
+ * admission by memory footprint.  0 if the precision was not built. */
+size_t kxg_kernel_bytes(const kxg_kernel *k, int32_t prec);
+
+/* Copy the FP64 tensors to host memory: A_host [n][n][n] (m fastest),
+ * R_host [n][n].  Either may be NULL.  Synchronous. */
+kxg_status kxg_kernel_export(const kxg_kernel *k, double *A_host, double *R_host);
+
+/* Host copies of the grid quantities the library uses: widths dp, energies
+ * E = sqrt(p^2+m^2), kinetic energies K = E - m, moment weights h = p^2 dp
+ * (App. B).  Any may be NULL. */
+kxg_status kxg_kernel_grid(const kxg_kernel *k, double *dp, double *E,
+                           double *K, double *h);
+
+/* Evaluation flags. */
+#define KXG_PROJECT 1u     /* apply the two-moment projection of App. C      */
+#define KXG_NDIAG 12       /* diagnostics per distribution, see kxg_eval     */
+
+/* Evaluate C[f] for B distributions (Sec. 4.1 eq. discrete_collision_
+ * operator; projection of App. C when flags has KXG_PROJECT).
+ *  f_dev   device [B][n] FP64 input distributions
+ *  C_dev   device [B][n] FP64 output (raw or projected)
+ *  diag_dev device [B][KXG_NDIAG] FP64 or NULL:
+ *          0 alpha, 1 beta (App. C, E-form: correction xi (alpha + beta E)),
+ *          2 eps_N raw, 3 eps_E raw, 4 eps_N projected, 5 eps_E projected
+ *          (eq. app_epsilon_definition), 6 R_N, 7 R_E
+ *          (eq. app_projection_relative_correction), 8 max_i sum_j R_ij f_j
+ *          (largest loss rate), 9 max_i |gain_i|, 10 status bits
+ *          (1 non-finite input, 2 negative input, 4 non-finite output),
+ *          11 number moment sum_i h_i f_i.
+ *  1 <= B <= b_cap of the handle.  Calls on one handle share its workspace:
+ *  serialise them on one stream.  Asynchronous.
+ * Errors: KXG_EINVAL, KXG_EUNSUPPORTED (precision not built), KXG_EHIP. */
+kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev,
+                    int32_t B, double *C_dev, uint32_t flags, double *diag_dev,
+                    void *stream);
+
+/* Discrete moments of B distributions (App. B): out_dev [B][3] =
+ * { sum h f, sum h E f, -sum_{f>0} h f (ln f - 1) }.  Asynchronous. */
+kxg_status kxg_moments(const kxg_kernel *k, const double *f_dev, int32_t B,
+                       double *out_dev, void *stream);
+
+/* Gauss-Legendre nodes (ascending) and weights on [-1,1] as the library
+ * computes them (Golub-Welsch), host memory, n >= 1. */
+kxg_status kxg_gauss_legendre(int32_t n, double *x, double *w);
+
+/* ---------------- on-device steppers (Sec. 4.2) -------------------------- */
+
+typedef enum { KXG_RK4 = 0, KXG_HEUN = 1 } kxg_stepper_kind;
+typedef enum { KXG_EXP_NONE = 0, KXG_EXP_RADIATION = 1 } kxg_expansion;
+
+typedef struct {
+    int32_t kind;       /* KXG_RK4: fixed classical RK4 in t on df/dt = lambda C.
+                           KXG_HEUN: adaptive Heun (Euler predictor, trapezoid
+                           corrector, their difference as error estimate)      */
+    int32_t prec;       /* kxg_prec of the contraction                          */
+    int32_t expansion;  /* KXG_EXP_RADIATION (Heun only): state g = a^3 p^3 f in
+                           u = ln a, H = h_i e^{-2u}, conservative upwind drift;
+                           KXG_EXP_NONE: state f                               */
+    int32_t project;    /* 1: evolve with the projected operator (App. C)       */
+    int32_t adapt;      /* Heun: 1 adapt dt, 0 take dt as set (replay)          */
+    int32_t b_cap;      /* number of slots                                      */
+    double rtol;        /* Heun controller: err = max |x_new - x*| /
+                           (atol + rtol max(|x|,|x_new|)), accept if err <= 1   */
+    double atol_rel;    /* atol = atol_rel * max |x(0)| per slot                */
+    double safety;      /* dt *= clamp(safety err^-1/2, fac_min, fac_max)       */
+    double fac_min, fac_max;
+    double dt_min;      /* Heun: a slot whose dt falls below this fails         */
+} kxg_stepper_params;
+
+typedef struct {
+    double lambda;      /* rate prefactor lambda of df/dt = lambda C             */
+    double h_i;         /* H at u = 0 (expansion) or 1 (none); <= 0 selects the
+                           largest initial loss rate max_i sum_j R_ij f_j(0)     */
+    double dt;          /* RK4: step in t; Heun: first step (u or t);
+                           <= 0 selects 0.1 / (lambda * rate0) for RK4, 1e-3 Heun */
+    double t_end;       /* end of t (RK4) or u (Heun)                            */
+    int32_t max_steps;  /* accepted-step cap (<= 0: none)                        */
+} kxg_solve_params;
+
+typedef struct {
+    double t;           /* time (RK4) or u = ln a (Heun)                        */
+    double dt;          /* next step                                           */
+    double outflow;     /* comoving number drifted out below p_0 (expansion)   */
+    double h_i;         /* the H_i (or rate0) in use                           */
+    int32_t steps;      /* accepted steps                                      */
+    int32_t rejected;   /* rejected Heun attempts                              */
+    int32_t status;     /* 0 running, 1 finished, -1 non-finite, -2 dt underflow,
+                           -3 free slot                                        */
+    int32_t pad;
+} kxg_slot_state;
+
+typedef struct kxg_stepper kxg_stepper;
+
+/* Create a stepper with b_cap slots over a kernel handle (which must outlive
+ * it and have params->prec built).  Allocates its own state and workspace.
+ * Errors: KXG_EINVAL, KXG_EUNSUPPORTED, KXG_ENOMEM, KXG_EHIP. */
+kxg_status kxg_stepper_create(const kxg_kernel *k, const kxg_stepper_params *params,
+                              kxg_stepper **out);
+void kxg_stepper_free(kxg_stepper *s);
+
+/* Load slot `slot` with the distribution f0_dev (device [n] FP64) and its
+ * solve parameters; the slot becomes active.  Asynchronous on stream. */
+kxg_status kxg_stepper_set(kxg_stepper *s, int32_t slot, const double *f0_dev,
+                           const kxg_solve_params *sp, void *stream);
+
+/* Free a slot: it stops being advanced, its state is zeroed and it counts
+ * as empty.  Asynchronous on stream. */
+kxg_status kxg_stepper_release(kxg_stepper *s, int32_t slot, void *stream);
+
+/* Advance every running slot by n_iter iterations (RK4: steps; Heun:
+ * attempted steps, two operator calls each).  Slots that reach t_end,
+ * max_steps or fail stop by themselves on the device.  Asynchronous. */
+kxg_status kxg_stepper_advance(kxg_stepper *s, int32_t n_iter, void *stream);
+
+/* Set the next dt of every slot from host memory dt_host [b_cap] (replay of
+ * a given step sequence with adapt = 0).  Asynchronous (copies first). */
+kxg_status kxg_stepper_set_dt(kxg_stepper *s, const double *dt_host, void *stream);
+
+/* Copy all slot states to host memory out [b_cap].  Synchronises stream. */
+kxg_status kxg_stepper_query(kxg_stepper *s, kxg_slot_state *out, void *stream);
+
+/* Copy a slot's distribution f (converted from g = a^3 p^3 f when expanding)
+ * into device memory f_dev [n].  Asynchronous. */
+kxg_status kxg_stepper_get(kxg_stepper *s, int32_t slot, double *f_dev, void *stream);
+
+/* Checkpoint of one slot (state vector, t, dt, counters, controller state)
+ * to host bytes: with buf == NULL sets *len to the size needed; otherwise
+ * writes *len bytes.  kxg_stepper_load restores it into a slot.  Both
+ * synchronise the stream. */
+kxg_status kxg_stepper_save(kxg_stepper *s, int32_t slot, void *buf, size_t *len,
+                            void *stream);
+kxg_status kxg_stepper_load(kxg_stepper *s, int32_t slot, const void *buf, size_t len,
+                            void *stream);
+
+/* ---------------- profiling -------------------------------------------------
+ * While a profile is open, every launch of a gain kernel (the MFMA GEMM or
+ * the single-distribution stream kernel, inside kxg_eval and the steppers)
+ * is bracketed by two HIP events on the stream it is launched on, for up to
+ * `capacity` launches (process-wide; not for concurrent use from several
+ * threads).  kxg_profile_end waits for the events and returns the summed
+ * kernel time in milliseconds and the number of launches measured. */
+kxg_status kxg_profile_begin(int32_t capacity);
+kxg_status kxg_profile_end(double *total_ms, int32_t *launches);
+
+/* Thread-local message of the last error ("" if none). */
+const char *kxg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KXG_H */

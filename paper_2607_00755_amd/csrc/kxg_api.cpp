@@ -1,0 +1,668 @@
+// C ABI of libkxg (declared in include/kxg.h): argument checks, handles,
+// device memory, and the order of kernel launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kxg_step.h"
+
+namespace kxg {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+// Gauss-Legendre rule by Golub-Welsch: the nodes are the eigenvalues of the
+// symmetric tridiagonal Jacobi matrix of the Legendre polynomials
+// (zero diagonal, off-diagonal k / sqrt(4k^2 - 1)), the weights 2 v_0^2 with
+// v_0 the first component of each normalised eigenvector.  Implicit QL with
+// Wilkinson-type shifts, tracking only the first row of the eigenvectors.
+void gauss_legendre(int n, double *x, double *w)
+{
+    std::vector<double> d(n, 0.0), e(n, 0.0), z(n, 0.0);
+    for (int k = 1; k < n; ++k) e[k - 1] = k / std::sqrt(4.0 * k * k - 1.0);
+    z[0] = 1.0;
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0; iter < 200; ++iter) {
+            int m = l;
+            for (; m < n - 1; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= 2.220446049250313e-16 * dd || e[m] == 0.0) break;
+            }
+            if (m == l) break;
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+            double s = 1.0, c = 1.0, p = 0.0;
+            int i = m - 1;
+            for (; i >= l; --i) {
+                double f = s * e[i];
+                const double b = c * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
+                f = z[i + 1];
+                z[i + 1] = s * z[i] + c * f;
+                z[i] = c * z[i] - s * f;
+            }
+            if (r == 0.0 && i >= l) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+    for (int i = 0; i < n; ++i) {
+        // symmetrise: the rule is exactly symmetric about 0
+        const int j = idx[i], jm = idx[n - 1 - i];
+        x[i] = 0.5 * (d[j] - d[jm]);
+        w[i] = 0.5 * (2.0 * z[j] * z[j] + 2.0 * z[jm] * z[jm]);
+    }
+}
+
+static int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Process-wide gain-kernel profile: pairs of timing events.
+struct Profile {
+    bool on = false;
+    std::vector<hipEvent_t> a, b;
+    int used = 0;
+};
+static Profile g_prof;
+
+void profile_mark_begin(hipStream_t s)
+{
+    if (g_prof.on && g_prof.used < (int)g_prof.a.size()) (void)hipEventRecord(g_prof.a[g_prof.used], s);
+}
+
+void profile_mark_end(hipStream_t s)
+{
+    if (g_prof.on && g_prof.used < (int)g_prof.a.size()) {
+        (void)hipEventRecord(g_prof.b[g_prof.used], s);
+        ++g_prof.used;
+    }
+}
+
+static void profile_clear()
+{
+    for (auto e : g_prof.a) (void)hipEventDestroy(e);
+    for (auto e : g_prof.b) (void)hipEventDestroy(e);
+    g_prof = Profile{};
+}
+
+static int choose_splits(const Geometry &g, int b_cap)
+{
+    const int bbw = b_cap <= 32 ? 1 : (b_cap <= 64 ? 2 : 4);
+    const int tiles = div_up(b_cap, 32 * bbw) * g.nib;
+    int s = div_up(512, tiles);                       // about two workgroups per CU
+    const int cap = (int)std::max<long>(1, g.dksteps / (kWaves * 4));  // >= 4 steps a wave
+    return std::max(1, std::min(s, cap));
+}
+
+template <typename T>
+static kxg_status dalloc(T **ptr, size_t count)
+{
+    if (hipMalloc((void **)ptr, count * sizeof(T)) != hipSuccess) {
+        *ptr = nullptr;
+        set_error("device allocation of %zu bytes failed", count * sizeof(T));
+        return KXG_ENOMEM;
+    }
+    return KXG_OK;
+}
+
+static void release(kxg_kernel *k)
+{
+    if (!k) return;
+    void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_A32,
+                    k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    free_workspace(k->ws);
+    delete k;
+}
+
+}  // namespace kxg
+
+using namespace kxg;
+
+struct kxg_stepper {
+    const kxg_kernel *k = nullptr;
+    kxg_stepper_params prm{};
+    SlotDev *d_slots = nullptr;
+    double *d_x = nullptr, *d_fb = nullptr, *d_C = nullptr, *d_acc = nullptr, *d_xs = nullptr;
+    double *d_dt = nullptr;
+    Workspace ws;
+    std::vector<char> used;
+    int b_hi = 0;
+};
+
+extern "C" {
+
+const char *kxg_last_error(void) { return g_err; }
+
+kxg_status kxg_profile_begin(int32_t capacity)
+{
+    g_err[0] = 0;
+    if (capacity < 1 || capacity > (1 << 20)) { set_error("kxg_profile_begin: bad capacity"); return KXG_EINVAL; }
+    profile_clear();
+    g_prof.a.resize(capacity);
+    g_prof.b.resize(capacity);
+    for (int i = 0; i < capacity; ++i) {
+        if (hipEventCreate(&g_prof.a[i]) != hipSuccess || hipEventCreate(&g_prof.b[i]) != hipSuccess) {
+            g_prof.a.resize(i);
+            g_prof.b.resize(i);
+            profile_clear();
+            set_error("kxg_profile_begin: hipEventCreate failed");
+            return KXG_EHIP;
+        }
+    }
+    g_prof.on = true;
+    return KXG_OK;
+}
+
+kxg_status kxg_profile_end(double *total_ms, int32_t *launches)
+{
+    g_err[0] = 0;
+    if (!total_ms || !launches) { set_error("kxg_profile_end: null output"); return KXG_EINVAL; }
+    double tot = 0.0;
+    for (int i = 0; i < g_prof.used; ++i) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(g_prof.b[i]) != hipSuccess ||
+            hipEventElapsedTime(&ms, g_prof.a[i], g_prof.b[i]) != hipSuccess) {
+            profile_clear();
+            set_error("kxg_profile_end: event query failed");
+            return KXG_EHIP;
+        }
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = g_prof.used;
+    profile_clear();
+    return KXG_OK;
+}
+
+kxg_status kxg_gauss_legendre(int32_t n, double *x, double *w)
+{
+    g_err[0] = 0;
+    if (n < 1 || n > 100000 || !x || !w) {
+        set_error("kxg_gauss_legendre: need n >= 1 and output arrays");
+        return KXG_EINVAL;
+    }
+    gauss_legendre(n, x, w);
+    return KXG_OK;
+}
+
+kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_cap,
+                            void *stream, kxg_kernel **out)
+{
+    g_err[0] = 0;
+    if (!grid || !out) { set_error("kxg_kernel_build: null grid or out"); return KXG_EINVAL; }
+    *out = nullptr;
+    const int n = grid->n;
+    if (n < 4 || n > kMaxN) { set_error("kxg_kernel_build: n=%d outside [4, %d]", n, kMaxN); return KXG_EINVAL; }
+    if (!grid->p) { set_error("kxg_kernel_build: p is NULL"); return KXG_EINVAL; }
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(grid->p[i]) || grid->p[i] <= 0.0) { set_error("kxg_kernel_build: p[%d] not finite and > 0", i); return KXG_EINVAL; }
+        if (i > 0 && !(grid->p[i] > grid->p[i - 1])) { set_error("kxg_kernel_build: p not strictly increasing at %d", i); return KXG_EINVAL; }
+        if (grid->dp && !(std::isfinite(grid->dp[i]) && grid->dp[i] > 0.0)) { set_error("kxg_kernel_build: dp[%d] not finite and > 0", i); return KXG_EINVAL; }
+    }
+    if (!(grid->mass > 0.0) || !(grid->g_dof > 0.0) || !(grid->m2 > 0.0) ||
+        !std::isfinite(grid->mass) || !std::isfinite(grid->g_dof) || !std::isfinite(grid->m2)) {
+        set_error("kxg_kernel_build: mass, g_dof and m2 must be finite and > 0");
+        return KXG_EINVAL;
+    }
+    if (grid->quad != KXG_QUAD_GL && grid->quad != KXG_QUAD_EXACT) { set_error("kxg_kernel_build: bad quad %d", grid->quad); return KXG_EINVAL; }
+    if (grid->quad == KXG_QUAD_GL && (grid->n_mu < 1 || grid->n_mu > 4096)) { set_error("kxg_kernel_build: n_mu=%d outside [1, 4096]", grid->n_mu); return KXG_EINVAL; }
+    if (b_cap < 1 || b_cap > (1 << 20)) { set_error("kxg_kernel_build: b_cap=%d outside [1, 2^20]", b_cap); return KXG_EINVAL; }
+    if (prec_mask & ~0xFu) { set_error("kxg_kernel_build: unknown precision bits 0x%x", prec_mask); return KXG_EINVAL; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    kxg_kernel *k = new (std::nothrow) kxg_kernel;
+    if (!k) { set_error("host allocation failed"); return KXG_ENOMEM; }
+    k->n = n;
+    k->mass = grid->mass;
+    k->gdof = grid->g_dof;
+    k->m2 = grid->m2;
+    k->quad = grid->quad;
+    k->nmu = grid->quad == KXG_QUAD_GL ? grid->n_mu : 0;
+    k->b_cap = b_cap;
+    k->prec_mask = prec_mask | KXG_PREC_BIT(KXG_F64);
+    k->p.assign(grid->p, grid->p + n);
+    k->dp.resize(n);
+    k->E.resize(n);
+    k->K.resize(n);
+    k->h.resize(n);
+    // Energies, kinetic energies (K = p^2/(E+m), no cancellation), widths
+    // (trapezoid in ln p unless given) and moment weights h = p^2 dp.
+    for (int i = 0; i < n; ++i) {
+        const double p = k->p[i];
+        k->E[i] = std::sqrt(p * p + k->mass * k->mass);
+        k->K[i] = (p * p) / (k->E[i] + k->mass);
+    }
+    for (int i = 0; i < n; ++i) {
+        if (grid->dp) {
+            k->dp[i] = grid->dp[i];
+        } else {
+            const double left = std::log(k->p[i > 0 ? i - 1 : i]);
+            const double right = std::log(k->p[i < n - 1 ? i + 1 : i]);
+            k->dp[i] = k->p[i] * (right - left) / 2.0;
+        }
+        k->h[i] = k->p[i] * k->p[i] * k->dp[i];
+    }
+    Geometry &g = k->geo;
+    g.nb = div_up(n, kBlk);
+    g.npairs = g.nb * (g.nb + 1) / 2;
+    g.nib = div_up(n, kIBlk);
+    g.ipad = g.nib * kIBlk;
+    g.dksteps = (long)g.npairs * kBlk;
+    k->gemm_splits = choose_splits(g, b_cap);
+
+    const size_t n3 = (size_t)n * n * n, n2 = (size_t)n * n;
+    const bool want32 = prec_mask & KXG_PREC_BIT(KXG_F32);
+    const bool wantbf = prec_mask & KXG_PREC_BIT(KXG_BF16X3);
+    const bool wanth = prec_mask & KXG_PREC_BIT(KXG_F16X3);
+    const size_t packed = (size_t)g.nib * g.npairs * kBlk * 512;   // elements per copy
+    kxg_status st = KXG_OK;
+#define KXG_ALLOC(ptr, cnt) \
+    if (st == KXG_OK) st = dalloc(&(ptr), (cnt))
+    KXG_ALLOC(k->d_p, n);
+    KXG_ALLOC(k->d_dp, n);
+    KXG_ALLOC(k->d_E, n);
+    KXG_ALLOC(k->d_K, n);
+    KXG_ALLOC(k->d_h, n);
+    KXG_ALLOC(k->d_A64, n3);
+    KXG_ALLOC(k->d_RT, n2);
+    KXG_ALLOC(k->d_pairs, 2 * (size_t)g.npairs);
+    if (want32) { KXG_ALLOC(k->d_A32, n3); KXG_ALLOC(k->d_G32, packed); }
+    if (wantbf) { KXG_ALLOC(k->d_Gbf, 2 * packed); }
+    if (wanth) { KXG_ALLOC(k->d_Gh, 2 * packed); KXG_ALLOC(k->d_hrow, (size_t)g.ipad); }
+    double *d_xmu = nullptr, *d_wmu = nullptr;
+    if (k->nmu > 0) { KXG_ALLOC(d_xmu, (size_t)k->nmu); KXG_ALLOC(d_wmu, (size_t)k->nmu); }
+#undef KXG_ALLOC
+    if (st != KXG_OK) {
+        if (d_xmu) (void)hipFree(d_xmu);
+        if (d_wmu) (void)hipFree(d_wmu);
+        release(k);
+        return st;
+    }
+    std::vector<int> pairs(2 * (size_t)g.npairs);
+    {
+        int q = 0;
+        for (int kb = 0; kb < g.nb; ++kb)
+            for (int mb = kb; mb < g.nb; ++mb) {
+                pairs[2 * q] = kb;
+                pairs[2 * q + 1] = mb;
+                ++q;
+            }
+    }
+    std::vector<double> xmu(k->nmu), wmu(k->nmu);
+    if (k->nmu > 0) gauss_legendre(k->nmu, xmu.data(), wmu.data());
+    hipError_t e = hipSuccess;
+#define KXG_H2D(dst, src, bytes) \
+    if (e == hipSuccess) e = hipMemcpy((dst), (src), (bytes), hipMemcpyHostToDevice)
+    KXG_H2D(k->d_p, k->p.data(), n * sizeof(double));
+    KXG_H2D(k->d_dp, k->dp.data(), n * sizeof(double));
+    KXG_H2D(k->d_E, k->E.data(), n * sizeof(double));
+    KXG_H2D(k->d_K, k->K.data(), n * sizeof(double));
+    KXG_H2D(k->d_h, k->h.data(), n * sizeof(double));
+    KXG_H2D(k->d_pairs, pairs.data(), pairs.size() * sizeof(int));
+    if (k->nmu > 0) {
+        KXG_H2D(d_xmu, xmu.data(), k->nmu * sizeof(double));
+        KXG_H2D(d_wmu, wmu.data(), k->nmu * sizeof(double));
+    }
+#undef KXG_H2D
+    if (e == hipSuccess) e = launch_build_A(*k, d_xmu, d_wmu, s);
+    if (e == hipSuccess) e = launch_build_R(*k, s);
+    if (e == hipSuccess) e = launch_derive(*k, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (d_xmu) (void)hipFree(d_xmu);
+    if (d_wmu) (void)hipFree(d_wmu);
+    if (e != hipSuccess) {
+        set_error("kxg_kernel_build: %s", hipGetErrorString(e));
+        release(k);
+        return KXG_EHIP;
+    }
+    st = alloc_workspace(*k, b_cap, k->ws);
+    if (st != KXG_OK) { release(k); return st; }
+    k->bytes[KXG_F64] = (n3 + n2) * sizeof(double);
+    if (want32) k->bytes[KXG_F32] = (n3 + packed) * sizeof(float) + n2 * sizeof(double);
+    if (wantbf) k->bytes[KXG_BF16X3] = 2 * packed * sizeof(uint16_t) + n2 * sizeof(double);
+    if (wanth) k->bytes[KXG_F16X3] = 2 * packed * sizeof(uint16_t) + n2 * sizeof(double);
+    *out = k;
+    return KXG_OK;
+}
+
+void kxg_kernel_free(kxg_kernel *k) { release(k); }
+
+int32_t kxg_kernel_n(const kxg_kernel *k) { return k ? k->n : 0; }
+
+size_t kxg_kernel_bytes(const kxg_kernel *k, int32_t prec)
+{
+    if (!k) return 0;
+    if (prec >= 0 && prec < 4) return k->bytes[prec];
+    size_t tot = k->ws.part_bytes;
+    const size_t n3 = (size_t)k->n * k->n * k->n;
+    tot += (n3 + (size_t)k->n * k->n) * sizeof(double);
+    for (int q = 1; q < 4; ++q)
+        if (k->bytes[q]) tot += k->bytes[q] - (size_t)k->n * k->n * sizeof(double);
+    return tot;
+}
+
+kxg_status kxg_kernel_export(const kxg_kernel *k, double *A_host, double *R_host)
+{
+    g_err[0] = 0;
+    if (!k) { set_error("kxg_kernel_export: null handle"); return KXG_EINVAL; }
+    const size_t n = k->n;
+    if (A_host) KXG_TRY_HIP(hipMemcpy(A_host, k->d_A64, n * n * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (R_host) {
+        std::vector<double> rt(n * n);
+        KXG_TRY_HIP(hipMemcpy(rt.data(), k->d_RT, n * n * sizeof(double), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < n; ++i)
+            for (size_t j = 0; j < n; ++j) R_host[i * n + j] = rt[j * n + i];
+    }
+    return KXG_OK;
+}
+
+kxg_status kxg_kernel_grid(const kxg_kernel *k, double *dp, double *E, double *K, double *h)
+{
+    g_err[0] = 0;
+    if (!k) { set_error("kxg_kernel_grid: null handle"); return KXG_EINVAL; }
+    const size_t b = k->n * sizeof(double);
+    if (dp) std::memcpy(dp, k->dp.data(), b);
+    if (E) std::memcpy(E, k->E.data(), b);
+    if (K) std::memcpy(K, k->K.data(), b);
+    if (h) std::memcpy(h, k->h.data(), b);
+    return KXG_OK;
+}
+
+static kxg_status check_prec(const kxg_kernel *k, int32_t prec)
+{
+    if (prec < 0 || prec > 3) { set_error("unknown precision %d", prec); return KXG_EINVAL; }
+    if (!(k->prec_mask & KXG_PREC_BIT(prec))) {
+        set_error("precision %d was not built into this kernel handle", prec);
+        return KXG_EUNSUPPORTED;
+    }
+    return KXG_OK;
+}
+
+kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev, int32_t B,
+                    double *C_dev, uint32_t flags, double *diag_dev, void *stream)
+{
+    g_err[0] = 0;
+    if (!k || !f_dev || !C_dev) { set_error("kxg_eval: null handle or buffer"); return KXG_EINVAL; }
+    if (B < 1 || B > k->b_cap) { set_error("kxg_eval: B=%d outside [1, b_cap=%d]", B, k->b_cap); return KXG_EINVAL; }
+    if (flags & ~KXG_PROJECT) { set_error("kxg_eval: unknown flags 0x%x", flags); return KXG_EINVAL; }
+    kxg_status st = check_prec(k, prec);
+    if (st != KXG_OK) return st;
+    return eval_impl(*k, k->ws, prec, f_dev, B, C_dev, flags, diag_dev,
+                     static_cast<hipStream_t>(stream));
+}
+
+kxg_status kxg_moments(const kxg_kernel *k, const double *f_dev, int32_t B, double *out_dev,
+                       void *stream)
+{
+    g_err[0] = 0;
+    if (!k || !f_dev || !out_dev || B < 1) { set_error("kxg_moments: bad arguments"); return KXG_EINVAL; }
+    KXG_TRY_HIP(launch_moments(*k, f_dev, B, out_dev, static_cast<hipStream_t>(stream)));
+    return KXG_OK;
+}
+
+// ------------------------------------------------------------------ steppers
+
+kxg_status kxg_stepper_create(const kxg_kernel *k, const kxg_stepper_params *prm,
+                              kxg_stepper **out)
+{
+    g_err[0] = 0;
+    if (!k || !prm || !out) { set_error("kxg_stepper_create: null argument"); return KXG_EINVAL; }
+    *out = nullptr;
+    if (prm->kind != KXG_RK4 && prm->kind != KXG_HEUN) { set_error("kxg_stepper_create: bad kind"); return KXG_EINVAL; }
+    if (prm->expansion != KXG_EXP_NONE && prm->expansion != KXG_EXP_RADIATION) { set_error("kxg_stepper_create: bad expansion"); return KXG_EINVAL; }
+    if (prm->expansion == KXG_EXP_RADIATION && prm->kind != KXG_HEUN) { set_error("kxg_stepper_create: expansion needs the Heun stepper"); return KXG_EINVAL; }
+    if (prm->b_cap < 1 || prm->b_cap > (1 << 20)) { set_error("kxg_stepper_create: bad b_cap"); return KXG_EINVAL; }
+    if (prm->kind == KXG_HEUN && prm->adapt &&
+        !(prm->rtol > 0 && prm->safety > 0 && prm->fac_min > 0 && prm->fac_max >= prm->fac_min)) {
+        set_error("kxg_stepper_create: bad Heun controller parameters");
+        return KXG_EINVAL;
+    }
+    kxg_status st = check_prec(k, prm->prec);
+    if (st != KXG_OK) return st;
+    kxg_stepper *s = new (std::nothrow) kxg_stepper;
+    if (!s) { set_error("host allocation failed"); return KXG_ENOMEM; }
+    s->k = k;
+    s->prm = *prm;
+    const size_t rows = (size_t)prm->b_cap * k->n;
+    if (st == KXG_OK) st = dalloc(&s->d_slots, (size_t)prm->b_cap);
+    if (st == KXG_OK) st = dalloc(&s->d_x, rows);
+    if (st == KXG_OK) st = dalloc(&s->d_fb, rows);
+    if (st == KXG_OK) st = dalloc(&s->d_C, rows);
+    if (st == KXG_OK) st = dalloc(&s->d_acc, rows);
+    if (st == KXG_OK) st = dalloc(&s->d_xs, rows);
+    if (st == KXG_OK) st = dalloc(&s->d_dt, (size_t)prm->b_cap);
+    if (st == KXG_OK) st = alloc_workspace(*k, prm->b_cap, s->ws);
+    if (st == KXG_OK) {
+        std::vector<SlotDev> init(prm->b_cap);
+        for (auto &q : init) {
+            std::memset(&q, 0, sizeof q);
+            q.status = -3;
+        }
+        if (hipMemcpy(s->d_slots, init.data(), init.size() * sizeof(SlotDev), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(s->d_x, 0, rows * sizeof(double)) != hipSuccess ||
+            hipMemset(s->d_fb, 0, rows * sizeof(double)) != hipSuccess) {
+            set_error("kxg_stepper_create: initialisation failed");
+            st = KXG_EHIP;
+        }
+    }
+    if (st != KXG_OK) {
+        kxg_stepper_free(s);
+        return st;
+    }
+    s->used.assign(prm->b_cap, 0);
+    *out = s;
+    return KXG_OK;
+}
+
+void kxg_stepper_free(kxg_stepper *s)
+{
+    if (!s) return;
+    void *ptrs[] = {s->d_slots, s->d_x, s->d_fb, s->d_C, s->d_acc, s->d_xs, s->d_dt};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    free_workspace(s->ws);
+    delete s;
+}
+
+static void update_hi(kxg_stepper *s)
+{
+    int hi = 0;
+    for (int b = 0; b < (int)s->used.size(); ++b)
+        if (s->used[b]) hi = b + 1;
+    s->b_hi = hi;
+}
+
+kxg_status kxg_stepper_set(kxg_stepper *s, int32_t slot, const double *f0_dev,
+                           const kxg_solve_params *sp, void *stream)
+{
+    g_err[0] = 0;
+    if (!s || !f0_dev || !sp) { set_error("kxg_stepper_set: null argument"); return KXG_EINVAL; }
+    if (slot < 0 || slot >= s->prm.b_cap) { set_error("kxg_stepper_set: slot %d out of range", slot); return KXG_EINVAL; }
+    if (!std::isfinite(sp->lambda) || sp->lambda < 0.0 || !std::isfinite(sp->t_end) || sp->t_end <= 0.0 ||
+        !std::isfinite(sp->dt) || !std::isfinite(sp->h_i)) {
+        set_error("kxg_stepper_set: lambda >= 0, finite dt/h_i and t_end > 0 required");
+        return KXG_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SlotDev init;
+    std::memset(&init, 0, sizeof init);
+    init.lam = sp->lambda;
+    init.hi_scale = sp->h_i;
+    init.dt = sp->dt;
+    init.t = 0.0;
+    init.tend = sp->t_end;
+    init.maxsteps = sp->max_steps;
+    init.status = 0;
+    KXG_TRY_HIP(launch_slot_init(slot, init, s->d_slots, st));
+    KXG_TRY_HIP(launch_slot_set(s->k->n, s->prm.kind, s->prm.expansion, s->prm.atol_rel, slot,
+                                s->d_slots, f0_dev, s->k->d_p, s->k->d_RT, s->d_x, s->d_fb, st));
+    s->used[slot] = 1;
+    update_hi(s);
+    return KXG_OK;
+}
+
+kxg_status kxg_stepper_release(kxg_stepper *s, int32_t slot, void *stream)
+{
+    g_err[0] = 0;
+    if (!s || slot < 0 || slot >= s->prm.b_cap) { set_error("kxg_stepper_release: bad slot"); return KXG_EINVAL; }
+    KXG_TRY_HIP(launch_slot_clear(s->k->n, slot, s->d_slots, s->d_x, s->d_fb,
+                                  static_cast<hipStream_t>(stream)));
+    s->used[slot] = 0;
+    update_hi(s);
+    return KXG_OK;
+}
+
+kxg_status kxg_stepper_advance(kxg_stepper *s, int32_t n_iter, void *stream)
+{
+    g_err[0] = 0;
+    if (!s || n_iter < 0) { set_error("kxg_stepper_advance: bad arguments"); return KXG_EINVAL; }
+    const int B = s->b_hi;
+    if (B == 0 || n_iter == 0) return KXG_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const kxg_kernel &k = *s->k;
+    const kxg_stepper_params &P = s->prm;
+    const uint32_t flags = P.project ? KXG_PROJECT : 0u;
+    for (int it = 0; it < n_iter; ++it) {
+        if (P.kind == KXG_RK4) {
+            for (int stage = 1; stage <= 4; ++stage) {
+                kxg_status r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
+                if (r != KXG_OK) return r;
+                KXG_TRY_HIP(launch_rk4_stage(stage, k.n, B, s->d_slots, s->d_x, s->d_acc, s->d_C, s->d_fb, st));
+            }
+        } else {
+            kxg_status r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
+            if (r != KXG_OK) return r;
+            KXG_TRY_HIP(launch_heun_pred(k.n, B, P.expansion, s->d_slots, k.d_p, k.d_dp, s->d_x,
+                                         s->d_acc, s->d_xs, s->d_C, s->d_fb, st));
+            r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
+            if (r != KXG_OK) return r;
+            KXG_TRY_HIP(launch_heun_corr(k.n, B, P.expansion, P.adapt, P.rtol, P.safety, P.fac_min,
+                                         P.fac_max, P.dt_min, s->d_slots, k.d_p, k.d_dp, s->d_x,
+                                         s->d_acc, s->d_xs, s->d_C, s->d_fb, st));
+        }
+    }
+    return KXG_OK;
+}
+
+kxg_status kxg_stepper_set_dt(kxg_stepper *s, const double *dt_host, void *stream)
+{
+    g_err[0] = 0;
+    if (!s || !dt_host) { set_error("kxg_stepper_set_dt: null argument"); return KXG_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    KXG_TRY_HIP(hipMemcpyAsync(s->d_dt, dt_host, s->prm.b_cap * sizeof(double), hipMemcpyHostToDevice, st));
+    KXG_TRY_HIP(launch_set_dt(s->prm.b_cap, s->d_dt, s->d_slots, st));
+    KXG_TRY_HIP(hipStreamSynchronize(st));
+    return KXG_OK;
+}
+
+kxg_status kxg_stepper_query(kxg_stepper *s, kxg_slot_state *out, void *stream)
+{
+    g_err[0] = 0;
+    if (!s || !out) { set_error("kxg_stepper_query: null argument"); return KXG_EINVAL; }
+    std::vector<SlotDev> h(s->prm.b_cap);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    KXG_TRY_HIP(hipMemcpyAsync(h.data(), s->d_slots, h.size() * sizeof(SlotDev), hipMemcpyDeviceToHost, st));
+    KXG_TRY_HIP(hipStreamSynchronize(st));
+    for (size_t b = 0; b < h.size(); ++b) {
+        out[b].t = h[b].t;
+        out[b].dt = h[b].dt;
+        out[b].outflow = h[b].outflow;
+        out[b].h_i = h[b].hi_scale;
+        out[b].steps = h[b].steps;
+        out[b].rejected = h[b].rejected;
+        out[b].status = s->used[b] ? h[b].status : -3;
+        out[b].pad = 0;
+    }
+    return KXG_OK;
+}
+
+kxg_status kxg_stepper_get(kxg_stepper *s, int32_t slot, double *f_dev, void *stream)
+{
+    g_err[0] = 0;
+    if (!s || !f_dev || slot < 0 || slot >= s->prm.b_cap) { set_error("kxg_stepper_get: bad arguments"); return KXG_EINVAL; }
+    KXG_TRY_HIP(launch_slot_get(s->k->n, s->prm.expansion, slot, s->d_slots, s->k->d_p, s->d_x,
+                                f_dev, static_cast<hipStream_t>(stream)));
+    return KXG_OK;
+}
+
+static const uint32_t kMagic = 0x4b584731u;   // "KXG1"
+
+kxg_status kxg_stepper_save(kxg_stepper *s, int32_t slot, void *buf, size_t *len, void *stream)
+{
+    g_err[0] = 0;
+    if (!s || !len || slot < 0 || slot >= s->prm.b_cap) { set_error("kxg_stepper_save: bad arguments"); return KXG_EINVAL; }
+    const int n = s->k->n;
+    const size_t need = 4 * sizeof(uint32_t) + sizeof(SlotDev) + n * sizeof(double);
+    if (!buf) { *len = need; return KXG_OK; }
+    if (*len < need) { set_error("kxg_stepper_save: buffer of %zu bytes, need %zu", *len, need); return KXG_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *c = static_cast<char *>(buf);
+    const uint32_t hdr[4] = {kMagic, (uint32_t)n, (uint32_t)s->prm.kind, (uint32_t)s->prm.expansion};
+    std::memcpy(c, hdr, sizeof hdr);
+    KXG_TRY_HIP(hipMemcpyAsync(c + sizeof hdr, s->d_slots + slot, sizeof(SlotDev), hipMemcpyDeviceToHost, st));
+    KXG_TRY_HIP(hipMemcpyAsync(c + sizeof hdr + sizeof(SlotDev), s->d_x + (size_t)slot * n,
+                               n * sizeof(double), hipMemcpyDeviceToHost, st));
+    KXG_TRY_HIP(hipStreamSynchronize(st));
+    *len = need;
+    return KXG_OK;
+}
+
+kxg_status kxg_stepper_load(kxg_stepper *s, int32_t slot, const void *buf, size_t len, void *stream)
+{
+    g_err[0] = 0;
+    if (!s || !buf || slot < 0 || slot >= s->prm.b_cap) { set_error("kxg_stepper_load: bad arguments"); return KXG_EINVAL; }
+    const int n = s->k->n;
+    const size_t need = 4 * sizeof(uint32_t) + sizeof(SlotDev) + n * sizeof(double);
+    uint32_t hdr[4];
+    if (len < need) { set_error("kxg_stepper_load: %zu bytes, need %zu", len, need); return KXG_EINVAL; }
+    std::memcpy(hdr, buf, sizeof hdr);
+    if (hdr[0] != kMagic || hdr[1] != (uint32_t)n || hdr[2] != (uint32_t)s->prm.kind ||
+        hdr[3] != (uint32_t)s->prm.expansion) {
+        set_error("kxg_stepper_load: checkpoint does not match this stepper");
+        return KXG_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const char *c = static_cast<const char *>(buf);
+    SlotDev sd;
+    std::memcpy(&sd, c + sizeof hdr, sizeof sd);
+    KXG_TRY_HIP(launch_slot_init(slot, sd, s->d_slots, st));
+    KXG_TRY_HIP(hipMemcpyAsync(s->d_x + (size_t)slot * n, c + sizeof hdr + sizeof(SlotDev),
+                               n * sizeof(double), hipMemcpyHostToDevice, st));
+    KXG_TRY_HIP(launch_slot_refresh(n, s->prm.expansion, slot, s->d_slots, s->k->d_p, s->d_x, s->d_fb, st));
+    KXG_TRY_HIP(hipStreamSynchronize(st));
+    s->used[slot] = 1;
+    update_hi(s);
+    return KXG_OK;
+}
+
+}  // extern "C"

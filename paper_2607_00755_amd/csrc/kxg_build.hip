@@ -1,0 +1,348 @@
+// Kernel-tensor build on the device (App. B of arXiv 2607.00755).
+//
+// Compiled with -ffp-contract=off: the kinematic cut and the interpolation
+// bracket of every (i,n,m) are decided on K~ = (K_n + K_m) - K_i with plain
+// IEEE double adds, from host-computed K, so that the decisions do not depend
+// on FMA contraction.
+#include "kxg_internal.h"
+
+#include <cmath>
+
+namespace kxg {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Angular factor of the reduced kernel by the paper's route (App. B,
+// eqs. app_cosphi to app_F_1d): Gauss-Legendre in mu; for each node the
+// quadratic a nu^2 + b nu + c >= 0 that encodes |cos phi| <= 1, its roots
+// clipped to [-1,1], and the analytic nu integral
+// I(mu) = [asin((2a nu_- + b)/sqrt(D)) - asin((2a nu_+ + b)/sqrt(D))]/sqrt(-a).
+// Returns p_n p_m sum_q w_q I(mu_q), i.e. the double integral over (mu, nu).
+__device__ double phi_gauss(double pi, double pn, double pm, double ki, double kn,
+                            double km, int nmu, const double *__restrict__ xmu,
+                            const double *__restrict__ wmu)
+{
+    // m^2 + E_n E_m - E_n E_i - E_m E_i == (K_n - K_i)(K_m - K_i) - p_i^2
+    const double base = (kn - ki) * (km - ki) - pi * pi;
+    const double pnpm = pn * pm;
+    double total = 0.0;
+    for (int q = 0; q < nmu; ++q) {
+        const double mu = xmu[q];
+        const double a0 = base + pi * pn * mu;
+        const double a1 = pi * pm - pnpm * mu;
+        const double kk = pnpm * pnpm * (1.0 - mu * mu);
+        const double qa = -(kk + a1 * a1);
+        const double qb = -2.0 * a0 * a1;
+        const double qc = kk - a0 * a0;
+        const double disc = qb * qb - 4.0 * qa * qc;
+        if (!(disc > 0.0) || !(qa < 0.0)) continue;
+        const double sq = sqrt(disc);
+        const double ra = (-qb + sq) / (2.0 * qa);
+        const double rb = (-qb - sq) / (2.0 * qa);
+        const double nlo = fmax(fmin(ra, rb), -1.0);
+        const double nhi = fmin(fmax(ra, rb), 1.0);
+        if (!(nlo < nhi)) continue;
+        const double ulo = fmin(fmax((2.0 * qa * nlo + qb) / sq, -1.0), 1.0);
+        const double uhi = fmin(fmax((2.0 * qa * nhi + qb) / sq, -1.0), 1.0);
+        total += wmu[q] * ((asin(ulo) - asin(uhi)) / sqrt(-qa));
+    }
+    return pnpm * total;
+}
+
+// Closed form of the same double integral for a constant matrix element:
+// pi S / (2 p1) with S the signed sum of |p1 +- p2 +- p3 +- p4| (momentum
+// delta written as a Fourier integral, solid angles done analytically).
+__device__ double phi_closed(double p1, double p2, double p3, double p4)
+{
+    const double pos = fabs(p1 - p2 - p3 - p4) + fabs(p1 - p2 + p3 + p4) +
+                       fabs(p1 + p2 - p3 + p4) + fabs(p1 + p2 + p3 - p4);
+    const double neg = fabs(p1 - p2 - p3 + p4) + fabs(p1 - p2 + p3 - p4) +
+                       fabs(p1 + p2 - p3 - p4) + (p1 + p2 + p3 + p4);
+    return kPi * (pos - neg) / (2.0 * p1);
+}
+
+// One thread per (i, n, m): the fourth momentum from energy conservation
+// (eq. app_fourth_momentum, in kinetic energy), the cuts E~ >= m and
+// q_min <= q~ <= q_max (K_0 <= K~ <= K_{N-1}), and
+// W_inm = dp_n dp_m F_inm / (2 E_i g) (eq. discrete_weight) with
+// F_inm = |M|^2 / (4 (2 pi)^4) (p_n p_m / (E_n E_m)) Phi_inm; the factor
+// p_n p_m/(E_n E_m) is the phase-space measure 1/(2E) of the two outgoing
+// legs that the reduction of eq. C22_general leaves behind.
+__global__ __launch_bounds__(256) void k_build_A(
+    int n, const double *__restrict__ p, const double *__restrict__ dp,
+    const double *__restrict__ E, const double *__restrict__ K, double mass, double gdof,
+    double m2, int quad, int nmu, const double *__restrict__ xmu,
+    const double *__restrict__ wmu, double *__restrict__ A)
+{
+    const long total = (long)n * n * n;
+    const double pref = m2 / (4.0 * (2.0 * kPi) * (2.0 * kPi) * (2.0 * kPi) * (2.0 * kPi));
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        const int m = (int)(idx % n);
+        const long r = idx / n;
+        const int a = (int)(r % n);
+        const int i = (int)(r / n);
+        const double kt = (K[a] + K[m]) - K[i];
+        double w = 0.0;
+        if (kt >= K[0] && kt <= K[n - 1]) {
+            double phi;
+            if (quad == KXG_QUAD_EXACT) {
+                const double pt = sqrt(kt * (kt + 2.0 * mass));
+                phi = phi_closed(p[i], pt, p[a], p[m]);
+            } else {
+                phi = phi_gauss(p[i], p[a], p[m], K[i], K[a], K[m], nmu, xmu, wmu);
+            }
+            const double jac = (p[a] * p[m]) / (E[a] * E[m]);
+            w = (dp[a] * dp[m]) * (pref * jac * phi) / (2.0 * E[i] * gdof);
+        }
+        A[idx] = w;
+    }
+}
+
+// First m in [0, n) whose K~ = (K_a + K_m) - K_i is >= x (strict: > x).
+__device__ int first_at_least(const double *__restrict__ K, int n, double ka, double ki,
+                              double x, bool strict)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const double kt = (ka + K[mid]) - ki;
+        const bool up = strict ? (kt > x) : (kt >= x);
+        if (up) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// One thread per (i, j): R[i][j] = sum over (n,m) of W_inm times the
+// energy-linear interpolation weight (eq. app_interp_weights) that the
+// fourth momentum puts on bin j.  The bracket is j_L = the largest
+// j <= N-2 with K_j <= K~; for fixed (i, n), K~ grows with m, so the m with
+// j_L = j form one contiguous range, found by bisection on the same K~
+// expression the weight kernel uses.  Summation order: n ascending, m
+// ascending.  Writes RT[j][i].
+__global__ __launch_bounds__(256) void k_build_R(int n, const double *__restrict__ K,
+                                                 const double *__restrict__ A,
+                                                 double *__restrict__ RT)
+{
+    const long total = (long)n * n;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / n);
+        const int j = (int)(idx % n);
+        const double ki = K[i];
+        double acc = 0.0;
+        for (int a = 0; a < n; ++a) {
+            const double ka = K[a];
+            const double *row = A + ((long)i * n + a) * n;
+            for (int side = 0; side < 2; ++side) {
+                // side 0: bracket j_L = j-1 (weight omega_R on j),
+                // side 1: bracket j_L = j   (weight omega_L on j)
+                const int jl = side == 0 ? j - 1 : j;
+                if (jl < 0 || jl > n - 2) continue;
+                const int lo = first_at_least(K, n, ka, ki, K[jl], false);
+                const int hi = (jl < n - 2) ? first_at_least(K, n, ka, ki, K[jl + 1], false)
+                                            : first_at_least(K, n, ka, ki, K[n - 1], true);
+                const double kl = K[jl], kr = K[jl + 1];
+                for (int m = lo; m < hi; ++m) {
+                    const double kt = (ka + K[m]) - ki;
+                    const double wr = (kt - kl) / (kr - kl);
+                    acc += side == 0 ? row[m] * wr : row[m] * (1.0 - wr);
+                }
+            }
+        }
+        RT[(long)j * n + i] = acc;
+    }
+}
+
+__global__ void k_to_f32(long count, const double *__restrict__ src, float *__restrict__ dst)
+{
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
+         idx += (long)gridDim.x * blockDim.x)
+        dst[idx] = (float)src[idx];
+}
+
+// Value of the block-packed operand for output row i and pair (kb <= mb),
+// block-local (dk, dm): off-diagonal blocks carry both orderings of (k,m).
+__device__ double packed_value(const double *__restrict__ A, int n, int i, int kb, int mb,
+                               int dk, int dm)
+{
+    const int k = kb * kBlk + dk, m = mb * kBlk + dm;
+    if (i >= n || k >= n || m >= n) return 0.0;
+    const long row = (long)i * n * n;
+    double v = A[row + (long)k * n + m];
+    if (kb != mb) v += A[row + (long)m * n + k];
+    return v;
+}
+
+// FP32 GEMM operand, ordered as the 32x32x2 MFMA consumes it:
+// [ib][pair][dk][half][lane][4]; lane l holds row i = ib*32 + l%32 and
+// K index 2t + l/32 of row dk of the block, t = 4*half + r.
+__global__ void k_pack_f32(int n, int npairs, int nib, const int *__restrict__ pairs,
+                           const double *__restrict__ A, float *__restrict__ G)
+{
+    const long total = (long)nib * npairs * kBlk * 2 * 64 * 4;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        long t = idx;
+        const int r = (int)(t % 4); t /= 4;
+        const int lane = (int)(t % 64); t /= 64;
+        const int half = (int)(t % 2); t /= 2;
+        const int dk = (int)(t % kBlk); t /= kBlk;
+        const int pr = (int)(t % npairs);
+        const int ib = (int)(t / npairs);
+        const int i = ib * kIBlk + (lane & 31);
+        const int dm = 2 * (4 * half + r) + (lane >> 5);
+        G[idx] = (float)packed_value(A, n, i, pairs[2 * pr], pairs[2 * pr + 1], dk, dm);
+    }
+}
+
+__device__ inline uint16_t bf16_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf/nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// BF16 hi/lo operand for the 32x32x16 MFMA: [ib][pair][dk][hilo][lane][8];
+// lane l holds row i = ib*32 + l%32 and the 8 consecutive K indices
+// 8*(l/32) + j of row dk of the block.  hi = bf16(v), lo = bf16(v - hi).
+__global__ void k_pack_bf16(int n, int npairs, int nib, const int *__restrict__ pairs,
+                            const double *__restrict__ A, uint16_t *__restrict__ G)
+{
+    const long total = (long)nib * npairs * kBlk * 64 * 8;   // hi/lo written together
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        long t = idx;
+        const int j = (int)(t % 8); t /= 8;
+        const int lane = (int)(t % 64); t /= 64;
+        const int dk = (int)(t % kBlk); t /= kBlk;
+        const int pr = (int)(t % npairs);
+        const int ib = (int)(t / npairs);
+        const int i = ib * kIBlk + (lane & 31);
+        const int dm = 8 * (lane >> 5) + j;
+        const double v = packed_value(A, n, i, pairs[2 * pr], pairs[2 * pr + 1], dk, dm);
+        const uint16_t hi = bf16_rne((float)v);
+        const uint16_t lo = bf16_rne((float)(v - (double)bf16_to_f32(hi)));
+        const long base = ((((long)ib * npairs + pr) * kBlk + dk) * 2) * 64 * 8;
+        G[base + (long)lane * 8 + j] = hi;
+        G[base + 64 * 8 + (long)lane * 8 + j] = lo;
+    }
+}
+
+// Power-of-two scale per output row for the FP16 operand: the largest
+// packed entry of row i (bounded by twice the row maximum of A) lands in
+// [2^13, 2^14].  One workgroup per row.
+__global__ __launch_bounds__(256) void k_row_scale(int n, int ipad, const double *__restrict__ A,
+                                                   float *__restrict__ scale)
+{
+    __shared__ double red[256];
+    const int i = blockIdx.x;
+    double mx = 0.0;
+    if (i < n) {
+        const double *row = A + (long)i * n * n;
+        for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) mx = fmax(mx, fabs(row[e]));
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double top = 2.0 * red[0];
+        float sc = 1.0f;
+        if (top > 0.0) {
+            const int e = 14 - (int)ceil(log2(top));
+            sc = (float)ldexp(1.0, e);
+        }
+        scale[i] = sc;
+    }
+}
+
+// FP16 hi/lo operand (same order as the BF16 one) of the row-scaled tensor.
+__global__ void k_pack_f16(int n, int npairs, int nib, const int *__restrict__ pairs,
+                           const double *__restrict__ A, const float *__restrict__ rs,
+                           uint16_t *__restrict__ G)
+{
+    const long total = (long)nib * npairs * kBlk * 64 * 8;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        long t = idx;
+        const int j = (int)(t % 8); t /= 8;
+        const int lane = (int)(t % 64); t /= 64;
+        const int dk = (int)(t % kBlk); t /= kBlk;
+        const int pr = (int)(t % npairs);
+        const int ib = (int)(t / npairs);
+        const int i = ib * kIBlk + (lane & 31);
+        const int dm = 8 * (lane >> 5) + j;
+        const double v = packed_value(A, n, i, pairs[2 * pr], pairs[2 * pr + 1], dk, dm) *
+                         (double)rs[i];
+        const _Float16 hi = (_Float16)(float)v;
+        const _Float16 lo = (_Float16)(float)(v - (double)(float)hi);
+        const long base = ((((long)ib * npairs + pr) * kBlk + dk) * 2) * 64 * 8;
+        G[base + (long)lane * 8 + j] = __builtin_bit_cast(uint16_t, hi);
+        G[base + 64 * 8 + (long)lane * 8 + j] = __builtin_bit_cast(uint16_t, lo);
+    }
+}
+
+inline int grid_for(long work, int block = 256, int cap = 1 << 20)
+{
+    long g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_build_A(const kxg_kernel &k, const double *d_xmu, const double *d_wmu,
+                          hipStream_t s)
+{
+    const long total = (long)k.n * k.n * k.n;
+    hipLaunchKernelGGL(k_build_A, dim3(grid_for(total)), dim3(256), 0, s, k.n, k.d_p, k.d_dp,
+                       k.d_E, k.d_K, k.mass, k.gdof, k.m2, k.quad, k.nmu, d_xmu, d_wmu,
+                       k.d_A64);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_R(const kxg_kernel &k, hipStream_t s)
+{
+    const long total = (long)k.n * k.n;
+    hipLaunchKernelGGL(k_build_R, dim3(grid_for(total, 64)), dim3(64), 0, s, k.n, k.d_K,
+                       k.d_A64, k.d_RT);
+    return hipGetLastError();
+}
+
+hipError_t launch_derive(kxg_kernel &k, hipStream_t s)
+{
+    const Geometry &g = k.geo;
+    const long dense = (long)k.n * k.n * k.n;
+    if (k.d_A32) {
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(dense)), dim3(256), 0, s, dense, k.d_A64,
+                           k.d_A32);
+    }
+    if (k.d_G32) {
+        const long tot = (long)g.nib * g.npairs * kBlk * 2 * 64 * 4;
+        hipLaunchKernelGGL(k_pack_f32, dim3(grid_for(tot)), dim3(256), 0, s, k.n, g.npairs,
+                           g.nib, k.d_pairs, k.d_A64, k.d_G32);
+    }
+    if (k.d_Gbf) {
+        const long tot = (long)g.nib * g.npairs * kBlk * 64 * 8;
+        hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(tot)), dim3(256), 0, s, k.n, g.npairs,
+                           g.nib, k.d_pairs, k.d_A64, k.d_Gbf);
+    }
+    if (k.d_Gh) {
+        hipLaunchKernelGGL(k_row_scale, dim3(g.ipad), dim3(256), 0, s, k.n, g.ipad, k.d_A64,
+                           k.d_hrow);
+        const long tot = (long)g.nib * g.npairs * kBlk * 64 * 8;
+        hipLaunchKernelGGL(k_pack_f16, dim3(grid_for(tot)), dim3(256), 0, s, k.n, g.npairs,
+                           g.nib, k.d_pairs, k.d_A64, k.d_hrow, k.d_Gh);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kxg

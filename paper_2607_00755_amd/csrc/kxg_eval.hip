@@ -1,0 +1,729 @@
+// Evaluation of C[f] = gain - loss for a batch of distributions
+// (Sec. 4.1 eq. discrete_collision_operator of arXiv 2607.00755, linear
+// interpolation form), with the FP64 epilogue: loss term, two-moment
+// projection (App. C) and diagnostics.
+//
+// gain paths
+//   * stream: one pass over the dense tensor A[i][k][m] per group of up to
+//     4 distributions, f staged in LDS; HBM-bound (single distribution).
+//   * GEMM: gain[b][i] = sum_K F2[b][K] A'[i][K] with K = (k,m) over the
+//     block-packed (k <= m) tensor, F2[b][(k,m)] = f_bk f_bm formed in
+//     registers, on the MFMA units (FP32 32x32x2, or BF16/FP16 32x32x16 with a
+//     hi+lo split of A' and of F2: hi*hi + hi*lo + lo*hi).  K is split over
+//     workgroups (and over the 4 waves of each); partials are reduced in FP64
+//     by the epilogue in a fixed order, independent of the batch size.
+#include "kxg_internal.h"
+
+#include <type_traits>
+
+namespace kxg {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap so that consecutive logical indices share an XCD: workgroups
+// that read the same slice of A (same i-block and K split, different batch
+// tiles) then hit the same L2.
+__device__ inline int xcd_logical(int bid, int nwg)
+{
+    if (nwg % 8 != 0) return bid;
+    return (bid % 8) * (nwg / 8) + bid / 8;
+}
+
+// ---------------------------------------------------------------------------
+// Stream gain: grid (split, i, group of BT distributions).  Each workgroup
+// reads a contiguous chunk of row i of the dense tensor once and forms
+// sum A[i][k][m] f_k f_m for its BT distributions, f taken from LDS; the
+// (k, m) position of each element is tracked incrementally.
+template <typename T, int VEC, int BT>
+__global__ __launch_bounds__(256) void k_stream(const T *__restrict__ A,
+                                                const double *__restrict__ f, int n, int B,
+                                                int chunk, double *__restrict__ part)
+{
+    extern __shared__ double smem_d[];
+    T *fs = reinterpret_cast<T *>(smem_d);
+    __shared__ double red[4][BT];
+    const int split = blockIdx.x, i = blockIdx.y, b0 = blockIdx.z * BT;
+    for (int q = threadIdx.x; q < BT * n; q += 256) {
+        const int bb = q / n, m = q - bb * n;
+        fs[q] = (b0 + bb < B) ? (T)f[(long)(b0 + bb) * n + m] : (T)0;
+    }
+    __syncthreads();
+    const long n2 = (long)n * n;
+    const T *row = A + (long)i * n2;
+    const long e_beg = (long)split * chunk;
+    const long e_end = e_beg + chunk < n2 ? e_beg + chunk : n2;
+    long e = e_beg + (long)threadIdx.x * VEC;
+    int k = (int)(e / n), m = (int)(e - (long)k * n);
+    constexpr int step = 256 * VEC;
+    const int sk = step / n, sm = step - (step / n) * n;
+    T acc[BT];
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) acc[bb] = (T)0;
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    // four loads in flight per thread
+    for (; e + 3 * step < e_end; e += 4 * step) {
+        vec_t a[4];
+        int kk[4], mm[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = *reinterpret_cast<const vec_t *>(row + e + (long)u * step);
+            kk[u] = k;
+            mm[u] = m;
+            m += sm;
+            k += sk;
+            if (m >= n) { m -= n; ++k; }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int bb = 0; bb < BT; ++bb) {
+                const T *fb = fs + bb * n;
+                T s = (T)0;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) s += a[u][v] * fb[mm[u] + v];
+                acc[bb] += fb[kk[u]] * s;
+            }
+        }
+    }
+    for (; e < e_end; e += step) {
+        const vec_t a = *reinterpret_cast<const vec_t *>(row + e);
+#pragma unroll
+        for (int bb = 0; bb < BT; ++bb) {
+            const T *fb = fs + bb * n;
+            T s = (T)0;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s += a[v] * fb[m + v];
+            acc[bb] += fb[k] * s;
+        }
+        m += sm;
+        k += sk;
+        if (m >= n) { m -= n; ++k; }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) {
+        double v = (double)acc[bb];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][bb] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < BT && b0 + (int)threadIdx.x < B) {
+        const int bb = threadIdx.x;
+        const double v = ((red[0][bb] + red[1][bb]) + red[2][bb]) + red[3][bb];
+        part[((long)split * B + b0 + bb) * n + i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA operand of the distributions: per 16-wide block of the grid, FP32
+// values in natural order [nb][bpad][16] and in parity order
+// [nb][bpad][2][8] (the 32x32x2 MFMA pairs K indices 2t and 2t+1).
+// For FP16 each distribution is scaled by a power of two so that
+// max f <= 2^7 (F2 <= 2^14).  One workgroup per (padded) distribution.
+__global__ __launch_bounds__(256) void k_prep(const double *__restrict__ f, int B, int n,
+                                              int nb, int bpad, int scale16,
+                                              float *__restrict__ fop,
+                                              float *__restrict__ fpar,
+                                              float *__restrict__ fscale)
+{
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    float sc = 1.0f;
+    if (scale16) {
+        double mx = 0.0;
+        if (b < B)
+            for (int q = threadIdx.x; q < n; q += 256) mx = fmax(mx, fabs(f[(long)b * n + q]));
+        red[threadIdx.x] = mx;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        mx = red[0];
+        if (mx > 0.0 && isfinite(mx)) sc = (float)ldexp(1.0, 7 - (int)ceil(log2(mx)));
+        if (threadIdx.x == 0) fscale[b] = sc;
+    }
+    for (int q = threadIdx.x; q < nb * kBlk; q += 256) {
+        const double v = (b < B && q < n) ? f[(long)b * n + q] : 0.0;
+        const float x = (float)v * sc;
+        const int blk = q / kBlk, d = q % kBlk;
+        fop[((long)blk * bpad + b) * kBlk + d] = x;
+        fpar[(((long)blk * bpad + b) * 2 + (d & 1)) * 8 + (d >> 1)] = x;
+    }
+}
+
+// Reduce the 4 waves' accumulators of a workgroup (fixed order 0+1+2+3) and
+// store the FP32 partial of this K split.  32x32 MFMA result layout: register
+// e of lane l holds row 8*(e/4) + 4*(l/32) + e%4, column l%32.
+template <int BBW>
+__device__ void store_tile(floatx16 (&acc)[BBW], float *lds, float *__restrict__ part, int sp,
+                           int bpad, int ipad, int brow0, int icol0)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave > 0) {
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                lds[(((wave - 1) * BBW + bb) * 16 + e) * 64 + lane] = acc[bb][e];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        float *dst = part + (long)sp * bpad * ipad;
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                float v = acc[bb][e];
+                v += lds[((0 * BBW + bb) * 16 + e) * 64 + lane];
+                v += lds[((1 * BBW + bb) * 16 + e) * 64 + lane];
+                v += lds[((2 * BBW + bb) * 16 + e) * 64 + lane];
+                const int row = brow0 + bb * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                dst[(long)row * ipad + icol0 + (lane & 31)] = v;
+            }
+    }
+}
+
+// FP32 GEMM on v_mfma_f32_32x32x2f32.  Workgroup = (batch tile of BBW*32
+// distributions, i-block of 32 rows, K split); its 4 waves take 4
+// consecutive sub-ranges of the split's dk steps.  Per dk step (one row k of a
+// (kb, mb) block, 16 K values) a wave issues 8*BBW MFMAs; the A operand
+// (F2 = f_k f_m) is one multiply per MFMA, the B operand (packed tensor)
+// comes straight from memory in MFMA order, prefetched one step ahead.
+template <int BBW>
+__global__ __launch_bounds__(256, 2) void k_gemm_f32(
+    const float *__restrict__ G, const float *__restrict__ fop, const float *__restrict__ fpar,
+    const int *__restrict__ pairs, int npairs, int bpad, int ipad, int nbt, int splits,
+    long dksteps, float *__restrict__ part)
+{
+    __shared__ float lds[3 * BBW * 16 * 64];
+    int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int bt = L % nbt;
+    L /= nbt;
+    const int sp = L % splits;
+    const int ib = L / splits;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 31, hb = lane >> 5;
+    const long w = (long)sp * kWaves + wave, nw = (long)splits * kWaves;
+    const long u0 = w * dksteps / nw, u1 = (w + 1) * dksteps / nw;
+    const int brow0 = bt * BBW * 32;
+    const float *Gi = G + (long)ib * npairs * kBlk * 512;
+
+    floatx16 acc[BBW];
+#pragma unroll
+    for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[bb][e] = 0.0f;
+
+    float fm[BBW][8];
+    int cur_pair = -1;
+    float4 nb0 = make_float4(0, 0, 0, 0), nb1 = nb0;
+    float nfk[BBW];
+    if (u0 < u1) {
+        const int pr = (int)(u0 >> 4), dk = (int)(u0 & 15);
+        const float *gp = Gi + u0 * 512;
+        nb0 = reinterpret_cast<const float4 *>(gp)[lane];
+        nb1 = reinterpret_cast<const float4 *>(gp + 256)[lane];
+        const int kb = pairs[2 * pr];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+            nfk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
+    }
+    for (long u = u0; u < u1; ++u) {
+        const int pr = (int)(u >> 4);
+        if (pr != cur_pair) {
+            cur_pair = pr;
+            const int mb = pairs[2 * pr + 1];
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb) {
+                const float4 *src = reinterpret_cast<const float4 *>(
+                    fpar + (((long)mb * bpad + brow0 + bb * 32 + r) * 2 + hb) * 8);
+                const float4 x0 = src[0], x1 = src[1];
+                fm[bb][0] = x0.x; fm[bb][1] = x0.y; fm[bb][2] = x0.z; fm[bb][3] = x0.w;
+                fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
+            }
+        }
+        const float4 b0 = nb0, b1 = nb1;
+        float fk[BBW];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb) fk[bb] = nfk[bb];
+        if (u + 1 < u1) {
+            const long un = u + 1;
+            const int prn = (int)(un >> 4), dkn = (int)(un & 15);
+            const float *gp = Gi + un * 512;
+            nb0 = reinterpret_cast<const float4 *>(gp)[lane];
+            nb1 = reinterpret_cast<const float4 *>(gp + 256)[lane];
+            const int kbn = pairs[2 * prn];
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb)
+                nfk[bb] = fop[((long)kbn * bpad + brow0 + bb * 32 + r) * kBlk + dkn];
+        }
+        const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb)
+                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fk[bb] * fm[bb][t], bv[t],
+                                                               acc[bb], 0, 0, 0);
+    }
+    store_tile<BBW>(acc, lds, part, sp, bpad, ipad, brow0, ib * kIBlk);
+}
+
+// 16-bit x3 GEMM on v_mfma_f32_32x32x16_{bf16,f16}: per dk step one MFMA
+// K-step of 16; F2 is formed in FP32 and split into hi + lo; the packed
+// tensor arrives pre-split.  gain ~ A_hi F2_hi + A_hi F2_lo + A_lo F2_hi.
+template <int BBW, bool F16>
+__global__ __launch_bounds__(256, 2) void k_gemm_x3(
+    const uint16_t *__restrict__ G, const float *__restrict__ fop, const int *__restrict__ pairs,
+    int npairs, int bpad, int ipad, int nbt, int splits, long dksteps,
+    float *__restrict__ part)
+{
+    typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
+    typedef typename std::conditional<F16, _Float16, __bf16>::type op_t;
+    __shared__ float lds[3 * BBW * 16 * 64];
+    int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int bt = L % nbt;
+    L /= nbt;
+    const int sp = L % splits;
+    const int ib = L / splits;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 31, hb = lane >> 5;
+    const long w = (long)sp * kWaves + wave, nw = (long)splits * kWaves;
+    const long u0 = w * dksteps / nw, u1 = (w + 1) * dksteps / nw;
+    const int brow0 = bt * BBW * 32;
+    const uint16_t *Gi = G + (long)ib * npairs * kBlk * 1024;
+
+    floatx16 acc[BBW];
+#pragma unroll
+    for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[bb][e] = 0.0f;
+
+    float fm[BBW][8];
+    int cur_pair = -1;
+    uint4 nh = make_uint4(0, 0, 0, 0), nl = nh;
+    float nfk[BBW];
+    if (u0 < u1) {
+        const int pr = (int)(u0 >> 4), dk = (int)(u0 & 15);
+        const uint16_t *gp = Gi + u0 * 1024;
+        nh = reinterpret_cast<const uint4 *>(gp)[lane];
+        nl = reinterpret_cast<const uint4 *>(gp + 512)[lane];
+        const int kb = pairs[2 * pr];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+            nfk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
+    }
+    for (long u = u0; u < u1; ++u) {
+        const int pr = (int)(u >> 4);
+        if (pr != cur_pair) {
+            cur_pair = pr;
+            const int mb = pairs[2 * pr + 1];
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb) {
+                const float4 *src = reinterpret_cast<const float4 *>(
+                    fop + ((long)mb * bpad + brow0 + bb * 32 + r) * kBlk + 8 * hb);
+                const float4 x0 = src[0], x1 = src[1];
+                fm[bb][0] = x0.x; fm[bb][1] = x0.y; fm[bb][2] = x0.z; fm[bb][3] = x0.w;
+                fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
+            }
+        }
+        const uint4 ah = nh, al = nl;
+        float fk[BBW];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb) fk[bb] = nfk[bb];
+        if (u + 1 < u1) {
+            const long un = u + 1;
+            const int prn = (int)(un >> 4), dkn = (int)(un & 15);
+            const uint16_t *gp = Gi + un * 1024;
+            nh = reinterpret_cast<const uint4 *>(gp)[lane];
+            nl = reinterpret_cast<const uint4 *>(gp + 512)[lane];
+            const int kbn = pairs[2 * prn];
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb)
+                nfk[bb] = fop[((long)kbn * bpad + brow0 + bb * 32 + r) * kBlk + dkn];
+        }
+        const opx8 Ah = __builtin_bit_cast(opx8, ah);
+        const opx8 Al = __builtin_bit_cast(opx8, al);
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb) {
+            opx8 ph, pl;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float pv = fk[bb] * fm[bb][j];
+                const op_t h = (op_t)pv;
+                ph[j] = h;
+                pl[j] = (op_t)(pv - (float)h);
+            }
+            if constexpr (F16) {
+                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(pl, Ah, acc[bb], 0, 0, 0);
+                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ph, Al, acc[bb], 0, 0, 0);
+                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ph, Ah, acc[bb], 0, 0, 0);
+            } else {
+                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, Ah, acc[bb], 0, 0, 0);
+                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, Al, acc[bb], 0, 0, 0);
+                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, Ah, acc[bb], 0, 0, 0);
+            }
+        }
+    }
+    store_tile<BBW>(acc, lds, part, sp, bpad, ipad, brow0, ib * kIBlk);
+}
+
+// ---------------------------------------------------------------------------
+// Loss rates rate[b][i] = sum_j R[i][j] f_bj in FP64 (8 distributions per
+// workgroup, so each R^T row read serves 8 of them).
+constexpr int kRateB = 8;
+__global__ __launch_bounds__(256) void k_rate(const double *__restrict__ RT,
+                                              const double *__restrict__ f, int n, int B,
+                                              double *__restrict__ rate)
+{
+    extern __shared__ double fs[];   // [kRateB][n]
+    const int b0 = blockIdx.x * kRateB;
+    for (int q = threadIdx.x; q < kRateB * n; q += 256) {
+        const int bb = q / n, j = q - bb * n;
+        fs[q] = (b0 + bb < B) ? f[(long)(b0 + bb) * n + j] : 0.0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 256) {
+        double acc[kRateB];
+#pragma unroll
+        for (int bb = 0; bb < kRateB; ++bb) acc[bb] = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double r = RT[(long)j * n + i];
+#pragma unroll
+            for (int bb = 0; bb < kRateB; ++bb) acc[bb] += r * fs[bb * n + j];
+        }
+#pragma unroll
+        for (int bb = 0; bb < kRateB; ++bb)
+            if (b0 + bb < B) rate[(long)(b0 + bb) * n + i] = acc[bb];
+    }
+}
+
+// Deterministic block sums/maxes over 256 threads (4 waves).
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double *lds)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = ((lds[j] + lds[NV + j]) + lds[2 * NV + j]) + lds[3 * NV + j];
+    __syncthreads();
+}
+
+template <int NV>
+__device__ void block_max(double (&v)[NV], double *lds)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        for (int off = 32; off > 0; off >>= 1) v[j] = fmax(v[j], __shfl_xor(v[j], off));
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        v[j] = fmax(fmax(lds[j], lds[NV + j]), fmax(lds[2 * NV + j], lds[3 * NV + j]));
+    __syncthreads();
+}
+
+// FP64 epilogue, one workgroup per distribution (App. C):
+//   gain = sum of the split partials (fixed order; FP16 scales undone),
+//   C_raw = gain - f * rate,
+//   xi_i = |f_i|/f_max above 1e-12, and the 2x2 system for the correction
+//   xi (alpha' + beta' K) written in kinetic energy K = E - m (the span of
+//   {xi, xi E} equals that of {xi, xi K}; alpha = alpha' - beta' m,
+//   beta = beta' in the paper's E-form), C_proj = C_raw - xi (alpha' + beta' K),
+//   and the diagnostics of eqs. app_epsilon_definition and
+//   app_projection_relative_correction.
+template <typename PT>
+__global__ __launch_bounds__(256) void k_epilogue(
+    const PT *__restrict__ part, int nsplit, long split_stride, int ld_b,
+    const float *__restrict__ fscale, const float *__restrict__ rscale,
+    const double *__restrict__ rate, const double *__restrict__ f,
+    const double *__restrict__ h, const double *__restrict__ K, const double *__restrict__ E,
+    double mass, int n, int project, double *__restrict__ C, double *__restrict__ diag)
+{
+    __shared__ double lds[4 * 12];
+    const int b = blockIdx.x;
+    constexpr int kPer = kMaxN / 256;
+    const double *fb = f + (long)b * n;
+    double fv[kPer], craw[kPer];
+    double mx[3] = {0.0, 0.0, 0.0};       // f_max, rate max, |gain| max
+    double flags[1] = {0.0};
+    double inv_s2 = 1.0;
+    if (fscale) {
+        const double s = fscale[b];
+        inv_s2 = 1.0 / (s * s);
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        fv[q] = 0.0;
+        craw[q] = 0.0;
+        if (i < n) {
+            const double x = fb[i];
+            fv[q] = x;
+            if (!isfinite(x)) flags[0] = fmax(flags[0], 1.0);
+            else if (x < 0.0) flags[0] = fmax(flags[0], 0.5);
+            mx[0] = fmax(mx[0], fabs(x));
+            double g = 0.0;
+            for (int s = 0; s < nsplit; ++s) g += (double)part[s * split_stride + (long)b * ld_b + i];
+            if (fscale) g *= inv_s2 / (double)rscale[i];
+            const double rt = rate[(long)b * n + i];
+            mx[1] = fmax(mx[1], rt);
+            mx[2] = fmax(mx[2], fabs(g));
+            craw[q] = g - x * rt;
+        }
+    }
+    block_max<3>(mx, lds);
+    block_max<1>(flags, lds);
+    const double fmaxv = mx[0];
+    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double xi[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        xi[q] = 0.0;
+        if (i < n) {
+            const double hi = h[i], ki = K[i], ei = E[i];
+            const double rel = fmaxv > 0.0 ? fabs(fv[q]) / fmaxv : 0.0;
+            xi[q] = rel > 1e-12 ? rel : 0.0;
+            s[0] += hi * craw[q];
+            s[1] += hi * ki * craw[q];
+            s[2] += hi * xi[q];
+            s[3] += hi * ki * xi[q];
+            s[4] += hi * ki * ki * xi[q];
+            s[5] += hi * fabs(craw[q]);
+            s[6] += hi * ei * fabs(craw[q]);
+            s[7] += hi * ei * craw[q];
+            s[8] += hi * fv[q];
+        }
+    }
+    block_sum<9>(s, lds);
+    double al = 0.0, be = 0.0;
+    const double det = s[2] * s[4] - s[3] * s[3];
+    if (project && det != 0.0 && isfinite(det)) {
+        al = (s[0] * s[4] - s[1] * s[3]) / det;
+        be = (s[1] * s[2] - s[0] * s[3]) / det;
+    }
+    double t[6] = {0, 0, 0, 0, 0, 0};
+    double bad[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        if (i < n) {
+            const double hi = h[i], ei = E[i];
+            const double cp = craw[q] - xi[q] * (al + be * K[i]);
+            const double d = fabs(cp - craw[q]);
+            t[0] += hi * cp;
+            t[1] += hi * ei * cp;
+            t[2] += hi * fabs(cp);
+            t[3] += hi * ei * fabs(cp);
+            t[4] += hi * d;
+            t[5] += hi * ei * d;
+            const double out = project ? cp : craw[q];
+            if (!isfinite(out)) bad[0] = 1.0;
+            C[(long)b * n + i] = out;
+        }
+    }
+    block_sum<6>(t, lds);
+    block_max<1>(bad, lds);
+    if (diag && threadIdx.x == 0) {
+        double *d = diag + (long)b * KXG_NDIAG;
+        d[0] = al - be * mass;
+        d[1] = be;
+        d[2] = s[5] > 0.0 ? s[0] / s[5] : 0.0;
+        d[3] = s[6] > 0.0 ? s[7] / s[6] : 0.0;
+        d[4] = t[2] > 0.0 ? t[0] / t[2] : 0.0;
+        d[5] = t[3] > 0.0 ? t[1] / t[3] : 0.0;
+        d[6] = s[5] > 0.0 ? t[4] / s[5] : 0.0;
+        d[7] = s[6] > 0.0 ? t[5] / s[6] : 0.0;
+        d[8] = mx[1];
+        d[9] = mx[2];
+        double st = 0.0;
+        if (flags[0] >= 1.0) st += 1.0;
+        else if (flags[0] > 0.0) st += 2.0;
+        if (bad[0] > 0.0) st += 4.0;
+        d[10] = st;
+        d[11] = s[8];
+    }
+}
+
+// Moments sum h f, sum h E f, -sum_{f>0} h f (ln f - 1); one workgroup per row.
+__global__ __launch_bounds__(256) void k_moments(const double *__restrict__ f, int n,
+                                                 const double *__restrict__ h,
+                                                 const double *__restrict__ E,
+                                                 double *__restrict__ out)
+{
+    __shared__ double lds[4 * 3];
+    const int b = blockIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double x = f[(long)b * n + i];
+        v[0] += h[i] * x;
+        v[1] += h[i] * E[i] * x;
+        if (x > 0.0) v[2] -= h[i] * x * (log(x) - 1.0);
+    }
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0) {
+        out[3 * b + 0] = v[0];
+        out[3 * b + 1] = v[1];
+        out[3 * b + 2] = v[2];
+    }
+}
+
+int stream_splits(int n)
+{
+    const long n2 = (long)n * n;
+    int s = div_up(2048, n);
+    const int cap = (int)(n2 / 2048);           // keep chunks >= 2048 elements
+    if (s > cap) s = cap;
+    if (s < 1) s = 1;
+    return s;
+}
+
+int gemm_bbw(int B) { return B <= 32 ? 1 : (B <= 64 ? 2 : 4); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws)
+{
+    const int n = k.n;
+    const int bpad = div_up(b_cap, 128) * 128;
+    size_t need = (size_t)stream_splits(n) * b_cap * n * sizeof(double);
+    if (k.d_G32 || k.d_Gbf || k.d_Gh) {
+        const size_t g = (size_t)k.gemm_splits * bpad * k.geo.ipad * sizeof(float);
+        if (g > need) need = g;
+    }
+    need += (size_t)b_cap * n * sizeof(double);      // loss rates
+    ws.part_bytes = need;
+    ws.bpad_cap = bpad;
+    ws.b_cap = b_cap;
+    if (hipMalloc(&ws.part, need) != hipSuccess) { set_error("workspace: out of memory"); return KXG_ENOMEM; }
+    const size_t fb = (size_t)k.geo.nb * bpad * kBlk * sizeof(float);
+    if (hipMalloc((void **)&ws.fop, fb) != hipSuccess || hipMalloc((void **)&ws.fpar, fb) != hipSuccess ||
+        hipMalloc((void **)&ws.fscale, bpad * sizeof(float)) != hipSuccess) {
+        set_error("workspace: out of memory");
+        return KXG_ENOMEM;
+    }
+    return KXG_OK;
+}
+
+void free_workspace(Workspace &ws)
+{
+    if (ws.part) (void)hipFree(ws.part);
+    if (ws.fop) (void)hipFree(ws.fop);
+    if (ws.fpar) (void)hipFree(ws.fpar);
+    if (ws.fscale) (void)hipFree(ws.fscale);
+    ws = Workspace{};
+}
+
+kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const double *f,
+                     int B, double *C, uint32_t flags, double *diag, hipStream_t s)
+{
+    const int n = k.n;
+    const Geometry &g = k.geo;
+    // the loss-rate buffer [b_cap][n] sits at the end of the workspace
+    double *rate = reinterpret_cast<double *>(static_cast<char *>(ws.part) + ws.part_bytes) -
+                   (size_t)ws.b_cap * n;
+    const bool use_stream = prec == KXG_F64 || (prec == KXG_F32 && B <= 4 && k.d_A32);
+    const int project = (flags & KXG_PROJECT) ? 1 : 0;
+    if (use_stream) {
+        const int ns = stream_splits(n);
+        const long n2 = (long)n * n;
+        const bool dbl = prec == KXG_F64;
+        const int vec = dbl ? ((n % 2 == 0) ? 2 : 1) : ((n % 4 == 0) ? 4 : ((n % 2 == 0) ? 2 : 1));
+        int chunk = div_up(n2, ns);
+        chunk = div_up(chunk, 256 * vec) * (256 * vec);
+        const int nsplit = (int)((n2 + chunk - 1) / chunk);
+        constexpr int BT = 4;
+        const dim3 grid(nsplit, n, div_up(B, BT));
+        const size_t shm = (size_t)BT * n * (dbl ? sizeof(double) : sizeof(float));
+        double *part = static_cast<double *>(ws.part);
+        profile_mark_begin(s);
+        if (dbl) {
+            if (vec == 2)
+                hipLaunchKernelGGL((k_stream<double, 2, BT>), grid, dim3(256), shm, s, k.d_A64, f, n, B, chunk, part);
+            else
+                hipLaunchKernelGGL((k_stream<double, 1, BT>), grid, dim3(256), shm, s, k.d_A64, f, n, B, chunk, part);
+        } else {
+            if (vec == 4)
+                hipLaunchKernelGGL((k_stream<float, 4, BT>), grid, dim3(256), shm, s, k.d_A32, f, n, B, chunk, part);
+            else if (vec == 2)
+                hipLaunchKernelGGL((k_stream<float, 2, BT>), grid, dim3(256), shm, s, k.d_A32, f, n, B, chunk, part);
+            else
+                hipLaunchKernelGGL((k_stream<float, 1, BT>), grid, dim3(256), shm, s, k.d_A32, f, n, B, chunk, part);
+        }
+        profile_mark_end(s);
+        KXG_TRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_rate, dim3(div_up(B, kRateB)), dim3(256), kRateB * n * sizeof(double), s,
+                           k.d_RT, f, n, B, rate);
+        hipLaunchKernelGGL(k_epilogue<double>, dim3(B), dim3(256), 0, s, part, nsplit,
+                           (long)B * n, n, (const float *)nullptr, (const float *)nullptr, rate, f,
+                           k.d_h, k.d_K, k.d_E, k.mass, n, project, C, diag);
+        KXG_TRY_HIP(hipGetLastError());
+        return KXG_OK;
+    }
+    // GEMM path
+    const int bbw = gemm_bbw(B);
+    const int tile = 32 * bbw;
+    const int bpad = div_up(B, tile) * tile;
+    const int nbt = bpad / tile;
+    const int splits = k.gemm_splits;
+    const int nwg = nbt * g.nib * splits;
+    const bool f16 = prec == KXG_F16X3;
+    hipLaunchKernelGGL(k_prep, dim3(bpad), dim3(256), 0, s, f, B, n, g.nb, bpad, f16 ? 1 : 0,
+                       ws.fop, ws.fpar, ws.fscale);
+    float *part = static_cast<float *>(ws.part);
+    profile_mark_begin(s);
+#define KXG_GEMM_F32(W)                                                                  \
+    hipLaunchKernelGGL(k_gemm_f32<W>, dim3(nwg), dim3(256), 0, s, k.d_G32, ws.fop, ws.fpar, \
+                       k.d_pairs, g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part)
+#define KXG_GEMM_X3(W, H, GP)                                                              \
+    hipLaunchKernelGGL((k_gemm_x3<W, H>), dim3(nwg), dim3(256), 0, s, GP, ws.fop, k.d_pairs, \
+                       g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part)
+    if (prec == KXG_F32) {
+        if (bbw == 1) KXG_GEMM_F32(1); else if (bbw == 2) KXG_GEMM_F32(2); else KXG_GEMM_F32(4);
+    } else if (prec == KXG_BF16X3) {
+        if (bbw == 1) KXG_GEMM_X3(1, false, k.d_Gbf);
+        else if (bbw == 2) KXG_GEMM_X3(2, false, k.d_Gbf);
+        else KXG_GEMM_X3(4, false, k.d_Gbf);
+    } else {
+        if (bbw == 1) KXG_GEMM_X3(1, true, k.d_Gh);
+        else if (bbw == 2) KXG_GEMM_X3(2, true, k.d_Gh);
+        else KXG_GEMM_X3(4, true, k.d_Gh);
+    }
+#undef KXG_GEMM_F32
+#undef KXG_GEMM_X3
+    profile_mark_end(s);
+    KXG_TRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_rate, dim3(div_up(B, kRateB)), dim3(256), kRateB * n * sizeof(double), s,
+                       k.d_RT, f, n, B, rate);
+    hipLaunchKernelGGL(k_epilogue<float>, dim3(B), dim3(256), 0, s, part, splits,
+                       (long)bpad * g.ipad, g.ipad, f16 ? ws.fscale : (const float *)nullptr,
+                       f16 ? k.d_hrow : (const float *)nullptr, rate, f, k.d_h, k.d_K, k.d_E,
+                       k.mass, n, project, C, diag);
+    KXG_TRY_HIP(hipGetLastError());
+    return KXG_OK;
+}
+
+hipError_t launch_moments(const kxg_kernel &k, const double *f, int B, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_moments, dim3(B), dim3(256), 0, s, f, k.n, k.d_h, k.d_E, out);
+    return hipGetLastError();
+}
+
+}  // namespace kxg

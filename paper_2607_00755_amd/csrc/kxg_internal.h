@@ -1,0 +1,100 @@
+// Internal declarations shared by the libkxg translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/kxg.h"
+
+namespace kxg {
+
+void set_error(const char *fmt, ...);
+
+#define KXG_TRY_HIP(expr)                                                   \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess) {                                             \
+            ::kxg::set_error("%s failed: %s", #expr, hipGetErrorString(e_)); \
+            return KXG_EHIP;                                                \
+        }                                                                   \
+    } while (0)
+
+constexpr int kMaxN = 1024;          // largest grid
+constexpr int kBlk = 16;             // (k,m) block edge of the packed GEMM layout
+constexpr int kIBlk = 32;            // output rows (i) per MFMA tile
+constexpr int kBRows = 32;           // distributions per MFMA tile
+constexpr int kWaves = 4;            // waves per GEMM workgroup (split K)
+
+// Geometry of the block-packed GEMM operand: the (k,m) plane is cut into
+// 16x16 blocks; only blocks with kb <= mb are stored (off-diagonal blocks hold
+// A[i,k,m] + A[i,m,k], diagonal blocks hold A as is), which is exact for the
+// gain sum_{k,m} A f_k f_m.  A unit of K progress ("dk step") is one row k of
+// one block: 16 values of K.
+struct Geometry {
+    int nb = 0;        // ceil(n/16)
+    int npairs = 0;    // nb (nb+1)/2 stored blocks
+    int nib = 0;       // ceil(n/32) output row tiles
+    int ipad = 0;      // nib * 32
+    long dksteps = 0;  // npairs * 16
+};
+
+// Per-handle (or per-stepper) evaluation workspace.
+struct Workspace {
+    void *part = nullptr;       // split partial gains
+    size_t part_bytes = 0;
+    float *fop = nullptr;       // FP32 operand, natural order  [nb][bpad][16]
+    float *fpar = nullptr;      // FP32 operand, parity order  [nb][bpad][2][8]
+    float *fscale = nullptr;    // per-distribution power-of-two scale [bpad]
+    int bpad_cap = 0;
+    int b_cap = 0;              // largest batch; the loss-rate buffer [b_cap][n] ends part
+};
+
+}  // namespace kxg
+
+struct kxg_kernel {
+    int n = 0;
+    double mass = 1, gdof = 1, m2 = 1;
+    int nmu = 18, quad = 0;
+    int b_cap = 1;
+    uint32_t prec_mask = 0;
+    std::vector<double> p, dp, E, K, h;
+    double *d_p = nullptr, *d_dp = nullptr, *d_E = nullptr, *d_K = nullptr, *d_h = nullptr;
+    double *d_A64 = nullptr;     // [n][n][n] FP64 master, m fastest
+    double *d_RT = nullptr;      // [n][n] R transposed: RT[j][i] = R[i][j]
+    float *d_A32 = nullptr;      // [n][n][n] FP32 copy (single-f stream)
+    float *d_G32 = nullptr;      // packed GEMM operand, FP32
+    uint16_t *d_Gbf = nullptr;   // packed GEMM operand, BF16 hi/lo
+    uint16_t *d_Gh = nullptr;    // packed GEMM operand, FP16 hi/lo (row-scaled)
+    float *d_hrow = nullptr;     // [ipad] FP16 row scales (powers of two)
+    int *d_pairs = nullptr;      // [npairs][2] (kb, mb)
+    kxg::Geometry geo;
+    int gemm_splits = 8;         // workgroup splits of K (fixed per handle)
+    size_t bytes[4] = {0, 0, 0, 0};
+    kxg::Workspace ws;
+};
+
+namespace kxg {
+
+// Launchers (device code in the .hip files).
+hipError_t launch_build_A(const kxg_kernel &k, const double *d_xmu, const double *d_wmu,
+                          hipStream_t s);
+hipError_t launch_build_R(const kxg_kernel &k, hipStream_t s);
+hipError_t launch_derive(kxg_kernel &k, hipStream_t s);
+
+kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const double *f,
+                     int B, double *C, uint32_t flags, double *diag, hipStream_t s);
+kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws);
+void free_workspace(Workspace &ws);
+hipError_t launch_moments(const kxg_kernel &k, const double *f, int B, double *out,
+                          hipStream_t s);
+
+void gauss_legendre(int n, double *x, double *w);
+
+// Gain-kernel profiling (events around each launch while a profile is open).
+void profile_mark_begin(hipStream_t s);
+void profile_mark_end(hipStream_t s);
+
+}  // namespace kxg
