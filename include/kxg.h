@@ -52,7 +52,7 @@ typedef enum {
  * projection and all state updates are FP64 in every case). */
 typedef enum {
     KXG_F64 = 0,     /* FP64 stream over the dense kernel tensor          */
-    KXG_F32 = 1,     /* FP32: stream for B <= 4, MFMA GEMM above          */
+    KXG_F32 = 1,     /* FP32: stream if b_cap <= 4, else MFMA GEMM        */
     KXG_BF16X3 = 2,  /* BF16 MFMA, hi+lo split of A and of f_n f_m,
                         3 products, FP32 accumulation                     */
     KXG_F16X3 = 3    /* FP16 MFMA, hi+lo split with power-of-two scaling  */

@@ -116,8 +116,11 @@ double or_angular_gl(double pi, double pn, double pm, double Ki, double Kn,
         double K2 = pn * pn * pm * pm * (1.0 - mu * mu);
         double a = -(K2 + A1 * A1);
         double b = -2.0 * A0 * A1;
-        double c = K2 - A0 * A0;
-        double disc = b * b - 4.0 * a * c;
+        /* discriminant b^2 - 4ac with c = K^2 - A0^2, written through the
+         * identity b^2 - 4ac = 4 K^2 (K^2 + A1^2 - A0^2): the same number,
+         * without the cancellation of the two O(A0^2 A1^2) terms that would
+         * otherwise decide its sign near zero */
+        double disc = 4.0 * K2 * ((K2 + A1 * A1) - A0 * A0);
         if (!(disc > 0.0) || !(a < 0.0))
             continue;                        /* no allowed nu interval */
         double sd = sqrt(disc);
@@ -125,12 +128,15 @@ double or_angular_gl(double pi, double pn, double pm, double Ki, double Kn,
         double r2 = (-b - sd) / (2.0 * a);
         double lo = r1 < r2 ? r1 : r2;
         double hi = r1 < r2 ? r2 : r1;
-        if (lo < -1.0) lo = -1.0;
-        if (hi > 1.0) hi = 1.0;
+        int lo_clip = lo < -1.0, hi_clip = hi > 1.0;
+        if (lo_clip) lo = -1.0;
+        if (hi_clip) hi = 1.0;
         if (!(lo < hi))
             continue;                        /* interval misses [-1,1] */
-        double s_lo = (2.0 * a * lo + b) / sd;
-        double s_hi = (2.0 * a * hi + b) / sd;
+        /* at an unclipped root (2a r + b)/sqrt(D) is exactly +1 (smaller
+         * root, a < 0) or -1 (larger root); only clipped limits are computed */
+        double s_lo = lo_clip ? (2.0 * a * lo + b) / sd : 1.0;
+        double s_hi = hi_clip ? (2.0 * a * hi + b) / sd : -1.0;
         if (s_lo > 1.0) s_lo = 1.0;
         if (s_lo < -1.0) s_lo = -1.0;
         if (s_hi > 1.0) s_hi = 1.0;

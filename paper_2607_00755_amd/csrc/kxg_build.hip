@@ -34,17 +34,21 @@ __device__ double phi_gauss(double pi, double pn, double pm, double ki, double k
         const double kk = pnpm * pnpm * (1.0 - mu * mu);
         const double qa = -(kk + a1 * a1);
         const double qb = -2.0 * a0 * a1;
-        const double qc = kk - a0 * a0;
-        const double disc = qb * qb - 4.0 * qa * qc;
+        // b^2 - 4ac (c = K^2 - A0^2) through the exact identity
+        // 4 K^2 (K^2 + A1^2 - A0^2): no cancellation in the sign decision
+        const double disc = 4.0 * kk * ((kk + a1 * a1) - a0 * a0);
         if (!(disc > 0.0) || !(qa < 0.0)) continue;
         const double sq = sqrt(disc);
         const double ra = (-qb + sq) / (2.0 * qa);
         const double rb = (-qb - sq) / (2.0 * qa);
-        const double nlo = fmax(fmin(ra, rb), -1.0);
-        const double nhi = fmin(fmax(ra, rb), 1.0);
+        const double rlo = fmin(ra, rb), rhi = fmax(ra, rb);
+        const double nlo = fmax(rlo, -1.0);
+        const double nhi = fmin(rhi, 1.0);
         if (!(nlo < nhi)) continue;
-        const double ulo = fmin(fmax((2.0 * qa * nlo + qb) / sq, -1.0), 1.0);
-        const double uhi = fmin(fmax((2.0 * qa * nhi + qb) / sq, -1.0), 1.0);
+        // the arcsine argument is exactly +1 / -1 at an unclipped smaller /
+        // larger root (qa < 0); only clipped limits are evaluated
+        const double ulo = rlo < -1.0 ? fmin(fmax((2.0 * qa * nlo + qb) / sq, -1.0), 1.0) : 1.0;
+        const double uhi = rhi > 1.0 ? fmin(fmax((2.0 * qa * nhi + qb) / sq, -1.0), 1.0) : -1.0;
         total += wmu[q] * ((asin(ulo) - asin(uhi)) / sqrt(-qa));
     }
     return pnpm * total;

@@ -639,7 +639,10 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     // the loss-rate buffer [b_cap][n] sits at the end of the workspace
     double *rate = reinterpret_cast<double *>(static_cast<char *>(ws.part) + ws.part_bytes) -
                    (size_t)ws.b_cap * n;
-    const bool use_stream = prec == KXG_F64 || (prec == KXG_F32 && B <= 4 && k.d_A32);
+    // FP32 takes the stream kernel only on handles built for tiny batches, so
+    // that on any one handle the path (and the rounding) of a row does not
+    // depend on how many rows share the call.
+    const bool use_stream = prec == KXG_F64 || (prec == KXG_F32 && B <= 4 && k.b_cap <= 4 && k.d_A32);
     const int project = (flags & KXG_PROJECT) ? 1 : 0;
     if (use_stream) {
         const int ns = stream_splits(n);

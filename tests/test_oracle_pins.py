@@ -46,8 +46,21 @@ def test_angular_gl_converges_to_closed_form(trip):
     ex = oracle.angular_exact(pi, partner(pi, pn, pm), pn, pm)
     errs = [abs(oracle.angular_gl(pi, pn, pm, nmu=k) - ex) / ex for k in (18, 100, 400)]
     assert errs[2] < 1e-2
-    # converges, down to the rounding floor of the printed discriminant b^2-4ac
-    assert errs[2] <= max(errs[0], 1e-6)
+    # converges (smooth cases reach machine precision already at N_mu = 100)
+    assert errs[2] <= max(errs[0], 1e-12)
+
+
+def test_discriminant_identity_exact():
+    # The oracle evaluates b^2 - 4ac of eq. app_I_mu's quadratic
+    # (a = -(K^2 + A1^2), b = -2 A0 A1, c = K^2 - A0^2) as
+    # 4 K^2 (K^2 + A1^2 - A0^2); check the identity in exact rationals.
+    from fractions import Fraction as Fr
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        A0, A1, K2 = (Fr(int(v), 997) for v in rng.integers(-10**6, 10**6, 3))
+        K2 = abs(K2)
+        a, b, c = -(K2 + A1 * A1), -2 * A0 * A1, K2 - A0 * A0
+        assert b * b - 4 * a * c == 4 * K2 * (K2 + A1 * A1 - A0 * A0)
 
 
 def test_angular_closed_form_special_values():
