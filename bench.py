@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=800,
+                    help="measured serving requests (after --serve-warm warm-up ones); 0 = skip")
+    ap.add_argument("--serve-warm", type=int, default=200)
     return ap.parse_args()
 
 
@@ -152,6 +155,24 @@ def main():
             log("%s B=4096: %.3f ms/call, gemm %.1f us" % (name, 1e3 * wl, g_us))
         del k4
 
+    # ---------------- serving loop (continuous batching) ----------------
+    serve = None
+    if args.serve_requests > 0:
+        from paper_2607_00755_amd import serving
+        reqs = inputs.serving_requests(args.serve_warm + args.serve_requests)
+        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16)
+        t0 = time.perf_counter()
+        done = srv.run(reqs)
+        el = time.perf_counter() - t0
+        serve = srv.stats(done, warm=args.serve_warm)
+        serve.update({"requests": args.serve_requests, "warmup_requests": args.serve_warm,
+                      "rate_req_per_s": 200.0, "wall_s": round(el, 2), "prec": "f32",
+                      "stepper": "adaptive Heun in ln a, rtol 1e-6, radiation drift"})
+        serve["mean_batch"] = {str(k): round(v, 1) for k, v in serve["mean_batch"].items()}
+        log("serving: p50 %.3f s p99 %.3f s, %.2f solves/s" %
+            (serve["p50_s"], serve["p99_s"], serve["solves_per_s"]))
+        del srv
+
     # ---------------- CPU oracle baseline ----------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -178,7 +199,10 @@ def main():
            "config": {"workload": w.name + " RK4 step (4 evals, projected, FP64 state)",
                       "n_grid": n, "batch": B, "p_range": [w.pmin, w.pmax], "n_mu": 18,
                       "parallelism": "1 GPU"},
-           "roofline": roofline, "cpu_baseline": cpu}
+           "roofline": roofline, "cpu_baseline": cpu,
+           "p50_solve_latency_s": None if serve is None else round(serve["p50_s"], 4),
+           "p99_solve_latency_s": None if serve is None else round(serve["p99_s"], 4),
+           "serving": serve}
     out.update(extras)
     print(json.dumps(out), flush=True)
 

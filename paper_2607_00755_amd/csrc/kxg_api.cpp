@@ -157,6 +157,10 @@ struct kxg_stepper {
     Workspace ws;
     std::vector<char> used;
     int b_hi = 0;
+    // one captured iteration (HIP graph) for the current batch bucket
+    hipGraphExec_t gexec = nullptr;
+    int g_batch = -1;
+    hipStream_t g_stream = nullptr;
 };
 
 extern "C" {
@@ -487,6 +491,7 @@ kxg_status kxg_stepper_create(const kxg_kernel *k, const kxg_stepper_params *prm
 void kxg_stepper_free(kxg_stepper *s)
 {
     if (!s) return;
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
     void *ptrs[] = {s->d_slots, s->d_x, s->d_fb, s->d_C, s->d_acc, s->d_xs, s->d_dt};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -542,6 +547,66 @@ kxg_status kxg_stepper_release(kxg_stepper *s, int32_t slot, void *stream)
     return KXG_OK;
 }
 
+// One iteration of the stepper over the first B slots: RK4 = 4 x (operator
+// call + stage update); Heun = operator call, predictor, operator call,
+// corrector with control.
+static kxg_status enqueue_iteration(kxg_stepper *s, int B, hipStream_t st)
+{
+    const kxg_kernel &k = *s->k;
+    const kxg_stepper_params &P = s->prm;
+    const uint32_t flags = P.project ? KXG_PROJECT : 0u;
+    if (P.kind == KXG_RK4) {
+        for (int stage = 1; stage <= 4; ++stage) {
+            kxg_status r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
+            if (r != KXG_OK) return r;
+            KXG_TRY_HIP(launch_rk4_stage(stage, k.n, B, s->d_slots, s->d_x, s->d_acc, s->d_C, s->d_fb, st));
+        }
+        return KXG_OK;
+    }
+    kxg_status r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
+    if (r != KXG_OK) return r;
+    KXG_TRY_HIP(launch_heun_pred(k.n, B, P.expansion, s->d_slots, k.d_p, k.d_dp, s->d_x,
+                                 s->d_acc, s->d_xs, s->d_C, s->d_fb, st));
+    r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
+    if (r != KXG_OK) return r;
+    KXG_TRY_HIP(launch_heun_corr(k.n, B, P.expansion, P.adapt, P.rtol, P.safety, P.fac_min,
+                                 P.fac_max, P.dt_min, s->d_slots, k.d_p, k.d_dp, s->d_x,
+                                 s->d_acc, s->d_xs, s->d_C, s->d_fb, st));
+    return KXG_OK;
+}
+
+// Capture one iteration over `batch` slots on stream st into an executable
+// graph (re-captured only when the batch bucket or the stream changes).
+static bool ensure_graph(kxg_stepper *s, int batch, hipStream_t st)
+{
+    if (s->gexec && s->g_batch == batch && s->g_stream == st) return true;
+    if (s->gexec) {
+        (void)hipGraphExecDestroy(s->gexec);
+        s->gexec = nullptr;
+    }
+    s->g_batch = -1;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    const kxg_status r = enqueue_iteration(s, batch, st);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (r != KXG_OK || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return false;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess || !exec) {
+        (void)hipGetLastError();
+        return false;
+    }
+    s->gexec = exec;
+    s->g_batch = batch;
+    s->g_stream = st;
+    return true;
+}
+
 kxg_status kxg_stepper_advance(kxg_stepper *s, int32_t n_iter, void *stream)
 {
     g_err[0] = 0;
@@ -549,27 +614,18 @@ kxg_status kxg_stepper_advance(kxg_stepper *s, int32_t n_iter, void *stream)
     const int B = s->b_hi;
     if (B == 0 || n_iter == 0) return KXG_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const kxg_kernel &k = *s->k;
-    const kxg_stepper_params &P = s->prm;
-    const uint32_t flags = P.project ? KXG_PROJECT : 0u;
+    // Launch-bound iterations replay a captured graph on a non-default stream
+    // (batch rounded up to a multiple of 16 slots; free slots are skipped by
+    // the kernels).  Direct launches while a profile is open or on the
+    // default stream.
+    const int bucket = std::min(s->prm.b_cap, (B + 15) / 16 * 16);
+    if (st != nullptr && !g_prof.on && ensure_graph(s, bucket, st)) {
+        for (int it = 0; it < n_iter; ++it) KXG_TRY_HIP(hipGraphLaunch(s->gexec, st));
+        return KXG_OK;
+    }
     for (int it = 0; it < n_iter; ++it) {
-        if (P.kind == KXG_RK4) {
-            for (int stage = 1; stage <= 4; ++stage) {
-                kxg_status r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
-                if (r != KXG_OK) return r;
-                KXG_TRY_HIP(launch_rk4_stage(stage, k.n, B, s->d_slots, s->d_x, s->d_acc, s->d_C, s->d_fb, st));
-            }
-        } else {
-            kxg_status r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
-            if (r != KXG_OK) return r;
-            KXG_TRY_HIP(launch_heun_pred(k.n, B, P.expansion, s->d_slots, k.d_p, k.d_dp, s->d_x,
-                                         s->d_acc, s->d_xs, s->d_C, s->d_fb, st));
-            r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
-            if (r != KXG_OK) return r;
-            KXG_TRY_HIP(launch_heun_corr(k.n, B, P.expansion, P.adapt, P.rtol, P.safety, P.fac_min,
-                                         P.fac_max, P.dt_min, s->d_slots, k.d_p, k.d_dp, s->d_x,
-                                         s->d_acc, s->d_xs, s->d_C, s->d_fb, st));
-        }
+        kxg_status r = enqueue_iteration(s, B, st);
+        if (r != KXG_OK) return r;
     }
     return KXG_OK;
 }

@@ -375,43 +375,71 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(
 }
 
 // ---------------------------------------------------------------------------
-// Loss rates rate[b][i] = sum_j R[i][j] f_bj in FP64 (8 distributions per
-// workgroup, so each R^T row read serves 8 of them).
+// Loss rates rate[b][i] = sum_j R[i][j] f_bj in FP64.  Workgroup tile: 8
+// distributions x 64 rows i; its 4 waves take the j sums j = w, w+4, ... and
+// the 4 partial sums are added in a fixed order.  Each R^T row segment read
+// (64 consecutive i, coalesced) serves the 8 distributions.
 constexpr int kRateB = 8;
+constexpr int kRateI = 64;
 __global__ __launch_bounds__(256) void k_rate(const double *__restrict__ RT,
                                               const double *__restrict__ f, int n, int B,
                                               double *__restrict__ rate)
 {
     extern __shared__ double fs[];   // [kRateB][n]
-    const int b0 = blockIdx.x * kRateB;
+    __shared__ double part[4][kRateB][kRateI];
+    const int b0 = blockIdx.x * kRateB, i0 = blockIdx.y * kRateI;
     for (int q = threadIdx.x; q < kRateB * n; q += 256) {
         const int bb = q / n, j = q - bb * n;
         fs[q] = (b0 + bb < B) ? f[(long)(b0 + bb) * n + j] : 0.0;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += 256) {
-        double acc[kRateB];
+    const int il = threadIdx.x & 63, jq = threadIdx.x >> 6;
+    const int i = i0 + il;
+    double acc[kRateB];
 #pragma unroll
-        for (int bb = 0; bb < kRateB; ++bb) acc[bb] = 0.0;
-        for (int j = 0; j < n; ++j) {
+    for (int bb = 0; bb < kRateB; ++bb) acc[bb] = 0.0;
+    if (i < n) {
+        for (int j = jq; j < n; j += 4) {
             const double r = RT[(long)j * n + i];
 #pragma unroll
             for (int bb = 0; bb < kRateB; ++bb) acc[bb] += r * fs[bb * n + j];
         }
+    }
 #pragma unroll
-        for (int bb = 0; bb < kRateB; ++bb)
-            if (b0 + bb < B) rate[(long)(b0 + bb) * n + i] = acc[bb];
+    for (int bb = 0; bb < kRateB; ++bb) part[jq][bb][il] = acc[bb];
+    __syncthreads();
+    for (int q = threadIdx.x; q < kRateB * kRateI; q += 256) {
+        const int bb = q / kRateI, l = q - bb * kRateI;
+        const int ii = i0 + l;
+        if (ii < n && b0 + bb < B)
+            rate[(long)(b0 + bb) * n + ii] =
+                ((part[0][bb][l] + part[1][bb][l]) + part[2][bb][l]) + part[3][bb][l];
     }
 }
 
-// Deterministic block sums/maxes over 256 threads (4 waves).
+// Wave-wide (64-lane) butterfly reductions; every lane ends with the same
+// value, since each pairwise step adds the same two operands.
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Deterministic block sums over 256 threads (4 waves), used by k_moments.
 template <int NV>
 __device__ void block_sum(double (&v)[NV], double *lds)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-    for (int j = 0; j < NV; ++j)
-        for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off);
+    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
     if (lane == 0)
 #pragma unroll
         for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
@@ -421,24 +449,8 @@ __device__ void block_sum(double (&v)[NV], double *lds)
     __syncthreads();
 }
 
-template <int NV>
-__device__ void block_max(double (&v)[NV], double *lds)
-{
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        for (int off = 32; off > 0; off >>= 1) v[j] = fmax(v[j], __shfl_xor(v[j], off));
-    if (lane == 0)
-#pragma unroll
-        for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        v[j] = fmax(fmax(lds[j], lds[NV + j]), fmax(lds[2 * NV + j], lds[3 * NV + j]));
-    __syncthreads();
-}
-
-// FP64 epilogue, one workgroup per distribution (App. C):
+// FP64 epilogue, one wave per distribution (4 per workgroup), PER grid
+// points per lane (App. C):
 //   gain = sum of the split partials (fixed order; FP16 scales undone),
 //   C_raw = gain - f * rate,
 //   xi_i = |f_i|/f_max above 1e-12, and the 2x2 system for the correction
@@ -447,118 +459,150 @@ __device__ void block_max(double (&v)[NV], double *lds)
 //   beta = beta' in the paper's E-form), C_proj = C_raw - xi (alpha' + beta' K),
 //   and the diagnostics of eqs. app_epsilon_definition and
 //   app_projection_relative_correction.
-template <typename PT>
+template <typename PT, int PER>
 __global__ __launch_bounds__(256) void k_epilogue(
     const PT *__restrict__ part, int nsplit, long split_stride, int ld_b,
     const float *__restrict__ fscale, const float *__restrict__ rscale,
     const double *__restrict__ rate, const double *__restrict__ f,
     const double *__restrict__ h, const double *__restrict__ K, const double *__restrict__ E,
-    double mass, int n, int project, double *__restrict__ C, double *__restrict__ diag)
+    double mass, int n, int B, int project, double *__restrict__ C, double *__restrict__ diag)
 {
-    __shared__ double lds[4 * 12];
-    const int b = blockIdx.x;
-    constexpr int kPer = kMaxN / 256;
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= B) return;                      // whole wave; no block barriers below
     const double *fb = f + (long)b * n;
-    double fv[kPer], craw[kPer];
-    double mx[3] = {0.0, 0.0, 0.0};       // f_max, rate max, |gain| max
-    double flags[1] = {0.0};
+    double fv[PER], craw[PER], xi[PER];
+    double fmaxv = 0.0, rmax = 0.0, gmax = 0.0, flag = 0.0;
     double inv_s2 = 1.0;
     if (fscale) {
-        const double s = fscale[b];
-        inv_s2 = 1.0 / (s * s);
+        const double sc = fscale[b];
+        inv_s2 = 1.0 / (sc * sc);
     }
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int i = threadIdx.x + 256 * q;
+    for (int q = 0; q < PER; ++q) {
+        const int i = lane + 64 * q;
         fv[q] = 0.0;
         craw[q] = 0.0;
         if (i < n) {
             const double x = fb[i];
             fv[q] = x;
-            if (!isfinite(x)) flags[0] = fmax(flags[0], 1.0);
-            else if (x < 0.0) flags[0] = fmax(flags[0], 0.5);
-            mx[0] = fmax(mx[0], fabs(x));
+            if (!isfinite(x)) flag = fmax(flag, 1.0);
+            else if (x < 0.0) flag = fmax(flag, 0.5);
+            fmaxv = fmax(fmaxv, fabs(x));
             double g = 0.0;
-            for (int s = 0; s < nsplit; ++s) g += (double)part[s * split_stride + (long)b * ld_b + i];
+            for (int sp = 0; sp < nsplit; ++sp) g += (double)part[sp * split_stride + (long)b * ld_b + i];
             if (fscale) g *= inv_s2 / (double)rscale[i];
             const double rt = rate[(long)b * n + i];
-            mx[1] = fmax(mx[1], rt);
-            mx[2] = fmax(mx[2], fabs(g));
+            rmax = fmax(rmax, rt);
+            gmax = fmax(gmax, fabs(g));
             craw[q] = g - x * rt;
         }
     }
-    block_max<3>(mx, lds);
-    block_max<1>(flags, lds);
-    const double fmaxv = mx[0];
-    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double xi[kPer];
+    fmaxv = wave_max(fmaxv);
+    rmax = wave_max(rmax);
+    gmax = wave_max(gmax);
+    flag = wave_max(flag);
+    double s0 = 0, s1 = 0, b00 = 0, b01 = 0, b11 = 0, an = 0, ae = 0, se = 0, num = 0;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int i = threadIdx.x + 256 * q;
+    for (int q = 0; q < PER; ++q) {
+        const int i = lane + 64 * q;
         xi[q] = 0.0;
         if (i < n) {
             const double hi = h[i], ki = K[i], ei = E[i];
-            const double rel = fmaxv > 0.0 ? fabs(fv[q]) / fmaxv : 0.0;
-            xi[q] = rel > 1e-12 ? rel : 0.0;
-            s[0] += hi * craw[q];
-            s[1] += hi * ki * craw[q];
-            s[2] += hi * xi[q];
-            s[3] += hi * ki * xi[q];
-            s[4] += hi * ki * ki * xi[q];
-            s[5] += hi * fabs(craw[q]);
-            s[6] += hi * ei * fabs(craw[q]);
-            s[7] += hi * ei * craw[q];
-            s[8] += hi * fv[q];
+            const double r = fmaxv > 0.0 ? fabs(fv[q]) / fmaxv : 0.0;
+            xi[q] = r > 1e-12 ? r : 0.0;
+            s0 += hi * craw[q];
+            s1 += hi * ki * craw[q];
+            b00 += hi * xi[q];
+            b01 += hi * ki * xi[q];
+            b11 += hi * ki * ki * xi[q];
+            an += hi * fabs(craw[q]);
+            ae += hi * ei * fabs(craw[q]);
+            se += hi * ei * craw[q];
+            num += hi * fv[q];
         }
     }
-    block_sum<9>(s, lds);
+    s0 = wave_sum(s0); s1 = wave_sum(s1);
+    b00 = wave_sum(b00); b01 = wave_sum(b01); b11 = wave_sum(b11);
+    an = wave_sum(an); ae = wave_sum(ae); se = wave_sum(se); num = wave_sum(num);
     double al = 0.0, be = 0.0;
-    const double det = s[2] * s[4] - s[3] * s[3];
+    const double det = b00 * b11 - b01 * b01;
     if (project && det != 0.0 && isfinite(det)) {
-        al = (s[0] * s[4] - s[1] * s[3]) / det;
-        be = (s[1] * s[2] - s[0] * s[3]) / det;
+        al = (s0 * b11 - s1 * b01) / det;
+        be = (s1 * b00 - s0 * b01) / det;
     }
-    double t[6] = {0, 0, 0, 0, 0, 0};
-    double bad[1] = {0.0};
+    double t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0, bad = 0.0;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int i = threadIdx.x + 256 * q;
+    for (int q = 0; q < PER; ++q) {
+        const int i = lane + 64 * q;
         if (i < n) {
             const double hi = h[i], ei = E[i];
             const double cp = craw[q] - xi[q] * (al + be * K[i]);
             const double d = fabs(cp - craw[q]);
-            t[0] += hi * cp;
-            t[1] += hi * ei * cp;
-            t[2] += hi * fabs(cp);
-            t[3] += hi * ei * fabs(cp);
-            t[4] += hi * d;
-            t[5] += hi * ei * d;
+            t0 += hi * cp;
+            t1 += hi * ei * cp;
+            t2 += hi * fabs(cp);
+            t3 += hi * ei * fabs(cp);
+            t4 += hi * d;
+            t5 += hi * ei * d;
             const double out = project ? cp : craw[q];
-            if (!isfinite(out)) bad[0] = 1.0;
+            if (!isfinite(out)) bad = 1.0;
             C[(long)b * n + i] = out;
         }
     }
-    block_sum<6>(t, lds);
-    block_max<1>(bad, lds);
-    if (diag && threadIdx.x == 0) {
-        double *d = diag + (long)b * KXG_NDIAG;
-        d[0] = al - be * mass;
-        d[1] = be;
-        d[2] = s[5] > 0.0 ? s[0] / s[5] : 0.0;
-        d[3] = s[6] > 0.0 ? s[7] / s[6] : 0.0;
-        d[4] = t[2] > 0.0 ? t[0] / t[2] : 0.0;
-        d[5] = t[3] > 0.0 ? t[1] / t[3] : 0.0;
-        d[6] = s[5] > 0.0 ? t[4] / s[5] : 0.0;
-        d[7] = s[6] > 0.0 ? t[5] / s[6] : 0.0;
-        d[8] = mx[1];
-        d[9] = mx[2];
-        double st = 0.0;
-        if (flags[0] >= 1.0) st += 1.0;
-        else if (flags[0] > 0.0) st += 2.0;
-        if (bad[0] > 0.0) st += 4.0;
-        d[10] = st;
-        d[11] = s[8];
+    if (diag) {
+        t0 = wave_sum(t0); t1 = wave_sum(t1); t2 = wave_sum(t2);
+        t3 = wave_sum(t3); t4 = wave_sum(t4); t5 = wave_sum(t5);
+        bad = wave_max(bad);
+        if (lane == 0) {
+            double *d = diag + (long)b * KXG_NDIAG;
+            d[0] = al - be * mass;
+            d[1] = be;
+            d[2] = an > 0.0 ? s0 / an : 0.0;
+            d[3] = ae > 0.0 ? se / ae : 0.0;
+            d[4] = t2 > 0.0 ? t0 / t2 : 0.0;
+            d[5] = t3 > 0.0 ? t1 / t3 : 0.0;
+            d[6] = an > 0.0 ? t4 / an : 0.0;
+            d[7] = ae > 0.0 ? t5 / ae : 0.0;
+            d[8] = rmax;
+            d[9] = gmax;
+            double st = 0.0;
+            if (flag >= 1.0) st += 1.0;
+            else if (flag > 0.0) st += 2.0;
+            if (bad > 0.0) st += 4.0;
+            d[10] = st;
+            d[11] = num;
+        }
     }
+}
+
+template <typename PT>
+hipError_t launch_epilogue(const PT *part, int nsplit, long split_stride, int ld_b,
+                           const float *fscale, const float *rscale, const double *rate,
+                           const double *f, const kxg_kernel &k, int B, int project, double *C,
+                           double *diag, hipStream_t s)
+{
+    const int n = k.n;
+    const dim3 grid((B + 3) / 4), blk(256);
+#define KXG_EPI(P)                                                                             \
+    hipLaunchKernelGGL((k_epilogue<PT, P>), grid, blk, 0, s, part, nsplit, split_stride, ld_b, \
+                       fscale, rscale, rate, f, k.d_h, k.d_K, k.d_E, k.mass, n, B, project, C, \
+                       diag)
+    if (n <= 64) KXG_EPI(1);
+    else if (n <= 128) KXG_EPI(2);
+    else if (n <= 256) KXG_EPI(4);
+    else if (n <= 512) KXG_EPI(8);
+    else KXG_EPI(16);
+#undef KXG_EPI
+    return hipGetLastError();
+}
+
+hipError_t launch_rate(const kxg_kernel &k, const double *f, int B, double *rate, hipStream_t s)
+{
+    const dim3 grid((B + kRateB - 1) / kRateB, (k.n + kRateI - 1) / kRateI);
+    hipLaunchKernelGGL(k_rate, grid, dim3(256), kRateB * k.n * sizeof(double), s, k.d_RT, f,
+                       k.n, B, rate);
+    return hipGetLastError();
 }
 
 // Moments sum h f, sum h E f, -sum_{f>0} h f (ln f - 1); one workgroup per row.
@@ -672,12 +716,9 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         }
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_rate, dim3(div_up(B, kRateB)), dim3(256), kRateB * n * sizeof(double), s,
-                           k.d_RT, f, n, B, rate);
-        hipLaunchKernelGGL(k_epilogue<double>, dim3(B), dim3(256), 0, s, part, nsplit,
-                           (long)B * n, n, (const float *)nullptr, (const float *)nullptr, rate, f,
-                           k.d_h, k.d_K, k.d_E, k.mass, n, project, C, diag);
-        KXG_TRY_HIP(hipGetLastError());
+        KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
+        KXG_TRY_HIP(launch_epilogue<double>(part, nsplit, (long)B * n, n, nullptr, nullptr, rate,
+                                            f, k, B, project, C, diag, s));
         return KXG_OK;
     }
     // GEMM path
@@ -713,13 +754,10 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
 #undef KXG_GEMM_X3
     profile_mark_end(s);
     KXG_TRY_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_rate, dim3(div_up(B, kRateB)), dim3(256), kRateB * n * sizeof(double), s,
-                       k.d_RT, f, n, B, rate);
-    hipLaunchKernelGGL(k_epilogue<float>, dim3(B), dim3(256), 0, s, part, splits,
-                       (long)bpad * g.ipad, g.ipad, f16 ? ws.fscale : (const float *)nullptr,
-                       f16 ? k.d_hrow : (const float *)nullptr, rate, f, k.d_h, k.d_K, k.d_E,
-                       k.mass, n, project, C, diag);
-    KXG_TRY_HIP(hipGetLastError());
+    KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
+    KXG_TRY_HIP(launch_epilogue<float>(part, splits, (long)bpad * g.ipad, g.ipad,
+                                       f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr, rate, f,
+                                       k, B, project, C, diag, s));
     return KXG_OK;
 }
 
