@@ -42,12 +42,102 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=800,
                     help="measured serving requests (after --serve-warm warm-up ones); 0 = skip")
     ap.add_argument("--serve-warm", type=int, default=200)
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for hardware counters: the timed RK4 steps, the plain FP64 "
+                         "path and a 1 GiB device copy (the calibration kernel), nothing else")
     return ap.parse_args()
 
 
 def packed_k(n):
     nb = (n + 15) // 16
     return nb * (nb + 1) // 2 * 256
+
+
+import numpy as np
+
+
+def single_paths(args, dev):
+    """The plain single-distribution paths: FP64 stream at N = 384 (A is
+    453 MB, larger than the 256 MB Infinity Cache, so the stream comes from
+    HBM), the N = 32 FP64 RK4 run (100 steps, launch-bound, graph replay) and
+    the N = 128 FP32 drift run (adaptive Heun until 1e4 accepted steps)."""
+    import torch
+    from paper_2607_00755_amd import inputs, kxg
+    out = {}
+    # HBM stream, N = 384 FP64
+    n = 384
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    k = kxg.Kernel(p, precs=(kxg.F64,), b_cap=1)
+    f = torch.tensor(inputs.draw_solves(1)[0].f0(p)[None, :], device=dev)
+    C = torch.empty_like(f)
+    d = torch.empty((1, kxg.NDIAG), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        k.eval(f, prec=kxg.F64, out=C, diag=d)
+    torch.cuda.synchronize()
+    reps = 100
+    kxg.profile_begin(reps + 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        k.eval(f, prec=kxg.F64, out=C, diag=d)
+    torch.cuda.synchronize()
+    wl = (time.perf_counter() - t0) / reps
+    ms, cnt = kxg.profile_end()
+    us = 1e3 * ms / max(cnt, 1)
+    gbps = 8.0 * n ** 3 / (us * 1e-6) / 1e9
+    out["plain_fp64_n384"] = {"evals_per_s": round(1.0 / wl, 1), "stream_kernel_us": round(us, 2),
+                              "stream_GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK, 4),
+                              "bytes_per_launch": 8 * n ** 3}
+    log("plain fp64 N=384 stream: %.1f us, %.0f GB/s" % (us, gbps))
+    del k
+    # N = 32 FP64, RK4, 100 steps on a side stream (captured graph)
+    w = inputs.single_fp64_n32()
+    p = w.grid()
+    k = kxg.Kernel(p, precs=(kxg.F64,), b_cap=1)
+    side = torch.cuda.Stream()
+    f0 = torch.tensor(w.f0()[0], device=dev)
+    times = []
+    for rep in range(3):
+        st = kxg.Stepper(k, kind=kxg.RK4, prec=kxg.F64, b_cap=1)
+        st.set(0, f0, lam=1.0, t_end=1e30, h_i=1.0, max_steps=100, stream=side)
+        st.advance(1, stream=side)          # capture
+        side.synchronize()
+        st.set(0, f0, lam=1.0, t_end=1e30, h_i=1.0, max_steps=100, stream=side)
+        side.synchronize()
+        t0 = time.perf_counter()
+        st.advance(100, stream=side)
+        side.synchronize()
+        times.append(time.perf_counter() - t0)
+    best = min(times)
+    out["single_fp64_n32_rk4"] = {"steps": 100, "ms_total": round(1e3 * best, 3),
+                                  "us_per_step": round(1e6 * best / 100, 2),
+                                  "us_per_eval": round(1e6 * best / 400, 2)}
+    log("N=32 fp64 RK4: %.1f us/step" % (1e6 * best / 100))
+    del k
+    # N = 128 FP32, adaptive Heun with radiation drift, until 1e4 accepted steps
+    w = inputs.single_fp32_n128()
+    p = w.grid()
+    s = w.solves[0]
+    k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=1)
+    st = kxg.Stepper(k, kind=kxg.HEUN, prec=kxg.F32, b_cap=1, expansion=kxg.EXP_RADIATION)
+    st.set(0, torch.tensor(w.f0()[0], device=dev), lam=s.lam, t_end=0.5 * np.log(2e4), dt=1e-3,
+           h_i=0.0, max_steps=10000, stream=side)
+    side.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    while True:
+        st.advance(256, stream=side)
+        it += 256
+        q = st.query(stream=side)[0]
+        if q["status"] != 0 or it > 60000:
+            break
+    el = time.perf_counter() - t0
+    out["single_fp32_n128_drift"] = {"accepted": q["steps"], "rejected": q["rejected"],
+                                     "u_reached": round(q["t"], 4), "status": q["status"],
+                                     "wall_s": round(el, 3),
+                                     "us_per_attempt": round(1e6 * el / (q["steps"] + q["rejected"]), 2),
+                                     "lambda": s.lam}
+    log("N=128 fp32 drift: %d steps in %.2f s" % (q["steps"], el))
+    return out
 
 
 def main():
@@ -101,6 +191,13 @@ def main():
                 "dense_equiv_flops_per_launch": flops_dense}
 
     extras = {}
+    if args.profile_run:
+        # calibration kernel for the HBM byte counters: a plain 1 GiB copy
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        args.no_extras, args.no_cpu_baseline, args.serve_requests = True, True, 0
     # ---------------- plain FP64 single distribution ----------------
     f1 = f0[:1].contiguous()
     C1 = torch.empty_like(f1)
@@ -154,6 +251,10 @@ def main():
                 "mfma_frac": round(fl / (g_us * 1e-6) / 1e12 / PEAK["bf16"], 4)}
             log("%s B=4096: %.3f ms/call, gemm %.1f us" % (name, 1e3 * wl, g_us))
         del k4
+
+    if not args.no_extras:
+        # ---------------- single-distribution paths ----------------
+        extras.update(single_paths(args, dev))
 
     # ---------------- serving loop (continuous batching) ----------------
     serve = None

@@ -399,7 +399,18 @@ __global__ __launch_bounds__(256) void k_rate(const double *__restrict__ RT,
 #pragma unroll
     for (int bb = 0; bb < kRateB; ++bb) acc[bb] = 0.0;
     if (i < n) {
-        for (int j = jq; j < n; j += 4) {
+        // eight R loads in flight per thread, then the FMAs in j order
+        int j = jq;
+        for (; j + 28 < n; j += 32) {
+            double r[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) r[u] = RT[(long)(j + 4 * u) * n + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int bb = 0; bb < kRateB; ++bb) acc[bb] += r[u] * fs[bb * n + j + 4 * u];
+        }
+        for (; j < n; j += 4) {
             const double r = RT[(long)j * n + i];
 #pragma unroll
             for (int bb = 0; bb < kRateB; ++bb) acc[bb] += r * fs[bb * n + j];
@@ -489,8 +500,18 @@ __global__ __launch_bounds__(256) void k_epilogue(
             if (!isfinite(x)) flag = fmax(flag, 1.0);
             else if (x < 0.0) flag = fmax(flag, 0.5);
             fmaxv = fmax(fmaxv, fabs(x));
+            // split partials: loads issued 8 at a time, added in split order
+            const PT *pp = part + (long)b * ld_b + i;
             double g = 0.0;
-            for (int sp = 0; sp < nsplit; ++sp) g += (double)part[sp * split_stride + (long)b * ld_b + i];
+            int sp = 0;
+            for (; sp + 8 <= nsplit; sp += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = (double)pp[(sp + u) * split_stride];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) g += v[u];
+            }
+            for (; sp < nsplit; ++sp) g += (double)pp[sp * split_stride];
             if (fscale) g *= inv_s2 / (double)rscale[i];
             const double rt = rate[(long)b * n + i];
             rmax = fmax(rmax, rt);
