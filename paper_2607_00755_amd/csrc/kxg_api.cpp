@@ -113,11 +113,19 @@ static void profile_clear()
     g_prof = Profile{};
 }
 
+// Workgroups aimed at per GEMM launch (at the handle's largest batch).
+#ifndef KXG_GEMM_WG_TARGET
+#define KXG_GEMM_WG_TARGET 512
+#endif
+#ifndef KXG_LDS_WG_TARGET
+#define KXG_LDS_WG_TARGET 256
+#endif
+
 static int choose_splits(const Geometry &g, int b_cap)
 {
     const int bbw = b_cap <= 32 ? 1 : (b_cap <= 64 ? 2 : 4);
     const int tiles = div_up(b_cap, 32 * bbw) * g.nib;
-    int s = div_up(512, tiles);                       // about two workgroups per CU
+    int s = div_up(KXG_GEMM_WG_TARGET, tiles);
     const int cap = (int)std::max<long>(1, g.dksteps / (kWaves * 4));  // >= 4 steps a wave
     return std::max(1, std::min(s, cap));
 }
@@ -283,6 +291,12 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     g.ipad = g.nib * kIBlk;
     g.dksteps = (long)g.npairs * kBlk;
     k->gemm_splits = choose_splits(g, b_cap);
+    {
+        // LDS-shared 16-bit GEMM: about one 512 x 64 tile per CU
+        const int tiles = div_up(b_cap, 512) * div_up(g.nib, 2);
+        const int cap = (int)std::max<long>(1, g.dksteps / 8);
+        k->lds_splits = std::max(1, std::min(div_up(KXG_LDS_WG_TARGET, tiles), cap));
+    }
 
     const size_t n3 = (size_t)n * n * n, n2 = (size_t)n * n;
     const bool want32 = prec_mask & KXG_PREC_BIT(KXG_F32);

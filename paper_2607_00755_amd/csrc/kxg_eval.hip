@@ -195,7 +195,47 @@ __device__ void store_tile(floatx16 (&acc)[BBW], float *lds, float *__restrict__
 // consecutive sub-ranges of the split's dk steps.  Per dk step (one row k of a
 // (kb, mb) block, 16 K values) a wave issues 8*BBW MFMAs; the A operand
 // (F2 = f_k f_m) is one multiply per MFMA, the B operand (packed tensor)
-// comes straight from memory in MFMA order, prefetched one step ahead.
+// comes straight from memory in MFMA order.  Software pipeline: the packed
+// fragment and f_k of step u+2 are requested while step u computes, and the
+// f_m values of the next (kb, mb) block one step before it starts.
+template <int BBW>
+struct F32Stage {
+    float4 b0, b1;
+    float fk[BBW];
+};
+
+template <int BBW>
+__device__ inline void f32_load_stage(F32Stage<BBW> &st, const float *__restrict__ Gi,
+                                      const float *__restrict__ fop,
+                                      const int *__restrict__ pairs, long u, int bpad,
+                                      int brow0, int r, int lane)
+{
+    const int pr = (int)(u >> 4), dk = (int)(u & 15);
+    const float *gp = Gi + u * 512;
+    st.b0 = reinterpret_cast<const float4 *>(gp)[lane];
+    st.b1 = reinterpret_cast<const float4 *>(gp + 256)[lane];
+    const int kb = pairs[2 * pr];
+#pragma unroll
+    for (int bb = 0; bb < BBW; ++bb)
+        st.fk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
+}
+
+template <int BBW>
+__device__ inline void f32_load_fm(float (&fm)[BBW][8], const float *__restrict__ fpar,
+                                   const int *__restrict__ pairs, int pr, int bpad, int brow0,
+                                   int r, int hb)
+{
+    const int mb = pairs[2 * pr + 1];
+#pragma unroll
+    for (int bb = 0; bb < BBW; ++bb) {
+        const float4 *src = reinterpret_cast<const float4 *>(
+            fpar + (((long)mb * bpad + brow0 + bb * 32 + r) * 2 + hb) * 8);
+        const float4 x0 = src[0], x1 = src[1];
+        fm[bb][0] = x0.x; fm[bb][1] = x0.y; fm[bb][2] = x0.z; fm[bb][3] = x0.w;
+        fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
+    }
+}
+
 template <int BBW>
 __global__ __launch_bounds__(256, 2) void k_gemm_f32(
     const float *__restrict__ G, const float *__restrict__ fop, const float *__restrict__ fpar,
@@ -221,56 +261,33 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[bb][e] = 0.0f;
 
-    float fm[BBW][8];
-    int cur_pair = -1;
-    float4 nb0 = make_float4(0, 0, 0, 0), nb1 = nb0;
-    float nfk[BBW];
+    float fm[BBW][8], nfm[BBW][8];
+    F32Stage<BBW> s0, s1;
     if (u0 < u1) {
-        const int pr = (int)(u0 >> 4), dk = (int)(u0 & 15);
-        const float *gp = Gi + u0 * 512;
-        nb0 = reinterpret_cast<const float4 *>(gp)[lane];
-        nb1 = reinterpret_cast<const float4 *>(gp + 256)[lane];
-        const int kb = pairs[2 * pr];
-#pragma unroll
-        for (int bb = 0; bb < BBW; ++bb)
-            nfk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
+        f32_load_fm<BBW>(fm, fpar, pairs, (int)(u0 >> 4), bpad, brow0, r, hb);
+        f32_load_stage<BBW>(s0, Gi, fop, pairs, u0, bpad, brow0, r, lane);
     }
+    if (u0 + 1 < u1) f32_load_stage<BBW>(s1, Gi, fop, pairs, u0 + 1, bpad, brow0, r, lane);
     for (long u = u0; u < u1; ++u) {
-        const int pr = (int)(u >> 4);
-        if (pr != cur_pair) {
-            cur_pair = pr;
-            const int mb = pairs[2 * pr + 1];
-#pragma unroll
-            for (int bb = 0; bb < BBW; ++bb) {
-                const float4 *src = reinterpret_cast<const float4 *>(
-                    fpar + (((long)mb * bpad + brow0 + bb * 32 + r) * 2 + hb) * 8);
-                const float4 x0 = src[0], x1 = src[1];
-                fm[bb][0] = x0.x; fm[bb][1] = x0.y; fm[bb][2] = x0.z; fm[bb][3] = x0.w;
-                fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
-            }
-        }
-        const float4 b0 = nb0, b1 = nb1;
-        float fk[BBW];
-#pragma unroll
-        for (int bb = 0; bb < BBW; ++bb) fk[bb] = nfk[bb];
-        if (u + 1 < u1) {
-            const long un = u + 1;
-            const int prn = (int)(un >> 4), dkn = (int)(un & 15);
-            const float *gp = Gi + un * 512;
-            nb0 = reinterpret_cast<const float4 *>(gp)[lane];
-            nb1 = reinterpret_cast<const float4 *>(gp + 256)[lane];
-            const int kbn = pairs[2 * prn];
-#pragma unroll
-            for (int bb = 0; bb < BBW; ++bb)
-                nfk[bb] = fop[((long)kbn * bpad + brow0 + bb * 32 + r) * kBlk + dkn];
-        }
-        const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+        const F32Stage<BBW> cur = s0;
+        s0 = s1;
+        if (u + 2 < u1) f32_load_stage<BBW>(s1, Gi, fop, pairs, u + 2, bpad, brow0, r, lane);
+        const bool next_block = (u + 1 < u1) && (((u + 1) & 15) == 0);
+        if (next_block) f32_load_fm<BBW>(nfm, fpar, pairs, (int)((u + 1) >> 4), bpad, brow0, r, hb);
+        const float bv[8] = {cur.b0.x, cur.b0.y, cur.b0.z, cur.b0.w,
+                             cur.b1.x, cur.b1.y, cur.b1.z, cur.b1.w};
 #pragma unroll
         for (int t = 0; t < 8; ++t)
 #pragma unroll
             for (int bb = 0; bb < BBW; ++bb)
-                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fk[bb] * fm[bb][t], bv[t],
+                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur.fk[bb] * fm[bb][t], bv[t],
                                                                acc[bb], 0, 0, 0);
+        if (next_block) {
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) fm[bb][t] = nfm[bb][t];
+        }
     }
     store_tile<BBW>(acc, lds, part, sp, bpad, ipad, brow0, ib * kIBlk);
 }
@@ -374,57 +391,191 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(
     store_tile<BBW>(acc, lds, part, sp, bpad, ipad, brow0, ib * kIBlk);
 }
 
+// 16-bit x3 GEMM for large batches, A operand shared through LDS.  A
+// workgroup's 4 waves work on the same K chunk (split) and the same IBW
+// i-blocks; wave w takes the BBW b-blocks [w*BBW, (w+1)*BBW) of the
+// workgroup's 4*BBW*32-row batch tile.  Per dk step the workgroup stages the
+// hi/lo A fragments of its i-blocks (2 KB each) once into a double-buffered
+// LDS ring; every wave forms and splits its F2 operand once and feeds it to
+// 3*IBW MFMAs.  One barrier per dk step.  Partials: one per K split.
+template <int BBW, int IBW, bool F16>
+__global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
+    const uint16_t *__restrict__ G, const float *__restrict__ fop, const int *__restrict__ pairs,
+    int npairs, int nib, int bpad, int ipad, int nbt, int nit, int splits, long dksteps,
+    float *__restrict__ part)
+{
+    typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
+    typedef typename std::conditional<F16, _Float16, __bf16>::type op_t;
+    constexpr int NV = IBW * 2 * 64;               // 16-byte vectors per dk step
+    static_assert(NV <= 256, "one vector per thread at most");
+    __shared__ uint4 sA[2][NV];
+    int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int bt = L % nbt;
+    L /= nbt;
+    const int sp = L % splits;
+    const int it = L / splits;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 31, hb = lane >> 5;
+    const long u0 = (long)sp * dksteps / splits, u1 = (long)(sp + 1) * dksteps / splits;
+    const int brow0 = bt * (4 * BBW * 32) + wave * (BBW * 32);
+    const int ib0 = it * IBW;
+    // loader role of this thread: vector q = threadIdx.x of the dk step
+    const int q = threadIdx.x;
+    const int qib = q / 128, qrest = q % 128;
+    const bool qload = q < NV && ib0 + qib < nib;
+    const uint4 *qsrc = reinterpret_cast<const uint4 *>(
+        G + (long)(ib0 + (qload ? qib : 0)) * npairs * kBlk * 1024) + qrest;
+    // (a dk step is 1024 16-bit values = 128 vectors: [hi|lo][lane][8])
+
+    floatx16 acc[BBW][IBW];
+#pragma unroll
+    for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+        for (int ib = 0; ib < IBW; ++ib)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[bb][ib][e] = 0.0f;
+
+    float fm[BBW][8];
+    int cur_pair = -1;
+    const uint4 zero4 = make_uint4(0, 0, 0, 0);
+    uint4 pre = (qload && u0 < u1) ? qsrc[u0 * 128] : zero4;
+    float nfk[BBW];
+    if (u0 < u1) {
+        const int pr = (int)(u0 >> 4), dk = (int)(u0 & 15);
+        const int kb = pairs[2 * pr];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+            nfk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
+    }
+    for (long u = u0; u < u1; ++u) {
+        const int buf = (int)((u - u0) & 1);
+        if (q < NV) sA[buf][q] = pre;
+        __syncthreads();
+        const int pr = (int)(u >> 4);
+        if (pr != cur_pair) {
+            cur_pair = pr;
+            const int mb = pairs[2 * pr + 1];
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb) {
+                const float4 *src = reinterpret_cast<const float4 *>(
+                    fop + ((long)mb * bpad + brow0 + bb * 32 + r) * kBlk + 8 * hb);
+                const float4 x0 = src[0], x1 = src[1];
+                fm[bb][0] = x0.x; fm[bb][1] = x0.y; fm[bb][2] = x0.z; fm[bb][3] = x0.w;
+                fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
+            }
+        }
+        float fk[BBW];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb) fk[bb] = nfk[bb];
+        if (u + 1 < u1) {
+            const long un = u + 1;
+            if (qload) pre = qsrc[un * 128];
+            const int prn = (int)(un >> 4), dkn = (int)(un & 15);
+            const int kbn = pairs[2 * prn];
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb)
+                nfk[bb] = fop[((long)kbn * bpad + brow0 + bb * 32 + r) * kBlk + dkn];
+        }
+        opx8 Ah[IBW], Al[IBW];
+#pragma unroll
+        for (int ib = 0; ib < IBW; ++ib) {
+            Ah[ib] = __builtin_bit_cast(opx8, sA[buf][ib * 128 + lane]);
+            Al[ib] = __builtin_bit_cast(opx8, sA[buf][ib * 128 + 64 + lane]);
+        }
+        opx8 ph[BBW], pl[BBW];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float pv = fk[bb] * fm[bb][j];
+                const op_t h = (op_t)pv;
+                ph[bb][j] = h;
+                pl[bb][j] = (op_t)(pv - (float)h);
+            }
+        // three products, smallest first; consecutive MFMAs hit different
+        // accumulators
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+                for (int ib = 0; ib < IBW; ++ib) {
+                    const opx8 &a = t == 0 ? pl[bb] : ph[bb];
+                    const opx8 &bm = t == 1 ? Al[ib] : Ah[ib];
+                    if constexpr (F16)
+                        acc[bb][ib] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bm, acc[bb][ib], 0, 0, 0);
+                    else
+                        acc[bb][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bm, acc[bb][ib], 0, 0, 0);
+                }
+    }
+    float *dst = part + (long)sp * bpad * ipad;
+#pragma unroll
+    for (int ib = 0; ib < IBW; ++ib) {
+        if (ib0 + ib >= nib) continue;
+        const int col = (ib0 + ib) * kIBlk + r;
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = brow0 + bb * 32 + 8 * (e >> 2) + 4 * hb + (e & 3);
+                dst[(long)row * ipad + col] = acc[bb][ib][e];
+            }
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Loss rates rate[b][i] = sum_j R[i][j] f_bj in FP64.  Workgroup tile: 8
-// distributions x 64 rows i; its 4 waves take the j sums j = w, w+4, ... and
-// the 4 partial sums are added in a fixed order.  Each R^T row segment read
-// (64 consecutive i, coalesced) serves the 8 distributions.
-constexpr int kRateB = 8;
-constexpr int kRateI = 64;
+// Loss rates rate[b][i] = sum_j R[i][j] f_bj in FP64 on v_mfma_f64_16x16x4f64.
+// Workgroup = one 16 (b) x 16 (i) output tile; its 4 waves take 4
+// consecutive j ranges and their accumulators are added in the fixed order
+// 0+1+2+3.  Operand/result layout of the instruction: A[row][k] at lane
+// row + 16k, B[k][col] at lane col + 16k, D[row][col] at lane
+// col + 16 (row % 4), register row / 4.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int kRateT = 16;
 __global__ __launch_bounds__(256) void k_rate(const double *__restrict__ RT,
                                               const double *__restrict__ f, int n, int B,
                                               double *__restrict__ rate)
 {
-    extern __shared__ double fs[];   // [kRateB][n]
-    __shared__ double part[4][kRateB][kRateI];
-    const int b0 = blockIdx.x * kRateB, i0 = blockIdx.y * kRateI;
-    for (int q = threadIdx.x; q < kRateB * n; q += 256) {
-        const int bb = q / n, j = q - bb * n;
-        fs[q] = (b0 + bb < B) ? f[(long)(b0 + bb) * n + j] : 0.0;
-    }
-    __syncthreads();
-    const int il = threadIdx.x & 63, jq = threadIdx.x >> 6;
-    const int i = i0 + il;
-    double acc[kRateB];
+    __shared__ double red[3][4][64];
+    const int b0 = blockIdx.x * kRateT, i0 = blockIdx.y * kRateT;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nsteps = (n + 3) / 4;                         // K steps of 4
+    const int per = (nsteps + 3) / 4;
+    const int s0 = wave * per, s1 = min(nsteps, s0 + per);
+    const int b = b0 + lr, i = i0 + lr;
+    const double *frow = f + (long)(b < B ? b : 0) * n;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    int st = s0;
+    for (; st + 4 <= s1; st += 4) {
+        double av[4], bv[4];
 #pragma unroll
-    for (int bb = 0; bb < kRateB; ++bb) acc[bb] = 0.0;
-    if (i < n) {
-        // eight R loads in flight per thread, then the FMAs in j order
-        int j = jq;
-        for (; j + 28 < n; j += 32) {
-            double r[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) r[u] = RT[(long)(j + 4 * u) * n + i];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int bb = 0; bb < kRateB; ++bb) acc[bb] += r[u] * fs[bb * n + j + 4 * u];
+        for (int u = 0; u < 4; ++u) {
+            const int j = 4 * (st + u) + lk;
+            av[u] = (b < B && j < n) ? frow[j] : 0.0;
+            bv[u] = (i < n && j < n) ? RT[(long)j * n + i] : 0.0;
         }
-        for (; j < n; j += 4) {
-            const double r = RT[(long)j * n + i];
 #pragma unroll
-            for (int bb = 0; bb < kRateB; ++bb) acc[bb] += r * fs[bb * n + j];
-        }
+        for (int u = 0; u < 4; ++u)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
     }
+    for (; st < s1; ++st) {
+        const int j = 4 * st + lk;
+        const double av = (b < B && j < n) ? frow[j] : 0.0;
+        const double bv = (i < n && j < n) ? RT[(long)j * n + i] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    if (wave > 0)
 #pragma unroll
-    for (int bb = 0; bb < kRateB; ++bb) part[jq][bb][il] = acc[bb];
+        for (int r = 0; r < 4; ++r) red[wave - 1][r][lane] = acc[r];
     __syncthreads();
-    for (int q = threadIdx.x; q < kRateB * kRateI; q += 256) {
-        const int bb = q / kRateI, l = q - bb * kRateI;
-        const int ii = i0 + l;
-        if (ii < n && b0 + bb < B)
-            rate[(long)(b0 + bb) * n + ii] =
-                ((part[0][bb][l] + part[1][bb][l]) + part[2][bb][l]) + part[3][bb][l];
+    if (wave == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double v = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+            const int bo = b0 + lk + 4 * r, io = i0 + lr;
+            if (bo < B && io < n) rate[(long)bo * n + io] = v;
+        }
     }
 }
 
@@ -620,9 +771,8 @@ hipError_t launch_epilogue(const PT *part, int nsplit, long split_stride, int ld
 
 hipError_t launch_rate(const kxg_kernel &k, const double *f, int B, double *rate, hipStream_t s)
 {
-    const dim3 grid((B + kRateB - 1) / kRateB, (k.n + kRateI - 1) / kRateI);
-    hipLaunchKernelGGL(k_rate, grid, dim3(256), kRateB * k.n * sizeof(double), s, k.d_RT, f,
-                       k.n, B, rate);
+    const dim3 grid((B + kRateT - 1) / kRateT, (k.n + kRateT - 1) / kRateT);
+    hipLaunchKernelGGL(k_rate, grid, dim3(256), 0, s, k.d_RT, f, k.n, B, rate);
     return hipGetLastError();
 }
 
@@ -673,14 +823,20 @@ kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws)
         const size_t g = (size_t)k.gemm_splits * bpad * k.geo.ipad * sizeof(float);
         if (g > need) need = g;
     }
+    if ((k.d_Gbf || k.d_Gh) && b_cap >= kLdsMinB) {
+        const size_t bl = (size_t)div_up(b_cap, 512) * 512;
+        const size_t g = (size_t)k.lds_splits * bl * k.geo.ipad * sizeof(float);
+        if (g > need) need = g;
+    }
     need += (size_t)b_cap * n * sizeof(double);      // loss rates
     ws.part_bytes = need;
     ws.bpad_cap = bpad;
     ws.b_cap = b_cap;
     if (hipMalloc(&ws.part, need) != hipSuccess) { set_error("workspace: out of memory"); return KXG_ENOMEM; }
-    const size_t fb = (size_t)k.geo.nb * bpad * kBlk * sizeof(float);
+    const int bpad_l = div_up(b_cap, 512) * 512;
+    const size_t fb = (size_t)k.geo.nb * (bpad_l > bpad ? bpad_l : bpad) * kBlk * sizeof(float);
     if (hipMalloc((void **)&ws.fop, fb) != hipSuccess || hipMalloc((void **)&ws.fpar, fb) != hipSuccess ||
-        hipMalloc((void **)&ws.fscale, bpad * sizeof(float)) != hipSuccess) {
+        hipMalloc((void **)&ws.fscale, (bpad_l > bpad ? bpad_l : bpad) * sizeof(float)) != hipSuccess) {
         set_error("workspace: out of memory");
         return KXG_ENOMEM;
     }
@@ -742,6 +898,33 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
                                             f, k, B, project, C, diag, s));
         return KXG_OK;
     }
+    const bool f16 = prec == KXG_F16X3;
+    if ((prec == KXG_BF16X3 || prec == KXG_F16X3) && B >= kLdsMinB) {
+        // large batch: 16-bit GEMM with the A operand shared through LDS
+        constexpr int BBW = 4, IBW = 2, TILE = 4 * BBW * 32;
+        const int bpad = div_up(B, TILE) * TILE;
+        const int nbt = bpad / TILE, nit = div_up(g.nib, IBW);
+        const int splits = k.lds_splits;
+        hipLaunchKernelGGL(k_prep, dim3(bpad), dim3(256), 0, s, f, B, n, g.nb, bpad, f16 ? 1 : 0,
+                           ws.fop, ws.fpar, ws.fscale);
+        float *part = static_cast<float *>(ws.part);
+        profile_mark_begin(s);
+        if (f16)
+            hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, true>), dim3(nbt * nit * splits), dim3(256), 0, s,
+                               k.d_Gh, ws.fop, k.d_pairs, g.npairs, g.nib, bpad, g.ipad, nbt, nit,
+                               splits, g.dksteps, part);
+        else
+            hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, false>), dim3(nbt * nit * splits), dim3(256), 0, s,
+                               k.d_Gbf, ws.fop, k.d_pairs, g.npairs, g.nib, bpad, g.ipad, nbt, nit,
+                               splits, g.dksteps, part);
+        profile_mark_end(s);
+        KXG_TRY_HIP(hipGetLastError());
+        KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
+        KXG_TRY_HIP(launch_epilogue<float>(part, splits, (long)bpad * g.ipad, g.ipad,
+                                           f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr, rate,
+                                           f, k, B, project, C, diag, s));
+        return KXG_OK;
+    }
     // GEMM path
     const int bbw = gemm_bbw(B);
     const int tile = 32 * bbw;
@@ -749,7 +932,6 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     const int nbt = bpad / tile;
     const int splits = k.gemm_splits;
     const int nwg = nbt * g.nib * splits;
-    const bool f16 = prec == KXG_F16X3;
     hipLaunchKernelGGL(k_prep, dim3(bpad), dim3(256), 0, s, f, B, n, g.nb, bpad, f16 ? 1 : 0,
                        ws.fop, ws.fpar, ws.fscale);
     float *part = static_cast<float *>(ws.part);

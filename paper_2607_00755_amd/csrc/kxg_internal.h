@@ -27,6 +27,7 @@ constexpr int kBlk = 16;             // (k,m) block edge of the packed GEMM layo
 constexpr int kIBlk = 32;            // output rows (i) per MFMA tile
 constexpr int kBRows = 32;           // distributions per MFMA tile
 constexpr int kWaves = 4;            // waves per GEMM workgroup (split K)
+constexpr int kLdsMinB = 512;        // batches from this size use the LDS-shared 16-bit GEMM
 
 // Geometry of the block-packed GEMM operand: the (k,m) plane is cut into
 // 16x16 blocks; only blocks with kb <= mb are stored (off-diagonal blocks hold
@@ -72,6 +73,7 @@ struct kxg_kernel {
     int *d_pairs = nullptr;      // [npairs][2] (kb, mb)
     kxg::Geometry geo;
     int gemm_splits = 8;         // workgroup splits of K (fixed per handle)
+    int lds_splits = 8;          // K splits of the LDS-shared 16-bit GEMM
     size_t bytes[4] = {0, 0, 0, 0};
     kxg::Workspace ws;
 };

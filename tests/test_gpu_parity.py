@@ -335,3 +335,22 @@ def test_graph_replay_matches_eager(dev, kind, prec, B):
             assert torch.equal(out[0], out[1]), (rnd, b)
         q0, q1 = steppers[0].query(stream=side), steppers[1].query()
         assert [x["steps"] for x in q0[:B]] == [x["steps"] for x in q1[:B]]
+
+
+@pytest.mark.parametrize("prec", [kxg.BF16X3, kxg.F16X3])
+def test_eval_16bit_large_batch_lds_path(dev, prec):
+    """B >= 512 takes the LDS-shared GEMM: ragged batch (600 -> 1024 rows) and
+    a ragged i-tile (n = 80: 3 blocks of 32 in tiles of 2)."""
+    n = 80
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    f0 = batch(p, 600, seed=14)
+    k = kxg.Kernel(p, precs=(prec,), b_cap=600)
+    f = torch.tensor(f0, device=dev)
+    C, _ = k.eval(f, prec=prec, project=True)
+    sub, _ = k.eval(f[:520].contiguous(), prec=prec, project=True)
+    torch.cuda.synchronize()
+    C, sub = C.cpu().numpy(), sub.cpu().numpy()
+    op = oracle.Operator(p)
+    for b in (0, 31, 32, 255, 511, 512, 599):
+        assert rel(C[b], oracle_C(op, f0[b:b + 1], True)[0]) <= TOL[prec], b
+    assert np.array_equal(sub, C[:520])
