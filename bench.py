@@ -48,6 +48,25 @@ def parse():
     return ap.parse_args()
 
 
+def counted_traffic(profile_md, source):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel source (sha1 recorded in the summary), else None."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", profile_md)).read()
+        sha = hashlib.sha1(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.split(":")[0].strip() in ("kernel_source_sha1", "traffic_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha1") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(float(fields["traffic_bytes_per_launch"]))
+
+
 def packed_k(n):
     nb = (n + 15) // 16
     return nb * (nb + 1) // 2 * 256
@@ -185,7 +204,9 @@ def main():
     flops_dense = 2.0 * B * n * n * n
     achieved = flops_exec / (gemm_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["f32"],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4),
+                "traffic": counted_traffic("gemm_f32_n256_b512.md",
+                                           "paper_2607_00755_amd/csrc/kxg_eval.hip"),
                 "kernel": "k_gemm_f32<4>", "avg_launch_us": round(gemm_avg_ms * 1e3, 2),
                 "launches": gemm_n, "flops_per_launch": flops_exec,
                 "dense_equiv_flops_per_launch": flops_dense}

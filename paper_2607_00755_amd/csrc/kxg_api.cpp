@@ -118,7 +118,13 @@ static void profile_clear()
 #define KXG_GEMM_WG_TARGET 512
 #endif
 #ifndef KXG_LDS_WG_TARGET
-#define KXG_LDS_WG_TARGET 256
+#define KXG_LDS_WG_TARGET 512
+#endif
+#ifndef KXG_LDS_BBW
+#define KXG_LDS_BBW 2
+#endif
+#ifndef KXG_LDS_IBW
+#define KXG_LDS_IBW 4
 #endif
 
 static int choose_splits(const Geometry &g, int b_cap)
@@ -160,7 +166,7 @@ struct kxg_stepper {
     const kxg_kernel *k = nullptr;
     kxg_stepper_params prm{};
     SlotDev *d_slots = nullptr;
-    double *d_x = nullptr, *d_fb = nullptr, *d_C = nullptr, *d_acc = nullptr, *d_xs = nullptr;
+    double *d_x = nullptr, *d_fb = nullptr, *d_acc = nullptr, *d_xs = nullptr;
     double *d_dt = nullptr;
     Workspace ws;
     std::vector<char> used;
@@ -292,8 +298,8 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     g.dksteps = (long)g.npairs * kBlk;
     k->gemm_splits = choose_splits(g, b_cap);
     {
-        // LDS-shared 16-bit GEMM: about one 512 x 64 tile per CU
-        const int tiles = div_up(b_cap, 512) * div_up(g.nib, 2);
+        // LDS-shared 16-bit GEMM (tiles of 4*KXG_LDS_BBW*32 x KXG_LDS_IBW*32)
+        const int tiles = div_up(b_cap, 4 * KXG_LDS_BBW * 32) * div_up(g.nib, KXG_LDS_IBW);
         const int cap = (int)std::max<long>(1, g.dksteps / 8);
         k->lds_splits = std::max(1, std::min(div_up(KXG_LDS_WG_TARGET, tiles), cap));
     }
@@ -475,7 +481,6 @@ kxg_status kxg_stepper_create(const kxg_kernel *k, const kxg_stepper_params *prm
     if (st == KXG_OK) st = dalloc(&s->d_slots, (size_t)prm->b_cap);
     if (st == KXG_OK) st = dalloc(&s->d_x, rows);
     if (st == KXG_OK) st = dalloc(&s->d_fb, rows);
-    if (st == KXG_OK) st = dalloc(&s->d_C, rows);
     if (st == KXG_OK) st = dalloc(&s->d_acc, rows);
     if (st == KXG_OK) st = dalloc(&s->d_xs, rows);
     if (st == KXG_OK) st = dalloc(&s->d_dt, (size_t)prm->b_cap);
@@ -506,7 +511,7 @@ void kxg_stepper_free(kxg_stepper *s)
 {
     if (!s) return;
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-    void *ptrs[] = {s->d_slots, s->d_x, s->d_fb, s->d_C, s->d_acc, s->d_xs, s->d_dt};
+    void *ptrs[] = {s->d_slots, s->d_x, s->d_fb, s->d_acc, s->d_xs, s->d_dt};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     free_workspace(s->ws);
@@ -569,24 +574,35 @@ static kxg_status enqueue_iteration(kxg_stepper *s, int B, hipStream_t st)
     const kxg_kernel &k = *s->k;
     const kxg_stepper_params &P = s->prm;
     const uint32_t flags = P.project ? KXG_PROJECT : 0u;
+    StepArgs a{};
+    a.sl = s->d_slots;
+    a.x = s->d_x;
+    a.acc = s->d_acc;
+    a.xs = s->d_xs;
+    a.fb = s->d_fb;
+    a.p = k.d_p;
+    a.dp = k.d_dp;
+    a.expansion = P.expansion;
+    a.adapt = P.adapt;
+    a.rtol = P.rtol;
+    a.safety = P.safety;
+    a.fac_lo = P.fac_min;
+    a.fac_hi = P.fac_max;
+    a.dt_min = P.dt_min;
     if (P.kind == KXG_RK4) {
+        a.mode = kStepRK4;
         for (int stage = 1; stage <= 4; ++stage) {
-            kxg_status r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
+            a.stage = stage;
+            kxg_status r = eval_impl(k, s->ws, P.prec, s->d_fb, B, nullptr, flags, nullptr, st, &a);
             if (r != KXG_OK) return r;
-            KXG_TRY_HIP(launch_rk4_stage(stage, k.n, B, s->d_slots, s->d_x, s->d_acc, s->d_C, s->d_fb, st));
         }
         return KXG_OK;
     }
-    kxg_status r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
+    a.mode = kStepHeunPred;
+    kxg_status r = eval_impl(k, s->ws, P.prec, s->d_fb, B, nullptr, flags, nullptr, st, &a);
     if (r != KXG_OK) return r;
-    KXG_TRY_HIP(launch_heun_pred(k.n, B, P.expansion, s->d_slots, k.d_p, k.d_dp, s->d_x,
-                                 s->d_acc, s->d_xs, s->d_C, s->d_fb, st));
-    r = eval_impl(k, s->ws, P.prec, s->d_fb, B, s->d_C, flags, nullptr, st);
-    if (r != KXG_OK) return r;
-    KXG_TRY_HIP(launch_heun_corr(k.n, B, P.expansion, P.adapt, P.rtol, P.safety, P.fac_min,
-                                 P.fac_max, P.dt_min, s->d_slots, k.d_p, k.d_dp, s->d_x,
-                                 s->d_acc, s->d_xs, s->d_C, s->d_fb, st));
-    return KXG_OK;
+    a.mode = kStepHeunCorr;
+    return eval_impl(k, s->ws, P.prec, s->d_fb, B, nullptr, flags, nullptr, st, &a);
 }
 
 // Capture one iteration over `batch` slots on stream st into an executable

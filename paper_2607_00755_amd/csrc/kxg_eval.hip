@@ -12,7 +12,7 @@
 //     hi+lo split of A' and of F2: hi*hi + hi*lo + lo*hi).  K is split over
 //     workgroups (and over the 4 waves of each); partials are reduced in FP64
 //     by the epilogue in a fixed order, independent of the batch size.
-#include "kxg_internal.h"
+#include "kxg_step.h"
 
 #include <type_traits>
 
@@ -24,6 +24,20 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+#ifndef KXG_STREAM_UNROLL
+#define KXG_STREAM_UNROLL 8
+#endif
+#ifndef KXG_STREAM_NT
+#define KXG_STREAM_NT 1
+#endif
+// shape of the LDS-shared 16-bit GEMM: b-blocks and i-blocks per wave
+#ifndef KXG_LDS_BBW
+#define KXG_LDS_BBW 2
+#endif
+#ifndef KXG_LDS_IBW
+#define KXG_LDS_IBW 4
+#endif
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Remap so that consecutive logical indices share an XCD: workgroups
@@ -66,13 +80,19 @@ __global__ __launch_bounds__(256) void k_stream(const T *__restrict__ A,
 #pragma unroll
     for (int bb = 0; bb < BT; ++bb) acc[bb] = (T)0;
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
-    // four loads in flight per thread
-    for (; e + 3 * step < e_end; e += 4 * step) {
-        vec_t a[4];
-        int kk[4], mm[4];
+    // KXG_STREAM_UNROLL loads in flight per thread; A is read once per call,
+    // so the loads are marked non-temporal
+    constexpr int UN = KXG_STREAM_UNROLL;
+    for (; e + (UN - 1) * step < e_end; e += UN * step) {
+        vec_t a[UN];
+        int kk[UN], mm[UN];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < UN; ++u) {
+#if KXG_STREAM_NT
+            a[u] = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(row + e + (long)u * step));
+#else
             a[u] = *reinterpret_cast<const vec_t *>(row + e + (long)u * step);
+#endif
             kk[u] = k;
             mm[u] = m;
             m += sm;
@@ -80,7 +100,7 @@ __global__ __launch_bounds__(256) void k_stream(const T *__restrict__ A,
             if (m >= n) { m -= n; ++k; }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < UN; ++u) {
 #pragma unroll
             for (int bb = 0; bb < BT; ++bb) {
                 const T *fb = fs + bb * n;
@@ -195,47 +215,7 @@ __device__ void store_tile(floatx16 (&acc)[BBW], float *lds, float *__restrict__
 // consecutive sub-ranges of the split's dk steps.  Per dk step (one row k of a
 // (kb, mb) block, 16 K values) a wave issues 8*BBW MFMAs; the A operand
 // (F2 = f_k f_m) is one multiply per MFMA, the B operand (packed tensor)
-// comes straight from memory in MFMA order.  Software pipeline: the packed
-// fragment and f_k of step u+2 are requested while step u computes, and the
-// f_m values of the next (kb, mb) block one step before it starts.
-template <int BBW>
-struct F32Stage {
-    float4 b0, b1;
-    float fk[BBW];
-};
-
-template <int BBW>
-__device__ inline void f32_load_stage(F32Stage<BBW> &st, const float *__restrict__ Gi,
-                                      const float *__restrict__ fop,
-                                      const int *__restrict__ pairs, long u, int bpad,
-                                      int brow0, int r, int lane)
-{
-    const int pr = (int)(u >> 4), dk = (int)(u & 15);
-    const float *gp = Gi + u * 512;
-    st.b0 = reinterpret_cast<const float4 *>(gp)[lane];
-    st.b1 = reinterpret_cast<const float4 *>(gp + 256)[lane];
-    const int kb = pairs[2 * pr];
-#pragma unroll
-    for (int bb = 0; bb < BBW; ++bb)
-        st.fk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
-}
-
-template <int BBW>
-__device__ inline void f32_load_fm(float (&fm)[BBW][8], const float *__restrict__ fpar,
-                                   const int *__restrict__ pairs, int pr, int bpad, int brow0,
-                                   int r, int hb)
-{
-    const int mb = pairs[2 * pr + 1];
-#pragma unroll
-    for (int bb = 0; bb < BBW; ++bb) {
-        const float4 *src = reinterpret_cast<const float4 *>(
-            fpar + (((long)mb * bpad + brow0 + bb * 32 + r) * 2 + hb) * 8);
-        const float4 x0 = src[0], x1 = src[1];
-        fm[bb][0] = x0.x; fm[bb][1] = x0.y; fm[bb][2] = x0.z; fm[bb][3] = x0.w;
-        fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
-    }
-}
-
+// comes straight from memory in MFMA order, prefetched one step ahead.
 template <int BBW>
 __global__ __launch_bounds__(256, 2) void k_gemm_f32(
     const float *__restrict__ G, const float *__restrict__ fop, const float *__restrict__ fpar,
@@ -261,33 +241,56 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[bb][e] = 0.0f;
 
-    float fm[BBW][8], nfm[BBW][8];
-    F32Stage<BBW> s0, s1;
+    float fm[BBW][8];
+    int cur_pair = -1;
+    float4 nb0 = make_float4(0, 0, 0, 0), nb1 = nb0;
+    float nfk[BBW];
     if (u0 < u1) {
-        f32_load_fm<BBW>(fm, fpar, pairs, (int)(u0 >> 4), bpad, brow0, r, hb);
-        f32_load_stage<BBW>(s0, Gi, fop, pairs, u0, bpad, brow0, r, lane);
+        const int pr = (int)(u0 >> 4), dk = (int)(u0 & 15);
+        const float *gp = Gi + u0 * 512;
+        nb0 = reinterpret_cast<const float4 *>(gp)[lane];
+        nb1 = reinterpret_cast<const float4 *>(gp + 256)[lane];
+        const int kb = pairs[2 * pr];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+            nfk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
     }
-    if (u0 + 1 < u1) f32_load_stage<BBW>(s1, Gi, fop, pairs, u0 + 1, bpad, brow0, r, lane);
     for (long u = u0; u < u1; ++u) {
-        const F32Stage<BBW> cur = s0;
-        s0 = s1;
-        if (u + 2 < u1) f32_load_stage<BBW>(s1, Gi, fop, pairs, u + 2, bpad, brow0, r, lane);
-        const bool next_block = (u + 1 < u1) && (((u + 1) & 15) == 0);
-        if (next_block) f32_load_fm<BBW>(nfm, fpar, pairs, (int)((u + 1) >> 4), bpad, brow0, r, hb);
-        const float bv[8] = {cur.b0.x, cur.b0.y, cur.b0.z, cur.b0.w,
-                             cur.b1.x, cur.b1.y, cur.b1.z, cur.b1.w};
+        const int pr = (int)(u >> 4);
+        if (pr != cur_pair) {
+            cur_pair = pr;
+            const int mb = pairs[2 * pr + 1];
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb) {
+                const float4 *src = reinterpret_cast<const float4 *>(
+                    fpar + (((long)mb * bpad + brow0 + bb * 32 + r) * 2 + hb) * 8);
+                const float4 x0 = src[0], x1 = src[1];
+                fm[bb][0] = x0.x; fm[bb][1] = x0.y; fm[bb][2] = x0.z; fm[bb][3] = x0.w;
+                fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
+            }
+        }
+        const float4 b0 = nb0, b1 = nb1;
+        float fk[BBW];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb) fk[bb] = nfk[bb];
+        if (u + 1 < u1) {
+            const long un = u + 1;
+            const int prn = (int)(un >> 4), dkn = (int)(un & 15);
+            const float *gp = Gi + un * 512;
+            nb0 = reinterpret_cast<const float4 *>(gp)[lane];
+            nb1 = reinterpret_cast<const float4 *>(gp + 256)[lane];
+            const int kbn = pairs[2 * prn];
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb)
+                nfk[bb] = fop[((long)kbn * bpad + brow0 + bb * 32 + r) * kBlk + dkn];
+        }
+        const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
         for (int t = 0; t < 8; ++t)
 #pragma unroll
             for (int bb = 0; bb < BBW; ++bb)
-                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur.fk[bb] * fm[bb][t], bv[t],
+                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fk[bb] * fm[bb][t], bv[t],
                                                                acc[bb], 0, 0, 0);
-        if (next_block) {
-#pragma unroll
-            for (int bb = 0; bb < BBW; ++bb)
-#pragma unroll
-                for (int t = 0; t < 8; ++t) fm[bb][t] = nfm[bb][t];
-        }
     }
     store_tile<BBW>(acc, lds, part, sp, bpad, ipad, brow0, ib * kIBlk);
 }
@@ -395,9 +398,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(
 // workgroup's 4 waves work on the same K chunk (split) and the same IBW
 // i-blocks; wave w takes the BBW b-blocks [w*BBW, (w+1)*BBW) of the
 // workgroup's 4*BBW*32-row batch tile.  Per dk step the workgroup stages the
-// hi/lo A fragments of its i-blocks (2 KB each) once into a double-buffered
-// LDS ring; every wave forms and splits its F2 operand once and feeds it to
-// 3*IBW MFMAs.  One barrier per dk step.  Partials: one per K split.
+// hi/lo A fragments of its i-blocks (2 KB each) once into a 3-deep LDS ring
+// (global loads issued two steps ahead); every wave forms and splits its F2
+// operand once per b-block and feeds it to 3*IBW MFMAs.  One barrier per dk
+// step.  Partials: one per K split.
 template <int BBW, int IBW, bool F16>
 __global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
     const uint16_t *__restrict__ G, const float *__restrict__ fop, const int *__restrict__ pairs,
@@ -407,8 +411,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
     typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
     typedef typename std::conditional<F16, _Float16, __bf16>::type op_t;
     constexpr int NV = IBW * 2 * 64;               // 16-byte vectors per dk step
-    static_assert(NV <= 256, "one vector per thread at most");
-    __shared__ uint4 sA[2][NV];
+    constexpr int PT = (NV + 255) / 256;           // vectors per thread
+    __shared__ uint4 sA[3][NV];
     int L = xcd_logical(blockIdx.x, gridDim.x);
     const int bt = L % nbt;
     L /= nbt;
@@ -419,13 +423,38 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
     const long u0 = (long)sp * dksteps / splits, u1 = (long)(sp + 1) * dksteps / splits;
     const int brow0 = bt * (4 * BBW * 32) + wave * (BBW * 32);
     const int ib0 = it * IBW;
-    // loader role of this thread: vector q = threadIdx.x of the dk step
-    const int q = threadIdx.x;
-    const int qib = q / 128, qrest = q % 128;
-    const bool qload = q < NV && ib0 + qib < nib;
-    const uint4 *qsrc = reinterpret_cast<const uint4 *>(
-        G + (long)(ib0 + (qload ? qib : 0)) * npairs * kBlk * 1024) + qrest;
-    // (a dk step is 1024 16-bit values = 128 vectors: [hi|lo][lane][8])
+    // loader role: vectors q = threadIdx.x + 256 c of each dk step; a dk step
+    // of one i-block is 1024 16-bit values = 128 vectors ([hi|lo][lane][8])
+    const uint4 *qsrc[PT];
+    bool qload[PT];
+#pragma unroll
+    for (int c = 0; c < PT; ++c) {
+        const int q = threadIdx.x + 256 * c;
+        const int qib = q / 128;
+        qload[c] = q < NV && ib0 + qib < nib;
+        qsrc[c] = reinterpret_cast<const uint4 *>(
+                      G + (long)(ib0 + (qload[c] ? qib : 0)) * npairs * kBlk * 1024) + (q % 128);
+    }
+    const uint4 zero4 = make_uint4(0, 0, 0, 0);
+    auto fetch = [&](long u, uint4 (&dst)[PT]) {
+#pragma unroll
+        for (int c = 0; c < PT; ++c) dst[c] = (qload[c] && u < u1) ? qsrc[c][u * 128] : zero4;
+    };
+    auto stash = [&](int slot, const uint4 (&src)[PT]) {
+#pragma unroll
+        for (int c = 0; c < PT; ++c) {
+            const int q = threadIdx.x + 256 * c;
+            if (q < NV) sA[slot][q] = src[c];
+        }
+    };
+    auto load_fk = [&](long u, float (&dst)[BBW]) {
+        if (u >= u1) return;
+        const int pr = (int)(u >> 4), dk = (int)(u & 15);
+        const int kb = pairs[2 * pr];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+            dst[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
+    };
 
     floatx16 acc[BBW][IBW];
 #pragma unroll
@@ -435,22 +464,30 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[bb][ib][e] = 0.0f;
 
-    float fm[BBW][8];
-    int cur_pair = -1;
-    const uint4 zero4 = make_uint4(0, 0, 0, 0);
-    uint4 pre = (qload && u0 < u1) ? qsrc[u0 * 128] : zero4;
-    float nfk[BBW];
+    uint4 ra[PT], rb[PT];
+    float fk1[BBW], fk2[BBW], fm[BBW][8];
     if (u0 < u1) {
-        const int pr = (int)(u0 >> 4), dk = (int)(u0 & 15);
-        const int kb = pairs[2 * pr];
-#pragma unroll
-        for (int bb = 0; bb < BBW; ++bb)
-            nfk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
+        uint4 r0[PT];
+        fetch(u0, r0);
+        stash(0, r0);
     }
+    fetch(u0 + 1, ra);
+    fetch(u0 + 2, rb);
+    load_fk(u0, fk1);
+    load_fk(u0 + 1, fk2);
+    int cur_pair = -1;
+    __syncthreads();
     for (long u = u0; u < u1; ++u) {
-        const int buf = (int)((u - u0) & 1);
-        if (q < NV) sA[buf][q] = pre;
-        __syncthreads();
+        const int idx = (int)(u - u0);
+        const int slot = idx % 3;
+        stash((idx + 1) % 3, ra);         // data of step u+1, read after the next barrier
+#pragma unroll
+        for (int c = 0; c < PT; ++c) ra[c] = rb[c];
+        fetch(u + 3, rb);
+        float fk[BBW];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb) { fk[bb] = fk1[bb]; fk1[bb] = fk2[bb]; }
+        load_fk(u + 2, fk2);
         const int pr = (int)(u >> 4);
         if (pr != cur_pair) {
             cur_pair = pr;
@@ -464,24 +501,6 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
                 fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
             }
         }
-        float fk[BBW];
-#pragma unroll
-        for (int bb = 0; bb < BBW; ++bb) fk[bb] = nfk[bb];
-        if (u + 1 < u1) {
-            const long un = u + 1;
-            if (qload) pre = qsrc[un * 128];
-            const int prn = (int)(un >> 4), dkn = (int)(un & 15);
-            const int kbn = pairs[2 * prn];
-#pragma unroll
-            for (int bb = 0; bb < BBW; ++bb)
-                nfk[bb] = fop[((long)kbn * bpad + brow0 + bb * 32 + r) * kBlk + dkn];
-        }
-        opx8 Ah[IBW], Al[IBW];
-#pragma unroll
-        for (int ib = 0; ib < IBW; ++ib) {
-            Ah[ib] = __builtin_bit_cast(opx8, sA[buf][ib * 128 + lane]);
-            Al[ib] = __builtin_bit_cast(opx8, sA[buf][ib * 128 + 64 + lane]);
-        }
         opx8 ph[BBW], pl[BBW];
 #pragma unroll
         for (int bb = 0; bb < BBW; ++bb)
@@ -492,6 +511,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
                 ph[bb][j] = h;
                 pl[bb][j] = (op_t)(pv - (float)h);
             }
+        opx8 Ah[IBW], Al[IBW];
+#pragma unroll
+        for (int ib = 0; ib < IBW; ++ib) {
+            Ah[ib] = __builtin_bit_cast(opx8, sA[slot][ib * 128 + lane]);
+            Al[ib] = __builtin_bit_cast(opx8, sA[slot][ib * 128 + 64 + lane]);
+        }
         // three products, smallest first; consecutive MFMAs hit different
         // accumulators
 #pragma unroll
@@ -507,6 +532,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
                     else
                         acc[bb][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bm, acc[bb][ib], 0, 0, 0);
                 }
+        __syncthreads();
     }
     float *dst = part + (long)sp * bpad * ipad;
 #pragma unroll
@@ -621,13 +647,17 @@ __device__ void block_sum(double (&v)[NV], double *lds)
 //   beta = beta' in the paper's E-form), C_proj = C_raw - xi (alpha' + beta' K),
 //   and the diagnostics of eqs. app_epsilon_definition and
 //   app_projection_relative_correction.
+template <int PER>
+__device__ void step_update(const StepArgs &A, int b, int n, const double (&out)[PER], int lane);
+
 template <typename PT, int PER>
 __global__ __launch_bounds__(256) void k_epilogue(
     const PT *__restrict__ part, int nsplit, long split_stride, int ld_b,
     const float *__restrict__ fscale, const float *__restrict__ rscale,
     const double *__restrict__ rate, const double *__restrict__ f,
     const double *__restrict__ h, const double *__restrict__ K, const double *__restrict__ E,
-    double mass, int n, int B, int project, double *__restrict__ C, double *__restrict__ diag)
+    double mass, int n, int B, int project, double *__restrict__ C, double *__restrict__ diag,
+    StepArgs step)
 {
     const int lane = threadIdx.x & 63;
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -704,9 +734,11 @@ __global__ __launch_bounds__(256) void k_epilogue(
         be = (s1 * b00 - s0 * b01) / det;
     }
     double t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0, bad = 0.0;
+    double out[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int i = lane + 64 * q;
+        out[q] = 0.0;
         if (i < n) {
             const double hi = h[i], ei = E[i];
             const double cp = craw[q] - xi[q] * (al + be * K[i]);
@@ -717,10 +749,18 @@ __global__ __launch_bounds__(256) void k_epilogue(
             t3 += hi * ei * fabs(cp);
             t4 += hi * d;
             t5 += hi * ei * d;
-            const double out = project ? cp : craw[q];
-            if (!isfinite(out)) bad = 1.0;
-            C[(long)b * n + i] = out;
+            out[q] = project ? cp : craw[q];
+            if (!isfinite(out[q])) bad = 1.0;
         }
+    }
+    if (step.mode != kStepNone) {
+        step_update<PER>(step, b, n, out, lane);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = lane + 64 * q;
+        if (i < n) C[(long)b * n + i] = out[q];
     }
     if (diag) {
         t0 = wave_sum(t0); t1 = wave_sum(t1); t2 = wave_sum(t2);
@@ -748,18 +788,155 @@ __global__ __launch_bounds__(256) void k_epilogue(
     }
 }
 
+
+// Stepper update of slot b from the operator output `out` (lane-strided,
+// element i = lane + 64 q), Sec. 4.2: RK4 stage, or Heun predictor
+// x* = x + dt k1, or Heun corrector x_new = x + dt (k1 + k2)/2 with the
+// predictor-corrector error err = max |x_new - x*| / (atol + rtol
+// max(|x|, |x_new|)), acceptance err <= 1 (always in replay mode) and
+// dt *= clamp(safety err^-1/2, fac_lo, fac_hi), clipped to end at t_end.
+// Every lane reaches the same decision (butterfly reductions); lane 0
+// writes the slot record.
+template <int PER>
+__device__ void step_update(const StepArgs &A, int b, int n, const double (&out)[PER], int lane)
+{
+    SlotDev &S = A.sl[b];
+    const int running = S.status == 0;
+    const long row = (long)b * n;
+    const double dt = S.dt, u = S.t;
+    if (A.mode == kStepRK4) {
+        const double lam = S.lam / S.hi_scale;
+        double bad = 0.0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = lane + 64 * q;
+            if (i >= n) continue;
+            const double xv = A.x[row + i];
+            if (!running) { A.fb[row + i] = xv; continue; }
+            const double k = lam * out[q];
+            if (A.stage == 1) { A.acc[row + i] = k; A.fb[row + i] = xv + 0.5 * dt * k; }
+            else if (A.stage == 2) { A.acc[row + i] += 2.0 * k; A.fb[row + i] = xv + 0.5 * dt * k; }
+            else if (A.stage == 3) { A.acc[row + i] += 2.0 * k; A.fb[row + i] = xv + dt * k; }
+            else {
+                const double xn = xv + dt / 6.0 * (A.acc[row + i] + k);
+                A.x[row + i] = xn;
+                A.fb[row + i] = xn;
+                if (!isfinite(xn)) bad = 1.0;
+            }
+        }
+        if (A.stage == 4) {
+            bad = wave_max(bad);
+            if (lane == 0 && running) {
+                S.t = u + dt;
+                S.steps += 1;
+                if (bad > 0.0) S.status = -1;
+                else if (S.t >= S.tend * (1.0 - 1e-14) || (S.maxsteps > 0 && S.steps >= S.maxsteps))
+                    S.status = 1;
+                else if (S.t + dt > S.tend) S.dt = S.tend - S.t;
+            }
+        }
+        return;
+    }
+    if (A.mode == kStepHeunPred) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = lane + 64 * q;
+            if (i >= n) continue;
+            const double xv = A.x[row + i];
+            if (!running) { A.xs[row + i] = xv; continue; }
+            const double nx = (i + 1 < n) ? A.x[row + i + 1] : 0.0;
+            const double k = rhs_u(A.expansion, xv, nx, out[q], A.p[i], A.dp[i], S.lam, S.hi_scale, u);
+            A.acc[row + i] = k;
+            const double v = xv + dt * k;
+            A.xs[row + i] = v;
+            A.fb[row + i] = A.expansion ? g_to_f(v, A.p[i], u + dt) : v;
+        }
+        return;
+    }
+    // Heun corrector and control
+    double xn[PER];
+    double err = 0.0, nonfin = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = lane + 64 * q;
+        xn[q] = 0.0;
+        if (i >= n || !running) continue;
+        const double xsv = A.xs[row + i];
+        const double nx = (i + 1 < n) ? A.xs[row + i + 1] : 0.0;
+        const double k2 = rhs_u(A.expansion, xsv, nx, out[q], A.p[i], A.dp[i], S.lam, S.hi_scale, u + dt);
+        const double x0 = A.x[row + i];
+        const double v = x0 + 0.5 * dt * (A.acc[row + i] + k2);
+        xn[q] = v;
+        const double sc = S.atol + A.rtol * fmax(fabs(x0), fabs(v));
+        const double e = fabs(v - xsv) / sc;
+        if (!isfinite(v)) nonfin = 1.0;
+        err = fmax(err, isfinite(e) ? e : 1e300);
+    }
+    err = wave_max(err);
+    nonfin = wave_max(nonfin);
+    int accept = 0, status = S.status, steps = S.steps, rej = S.rejected;
+    double tnew = u, dtnew = dt, outflow = S.outflow;
+    if (running) {
+        if (nonfin > 0.0) {
+            status = -1;
+        } else {
+            accept = (!A.adapt) || err <= 1.0;
+            if (accept) {
+                if (A.expansion) outflow += 0.5 * dt * (A.x[row] + A.xs[row]);
+                tnew = u + dt;
+                steps += 1;
+            } else {
+                rej += 1;
+            }
+            if (A.adapt) {
+                double fac = err > 0.0 ? A.safety / sqrt(err) : A.fac_hi;
+                fac = fmin(A.fac_hi, fmax(A.fac_lo, fac));
+                dtnew = dt * fac;
+            }
+            if (accept && (tnew >= S.tend * (1.0 - 1e-14) || (S.maxsteps > 0 && steps >= S.maxsteps))) {
+                status = 1;
+            } else {
+                if (tnew + dtnew > S.tend) dtnew = S.tend - tnew;
+                if (A.adapt && dtnew < A.dt_min) status = -2;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = lane + 64 * q;
+        if (i >= n) continue;
+        double v = A.x[row + i];
+        if (accept) {
+            v = xn[q];
+            A.x[row + i] = v;
+        }
+        A.fb[row + i] = A.expansion ? g_to_f(v, A.p[i], tnew) : v;
+    }
+    if (lane == 0 && running) {
+        S.t = tnew;
+        S.dt = dtnew;
+        S.steps = steps;
+        S.rejected = rej;
+        S.status = status;
+        S.outflow = outflow;
+    }
+}
+
 template <typename PT>
 hipError_t launch_epilogue(const PT *part, int nsplit, long split_stride, int ld_b,
                            const float *fscale, const float *rscale, const double *rate,
                            const double *f, const kxg_kernel &k, int B, int project, double *C,
-                           double *diag, hipStream_t s)
+                           double *diag, const StepArgs *step, hipStream_t s)
 {
     const int n = k.n;
     const dim3 grid((B + 3) / 4), blk(256);
+    StepArgs sa{};
+    if (step) sa = *step;
+    else sa.mode = kStepNone;
 #define KXG_EPI(P)                                                                             \
     hipLaunchKernelGGL((k_epilogue<PT, P>), grid, blk, 0, s, part, nsplit, split_stride, ld_b, \
                        fscale, rscale, rate, f, k.d_h, k.d_K, k.d_E, k.mass, n, B, project, C, \
-                       diag)
+                       diag, sa)
     if (n <= 64) KXG_EPI(1);
     else if (n <= 128) KXG_EPI(2);
     else if (n <= 256) KXG_EPI(4);
@@ -853,7 +1030,8 @@ void free_workspace(Workspace &ws)
 }
 
 kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const double *f,
-                     int B, double *C, uint32_t flags, double *diag, hipStream_t s)
+                     int B, double *C, uint32_t flags, double *diag, hipStream_t s,
+                     const StepArgs *step)
 {
     const int n = k.n;
     const Geometry &g = k.geo;
@@ -895,13 +1073,13 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         KXG_TRY_HIP(hipGetLastError());
         KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
         KXG_TRY_HIP(launch_epilogue<double>(part, nsplit, (long)B * n, n, nullptr, nullptr, rate,
-                                            f, k, B, project, C, diag, s));
+                                            f, k, B, project, C, diag, step, s));
         return KXG_OK;
     }
     const bool f16 = prec == KXG_F16X3;
     if ((prec == KXG_BF16X3 || prec == KXG_F16X3) && B >= kLdsMinB) {
         // large batch: 16-bit GEMM with the A operand shared through LDS
-        constexpr int BBW = 4, IBW = 2, TILE = 4 * BBW * 32;
+        constexpr int BBW = KXG_LDS_BBW, IBW = KXG_LDS_IBW, TILE = 4 * BBW * 32;
         const int bpad = div_up(B, TILE) * TILE;
         const int nbt = bpad / TILE, nit = div_up(g.nib, IBW);
         const int splits = k.lds_splits;
@@ -922,7 +1100,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
         KXG_TRY_HIP(launch_epilogue<float>(part, splits, (long)bpad * g.ipad, g.ipad,
                                            f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr, rate,
-                                           f, k, B, project, C, diag, s));
+                                           f, k, B, project, C, diag, step, s));
         return KXG_OK;
     }
     // GEMM path
@@ -960,7 +1138,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
     KXG_TRY_HIP(launch_epilogue<float>(part, splits, (long)bpad * g.ipad, g.ipad,
                                        f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr, rate, f,
-                                       k, B, project, C, diag, s));
+                                       k, B, project, C, diag, step, s));
     return KXG_OK;
 }
 

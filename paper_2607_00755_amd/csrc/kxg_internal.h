@@ -86,8 +86,12 @@ hipError_t launch_build_A(const kxg_kernel &k, const double *d_xmu, const double
 hipError_t launch_build_R(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_derive(kxg_kernel &k, hipStream_t s);
 
+struct StepArgs;
+// Evaluate C[f] for B rows; with `step` the epilogue applies that stepper
+// update instead of writing C (C and diag may then be null).
 kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const double *f,
-                     int B, double *C, uint32_t flags, double *diag, hipStream_t s);
+                     int B, double *C, uint32_t flags, double *diag, hipStream_t s,
+                     const StepArgs *step = nullptr);
 kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws);
 void free_workspace(Workspace &ws);
 hipError_t launch_moments(const kxg_kernel &k, const double *f, int B, double *out,

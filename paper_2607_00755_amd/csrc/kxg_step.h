@@ -18,15 +18,37 @@ struct SlotDev {
     int steps, rejected, status, maxsteps;
 };
 
-hipError_t launch_rk4_stage(int stage, int n, int B, SlotDev *sl, double *x, double *acc,
-                            const double *C, double *fb, hipStream_t s);
-hipError_t launch_heun_pred(int n, int B, int expansion, SlotDev *sl, const double *p,
-                            const double *dp, const double *x, double *k1, double *xs,
-                            const double *C, double *fb, hipStream_t s);
-hipError_t launch_heun_corr(int n, int B, int expansion, int adapt, double rtol, double safety,
-                            double fmin, double fmaxf, double dt_min, SlotDev *sl,
-                            const double *p, const double *dp, double *x, const double *k1,
-                            const double *xs, const double *C, double *fb, hipStream_t s);
+// Stepper update applied by the evaluation epilogue to the operator output
+// of every slot (one wave per slot), instead of writing C.
+enum StepMode { kStepNone = 0, kStepRK4 = 1, kStepHeunPred = 2, kStepHeunCorr = 3 };
+struct StepArgs {
+    SlotDev *sl;
+    double *x;        // state [B][n]
+    double *acc;      // RK4 stage accumulator / Heun k1 [B][n]
+    double *xs;       // Heun predictor state [B][n]
+    double *fb;       // next operator input f [B][n]
+    const double *p, *dp;
+    int mode, stage, expansion, adapt;
+    double rtol, safety, fac_lo, fac_hi, dt_min;
+};
+
+// f on the physical grid from the comoving state g = a^3 p^3 f at u = ln a.
+__device__ inline double g_to_f(double g, double p, double u)
+{
+    return g / (exp(3.0 * u) * (p * p * p));
+}
+
+// Right-hand side in u: drift (conservative upwind on g, cell sizes
+// V_i = dp_i/p_i, nothing enters at p_max) plus the collision term
+// a^3 p^3 lambda C / H with H = h_i e^{-2u}; without expansion lambda C / h_i.
+// `next` is the state at i+1 (0 beyond the grid).
+__device__ inline double rhs_u(int expansion, double xi, double next, double c, double p,
+                               double dp, double lam, double hsc, double u)
+{
+    if (!expansion) return lam * c / hsc;
+    const double drift = (next - xi) / (dp / p);
+    return drift + exp(5.0 * u) * (p * p * p) * lam * c / hsc;
+}
 hipError_t launch_slot_set(int n, int kind, int expansion, double atol_rel, int slot,
                            SlotDev *sl, const double *f0, const double *p, const double *RT,
                            double *x, double *fb, hipStream_t s);

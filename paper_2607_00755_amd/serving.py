@@ -89,8 +89,8 @@ class Server:
 
     # ---------------------------------------------------------------- memory
     def slot_bytes(self, n: int) -> int:
-        # stepper state (x, operator input, C, k1, x*) + workspace row + slot record
-        return 6 * n * 8 + 96
+        # stepper state (x, operator input, k1, x*) + loss-rate row + slot record
+        return 5 * n * 8 + 96
 
     def group_bytes(self, n: int) -> int:
         g = self.groups.get(n)
