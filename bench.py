@@ -159,6 +159,42 @@ def single_paths(args, dev):
     return out
 
 
+def paper_timing_curve(dev):
+    """The paper's own timing workload (Sec. 5, Fig. run_time): one full-grid
+    evaluation of the contact operator for the two-bump input of
+    eq. benchmark_two_bump on q in [1e-3, 1e2] (m = lambda = a = 1), log grid,
+    N_mu = 18, Bose-Einstein factors and log interpolation, no projection;
+    FP64 and FP32, per N.  The kernel build (done once per grid here, per
+    call in the paper's formulation) is timed separately."""
+    import torch
+    from paper_2607_00755_amd import inputs, kxg
+    rows = []
+    for n in (32, 64, 96, 128, 192, 256, 384):
+        q = inputs.log_grid(n, 1e-3, 1e2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = kxg.Kernel(q, precs=(kxg.F64, kxg.F32), b_cap=1, brackets=True)
+        build_ms = 1e3 * (time.perf_counter() - t0)
+        f = torch.tensor(inputs.two_bump_benchmark(q)[None, :], device=dev)
+        C = torch.empty_like(f)
+        d = torch.empty((1, kxg.NDIAG), dtype=torch.float64, device=dev)
+        row = {"n": n, "build_ms": round(build_ms, 2)}
+        for prec in (kxg.F64, kxg.F32):
+            for _ in range(3):
+                k.eval(f, prec=prec, project=False, log_interp=True, eta=1, out=C, diag=d)
+            torch.cuda.synchronize()
+            reps = 30
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                k.eval(f, prec=prec, project=False, log_interp=True, eta=1, out=C, diag=d)
+            torch.cuda.synchronize()
+            row["us_per_eval_" + kxg.PREC_NAMES[prec]] = round(1e6 * (time.perf_counter() - t0) / reps, 2)
+        rows.append(row)
+        del k
+        log("paper workload N=%d: %s" % (n, row))
+    return rows
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -276,6 +312,7 @@ def main():
     if not args.no_extras:
         # ---------------- single-distribution paths ----------------
         extras.update(single_paths(args, dev))
+        extras["paper_timing_workload_be_log"] = paper_timing_curve(dev)
 
     # ---------------- serving loop (continuous batching) ----------------
     serve = None

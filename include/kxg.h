@@ -58,6 +58,10 @@ typedef enum {
     KXG_F16X3 = 3    /* FP16 MFMA, hi+lo split with power-of-two scaling  */
 } kxg_prec;
 #define KXG_PREC_BIT(p) (1u << (p))
+/* Extra bit of kxg_kernel_build's prec_mask: also build the interpolation
+ * bracket table j_L[i][n][m] (2 bytes per entry) that the exact-form
+ * evaluations (KXG_INTERP_LOG, KXG_STAT_BOSE, KXG_STAT_FERMI) stream. */
+#define KXG_WITH_BRACKETS (1u << 8)
 
 /* Angular integral of the reduced kernel (App. B). */
 typedef enum {
@@ -118,10 +122,22 @@ kxg_status kxg_kernel_grid(const kxg_kernel *k, double *dp, double *E,
 
 /* Evaluation flags. */
 #define KXG_PROJECT 1u     /* apply the two-moment projection of App. C      */
+#define KXG_INTERP_LOG 2u  /* f at the fourth momentum by the paper's log
+                              interpolation (App. B eq. app_log_interp, floor
+                              1e-300) instead of linear interpolation of f    */
+#define KXG_STAT_BOSE 4u   /* Bose-Einstein factors (eq. Lambda_quantum, eta=+1) */
+#define KXG_STAT_FERMI 8u  /* Fermi-Dirac factors (eq. Lambda_quantum, eta=-1)   */
 #define KXG_NDIAG 12       /* diagnostics per distribution, see kxg_eval     */
 
 /* Evaluate C[f] for B distributions (Sec. 4.1 eq. discrete_collision_
  * operator; projection of App. C when flags has KXG_PROJECT).
+ * Without KXG_INTERP_LOG / KXG_STAT_* the operator is the precomputed
+ * linear-interpolation form gain - f R f (any precision).  With them it is
+ * eq. app_dense_collision with the statistical factor of eq. Lambda_quantum
+ * (eta = +1, -1, or 0 for the dilute limit) and f at the fourth momentum
+ * interpolated linearly or in log f; this exact form streams A and the
+ * bracket table once per group of distributions (precisions KXG_F64 and
+ * KXG_F32 only; the handle must be built with KXG_WITH_BRACKETS).
  *  f_dev   device [B][n] FP64 input distributions
  *  C_dev   device [B][n] FP64 output (raw or projected)
  *  diag_dev device [B][KXG_NDIAG] FP64 or NULL:
@@ -134,7 +150,8 @@ kxg_status kxg_kernel_grid(const kxg_kernel *k, double *dp, double *E,
  *          11 number moment sum_i h_i f_i.
  *  1 <= B <= b_cap of the handle.  Calls on one handle share its workspace:
  *  serialise them on one stream.  Asynchronous.
- * Errors: KXG_EINVAL, KXG_EUNSUPPORTED (precision not built), KXG_EHIP. */
+ * Errors: KXG_EINVAL (bad flags, both statistics), KXG_EUNSUPPORTED
+ * (precision or bracket table not built, exact form at 16-bit), KXG_EHIP. */
 kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev,
                     int32_t B, double *C_dev, uint32_t flags, double *diag_dev,
                     void *stream);

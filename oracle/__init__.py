@@ -194,15 +194,17 @@ class Operator:
 
 
 def direct(p, f, mass=1.0, gdof=1.0, m2=1.0, quad=GL, nmu=18, interp=LIN,
-           dp: Optional[np.ndarray] = None):
-    """Direct per-(i,n,m) evaluation of eq. app_dense_collision."""
+           dp: Optional[np.ndarray] = None, eta: int = 0):
+    """Direct per-(i,n,m) evaluation of eq. app_dense_collision; eta = +1/-1
+    adds the Bose-Einstein/Fermi-Dirac factors of eq. Lambda_quantum."""
     p, f = _f64(p), _f64(f)
     n = len(p)
     g, l, c = np.empty(n), np.empty(n), np.empty(n)
-    lib().or_collision_direct(ctypes.c_int(n), _p(p), _p(None if dp is None else _f64(dp)),
-                              ctypes.c_double(mass), ctypes.c_double(gdof),
-                              ctypes.c_double(m2), ctypes.c_int(quad), ctypes.c_int(nmu),
-                              ctypes.c_int(interp), _p(f), _p(g), _p(l), _p(c))
+    lib().or_collision_direct_q(ctypes.c_int(n), _p(p), _p(None if dp is None else _f64(dp)),
+                                ctypes.c_double(mass), ctypes.c_double(gdof),
+                                ctypes.c_double(m2), ctypes.c_int(quad), ctypes.c_int(nmu),
+                                ctypes.c_int(interp), ctypes.c_int(int(eta)), _p(f), _p(g),
+                                _p(l), _p(c))
     return c, g, l
 
 

@@ -259,15 +259,34 @@ void or_kernel_build(int n, const double *p, const double *dp_override,
 /* ------------------------------------------------------------------------ */
 /* Direct evaluation of eq. app_dense_collision: for every (i,n,m) recompute */
 /* W_inm, the fourth momentum and the interpolated f_j~, then sum           */
-/* W [f_n f_m - f_i f_j~].  interp = 0: energy-linear interpolation of f    */
-/* (the form that the precomputed A/R tensors represent); interp = 1: the   */
-/* paper's log interpolation (eq. app_log_interp) with an absolute floor    */
-/* of 1e-300 under the logarithm.  Outputs gain, loss and C = gain - loss.  */
+/* W Lambda.  interp = 0: energy-linear interpolation of f (the form that   */
+/* the precomputed A/R tensors represent); interp = 1: the paper's log      */
+/* interpolation (eq. app_log_interp) with an absolute floor of 1e-300     */
+/* under the logarithm.  eta = 0: dilute limit, Lambda = f_n f_m - f_i f_j~;*/
+/* eta = +1 / -1: Bose-Einstein / Fermi-Dirac factors of eq.                */
+/* Lambda_quantum with particles 1 = i, 2 = j~, 3 = n, 4 = m:               */
+/*   Lambda = f_n f_m (1 + eta f_i)(1 + eta f_j~)                           */
+/*          - f_i f_j~ (1 + eta f_n)(1 + eta f_m).                          */
+/* Outputs gain (first product), loss (second) and C = gain - loss.         */
 /* ------------------------------------------------------------------------ */
+void or_collision_direct_q(int n, const double *p, const double *dp_override,
+                           double mass, double gdof, double m2, int quad, int nmu,
+                           int interp, int eta, const double *f, double *gain,
+                           double *loss, double *C);
+
 void or_collision_direct(int n, const double *p, const double *dp_override,
                          double mass, double gdof, double m2, int quad, int nmu,
                          int interp, const double *f, double *gain,
                          double *loss, double *C)
+{
+    or_collision_direct_q(n, p, dp_override, mass, gdof, m2, quad, nmu, interp, 0, f,
+                          gain, loss, C);
+}
+
+void or_collision_direct_q(int n, const double *p, const double *dp_override,
+                           double mass, double gdof, double m2, int quad, int nmu,
+                           int interp, int eta, const double *f, double *gain,
+                           double *loss, double *C)
 {
     const double floor_ = 1e-300;
     double *dp = malloc(sizeof(double) * n), *E = malloc(sizeof(double) * n);
@@ -296,8 +315,8 @@ void or_collision_direct(int n, const double *p, const double *dp_override,
                     double fr = f[jl + 1] > floor_ ? f[jl + 1] : floor_;
                     ft = exp((1.0 - wr) * log(fl) + wr * log(fr));
                 }
-                g += W * f[a] * f[b];
-                l += W * f[i] * ft;
+                g += W * f[a] * f[b] * (1.0 + eta * f[i]) * (1.0 + eta * ft);
+                l += W * f[i] * ft * (1.0 + eta * f[a]) * (1.0 + eta * f[b]);
             }
         }
         gain[i] = g;

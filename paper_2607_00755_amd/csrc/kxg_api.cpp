@@ -121,10 +121,10 @@ static void profile_clear()
 #define KXG_LDS_WG_TARGET 512
 #endif
 #ifndef KXG_LDS_BBW
-#define KXG_LDS_BBW 2
+#define KXG_LDS_BBW 4
 #endif
 #ifndef KXG_LDS_IBW
-#define KXG_LDS_IBW 4
+#define KXG_LDS_IBW 2
 #endif
 
 static int choose_splits(const Geometry &g, int b_cap)
@@ -151,7 +151,7 @@ static void release(kxg_kernel *k)
 {
     if (!k) return;
     void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_A32,
-                    k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs};
+                    k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs, k->d_JL, k->d_invdK};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     free_workspace(k->ws);
@@ -255,7 +255,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     if (grid->quad != KXG_QUAD_GL && grid->quad != KXG_QUAD_EXACT) { set_error("kxg_kernel_build: bad quad %d", grid->quad); return KXG_EINVAL; }
     if (grid->quad == KXG_QUAD_GL && (grid->n_mu < 1 || grid->n_mu > 4096)) { set_error("kxg_kernel_build: n_mu=%d outside [1, 4096]", grid->n_mu); return KXG_EINVAL; }
     if (b_cap < 1 || b_cap > (1 << 20)) { set_error("kxg_kernel_build: b_cap=%d outside [1, 2^20]", b_cap); return KXG_EINVAL; }
-    if (prec_mask & ~0xFu) { set_error("kxg_kernel_build: unknown precision bits 0x%x", prec_mask); return KXG_EINVAL; }
+    if (prec_mask & ~(0xFu | KXG_WITH_BRACKETS)) { set_error("kxg_kernel_build: unknown precision bits 0x%x", prec_mask); return KXG_EINVAL; }
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     kxg_kernel *k = new (std::nothrow) kxg_kernel;
@@ -267,7 +267,8 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     k->quad = grid->quad;
     k->nmu = grid->quad == KXG_QUAD_GL ? grid->n_mu : 0;
     k->b_cap = b_cap;
-    k->prec_mask = prec_mask | KXG_PREC_BIT(KXG_F64);
+    k->prec_mask = (prec_mask & 0xFu) | KXG_PREC_BIT(KXG_F64);
+    const bool want_jl = (prec_mask & KXG_WITH_BRACKETS) != 0;
     k->p.assign(grid->p, grid->p + n);
     k->dp.resize(n);
     k->E.resize(n);
@@ -323,6 +324,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     if (want32) { KXG_ALLOC(k->d_A32, n3); KXG_ALLOC(k->d_G32, packed); }
     if (wantbf) { KXG_ALLOC(k->d_Gbf, 2 * packed); }
     if (wanth) { KXG_ALLOC(k->d_Gh, 2 * packed); KXG_ALLOC(k->d_hrow, (size_t)g.ipad); }
+    if (want_jl) { KXG_ALLOC(k->d_JL, n3); KXG_ALLOC(k->d_invdK, (size_t)n); }
     double *d_xmu = nullptr, *d_wmu = nullptr;
     if (k->nmu > 0) { KXG_ALLOC(d_xmu, (size_t)k->nmu); KXG_ALLOC(d_wmu, (size_t)k->nmu); }
 #undef KXG_ALLOC
@@ -357,10 +359,16 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
         KXG_H2D(d_xmu, xmu.data(), k->nmu * sizeof(double));
         KXG_H2D(d_wmu, wmu.data(), k->nmu * sizeof(double));
     }
+    if (want_jl) {
+        std::vector<double> inv(n, 0.0);
+        for (int j = 0; j + 1 < n; ++j) inv[j] = 1.0 / (k->K[j + 1] - k->K[j]);
+        KXG_H2D(k->d_invdK, inv.data(), n * sizeof(double));
+    }
 #undef KXG_H2D
     if (e == hipSuccess) e = launch_build_A(*k, d_xmu, d_wmu, s);
     if (e == hipSuccess) e = launch_build_R(*k, s);
     if (e == hipSuccess) e = launch_derive(*k, s);
+    if (e == hipSuccess && want_jl) e = launch_brackets(*k, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (d_xmu) (void)hipFree(d_xmu);
     if (d_wmu) (void)hipFree(d_wmu);
@@ -371,7 +379,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     }
     st = alloc_workspace(*k, b_cap, k->ws);
     if (st != KXG_OK) { release(k); return st; }
-    k->bytes[KXG_F64] = (n3 + n2) * sizeof(double);
+    k->bytes[KXG_F64] = (n3 + n2) * sizeof(double) + (want_jl ? n3 * sizeof(uint16_t) : 0);
     if (want32) k->bytes[KXG_F32] = (n3 + packed) * sizeof(float) + n2 * sizeof(double);
     if (wantbf) k->bytes[KXG_BF16X3] = 2 * packed * sizeof(uint16_t) + n2 * sizeof(double);
     if (wanth) k->bytes[KXG_F16X3] = 2 * packed * sizeof(uint16_t) + n2 * sizeof(double);
@@ -438,9 +446,15 @@ kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev, int3
     g_err[0] = 0;
     if (!k || !f_dev || !C_dev) { set_error("kxg_eval: null handle or buffer"); return KXG_EINVAL; }
     if (B < 1 || B > k->b_cap) { set_error("kxg_eval: B=%d outside [1, b_cap=%d]", B, k->b_cap); return KXG_EINVAL; }
-    if (flags & ~KXG_PROJECT) { set_error("kxg_eval: unknown flags 0x%x", flags); return KXG_EINVAL; }
+    if (flags & ~(KXG_PROJECT | KXG_INTERP_LOG | KXG_STAT_BOSE | KXG_STAT_FERMI)) { set_error("kxg_eval: unknown flags 0x%x", flags); return KXG_EINVAL; }
+    if ((flags & KXG_STAT_BOSE) && (flags & KXG_STAT_FERMI)) { set_error("kxg_eval: Bose and Fermi statistics together"); return KXG_EINVAL; }
     kxg_status st = check_prec(k, prec);
     if (st != KXG_OK) return st;
+    if (flags & (KXG_INTERP_LOG | KXG_STAT_BOSE | KXG_STAT_FERMI)) {
+        if (!k->d_JL) { set_error("kxg_eval: exact-form evaluation needs a handle built with KXG_WITH_BRACKETS"); return KXG_EUNSUPPORTED; }
+        if (prec != KXG_F64 && prec != KXG_F32) { set_error("kxg_eval: exact-form evaluation runs in FP64 or FP32 only"); return KXG_EUNSUPPORTED; }
+        if (prec == KXG_F32 && !k->d_A32) { set_error("kxg_eval: FP32 tensor not built"); return KXG_EUNSUPPORTED; }
+    }
     return eval_impl(*k, k->ws, prec, f_dev, B, C_dev, flags, diag_dev,
                      static_cast<hipStream_t>(stream));
 }

@@ -159,6 +159,34 @@ __global__ __launch_bounds__(256) void k_build_R(int n, const double *__restrict
     }
 }
 
+// Interpolation bracket per (i, n, m) for the exact-form evaluations: the
+// largest j <= N-2 with K_j <= K~ (eq. app_interp_weights; the same K~
+// expression and comparisons as the weight kernel), 0xFFFF where the entry
+// is cut.  Bisection over the grid.
+__global__ __launch_bounds__(256) void k_brackets(int n, const double *__restrict__ K,
+                                                  uint16_t *__restrict__ JL)
+{
+    const long total = (long)n * n * n;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        const int m = (int)(idx % n);
+        const long r = idx / n;
+        const int a = (int)(r % n);
+        const int i = (int)(r / n);
+        const double kt = (K[a] + K[m]) - K[i];
+        uint16_t out = 0xFFFF;
+        if (kt >= K[0] && kt <= K[n - 1]) {
+            int lo = 0, hi = n - 2;                 // invariant: K[lo] <= kt
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (K[mid] <= kt) lo = mid; else hi = mid - 1;
+            }
+            out = (uint16_t)lo;
+        }
+        JL[idx] = out;
+    }
+}
+
 __global__ void k_to_f32(long count, const double *__restrict__ src, float *__restrict__ dst)
 {
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
@@ -318,6 +346,13 @@ hipError_t launch_build_R(const kxg_kernel &k, hipStream_t s)
     const long total = (long)k.n * k.n;
     hipLaunchKernelGGL(k_build_R, dim3(grid_for(total, 64)), dim3(64), 0, s, k.n, k.d_K,
                        k.d_A64, k.d_RT);
+    return hipGetLastError();
+}
+
+hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s)
+{
+    const long total = (long)k.n * k.n * k.n;
+    hipLaunchKernelGGL(k_brackets, dim3(grid_for(total)), dim3(256), 0, s, k.n, k.d_K, k.d_JL);
     return hipGetLastError();
 }
 

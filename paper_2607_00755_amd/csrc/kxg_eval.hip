@@ -33,10 +33,10 @@ inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 #endif
 // shape of the LDS-shared 16-bit GEMM: b-blocks and i-blocks per wave
 #ifndef KXG_LDS_BBW
-#define KXG_LDS_BBW 2
+#define KXG_LDS_BBW 4
 #endif
 #ifndef KXG_LDS_IBW
-#define KXG_LDS_IBW 4
+#define KXG_LDS_IBW 2
 #endif
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -137,6 +137,115 @@ __global__ __launch_bounds__(256) void k_stream(const T *__restrict__ A,
         const int bb = threadIdx.x;
         const double v = ((red[0][bb] + red[1][bb]) + red[2][bb]) + red[3][bb];
         part[((long)split * B + b0 + bb) * n + i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exact-form stream (eq. app_dense_collision with the statistical factor of
+// eq. Lambda_quantum): one pass over the dense weights and the bracket table;
+// per (i, n, m) the fourth-momentum value f~ is interpolated with the
+// energy-linear weights omega_R = (K~ - K_jL) / (K_jL+1 - K_jL), linearly in
+// f or (LOGI) in ln max(f, 1e-300), and four sums are accumulated per
+// distribution: gain = sum W f_n f_m, S0 = sum W f~, S1 = sum W f~ (f_n + f_m),
+// T1 = sum W f~ f_n f_m (the last two only with quantum statistics).  The
+// epilogue forms C = (1 + eta f_i)(gain + eta T1) - f_i (S0 + eta S1 + eta^2 T1).
+template <typename T, int VEC, int BT, bool LOGI, bool QUANT>
+__global__ __launch_bounds__(256) void k_stream_x(const T *__restrict__ A,
+                                                  const uint16_t *__restrict__ JL,
+                                                  const double *__restrict__ f,
+                                                  const double *__restrict__ K,
+                                                  const double *__restrict__ invdK, int n, int B,
+                                                  int chunk, double *__restrict__ part)
+{
+    constexpr int NA = QUANT ? 4 : 2;
+    extern __shared__ double smem_d[];
+    double *Ks = smem_d;                       // [n]
+    double *iK = Ks + n;                       // [n]
+    T *fs = reinterpret_cast<T *>(iK + n);     // [BT][n]
+    T *ls = fs + BT * n;                       // [BT][n] ln max(f, floor) (LOGI)
+    __shared__ double red[4][BT][NA];
+    const int split = blockIdx.x, i = blockIdx.y, b0 = blockIdx.z * BT;
+    for (int q = threadIdx.x; q < n; q += 256) {
+        Ks[q] = K[q];
+        iK[q] = invdK[q];
+    }
+    for (int q = threadIdx.x; q < BT * n; q += 256) {
+        const int bb = q / n, m = q - bb * n;
+        const double v = (b0 + bb < B) ? f[(long)(b0 + bb) * n + m] : 0.0;
+        fs[q] = (T)v;
+        if (LOGI) ls[q] = (T)log(v > 1e-300 ? v : 1e-300);
+    }
+    __syncthreads();
+    const long n2 = (long)n * n;
+    const T *row = A + (long)i * n2;
+    const uint16_t *jrow = JL + (long)i * n2;
+    const double ki = Ks[i];
+    const long e_beg = (long)split * chunk;
+    const long e_end = e_beg + chunk < n2 ? e_beg + chunk : n2;
+    long e = e_beg + (long)threadIdx.x * VEC;
+    int k = (int)(e / n), m = (int)(e - (long)k * n);
+    constexpr int step = 256 * VEC;
+    const int sk = step / n, sm = step - (step / n) * n;
+    T acc[BT][NA];
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+        for (int c = 0; c < NA; ++c) acc[bb][c] = (T)0;
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    for (; e < e_end; e += step) {
+        const vec_t a = *reinterpret_cast<const vec_t *>(row + e);
+        const double kk = Ks[k];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const int mv = m + v;
+            const int jl = jrow[e + v];
+            if (jl == 0xFFFF) continue;
+            const double kt = (kk + Ks[mv]) - ki;
+            const T wr = (T)((kt - Ks[jl]) * iK[jl]);
+            const T wl = (T)1 - wr;
+            const T w = a[v];
+#pragma unroll
+            for (int bb = 0; bb < BT; ++bb) {
+                const T *fb = fs + bb * n;
+                const T fn = fb[k], fm = fb[mv];
+                T ft;
+                if (LOGI) {
+                    const T *lb = ls + bb * n;
+                    ft = (T)exp(wl * lb[jl] + wr * lb[jl + 1]);
+                } else {
+                    ft = wl * fb[jl] + wr * fb[jl + 1];
+                }
+                const T wf = w * ft;
+                acc[bb][0] += w * fn * fm;
+                acc[bb][1] += wf;
+                if constexpr (QUANT) {
+                    acc[bb][2] += wf * (fn + fm);
+                    acc[bb][3] += wf * fn * fm;
+                }
+            }
+        }
+        m += sm;
+        k += sk;
+        if (m >= n) { m -= n; ++k; }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb)
+#pragma unroll
+        for (int c = 0; c < NA; ++c) {
+            double v = (double)acc[bb][c];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) red[wave][bb][c] = v;
+        }
+    __syncthreads();
+    if ((int)threadIdx.x < BT * 4) {
+        // all four sums are written (zeros for the quantum ones in the dilute form)
+        const int bb = threadIdx.x / 4, c = threadIdx.x % 4;
+        if (b0 + bb < B) {
+            const double v = c < NA ? ((red[0][bb][c] + red[1][bb][c]) + red[2][bb][c]) + red[3][bb][c]
+                                    : 0.0;
+            part[(((long)split * B + b0 + bb) * 4 + c) * n + i] = v;
+        }
     }
 }
 
@@ -657,7 +766,7 @@ __global__ __launch_bounds__(256) void k_epilogue(
     const double *__restrict__ rate, const double *__restrict__ f,
     const double *__restrict__ h, const double *__restrict__ K, const double *__restrict__ E,
     double mass, int n, int B, int project, double *__restrict__ C, double *__restrict__ diag,
-    StepArgs step)
+    StepArgs step, const double *__restrict__ ext, double eta)
 {
     const int lane = threadIdx.x & 63;
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -681,23 +790,36 @@ __global__ __launch_bounds__(256) void k_epilogue(
             if (!isfinite(x)) flag = fmax(flag, 1.0);
             else if (x < 0.0) flag = fmax(flag, 0.5);
             fmaxv = fmax(fmaxv, fabs(x));
-            // split partials: loads issued 8 at a time, added in split order
-            const PT *pp = part + (long)b * ld_b + i;
-            double g = 0.0;
-            int sp = 0;
-            for (; sp + 8 <= nsplit; sp += 8) {
-                double v[8];
+            if (ext) {
+                // exact form: four split sums per row, layout [split][B][4][n]
+                double a4[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int sp = 0; sp < nsplit; ++sp)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = (double)pp[(sp + u) * split_stride];
+                    for (int c = 0; c < 4; ++c) a4[c] += ext[(((long)sp * B + b) * 4 + c) * n + i];
+                const double gq = (1.0 + eta * x) * (a4[0] + eta * a4[3]);
+                const double lq = x * (a4[1] + eta * a4[2] + eta * eta * a4[3]);
+                rmax = fmax(rmax, a4[1]);
+                gmax = fmax(gmax, fabs(gq));
+                craw[q] = gq - lq;
+            } else {
+                // split partials: loads issued 8 at a time, added in split order
+                const PT *pp = part + (long)b * ld_b + i;
+                double g = 0.0;
+                int sp = 0;
+                for (; sp + 8 <= nsplit; sp += 8) {
+                    double v[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) g += v[u];
+                    for (int u = 0; u < 8; ++u) v[u] = (double)pp[(sp + u) * split_stride];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) g += v[u];
+                }
+                for (; sp < nsplit; ++sp) g += (double)pp[sp * split_stride];
+                if (fscale) g *= inv_s2 / (double)rscale[i];
+                const double rt = rate[(long)b * n + i];
+                rmax = fmax(rmax, rt);
+                gmax = fmax(gmax, fabs(g));
+                craw[q] = g - x * rt;
             }
-            for (; sp < nsplit; ++sp) g += (double)pp[sp * split_stride];
-            if (fscale) g *= inv_s2 / (double)rscale[i];
-            const double rt = rate[(long)b * n + i];
-            rmax = fmax(rmax, rt);
-            gmax = fmax(gmax, fabs(g));
-            craw[q] = g - x * rt;
         }
     }
     fmaxv = wave_max(fmaxv);
@@ -926,7 +1048,8 @@ template <typename PT>
 hipError_t launch_epilogue(const PT *part, int nsplit, long split_stride, int ld_b,
                            const float *fscale, const float *rscale, const double *rate,
                            const double *f, const kxg_kernel &k, int B, int project, double *C,
-                           double *diag, const StepArgs *step, hipStream_t s)
+                           double *diag, const StepArgs *step, hipStream_t s,
+                           const double *ext = nullptr, double eta = 0.0)
 {
     const int n = k.n;
     const dim3 grid((B + 3) / 4), blk(256);
@@ -936,7 +1059,7 @@ hipError_t launch_epilogue(const PT *part, int nsplit, long split_stride, int ld
 #define KXG_EPI(P)                                                                             \
     hipLaunchKernelGGL((k_epilogue<PT, P>), grid, blk, 0, s, part, nsplit, split_stride, ld_b, \
                        fscale, rscale, rate, f, k.d_h, k.d_K, k.d_E, k.mass, n, B, project, C, \
-                       diag, sa)
+                       diag, sa, ext, eta)
     if (n <= 64) KXG_EPI(1);
     else if (n <= 128) KXG_EPI(2);
     else if (n <= 256) KXG_EPI(4);
@@ -996,6 +1119,7 @@ kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws)
     const int n = k.n;
     const int bpad = div_up(b_cap, 128) * 128;
     size_t need = (size_t)stream_splits(n) * b_cap * n * sizeof(double);
+    if (k.d_JL) need = (size_t)stream_splits(n) * b_cap * 4 * n * sizeof(double);
     if (k.d_G32 || k.d_Gbf || k.d_Gh) {
         const size_t g = (size_t)k.gemm_splits * bpad * k.geo.ipad * sizeof(float);
         if (g > need) need = g;
@@ -1041,6 +1165,45 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     // FP32 takes the stream kernel only on handles built for tiny batches, so
     // that on any one handle the path (and the rounding) of a row does not
     // depend on how many rows share the call.
+    const bool exact = (flags & (KXG_INTERP_LOG | KXG_STAT_BOSE | KXG_STAT_FERMI)) != 0;
+    if (exact) {
+        const bool logi = (flags & KXG_INTERP_LOG) != 0;
+        const bool quant = (flags & (KXG_STAT_BOSE | KXG_STAT_FERMI)) != 0;
+        const double eta = (flags & KXG_STAT_BOSE) ? 1.0 : ((flags & KXG_STAT_FERMI) ? -1.0 : 0.0);
+        const int ns = stream_splits(n);
+        const long n2 = (long)n * n;
+        const bool dbl = prec == KXG_F64;
+        const int vec = (n % 2 == 0) ? 2 : 1;
+        int chunk = div_up(n2, ns);
+        chunk = div_up(chunk, 256 * vec) * (256 * vec);
+        const int nsplit = (int)((n2 + chunk - 1) / chunk);
+        constexpr int BT = 2;
+        const dim3 grid(nsplit, n, div_up(B, BT));
+        const size_t shm = 2 * n * sizeof(double) + 2 * (size_t)BT * n * (dbl ? sizeof(double) : sizeof(float));
+        double *ext = static_cast<double *>(ws.part);
+#define KXG_SX(T, V, L, Q)                                                                        \
+    hipLaunchKernelGGL((k_stream_x<T, V, BT, L, Q>), grid, dim3(256), shm, s,                     \
+                       reinterpret_cast<const T *>(dbl ? (const void *)k.d_A64 : (const void *)k.d_A32), \
+                       k.d_JL, f, k.d_K, k.d_invdK, n, B, chunk, ext)
+#define KXG_SX2(T, V)                                                                             \
+    if (logi && quant) KXG_SX(T, V, true, true);                                                  \
+    else if (logi) KXG_SX(T, V, true, false);                                                     \
+    else KXG_SX(T, V, false, true)
+        profile_mark_begin(s);
+        if (dbl) {
+            if (vec == 2) { KXG_SX2(double, 2); } else { KXG_SX2(double, 1); }
+        } else {
+            if (vec == 2) { KXG_SX2(float, 2); } else { KXG_SX2(float, 1); }
+        }
+#undef KXG_SX2
+#undef KXG_SX
+        profile_mark_end(s);
+        KXG_TRY_HIP(hipGetLastError());
+        KXG_TRY_HIP(launch_epilogue<double>(ext, nsplit, 0, 0, nullptr, nullptr, rate, f, k, B,
+                                            (flags & KXG_PROJECT) ? 1 : 0, C, diag, step, s, ext,
+                                            eta));
+        return KXG_OK;
+    }
     const bool use_stream = prec == KXG_F64 || (prec == KXG_F32 && B <= 4 && k.b_cap <= 4 && k.d_A32);
     const int project = (flags & KXG_PROJECT) ? 1 : 0;
     if (use_stream) {
@@ -1051,24 +1214,25 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         int chunk = div_up(n2, ns);
         chunk = div_up(chunk, 256 * vec) * (256 * vec);
         const int nsplit = (int)((n2 + chunk - 1) / chunk);
-        constexpr int BT = 4;
+        // distributions per pass: one for a single distribution (no idle
+        // lanes of work), four otherwise
+        const int BT = B == 1 ? 1 : (B == 2 ? 2 : 4);
         const dim3 grid(nsplit, n, div_up(B, BT));
         const size_t shm = (size_t)BT * n * (dbl ? sizeof(double) : sizeof(float));
         double *part = static_cast<double *>(ws.part);
         profile_mark_begin(s);
+#define KXG_ST(T, V, BTV) \
+    hipLaunchKernelGGL((k_stream<T, V, BTV>), grid, dim3(256), shm, s, \
+                       reinterpret_cast<const T *>(dbl ? (const void *)k.d_A64 : (const void *)k.d_A32), f, n, B, chunk, part)
+#define KXG_ST2(T, V) \
+    if (BT == 1) KXG_ST(T, V, 1); else if (BT == 2) KXG_ST(T, V, 2); else KXG_ST(T, V, 4)
         if (dbl) {
-            if (vec == 2)
-                hipLaunchKernelGGL((k_stream<double, 2, BT>), grid, dim3(256), shm, s, k.d_A64, f, n, B, chunk, part);
-            else
-                hipLaunchKernelGGL((k_stream<double, 1, BT>), grid, dim3(256), shm, s, k.d_A64, f, n, B, chunk, part);
+            if (vec == 2) { KXG_ST2(double, 2); } else { KXG_ST2(double, 1); }
         } else {
-            if (vec == 4)
-                hipLaunchKernelGGL((k_stream<float, 4, BT>), grid, dim3(256), shm, s, k.d_A32, f, n, B, chunk, part);
-            else if (vec == 2)
-                hipLaunchKernelGGL((k_stream<float, 2, BT>), grid, dim3(256), shm, s, k.d_A32, f, n, B, chunk, part);
-            else
-                hipLaunchKernelGGL((k_stream<float, 1, BT>), grid, dim3(256), shm, s, k.d_A32, f, n, B, chunk, part);
+            if (vec == 4) { KXG_ST2(float, 4); } else if (vec == 2) { KXG_ST2(float, 2); } else { KXG_ST2(float, 1); }
         }
+#undef KXG_ST2
+#undef KXG_ST
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
         KXG_TRY_HIP(launch_rate(k, f, B, rate, s));

@@ -71,6 +71,8 @@ struct kxg_kernel {
     uint16_t *d_Gh = nullptr;    // packed GEMM operand, FP16 hi/lo (row-scaled)
     float *d_hrow = nullptr;     // [ipad] FP16 row scales (powers of two)
     int *d_pairs = nullptr;      // [npairs][2] (kb, mb)
+    uint16_t *d_JL = nullptr;    // [n][n][n] interpolation bracket j_L (0xFFFF: cut)
+    double *d_invdK = nullptr;   // [n] 1 / (K_{j+1} - K_j) (0 for the last point)
     kxg::Geometry geo;
     int gemm_splits = 8;         // workgroup splits of K (fixed per handle)
     int lds_splits = 8;          // K splits of the LDS-shared 16-bit GEMM
@@ -85,6 +87,7 @@ hipError_t launch_build_A(const kxg_kernel &k, const double *d_xmu, const double
                           hipStream_t s);
 hipError_t launch_build_R(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_derive(kxg_kernel &k, hipStream_t s);
+hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s);
 
 struct StepArgs;
 // Evaluate C[f] for B rows; with `step` the epilogue applies that stepper

@@ -23,6 +23,10 @@ F64, F32, BF16X3, F16X3 = 0, 1, 2, 3
 PREC_NAMES = {F64: "f64", F32: "f32", BF16X3: "bf16x3", F16X3: "f16x3"}
 QUAD_GL, QUAD_EXACT = 0, 1
 PROJECT = 1
+INTERP_LOG = 2
+STAT_BOSE = 4
+STAT_FERMI = 8
+WITH_BRACKETS = 1 << 8
 NDIAG = 12
 RK4, HEUN = 0, 1
 EXP_NONE, EXP_RADIATION = 0, 1
@@ -169,7 +173,7 @@ class Kernel:
 
     def __init__(self, p: Sequence[float], precs=(F64,), b_cap: int = 1, mass: float = 1.0,
                  g_dof: float = 1.0, m2: float = 1.0, n_mu: int = 18, quad: int = QUAD_GL,
-                 dp: Optional[Sequence[float]] = None, stream=None):
+                 dp: Optional[Sequence[float]] = None, stream=None, brackets: bool = False):
         self._h = None
         self.p = np.ascontiguousarray(p, dtype=np.float64)
         self.n = len(self.p)
@@ -178,7 +182,7 @@ class Kernel:
         g = Grid(self.n, self.p.ctypes.data_as(_dp),
                  None if self._dp is None else self._dp.ctypes.data_as(_dp),
                  float(mass), float(g_dof), float(m2), int(n_mu), int(quad))
-        mask = 0
+        mask = WITH_BRACKETS if brackets else 0
         for q in precs:
             mask |= 1 << int(q)
         h = _vp()
@@ -211,8 +215,11 @@ class Kernel:
         _check(lib().kxg_kernel_grid(self._h, *(a.ctypes.data_as(_dp) for a in out)))
         return dict(zip(("dp", "E", "K", "h"), out))
 
-    def eval(self, f, prec: int = F64, project: bool = True, out=None, diag=None, stream=None):
-        """C[f] for f of shape [B, n] (device float64).  Returns (C, diag)."""
+    def eval(self, f, prec: int = F64, project: bool = True, out=None, diag=None, stream=None,
+             log_interp: bool = False, eta: int = 0):
+        """C[f] for f of shape [B, n] (device float64).  Returns (C, diag).
+        log_interp / eta (+1 Bose-Einstein, -1 Fermi-Dirac) select the exact
+        form of the operator (handle built with brackets=True)."""
         import torch
         if f.dim() == 1:
             f = f.view(1, -1)
@@ -221,8 +228,10 @@ class Kernel:
             out = torch.empty_like(f)
         if diag is None:
             diag = torch.empty((B, NDIAG), dtype=torch.float64, device=f.device)
+        flags = (PROJECT if project else 0) | (INTERP_LOG if log_interp else 0)
+        flags |= STAT_BOSE if eta > 0 else (STAT_FERMI if eta < 0 else 0)
         _check(lib().kxg_eval(self._h, int(prec), _dev_ptr(f, B * self.n, "f"), B,
-                              _dev_ptr(out, B * self.n, "C"), PROJECT if project else 0,
+                              _dev_ptr(out, B * self.n, "C"), flags,
                               _dev_ptr(diag, B * NDIAG, "diag"), _stream_ptr(stream)))
         return out, diag
 

@@ -11,6 +11,15 @@ import numpy as np
 
 
 def gain(p1, f, mass=1.0, gdof=1.0, m2=1.0, lo=1e-3, hi=30.0, ns=2_000_000, seed=1):
+    """Gain term (dilute) at momentum p1: (mean, standard error)."""
+    g, l = collision(p1, f, 0, mass, gdof, m2, lo, hi, ns, seed)
+    return g
+
+
+def collision(p1, f, eta, mass=1.0, gdof=1.0, m2=1.0, lo=1e-3, hi=30.0, ns=2_000_000, seed=1):
+    """Gain and loss parts of eq. C22_general with the statistical factor of
+    eq. Lambda_quantum: gain = f3 f4 (1 + eta f1)(1 + eta f2), loss = f1 f2
+    (1 + eta f3)(1 + eta f4).  Returns ((gain, se), (loss, se))."""
     rng = np.random.default_rng(seed)
     e1 = np.sqrt(p1 * p1 + mass * mass)
     p2 = np.exp(rng.uniform(np.log(lo), np.log(hi), ns))
@@ -41,7 +50,10 @@ def gain(p1, f, mass=1.0, gdof=1.0, m2=1.0, lo=1e-3, hi=30.0, ns=2_000_000, seed
     q3 = np.sqrt((p3 * p3).sum(1))
     q4 = np.sqrt((p4 * p4).sum(1))
     vol = (np.log(hi) - np.log(lo)) * 2.0 * 4.0 * np.pi
-    w = (2.0 * np.pi * p2 ** 3 / ((2.0 * np.pi) ** 3 * 2.0 * e2)) \
-        * (pstar / (16.0 * np.pi ** 2 * rs)) * m2 * f(q3) * f(q4)
-    vals = w * vol / (2.0 * e1 * gdof)
-    return float(vals.mean()), float(vals.std() / np.sqrt(ns))
+    meas = (2.0 * np.pi * p2 ** 3 / ((2.0 * np.pi) ** 3 * 2.0 * e2)) \
+        * (pstar / (16.0 * np.pi ** 2 * rs)) * m2 * vol / (2.0 * e1 * gdof)
+    f1, f2, f3, f4 = f(np.array([p1]))[0], f(p2), f(q3), f(q4)
+    g = meas * f3 * f4 * (1.0 + eta * f1) * (1.0 + eta * f2)
+    l = meas * f1 * f2 * (1.0 + eta * f3) * (1.0 + eta * f4)
+    se = lambda v: float(v.std() / np.sqrt(ns))
+    return (float(g.mean()), se(g)), (float(l.mean()), se(l))

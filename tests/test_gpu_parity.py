@@ -354,3 +354,51 @@ def test_eval_16bit_large_batch_lds_path(dev, prec):
     for b in (0, 31, 32, 255, 511, 512, 599):
         assert rel(C[b], oracle_C(op, f0[b:b + 1], True)[0]) <= TOL[prec], b
     assert np.array_equal(sub, C[:520])
+
+
+# ---------------------------------------------------------------- exact forms
+@pytest.mark.parametrize("n,B", [(37, 1), (48, 3)])
+@pytest.mark.parametrize("log_interp,eta", [(True, 0), (False, 1), (False, -1), (True, 1),
+                                            (True, -1)])
+def test_exact_forms_match_oracle_direct(dev, n, B, log_interp, eta):
+    """Paper's log interpolation (eq. app_log_interp) and Bose-Einstein /
+    Fermi-Dirac factors (eq. Lambda_quantum) against the oracle's direct
+    per-(i,n,m) evaluation with the product form of Lambda."""
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    f0 = batch(p, B, seed=23) * 0.3          # occupations below one
+    k = kxg.Kernel(p, precs=(kxg.F64, kxg.F32), b_cap=4, brackets=True)
+    f = torch.tensor(f0, device=dev)
+    interp = oracle.LOG if log_interp else oracle.LIN
+    ref = np.stack([oracle.direct(p, f0[b], interp=interp, eta=eta)[0] for b in range(B)])
+    for prec in (kxg.F64, kxg.F32):
+        C, d = k.eval(f, prec=prec, project=False, log_interp=log_interp, eta=eta)
+        torch.cuda.synchronize()
+        assert rel(C.cpu().numpy(), ref) <= TOL[prec], (prec, rel(C.cpu().numpy(), ref))
+    op = oracle.Operator(p)
+    Cp, _ = k.eval(f, prec=kxg.F64, project=True, log_interp=log_interp, eta=eta)
+    torch.cuda.synchronize()
+    refp = np.stack([op.project(f0[b], ref[b])[0] for b in range(B)])
+    assert rel(Cp.cpu().numpy(), refp) <= TOL[kxg.F64]
+
+
+def test_exact_form_log_interp_keeps_maxwell_boltzmann(dev):
+    p = inputs.log_grid(40, 1e-2, 10.0)
+    f0 = inputs.maxwell_boltzmann(p, 1.0, 0.4, 2.0)[None, :]
+    k = kxg.Kernel(p, precs=(kxg.F64,), brackets=True)
+    C, d = k.eval(torch.tensor(f0, device=dev), project=False, log_interp=True)
+    torch.cuda.synchronize()
+    gain_max = d[0, 9].item()
+    assert torch.max(torch.abs(C)).item() <= 1e-13 * gain_max
+
+
+def test_exact_form_needs_brackets(dev):
+    p = inputs.log_grid(16, 1e-2, 5.0)
+    k = kxg.Kernel(p, precs=(kxg.F64, kxg.BF16X3), b_cap=2)
+    f = torch.ones((1, 16), dtype=torch.float64, device=dev)
+    with pytest.raises(kxg.KxgError) as ei:
+        k.eval(f, log_interp=True)
+    assert ei.value.status == kxg.EUNSUPPORTED
+    kb = kxg.Kernel(p, precs=(kxg.F64, kxg.BF16X3), b_cap=2, brackets=True)
+    with pytest.raises(kxg.KxgError) as ei:
+        kb.eval(f, prec=kxg.BF16X3, eta=1)
+    assert ei.value.status == kxg.EUNSUPPORTED

@@ -369,3 +369,42 @@ def test_projection_pointwise_correction_below_percent(n):
     Cp, d = op.project(f, C)
     assert np.max(np.abs(Cp - C)) < 1e-2 * np.max(np.abs(C))
     assert d[6] < 5e-2 and d[7] < 5e-2
+
+
+# --------------------------------------------------------------------------
+# Quantum statistics (eq. Lambda_quantum): the direct evaluation with
+# Bose-Einstein / Fermi-Dirac factors against the Monte Carlo of the same
+# continuum integral, Richardson-extrapolated in the grid; eta = 0 is the
+# dilute operator.
+@pytest.mark.parametrize("eta,amp", [(1, 1.0), (-1, 0.9)])
+def test_quantum_operator_matches_monte_carlo(eta, amp):
+    f = lambda q: inputs.bump_pair(q, 0.3, 1.5, amp, 0.5 * amp, 0.35, 0.35)
+    picks = [4, 8, 11]
+    res = {}
+    for n in (61, 121):
+        p = inputs.log_grid(n, 1e-2, 20.0)
+        _, g, l = oracle.direct(p, f(p), quad=oracle.EXACT, interp=oracle.LIN, eta=eta)
+        k = (n - 1) // 15
+        idx = [k * j for j in picks]
+        res[n] = (g[idx], l[idx])
+    targets = inputs.log_grid(16, 1e-2, 20.0)[picks]
+    for t, x in enumerate(targets):
+        (mg, sg), (ml, sl) = mc_collision.collision(x, f, eta, ns=2_000_000, seed=17 + t)
+        rg = res[121][0][t] + (res[121][0][t] - res[61][0][t]) / 3.0
+        rl = res[121][1][t] + (res[121][1][t] - res[61][1][t]) / 3.0
+        assert abs(rg - mg) < 4.0 * sg + 3e-3 * mg, (x, rg, mg, sg)
+        assert abs(rl - ml) < 4.0 * sl + 3e-3 * ml, (x, rl, ml, sl)
+
+
+def test_quantum_operator_dilute_limit_and_statistics_sign():
+    p = inputs.log_grid(28, 1e-2, 10.0)
+    f = inputs.bump_pair(p, 0.2, 2.0, 0.8, 0.4, 0.3, 0.3)
+    c0, g0, l0 = oracle.direct(p, f, interp=oracle.LOG)
+    cd, gd, ld = oracle.direct(p, f, interp=oracle.LOG, eta=0)
+    assert np.array_equal(c0, cd)
+    cb, gb, lb = oracle.direct(p, f, interp=oracle.LOG, eta=1)
+    cf, gf, lf = oracle.direct(p, f, interp=oracle.LOG, eta=-1)
+    # Bose enhancement raises both rates, Pauli blocking lowers them
+    assert np.all(gb >= g0) and np.all(gf <= g0) and np.all(lb >= l0) and np.all(lf <= l0)
+    # the eta-odd parts are equal and opposite (the eta^2 terms cancel in Lambda)
+    assert np.allclose((cb - c0), -(cf - c0), rtol=1e-10, atol=1e-14 * np.max(np.abs(gb)))
