@@ -42,9 +42,11 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=800,
                     help="measured serving requests (after --serve-warm warm-up ones); 0 = skip")
     ap.add_argument("--serve-warm", type=int, default=200)
-    ap.add_argument("--profile-run", action="store_true",
-                    help="short run for hardware counters: the timed RK4 steps, the plain FP64 "
-                         "path and a 1 GiB device copy (the calibration kernel), nothing else")
+    ap.add_argument("--profile-run", nargs="?", const="gemm", default=None,
+                    choices=("gemm", "stream384"),
+                    help="short run for profilers: 'gemm' = the timed RK4 steps, the plain "
+                         "FP64 path and a 1 GiB device copy (the calibration kernel); "
+                         "'stream384' = 50 plain FP64 evaluations at N = 384 and the copy")
     return ap.parse_args()
 
 
@@ -209,6 +211,20 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if args.profile_run == "stream384":
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        n = 384
+        p = inputs.log_grid(n, 1e-3, 20.0)
+        k = kxg.Kernel(p, precs=(kxg.F64,), b_cap=1)
+        f = torch.tensor(inputs.draw_solves(1)[0].f0(p)[None, :], device=dev)
+        C = torch.empty_like(f)
+        for _ in range(50):
+            k.eval(f, prec=kxg.F64, out=C)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": "stream384", "evals": 50}), flush=True)
+        return
 
     # ---------------- batched FP32 RK4 (the timed step) ----------------
     w = inputs.batched_fp32_n256(512)

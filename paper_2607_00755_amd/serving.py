@@ -64,6 +64,8 @@ class Group:
     bytes: int = 0
     iters: int = 0
     batch_sum: int = 0
+    event: object = None          # completion event of the last enqueued chunk
+    busy: bool = False
 
 
 class Server:
@@ -112,7 +114,8 @@ class Server:
         st = kxg.Stepper(ker, kind=kxg.HEUN, prec=self.prec, b_cap=self.b_cap,
                          expansion=kxg.EXP_RADIATION, rtol=self.rtol)
         real = ker.bytes(-1) + self.b_cap * self.slot_bytes(n)
-        g = Group(n, ker, st, stream, self.b_cap, free=list(range(self.b_cap)), p=p, bytes=real)
+        g = Group(n, ker, st, stream, self.b_cap, free=list(range(self.b_cap)), p=p, bytes=real,
+                  event=torch.cuda.Event())
         self.groups[n] = g
         self.used_bytes += real
         return g
@@ -200,15 +203,28 @@ class Server:
                 if nxt < len(pending) and realtime:
                     time.sleep(max(0.0, min(pending[nxt].arrival - now, 0.002)))
                 continue
+            # Each group runs on its own stream and is re-fed as soon as its own
+            # previous chunk of iterations has completed (non-blocking poll), so
+            # fast groups never wait for slow ones.
+            progressed = False
             for g in active:
-                g.stepper.advance(self.iters_per_tick, stream=g.stream)
-                g.iters += self.iters_per_tick
-                g.batch_sum += self.iters_per_tick * len(g.slots)
-            now = time.perf_counter() - t0
-            for g in active:
-                self._retire(g, time.perf_counter() - t0, done)
+                if g.busy:
+                    if not g.event.query():
+                        continue
+                    g.busy = False
+                    self._retire(g, time.perf_counter() - t0, done)
+                    progressed = True
+                if g.slots:
+                    g.stepper.advance(self.iters_per_tick, stream=g.stream)
+                    g.iters += self.iters_per_tick
+                    g.batch_sum += self.iters_per_tick * len(g.slots)
+                    g.event.record(g.stream)
+                    g.busy = True
+                    progressed = True
+            if not progressed:
+                time.sleep(5e-5)
             # release the tensors of groups that drained and are not needed
-            for n in [n for n, g in self.groups.items() if not g.slots]:
+            for n in [n for n, g in self.groups.items() if not g.slots and not g.busy]:
                 if not any(r.solve.n == n for r in waiting) and self.used_bytes > self.budget // 2:
                     self._close_group(n)
             if on_tick:
