@@ -121,7 +121,7 @@ static void profile_clear()
 #define KXG_LDS_WG_TARGET 512
 #endif
 #ifndef KXG_LDS_BBW
-#define KXG_LDS_BBW 4
+#define KXG_LDS_BBW 2
 #endif
 #ifndef KXG_LDS_IBW
 #define KXG_LDS_IBW 2
@@ -603,6 +603,10 @@ static kxg_status enqueue_iteration(kxg_stepper *s, int B, hipStream_t st)
     a.fac_lo = P.fac_min;
     a.fac_hi = P.fac_max;
     a.dt_min = P.dt_min;
+    // every operator call of the iteration takes its GEMM operand from the
+    // epilogue of the call before (the first from kxg_stepper_advance)
+    a.write_op = 1;
+    a.op_ready = 1;
     if (P.kind == KXG_RK4) {
         a.mode = kStepRK4;
         for (int stage = 1; stage <= 4; ++stage) {
@@ -664,9 +668,13 @@ kxg_status kxg_stepper_advance(kxg_stepper *s, int32_t n_iter, void *stream)
     // default stream.
     const int bucket = std::min(s->prm.b_cap, (B + 15) / 16 * 16);
     if (st != nullptr && !g_prof.on && ensure_graph(s, bucket, st)) {
+        kxg_status r = prep_operands(*s->k, s->ws, s->prm.prec, s->d_fb, bucket, st);
+        if (r != KXG_OK) return r;
         for (int it = 0; it < n_iter; ++it) KXG_TRY_HIP(hipGraphLaunch(s->gexec, st));
         return KXG_OK;
     }
+    kxg_status r0 = prep_operands(*s->k, s->ws, s->prm.prec, s->d_fb, B, st);
+    if (r0 != KXG_OK) return r0;
     for (int it = 0; it < n_iter; ++it) {
         kxg_status r = enqueue_iteration(s, B, st);
         if (r != KXG_OK) return r;

@@ -22,6 +22,7 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
@@ -32,8 +33,17 @@ inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 #define KXG_STREAM_NT 1
 #endif
 // shape of the LDS-shared 16-bit GEMM: b-blocks and i-blocks per wave
+#ifndef KXG_F32_SS
+#define KXG_F32_SS 4         // dk steps per register stage of the FP32 GEMM
+#endif
+#ifndef KXG_F32_NST
+#define KXG_F32_NST 2        // register stages of the FP32 GEMM
+#endif
+#ifndef KXG_LDS_SS
+#define KXG_LDS_SS 4         // dk steps per LDS stage of the 16-bit GEMM
+#endif
 #ifndef KXG_LDS_BBW
-#define KXG_LDS_BBW 4
+#define KXG_LDS_BBW 2
 #endif
 #ifndef KXG_LDS_IBW
 #define KXG_LDS_IBW 2
@@ -287,6 +297,85 @@ __global__ __launch_bounds__(256) void k_prep(const double *__restrict__ f, int 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Loss rates rate[b][i] = sum_j R[i][j] f_bj in FP64 on v_mfma_f64_16x16x4f64.
+// One 16 (b) x 16 (i) output tile per call by a whole workgroup: its 4 waves
+// take 4 consecutive j ranges (all loads of a wave in flight at once at
+// n = 256) and their accumulators are added in the fixed order 0+1+2+3, so a
+// row's rates do not depend on B.  Operand/result layout of the
+// instruction: A[row][k] at lane row + 16k, B[k][col] at lane col + 16k,
+// D[row][col] at lane col + 16 (row % 4), register row / 4.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int kRateT = 16;
+struct RateArgs {
+    const double *RT;     // R transposed [n][n]
+    const double *f;      // [B][n]
+    int n, B;
+    double *rate;         // [B][n]
+    int tiles_b;          // ceil(B / 16)
+};
+// `red`: 3*4*64 doubles of LDS; ends with a barrier, so the caller may reuse it.
+__device__ void rate_tile(const RateArgs &ra, int tile, double *red)
+{
+    const int n = ra.n, B = ra.B;
+    const int b0 = (tile % ra.tiles_b) * kRateT, i0 = (tile / ra.tiles_b) * kRateT;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nsteps = (n + 3) / 4;                         // K steps of 4
+    const int per = (nsteps + 3) / 4;
+    const int s0 = wave * per, s1 = min(nsteps, s0 + per);
+    const int b = b0 + lr, i = i0 + lr;
+    const double *frow = ra.f + (long)(b < B ? b : 0) * n;
+    const double *RT = ra.RT;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    int st = s0;
+    for (; st + 16 <= s1; st += 16) {
+        double av[16], bv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int j = 4 * (st + u) + lk;
+            av[u] = (b < B && j < n) ? frow[j] : 0.0;
+            bv[u] = (i < n && j < n) ? RT[(long)j * n + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    }
+    for (; st < s1; ++st) {
+        const int j = 4 * st + lk;
+        const double av = (b < B && j < n) ? frow[j] : 0.0;
+        const double bv = (i < n && j < n) ? RT[(long)j * n + i] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[((wave - 1) * 4 + r) * 64 + lane] = acc[r];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double v = ((acc[r] + red[(0 * 4 + r) * 64 + lane]) + red[(1 * 4 + r) * 64 + lane]) +
+                             red[(2 * 4 + r) * 64 + lane];
+            const int bo = b0 + lk + 4 * r, io = i0 + lr;
+            if (bo < B && io < n) ra.rate[(long)bo * n + io] = v;
+        }
+    }
+    __syncthreads();
+}
+
+// The tiles of a GEMM workgroup: g, g + ngemm, ... (done in its prologue,
+// while the first loads of its own operands are in flight).
+__device__ void rate_tiles_of(const RateArgs &ra, int ntiles, int g, int ngemm, double *red)
+{
+    for (int t = g; t < ntiles; t += ngemm) rate_tile(ra, t, red);
+}
+
+__global__ __launch_bounds__(256) void k_rate(RateArgs ra)
+{
+    __shared__ double red[3 * 4 * 64];
+    rate_tile(ra, blockIdx.x, red);
+}
+
 // Reduce the 4 waves' accumulators of a workgroup (fixed order 0+1+2+3) and
 // store the FP32 partial of this K split.  32x32 MFMA result layout: register
 // e of lane l holds row 8*(e/4) + 4*(l/32) + e%4, column l%32.
@@ -324,25 +413,49 @@ __device__ void store_tile(floatx16 (&acc)[BBW], float *lds, float *__restrict__
 // consecutive sub-ranges of the split's dk steps.  Per dk step (one row k of a
 // (kb, mb) block, 16 K values) a wave issues 8*BBW MFMAs; the A operand
 // (F2 = f_k f_m) is one multiply per MFMA, the B operand (packed tensor)
-// comes straight from memory in MFMA order, prefetched one step ahead.
-template <int BBW>
+// comes straight from memory in MFMA order.
+//
+// The loop runs over super-steps of SS dk steps with NST register stages
+// (packed tensor, f_k and f_m of one super-step) used in rotation, so that
+// the loads of the next NST-1 super-steps are in flight during the MFMAs of
+// the current one without any register copy or branch around them (either
+// would make the compiler wait for them early); a prefetch past the end of
+// the range re-reads the last super-step.  The wave index is made uniform so
+// that the pair table is read through scalar loads.
+template <int BBW, int SS>
+struct F32Stage {
+    float4 g[2 * SS];          // packed tensor, two 16-byte vectors per dk step
+    float fk[BBW][SS];         // f_k of each batch sub-tile, per dk step
+    float4 fm[BBW][2];         // f_m of the (kb, mb) block in parity order
+};
+
+template <int BBW, int SS = 2, int NST = 2>
 __global__ __launch_bounds__(256, 2) void k_gemm_f32(
     const float *__restrict__ G, const float *__restrict__ fop, const float *__restrict__ fpar,
     const int *__restrict__ pairs, int npairs, int bpad, int ipad, int nbt, int splits,
-    long dksteps, float *__restrict__ part)
+    long dksteps, float *__restrict__ part, int nrate, RateArgs rargs)
 {
-    __shared__ float lds[3 * BBW * 16 * 64];
+    static_assert(SS == 2 || SS == 4, "super-step of 2 or 4 dk steps");
+    static_assert(NST == 2 || NST == 3, "2 or 3 register stages");
+    typedef float fkvec __attribute__((ext_vector_type(SS)));
+    constexpr int PPS = kBlk / SS;                 // super-steps per (kb, mb) pair
+    __shared__ __align__(16) float lds[3 * BBW * 16 * 64];
     int L = xcd_logical(blockIdx.x, gridDim.x);
     const int bt = L % nbt;
     L /= nbt;
     const int sp = L % splits;
     const int ib = L / splits;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
     const int r = lane & 31, hb = lane >> 5;
     const long w = (long)sp * kWaves + wave, nw = (long)splits * kWaves;
-    const long u0 = w * dksteps / nw, u1 = (w + 1) * dksteps / nw;
+    const long nss = dksteps / SS;                 // super-steps (dksteps is a multiple of 16)
+    const long s0 = w * nss / nw, s1 = (w + 1) * nss / nw;
     const int brow0 = bt * BBW * 32;
     const float *Gi = G + (long)ib * npairs * kBlk * 512;
+    const float *fkb = fop + (long)(brow0 + r) * kBlk;
+    const float *fmb = fpar + ((long)(brow0 + r) * 2 + hb) * 8;
+    const long bstride = (long)bpad * kBlk;        // one 16-block of the grid, all rows
 
     floatx16 acc[BBW];
 #pragma unroll
@@ -350,57 +463,67 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[bb][e] = 0.0f;
 
-    float fm[BBW][8];
-    int cur_pair = -1;
-    float4 nb0 = make_float4(0, 0, 0, 0), nb1 = nb0;
-    float nfk[BBW];
-    if (u0 < u1) {
-        const int pr = (int)(u0 >> 4), dk = (int)(u0 & 15);
-        const float *gp = Gi + u0 * 512;
-        nb0 = reinterpret_cast<const float4 *>(gp)[lane];
-        nb1 = reinterpret_cast<const float4 *>(gp + 256)[lane];
-        const int kb = pairs[2 * pr];
+    F32Stage<BBW, SS> st[NST];
+
+    auto load_stage = [&](long s, F32Stage<BBW, SS> &x) {
+        s = s < s1 ? s : s1 - 1;
+        const float4 *gp = reinterpret_cast<const float4 *>(Gi + s * (SS * 512));
 #pragma unroll
-        for (int bb = 0; bb < BBW; ++bb)
-            nfk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
-    }
-    for (long u = u0; u < u1; ++u) {
-        const int pr = (int)(u >> 4);
-        if (pr != cur_pair) {
-            cur_pair = pr;
-            const int mb = pairs[2 * pr + 1];
-#pragma unroll
-            for (int bb = 0; bb < BBW; ++bb) {
-                const float4 *src = reinterpret_cast<const float4 *>(
-                    fpar + (((long)mb * bpad + brow0 + bb * 32 + r) * 2 + hb) * 8);
-                const float4 x0 = src[0], x1 = src[1];
-                fm[bb][0] = x0.x; fm[bb][1] = x0.y; fm[bb][2] = x0.z; fm[bb][3] = x0.w;
-                fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
-            }
+        for (int d = 0; d < SS; ++d) {
+            x.g[2 * d] = gp[d * 128 + lane];
+            x.g[2 * d + 1] = gp[d * 128 + 64 + lane];
         }
-        const float4 b0 = nb0, b1 = nb1;
-        float fk[BBW];
+        const int pr = (int)(s / PPS);
+        const int kb = pairs[2 * pr], mb = pairs[2 * pr + 1];
+        const int dk = (int)(s % PPS) * SS;
 #pragma unroll
-        for (int bb = 0; bb < BBW; ++bb) fk[bb] = nfk[bb];
-        if (u + 1 < u1) {
-            const long un = u + 1;
-            const int prn = (int)(un >> 4), dkn = (int)(un & 15);
-            const float *gp = Gi + un * 512;
-            nb0 = reinterpret_cast<const float4 *>(gp)[lane];
-            nb1 = reinterpret_cast<const float4 *>(gp + 256)[lane];
-            const int kbn = pairs[2 * prn];
+        for (int bb = 0; bb < BBW; ++bb) {
+            const fkvec v = *reinterpret_cast<const fkvec *>(fkb + kb * bstride + bb * 32 * kBlk + dk);
 #pragma unroll
-            for (int bb = 0; bb < BBW; ++bb)
-                nfk[bb] = fop[((long)kbn * bpad + brow0 + bb * 32 + r) * kBlk + dkn];
+            for (int d = 0; d < SS; ++d) x.fk[bb][d] = v[d];
+            const float4 *src = reinterpret_cast<const float4 *>(fmb + mb * bstride + bb * 32 * kBlk);
+            x.fm[bb][0] = src[0];
+            x.fm[bb][1] = src[1];
         }
-        const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+    };
+    auto compute = [&](const F32Stage<BBW, SS> &x) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
+        for (int d = 0; d < SS; ++d) {
+            const float bv[8] = {x.g[2 * d].x, x.g[2 * d].y, x.g[2 * d].z, x.g[2 * d].w,
+                                 x.g[2 * d + 1].x, x.g[2 * d + 1].y, x.g[2 * d + 1].z, x.g[2 * d + 1].w};
 #pragma unroll
-            for (int bb = 0; bb < BBW; ++bb)
-                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fk[bb] * fm[bb][t], bv[t],
-                                                               acc[bb], 0, 0, 0);
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int bb = 0; bb < BBW; ++bb) {
+                    const float fm = x.fm[bb][t >> 2][t & 3];
+                    acc[bb] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.fk[bb][d] * fm, bv[t], acc[bb], 0, 0, 0);
+                }
+        }
+    };
+
+    // Rounds of NST super-steps with no exit between them (a conditional exit
+    // would let the compiler sink the prefetch below it); at the start of a
+    // round st[j] holds super-step s + j for j < NST - 1, and the last
+    // s1 - s < NST super-steps are done after the loop from those stages.
+    if (s0 < s1) {
+#pragma unroll
+        for (int j = 0; j < NST - 1; ++j) load_stage(s0 + j, st[j]);
     }
+    // loss-rate tiles of this workgroup while those loads are in flight
+    rate_tiles_of(rargs, nrate, blockIdx.x, gridDim.x, reinterpret_cast<double *>(lds));
+    long s = s0;
+    for (; s + NST <= s1; s += NST) {
+#pragma unroll
+        for (int j = 0; j < NST; ++j) {
+            load_stage(s + j + NST - 1, st[(j + NST - 1) % NST]);
+            __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
+            compute(st[j]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NST - 1; ++j)
+        if (s + j < s1) compute(st[j]);
     store_tile<BBW>(acc, lds, part, sp, bpad, ipad, brow0, ib * kIBlk);
 }
 
@@ -411,11 +534,11 @@ template <int BBW, bool F16>
 __global__ __launch_bounds__(256, 2) void k_gemm_x3(
     const uint16_t *__restrict__ G, const float *__restrict__ fop, const int *__restrict__ pairs,
     int npairs, int bpad, int ipad, int nbt, int splits, long dksteps,
-    float *__restrict__ part)
+    float *__restrict__ part, int nrate, RateArgs rargs)
 {
     typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
     typedef typename std::conditional<F16, _Float16, __bf16>::type op_t;
-    __shared__ float lds[3 * BBW * 16 * 64];
+    __shared__ __align__(16) float lds[3 * BBW * 16 * 64];
     int L = xcd_logical(blockIdx.x, gridDim.x);
     const int bt = L % nbt;
     L /= nbt;
@@ -448,6 +571,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(
         for (int bb = 0; bb < BBW; ++bb)
             nfk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
     }
+    // loss-rate tiles of this workgroup while the first loads are in flight
+    rate_tiles_of(rargs, nrate, blockIdx.x, gridDim.x, reinterpret_cast<double *>(lds));
     for (long u = u0; u < u1; ++u) {
         const int pr = (int)(u >> 4);
         if (pr != cur_pair) {
@@ -503,67 +628,66 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(
     store_tile<BBW>(acc, lds, part, sp, bpad, ipad, brow0, ib * kIBlk);
 }
 
-// 16-bit x3 GEMM for large batches, A operand shared through LDS.  A
-// workgroup's 4 waves work on the same K chunk (split) and the same IBW
-// i-blocks; wave w takes the BBW b-blocks [w*BBW, (w+1)*BBW) of the
-// workgroup's 4*BBW*32-row batch tile.  Per dk step the workgroup stages the
-// hi/lo A fragments of its i-blocks (2 KB each) once into a 3-deep LDS ring
-// (global loads issued two steps ahead); every wave forms and splits its F2
-// operand once per b-block and feeds it to 3*IBW MFMAs.  One barrier per dk
-// step.  Partials: one per K split.
-template <int BBW, int IBW, bool F16>
-__global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
-    const uint16_t *__restrict__ G, const float *__restrict__ fop, const int *__restrict__ pairs,
+// 16-bit x3 GEMM for large batches, the packed tensor shared through LDS.
+// A workgroup's 4 waves work on the same K split and the same IBW i-blocks;
+// wave w takes the BBW b-blocks [w*BBW, (w+1)*BBW) of the workgroup's
+// 4*BBW*32-row batch tile.  The K range runs in super-steps of SS dk steps:
+// the workgroup stages the hi/lo fragments of its i-blocks for one
+// super-step (IBW*SS*2 KB) into one of two LDS slots, each thread carrying
+// IBW*SS/2 16-byte vectors through registers.  Two register stages (the
+// vectors in transit, f_k and f_m of the super-step) alternate without
+// copies: the global loads of super-step s+1 are in flight while the MFMAs
+// of super-step s run, and are written to the other LDS slot after them;
+// one barrier per super-step.  Every wave forms and splits its F2 operand
+// once per (b-block, dk) and feeds it to 3*IBW MFMAs.  Partials: one per K
+// split.
+template <int BBW, int SS, int NQ>
+struct X3Stage {
+    u32x4 gv[NQ];              // packed-tensor vectors in transit to LDS
+    float fk[BBW][SS];         // f_k per b-block and dk step
+    float4 fm[BBW][2];         // f_m (the 8 values of this lane's K half)
+};
+
+template <int BBW, int IBW, int SS, bool F16>
+__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_gemm_x3_lds(
+    const uint16_t *G, const float *__restrict__ fop, const int *__restrict__ pairs,
     int npairs, int nib, int bpad, int ipad, int nbt, int nit, int splits, long dksteps,
-    float *__restrict__ part)
+    float *__restrict__ part, int nrate, RateArgs rargs)
 {
     typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
     typedef typename std::conditional<F16, _Float16, __bf16>::type op_t;
-    constexpr int NV = IBW * 2 * 64;               // 16-byte vectors per dk step
-    constexpr int PT = (NV + 255) / 256;           // vectors per thread
-    __shared__ uint4 sA[3][NV];
+    typedef float fkvec __attribute__((ext_vector_type(SS)));
+    constexpr int VPS = SS * 128;                  // 16-byte vectors per i-block and super-step
+    constexpr int NV = IBW * VPS;                  // per super-step
+    constexpr int NQ = NV / 256;                   // per thread
+    constexpr int PPS = kBlk / SS;                 // super-steps per (kb, mb) pair
+    static_assert(NV % 256 == 0, "a super-step must split evenly over 256 threads");
+    typedef X3Stage<BBW, SS, NQ> Stage;
+    __shared__ u32x4 sA[2][NV];
     int L = xcd_logical(blockIdx.x, gridDim.x);
     const int bt = L % nbt;
     L /= nbt;
     const int sp = L % splits;
     const int it = L / splits;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
     const int r = lane & 31, hb = lane >> 5;
-    const long u0 = (long)sp * dksteps / splits, u1 = (long)(sp + 1) * dksteps / splits;
+    const long nss = dksteps / SS;
+    const long s0 = (long)sp * nss / splits, s1 = (long)(sp + 1) * nss / splits;
     const int brow0 = bt * (4 * BBW * 32) + wave * (BBW * 32);
     const int ib0 = it * IBW;
-    // loader role: vectors q = threadIdx.x + 256 c of each dk step; a dk step
-    // of one i-block is 1024 16-bit values = 128 vectors ([hi|lo][lane][8])
-    const uint4 *qsrc[PT];
-    bool qload[PT];
+    const long bstride = (long)bpad * kBlk;
+    const float *fkb = fop + (long)(brow0 + r) * kBlk;
+    const float *fmb = fop + (long)(brow0 + r) * kBlk + 8 * hb;
+    // loader role: vector q = threadIdx.x + 256 c of a super-step belongs to
+    // i-block q / VPS (clamped to the last one; such rows are never stored)
+    const u32x4 *qsrc[NQ];
 #pragma unroll
-    for (int c = 0; c < PT; ++c) {
+    for (int c = 0; c < NQ; ++c) {
         const int q = threadIdx.x + 256 * c;
-        const int qib = q / 128;
-        qload[c] = q < NV && ib0 + qib < nib;
-        qsrc[c] = reinterpret_cast<const uint4 *>(
-                      G + (long)(ib0 + (qload[c] ? qib : 0)) * npairs * kBlk * 1024) + (q % 128);
+        const int ibq = min(ib0 + q / VPS, nib - 1);
+        qsrc[c] = reinterpret_cast<const u32x4 *>(G) + (long)ibq * npairs * kBlk * 128 + (q % VPS);
     }
-    const uint4 zero4 = make_uint4(0, 0, 0, 0);
-    auto fetch = [&](long u, uint4 (&dst)[PT]) {
-#pragma unroll
-        for (int c = 0; c < PT; ++c) dst[c] = (qload[c] && u < u1) ? qsrc[c][u * 128] : zero4;
-    };
-    auto stash = [&](int slot, const uint4 (&src)[PT]) {
-#pragma unroll
-        for (int c = 0; c < PT; ++c) {
-            const int q = threadIdx.x + 256 * c;
-            if (q < NV) sA[slot][q] = src[c];
-        }
-    };
-    auto load_fk = [&](long u, float (&dst)[BBW]) {
-        if (u >= u1) return;
-        const int pr = (int)(u >> 4), dk = (int)(u & 15);
-        const int kb = pairs[2 * pr];
-#pragma unroll
-        for (int bb = 0; bb < BBW; ++bb)
-            dst[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
-    };
 
     floatx16 acc[BBW][IBW];
 #pragma unroll
@@ -573,76 +697,92 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[bb][ib][e] = 0.0f;
 
-    uint4 ra[PT], rb[PT];
-    float fk1[BBW], fk2[BBW], fm[BBW][8];
-    if (u0 < u1) {
-        uint4 r0[PT];
-        fetch(u0, r0);
-        stash(0, r0);
-    }
-    fetch(u0 + 1, ra);
-    fetch(u0 + 2, rb);
-    load_fk(u0, fk1);
-    load_fk(u0 + 1, fk2);
-    int cur_pair = -1;
-    __syncthreads();
-    for (long u = u0; u < u1; ++u) {
-        const int idx = (int)(u - u0);
-        const int slot = idx % 3;
-        stash((idx + 1) % 3, ra);         // data of step u+1, read after the next barrier
+    Stage sa, sb;
+    auto load_stage = [&](long s, Stage &x) {
+        s = s < s1 ? s : s1 - 1;
 #pragma unroll
-        for (int c = 0; c < PT; ++c) ra[c] = rb[c];
-        fetch(u + 3, rb);
-        float fk[BBW];
+        for (int c = 0; c < NQ; ++c) x.gv[c] = qsrc[c][s * VPS];
+        const int pr = (int)(s / PPS);
+        const int kb = pairs[2 * pr], mb = pairs[2 * pr + 1];
+        const int dk = (int)(s % PPS) * SS;
 #pragma unroll
-        for (int bb = 0; bb < BBW; ++bb) { fk[bb] = fk1[bb]; fk1[bb] = fk2[bb]; }
-        load_fk(u + 2, fk2);
-        const int pr = (int)(u >> 4);
-        if (pr != cur_pair) {
-            cur_pair = pr;
-            const int mb = pairs[2 * pr + 1];
+        for (int bb = 0; bb < BBW; ++bb) {
+            const fkvec v = *reinterpret_cast<const fkvec *>(fkb + kb * bstride + bb * 32 * kBlk + dk);
+#pragma unroll
+            for (int d = 0; d < SS; ++d) x.fk[bb][d] = v[d];
+            const float4 *src = reinterpret_cast<const float4 *>(fmb + mb * bstride + bb * 32 * kBlk);
+            x.fm[bb][0] = src[0];
+            x.fm[bb][1] = src[1];
+        }
+    };
+    auto stash = [&](int slot, const Stage &x) {
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) sA[slot][threadIdx.x + 256 * c] = x.gv[c];
+    };
+    auto compute = [&](int slot, const Stage &x) {
+#pragma unroll
+        for (int d = 0; d < SS; ++d) {
+            opx8 Ah[IBW], Al[IBW];
+#pragma unroll
+            for (int ib = 0; ib < IBW; ++ib) {
+                Ah[ib] = __builtin_bit_cast(opx8, sA[slot][ib * VPS + d * 128 + lane]);
+                Al[ib] = __builtin_bit_cast(opx8, sA[slot][ib * VPS + d * 128 + 64 + lane]);
+            }
 #pragma unroll
             for (int bb = 0; bb < BBW; ++bb) {
-                const float4 *src = reinterpret_cast<const float4 *>(
-                    fop + ((long)mb * bpad + brow0 + bb * 32 + r) * kBlk + 8 * hb);
-                const float4 x0 = src[0], x1 = src[1];
-                fm[bb][0] = x0.x; fm[bb][1] = x0.y; fm[bb][2] = x0.z; fm[bb][3] = x0.w;
-                fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
-            }
-        }
-        opx8 ph[BBW], pl[BBW];
+                const float fmv[8] = {x.fm[bb][0].x, x.fm[bb][0].y, x.fm[bb][0].z, x.fm[bb][0].w,
+                                      x.fm[bb][1].x, x.fm[bb][1].y, x.fm[bb][1].z, x.fm[bb][1].w};
+                opx8 ph, pl;
 #pragma unroll
-        for (int bb = 0; bb < BBW; ++bb)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float pv = fk[bb] * fm[bb][j];
-                const op_t h = (op_t)pv;
-                ph[bb][j] = h;
-                pl[bb][j] = (op_t)(pv - (float)h);
-            }
-        opx8 Ah[IBW], Al[IBW];
-#pragma unroll
-        for (int ib = 0; ib < IBW; ++ib) {
-            Ah[ib] = __builtin_bit_cast(opx8, sA[slot][ib * 128 + lane]);
-            Al[ib] = __builtin_bit_cast(opx8, sA[slot][ib * 128 + 64 + lane]);
-        }
-        // three products, smallest first; consecutive MFMAs hit different
-        // accumulators
-#pragma unroll
-        for (int t = 0; t < 3; ++t)
-#pragma unroll
-            for (int bb = 0; bb < BBW; ++bb)
-#pragma unroll
-                for (int ib = 0; ib < IBW; ++ib) {
-                    const opx8 &a = t == 0 ? pl[bb] : ph[bb];
-                    const opx8 &bm = t == 1 ? Al[ib] : Ah[ib];
-                    if constexpr (F16)
-                        acc[bb][ib] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bm, acc[bb][ib], 0, 0, 0);
-                    else
-                        acc[bb][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bm, acc[bb][ib], 0, 0, 0);
+                for (int j = 0; j < 8; ++j) {
+                    const float pv = x.fk[bb][d] * fmv[j];
+                    const op_t h = (op_t)pv;
+                    ph[j] = h;
+                    pl[j] = (op_t)(pv - (float)h);
                 }
+                // three products, smallest first
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+#pragma unroll
+                    for (int ib = 0; ib < IBW; ++ib) {
+                        const opx8 &av = t == 0 ? pl : ph;
+                        const opx8 &bv = t == 1 ? Al[ib] : Ah[ib];
+                        if constexpr (F16)
+                            acc[bb][ib] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[bb][ib], 0, 0, 0);
+                        else
+                            acc[bb][ib] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[bb][ib], 0, 0, 0);
+                    }
+            }
+        }
+    };
+
+    // Pairs of super-steps with no exit between them (a conditional exit
+    // would let the compiler sink the prefetch below it); an odd last one is
+    // done after the loop from stage a and slot 0, which then hold it.
+    if (s0 < s1) load_stage(s0, sa);
+    // loss-rate tiles of this workgroup while those loads are in flight
+    // (through the LDS of the ring, which is free until the first stash)
+    rate_tiles_of(rargs, nrate, blockIdx.x, gridDim.x, reinterpret_cast<double *>(&sA[0][0]));
+    if (s0 < s1) stash(0, sa);
+    __syncthreads();
+    long s = s0;
+    // (the tensor pointer is not restrict-qualified: loads through it are
+    // then not moved down to their use in stash)
+    for (; s + 1 < s1; s += 2) {
+        load_stage(s + 1, sb);
+        __builtin_amdgcn_sched_barrier(0);      // keep the prefetch ahead of the MFMAs
+        compute(0, sa);
+        __builtin_amdgcn_sched_barrier(0);
+        stash(1, sb);
+        __syncthreads();
+        load_stage(s + 2, sa);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(1, sb);
+        __builtin_amdgcn_sched_barrier(0);
+        stash(0, sa);
         __syncthreads();
     }
+    if (s < s1) compute(0, sa);
     float *dst = part + (long)sp * bpad * ipad;
 #pragma unroll
     for (int ib = 0; ib < IBW; ++ib) {
@@ -655,62 +795,6 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3_lds(
                 const int row = brow0 + bb * 32 + 8 * (e >> 2) + 4 * hb + (e & 3);
                 dst[(long)row * ipad + col] = acc[bb][ib][e];
             }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Loss rates rate[b][i] = sum_j R[i][j] f_bj in FP64 on v_mfma_f64_16x16x4f64.
-// Workgroup = one 16 (b) x 16 (i) output tile; its 4 waves take 4
-// consecutive j ranges and their accumulators are added in the fixed order
-// 0+1+2+3.  Operand/result layout of the instruction: A[row][k] at lane
-// row + 16k, B[k][col] at lane col + 16k, D[row][col] at lane
-// col + 16 (row % 4), register row / 4.
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-constexpr int kRateT = 16;
-__global__ __launch_bounds__(256) void k_rate(const double *__restrict__ RT,
-                                              const double *__restrict__ f, int n, int B,
-                                              double *__restrict__ rate)
-{
-    __shared__ double red[3][4][64];
-    const int b0 = blockIdx.x * kRateT, i0 = blockIdx.y * kRateT;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int nsteps = (n + 3) / 4;                         // K steps of 4
-    const int per = (nsteps + 3) / 4;
-    const int s0 = wave * per, s1 = min(nsteps, s0 + per);
-    const int b = b0 + lr, i = i0 + lr;
-    const double *frow = f + (long)(b < B ? b : 0) * n;
-    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-    int st = s0;
-    for (; st + 4 <= s1; st += 4) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int j = 4 * (st + u) + lk;
-            av[u] = (b < B && j < n) ? frow[j] : 0.0;
-            bv[u] = (i < n && j < n) ? RT[(long)j * n + i] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
-    }
-    for (; st < s1; ++st) {
-        const int j = 4 * st + lk;
-        const double av = (b < B && j < n) ? frow[j] : 0.0;
-        const double bv = (i < n && j < n) ? RT[(long)j * n + i] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
-    if (wave > 0)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[wave - 1][r][lane] = acc[r];
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const double v = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
-            const int bo = b0 + lk + 4 * r, io = i0 + lr;
-            if (bo < B && io < n) rate[(long)bo * n + io] = v;
-        }
     }
 }
 
@@ -746,8 +830,59 @@ __device__ void block_sum(double (&v)[NV], double *lds)
     __syncthreads();
 }
 
-// FP64 epilogue, one wave per distribution (4 per workgroup), PER grid
-// points per lane (App. C):
+template <int NV>
+__device__ void block_max(double (&v)[NV], double *lds)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = wave_max(v[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        v[j] = fmax(fmax(fmax(lds[j], lds[NV + j]), lds[2 * NV + j]), lds[3 * NV + j]);
+    __syncthreads();
+}
+
+// Stepper inputs of one slot, loaded at the start of the epilogue so that
+// their latency overlaps that of the split partials.
+template <int PER>
+struct StepIn {
+    double x[PER], acc[PER], xs[PER], nx[PER];
+};
+
+template <int PER>
+__device__ void load_step_inputs(const StepArgs &A, int b, int n, StepIn<PER> &in)
+{
+    const long row = (long)b * n;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        in.x[q] = in.acc[q] = in.xs[q] = in.nx[q] = 0.0;
+        if (i >= n) continue;
+        if (A.mode == kStepRK4) {
+            in.x[q] = A.x[row + i];
+            if (A.stage > 1) in.acc[q] = A.acc[row + i];
+        } else if (A.mode == kStepHeunPred) {
+            in.x[q] = A.x[row + i];
+            in.nx[q] = (i + 1 < n) ? A.x[row + i + 1] : 0.0;
+        } else if (A.mode == kStepHeunCorr) {
+            in.xs[q] = A.xs[row + i];
+            in.nx[q] = (i + 1 < n) ? A.xs[row + i + 1] : 0.0;
+            in.x[q] = A.x[row + i];
+            in.acc[q] = A.acc[row + i];
+        }
+    }
+}
+
+template <int PER>
+__device__ void step_update(const StepArgs &A, int b, int n, const double (&out)[PER],
+                            const StepIn<PER> &in, double *lds);
+
+// FP64 epilogue, one 256-thread workgroup per distribution, PER grid points
+// per thread (element i = thread + 256 q), App. C:
 //   gain = sum of the split partials (fixed order; FP16 scales undone),
 //   C_raw = gain - f * rate,
 //   xi_i = |f_i|/f_max above 1e-12, and the 2x2 system for the correction
@@ -756,9 +891,9 @@ __device__ void block_sum(double (&v)[NV], double *lds)
 //   beta = beta' in the paper's E-form), C_proj = C_raw - xi (alpha' + beta' K),
 //   and the diagnostics of eqs. app_epsilon_definition and
 //   app_projection_relative_correction.
-template <int PER>
-__device__ void step_update(const StepArgs &A, int b, int n, const double (&out)[PER], int lane);
-
+// All loads of a thread (partials, rates, stepper state) are issued before
+// the first reduction; the block reductions add the four waves in a fixed
+// order, so the result of a distribution does not depend on B.
 template <typename PT, int PER>
 __global__ __launch_bounds__(256) void k_epilogue(
     const PT *__restrict__ part, int nsplit, long split_stride, int ld_b,
@@ -768,12 +903,21 @@ __global__ __launch_bounds__(256) void k_epilogue(
     double mass, int n, int B, int project, double *__restrict__ C, double *__restrict__ diag,
     StepArgs step, const double *__restrict__ ext, double eta)
 {
-    const int lane = threadIdx.x & 63;
-    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (b >= B) return;                      // whole wave; no block barriers below
+    __shared__ double red[4 * 12];
+    const int b = blockIdx.x;
     const double *fb = f + (long)b * n;
+    StepIn<PER> in;
+    load_step_inputs<PER>(step, b, n, in);
+    double hv[PER], kv[PER], ev[PER];          // grid constants, loaded up front
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        hv[q] = i < n ? h[i] : 0.0;
+        kv[q] = i < n ? K[i] : 0.0;
+        ev[q] = i < n ? E[i] : 0.0;
+    }
     double fv[PER], craw[PER], xi[PER];
-    double fmaxv = 0.0, rmax = 0.0, gmax = 0.0, flag = 0.0;
+    double mx[4] = {0.0, 0.0, 0.0, 0.0};      // f_max, largest rate, largest |gain|, input flag
     double inv_s2 = 1.0;
     if (fscale) {
         const double sc = fscale[b];
@@ -781,129 +925,137 @@ __global__ __launch_bounds__(256) void k_epilogue(
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = lane + 64 * q;
+        const int i = threadIdx.x + 256 * q;
         fv[q] = 0.0;
         craw[q] = 0.0;
         if (i < n) {
             const double x = fb[i];
             fv[q] = x;
-            if (!isfinite(x)) flag = fmax(flag, 1.0);
-            else if (x < 0.0) flag = fmax(flag, 0.5);
-            fmaxv = fmax(fmaxv, fabs(x));
+            if (!isfinite(x)) mx[3] = fmax(mx[3], 1.0);
+            else if (x < 0.0) mx[3] = fmax(mx[3], 0.5);
+            mx[0] = fmax(mx[0], fabs(x));
             if (ext) {
                 // exact form: four split sums per row, layout [split][B][4][n]
                 double a4[4] = {0.0, 0.0, 0.0, 0.0};
-                for (int sp = 0; sp < nsplit; ++sp)
+                for (int sp0 = 0; sp0 < nsplit; sp0 += 4) {
+                    double v[4][4];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) a4[c] += ext[(((long)sp * B + b) * 4 + c) * n + i];
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            v[u][c] = (sp0 + u < nsplit)
+                                          ? ext[(((long)(sp0 + u) * B + b) * 4 + c) * n + i] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) a4[c] += v[u][c];
+                }
                 const double gq = (1.0 + eta * x) * (a4[0] + eta * a4[3]);
                 const double lq = x * (a4[1] + eta * a4[2] + eta * eta * a4[3]);
-                rmax = fmax(rmax, a4[1]);
-                gmax = fmax(gmax, fabs(gq));
+                mx[1] = fmax(mx[1], a4[1]);
+                mx[2] = fmax(mx[2], fabs(gq));
                 craw[q] = gq - lq;
             } else {
-                // split partials: loads issued 8 at a time, added in split order
+                // split partials: 16 loads in flight, added in split order
                 const PT *pp = part + (long)b * ld_b + i;
-                double g = 0.0;
-                int sp = 0;
-                for (; sp + 8 <= nsplit; sp += 8) {
-                    double v[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) v[u] = (double)pp[(sp + u) * split_stride];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) g += v[u];
-                }
-                for (; sp < nsplit; ++sp) g += (double)pp[sp * split_stride];
-                if (fscale) g *= inv_s2 / (double)rscale[i];
                 const double rt = rate[(long)b * n + i];
-                rmax = fmax(rmax, rt);
-                gmax = fmax(gmax, fabs(g));
+                double g = 0.0;
+                for (int sp0 = 0; sp0 < nsplit; sp0 += 16) {
+                    PT v[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        v[u] = (sp0 + u < nsplit) ? pp[(long)(sp0 + u) * split_stride] : (PT)0;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) g += (double)v[u];
+                }
+                if (fscale) g *= inv_s2 / (double)rscale[i];
+                mx[1] = fmax(mx[1], rt);
+                mx[2] = fmax(mx[2], fabs(g));
                 craw[q] = g - x * rt;
             }
         }
     }
-    fmaxv = wave_max(fmaxv);
-    rmax = wave_max(rmax);
-    gmax = wave_max(gmax);
-    flag = wave_max(flag);
-    double s0 = 0, s1 = 0, b00 = 0, b01 = 0, b11 = 0, an = 0, ae = 0, se = 0, num = 0;
+    block_max<4>(mx, red);
+    const double fmaxv = mx[0];
+    // s0, s1, b00, b01, b11, sum h|C|, sum hE|C|, sum hEC, number
+    double sm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = lane + 64 * q;
+        const int i = threadIdx.x + 256 * q;
         xi[q] = 0.0;
         if (i < n) {
-            const double hi = h[i], ki = K[i], ei = E[i];
+            const double hi = hv[q], ki = kv[q], ei = ev[q];
             const double r = fmaxv > 0.0 ? fabs(fv[q]) / fmaxv : 0.0;
             xi[q] = r > 1e-12 ? r : 0.0;
-            s0 += hi * craw[q];
-            s1 += hi * ki * craw[q];
-            b00 += hi * xi[q];
-            b01 += hi * ki * xi[q];
-            b11 += hi * ki * ki * xi[q];
-            an += hi * fabs(craw[q]);
-            ae += hi * ei * fabs(craw[q]);
-            se += hi * ei * craw[q];
-            num += hi * fv[q];
+            sm[0] += hi * craw[q];
+            sm[1] += hi * ki * craw[q];
+            sm[2] += hi * xi[q];
+            sm[3] += hi * ki * xi[q];
+            sm[4] += hi * ki * ki * xi[q];
+            sm[5] += hi * fabs(craw[q]);
+            sm[6] += hi * ei * fabs(craw[q]);
+            sm[7] += hi * ei * craw[q];
+            sm[8] += hi * fv[q];
         }
     }
-    s0 = wave_sum(s0); s1 = wave_sum(s1);
-    b00 = wave_sum(b00); b01 = wave_sum(b01); b11 = wave_sum(b11);
-    an = wave_sum(an); ae = wave_sum(ae); se = wave_sum(se); num = wave_sum(num);
+    block_sum<9>(sm, red);
+    const double s0 = sm[0], s1 = sm[1], b00 = sm[2], b01 = sm[3], b11 = sm[4];
+    const double an = sm[5], ae = sm[6], se = sm[7], num = sm[8];
     double al = 0.0, be = 0.0;
     const double det = b00 * b11 - b01 * b01;
     if (project && det != 0.0 && isfinite(det)) {
         al = (s0 * b11 - s1 * b01) / det;
         be = (s1 * b00 - s0 * b01) / det;
     }
-    double t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0, bad = 0.0;
+    double tt[6] = {0, 0, 0, 0, 0, 0};
+    double bad[1] = {0.0};
     double out[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = lane + 64 * q;
+        const int i = threadIdx.x + 256 * q;
         out[q] = 0.0;
         if (i < n) {
-            const double hi = h[i], ei = E[i];
-            const double cp = craw[q] - xi[q] * (al + be * K[i]);
+            const double hi = hv[q], ei = ev[q];
+            const double cp = craw[q] - xi[q] * (al + be * kv[q]);
             const double d = fabs(cp - craw[q]);
-            t0 += hi * cp;
-            t1 += hi * ei * cp;
-            t2 += hi * fabs(cp);
-            t3 += hi * ei * fabs(cp);
-            t4 += hi * d;
-            t5 += hi * ei * d;
+            tt[0] += hi * cp;
+            tt[1] += hi * ei * cp;
+            tt[2] += hi * fabs(cp);
+            tt[3] += hi * ei * fabs(cp);
+            tt[4] += hi * d;
+            tt[5] += hi * ei * d;
             out[q] = project ? cp : craw[q];
-            if (!isfinite(out[q])) bad = 1.0;
+            if (!isfinite(out[q])) bad[0] = 1.0;
         }
     }
     if (step.mode != kStepNone) {
-        step_update<PER>(step, b, n, out, lane);
+        step_update<PER>(step, b, n, out, in, red);
         return;
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = lane + 64 * q;
+        const int i = threadIdx.x + 256 * q;
         if (i < n) C[(long)b * n + i] = out[q];
     }
     if (diag) {
-        t0 = wave_sum(t0); t1 = wave_sum(t1); t2 = wave_sum(t2);
-        t3 = wave_sum(t3); t4 = wave_sum(t4); t5 = wave_sum(t5);
-        bad = wave_max(bad);
-        if (lane == 0) {
+        block_sum<6>(tt, red);
+        block_max<1>(bad, red);
+        if (threadIdx.x == 0) {
             double *d = diag + (long)b * KXG_NDIAG;
             d[0] = al - be * mass;
             d[1] = be;
             d[2] = an > 0.0 ? s0 / an : 0.0;
             d[3] = ae > 0.0 ? se / ae : 0.0;
-            d[4] = t2 > 0.0 ? t0 / t2 : 0.0;
-            d[5] = t3 > 0.0 ? t1 / t3 : 0.0;
-            d[6] = an > 0.0 ? t4 / an : 0.0;
-            d[7] = ae > 0.0 ? t5 / ae : 0.0;
-            d[8] = rmax;
-            d[9] = gmax;
+            d[4] = tt[2] > 0.0 ? tt[0] / tt[2] : 0.0;
+            d[5] = tt[3] > 0.0 ? tt[1] / tt[3] : 0.0;
+            d[6] = an > 0.0 ? tt[4] / an : 0.0;
+            d[7] = ae > 0.0 ? tt[5] / ae : 0.0;
+            d[8] = mx[1];
+            d[9] = mx[2];
             double st = 0.0;
-            if (flag >= 1.0) st += 1.0;
-            else if (flag > 0.0) st += 2.0;
-            if (bad > 0.0) st += 4.0;
+            if (mx[3] >= 1.0) st += 1.0;
+            else if (mx[3] > 0.0) st += 2.0;
+            if (bad[0] > 0.0) st += 4.0;
             d[10] = st;
             d[11] = num;
         }
@@ -911,47 +1063,83 @@ __global__ __launch_bounds__(256) void k_epilogue(
 }
 
 
-// Stepper update of slot b from the operator output `out` (lane-strided,
-// element i = lane + 64 q), Sec. 4.2: RK4 stage, or Heun predictor
+// GEMM operand of the next operator call from the new f of slot b (element
+// i = thread + 256 q), in the layouts and with the FP16 scaling of k_prep;
+// the padding (grid points n.. and rows beyond the batch) keeps the zeros
+// written by k_prep at the start of the run.
+template <int PER>
+__device__ void write_operand(const StepArgs &A, int b, int n, const double (&nf)[PER],
+                              double *lds)
+{
+    float sc = 1.0f;
+    if (A.scale16) {
+        double m[1] = {0.0};
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if ((int)threadIdx.x + 256 * q < n) m[0] = fmax(m[0], fabs(nf[q]));
+        block_max<1>(m, lds);
+        if (m[0] > 0.0 && isfinite(m[0])) sc = (float)ldexp(1.0, 7 - (int)ceil(log2(m[0])));
+        if (threadIdx.x == 0) A.fscale[b] = sc;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        if (i >= n) continue;
+        const float x = (float)nf[q] * sc;
+        const int blk = i / kBlk, d = i % kBlk;
+        A.fop[((long)blk * A.bpad + b) * kBlk + d] = x;
+        A.fpar[(((long)blk * A.bpad + b) * 2 + (d & 1)) * 8 + (d >> 1)] = x;
+    }
+}
+
+// Stepper update of slot b from the operator output `out` (element
+// i = thread + 256 q), Sec. 4.2: RK4 stage, or Heun predictor
 // x* = x + dt k1, or Heun corrector x_new = x + dt (k1 + k2)/2 with the
 // predictor-corrector error err = max |x_new - x*| / (atol + rtol
 // max(|x|, |x_new|)), acceptance err <= 1 (always in replay mode) and
 // dt *= clamp(safety err^-1/2, fac_lo, fac_hi), clipped to end at t_end.
-// Every lane reaches the same decision (butterfly reductions); lane 0
+// Every thread reaches the same decision (block reductions); thread 0
 // writes the slot record.
 template <int PER>
-__device__ void step_update(const StepArgs &A, int b, int n, const double (&out)[PER], int lane)
+__device__ void step_update(const StepArgs &A, int b, int n, const double (&out)[PER],
+                            const StepIn<PER> &in, double *lds)
 {
     SlotDev &S = A.sl[b];
     const int running = S.status == 0;
     const long row = (long)b * n;
     const double dt = S.dt, u = S.t;
+    double nf[PER];                            // the next operator input
     if (A.mode == kStepRK4) {
         const double lam = S.lam / S.hi_scale;
-        double bad = 0.0;
+        double bad[1] = {0.0};
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int i = lane + 64 * q;
+            const int i = threadIdx.x + 256 * q;
+            nf[q] = 0.0;
             if (i >= n) continue;
-            const double xv = A.x[row + i];
-            if (!running) { A.fb[row + i] = xv; continue; }
-            const double k = lam * out[q];
-            if (A.stage == 1) { A.acc[row + i] = k; A.fb[row + i] = xv + 0.5 * dt * k; }
-            else if (A.stage == 2) { A.acc[row + i] += 2.0 * k; A.fb[row + i] = xv + 0.5 * dt * k; }
-            else if (A.stage == 3) { A.acc[row + i] += 2.0 * k; A.fb[row + i] = xv + dt * k; }
-            else {
-                const double xn = xv + dt / 6.0 * (A.acc[row + i] + k);
-                A.x[row + i] = xn;
-                A.fb[row + i] = xn;
-                if (!isfinite(xn)) bad = 1.0;
+            const double xv = in.x[q];
+            double v = xv;
+            if (running) {
+                const double k = lam * out[q];
+                if (A.stage == 1) { A.acc[row + i] = k; v = xv + 0.5 * dt * k; }
+                else if (A.stage == 2) { A.acc[row + i] = in.acc[q] + 2.0 * k; v = xv + 0.5 * dt * k; }
+                else if (A.stage == 3) { A.acc[row + i] = in.acc[q] + 2.0 * k; v = xv + dt * k; }
+                else {
+                    v = xv + dt / 6.0 * (in.acc[q] + k);
+                    A.x[row + i] = v;
+                    if (!isfinite(v)) bad[0] = 1.0;
+                }
             }
+            A.fb[row + i] = v;
+            nf[q] = v;
         }
+        if (A.write_op) write_operand<PER>(A, b, n, nf, lds);
         if (A.stage == 4) {
-            bad = wave_max(bad);
-            if (lane == 0 && running) {
+            block_max<1>(bad, lds);
+            if (threadIdx.x == 0 && running) {
                 S.t = u + dt;
                 S.steps += 1;
-                if (bad > 0.0) S.status = -1;
+                if (bad[0] > 0.0) S.status = -1;
                 else if (S.t >= S.tend * (1.0 - 1e-14) || (S.maxsteps > 0 && S.steps >= S.maxsteps))
                     S.status = 1;
                 else if (S.t + dt > S.tend) S.dt = S.tend - S.t;
@@ -962,40 +1150,46 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
     if (A.mode == kStepHeunPred) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int i = lane + 64 * q;
+            const int i = threadIdx.x + 256 * q;
+            nf[q] = 0.0;
             if (i >= n) continue;
-            const double xv = A.x[row + i];
-            if (!running) { A.xs[row + i] = xv; continue; }
-            const double nx = (i + 1 < n) ? A.x[row + i + 1] : 0.0;
-            const double k = rhs_u(A.expansion, xv, nx, out[q], A.p[i], A.dp[i], S.lam, S.hi_scale, u);
+            const double xv = in.x[q];
+            if (!running) {
+                // f of a stopped slot is left as it is (f of x at its last t)
+                A.xs[row + i] = xv;
+                nf[q] = A.expansion ? g_to_f(xv, A.p[i], u) : xv;
+                continue;
+            }
+            const double k = rhs_u(A.expansion, xv, in.nx[q], out[q], A.p[i], A.dp[i], S.lam, S.hi_scale, u);
             A.acc[row + i] = k;
             const double v = xv + dt * k;
             A.xs[row + i] = v;
-            A.fb[row + i] = A.expansion ? g_to_f(v, A.p[i], u + dt) : v;
+            nf[q] = A.expansion ? g_to_f(v, A.p[i], u + dt) : v;
+            A.fb[row + i] = nf[q];
         }
+        if (A.write_op) write_operand<PER>(A, b, n, nf, lds);
         return;
     }
     // Heun corrector and control
     double xn[PER];
-    double err = 0.0, nonfin = 0.0;
+    double ev[2] = {0.0, 0.0};              // err, non-finite flag
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = lane + 64 * q;
+        const int i = threadIdx.x + 256 * q;
         xn[q] = 0.0;
         if (i >= n || !running) continue;
-        const double xsv = A.xs[row + i];
-        const double nx = (i + 1 < n) ? A.xs[row + i + 1] : 0.0;
-        const double k2 = rhs_u(A.expansion, xsv, nx, out[q], A.p[i], A.dp[i], S.lam, S.hi_scale, u + dt);
-        const double x0 = A.x[row + i];
-        const double v = x0 + 0.5 * dt * (A.acc[row + i] + k2);
+        const double xsv = in.xs[q];
+        const double k2 = rhs_u(A.expansion, xsv, in.nx[q], out[q], A.p[i], A.dp[i], S.lam, S.hi_scale, u + dt);
+        const double x0 = in.x[q];
+        const double v = x0 + 0.5 * dt * (in.acc[q] + k2);
         xn[q] = v;
         const double sc = S.atol + A.rtol * fmax(fabs(x0), fabs(v));
         const double e = fabs(v - xsv) / sc;
-        if (!isfinite(v)) nonfin = 1.0;
-        err = fmax(err, isfinite(e) ? e : 1e300);
+        if (!isfinite(v)) ev[1] = 1.0;
+        ev[0] = fmax(ev[0], isfinite(e) ? e : 1e300);
     }
-    err = wave_max(err);
-    nonfin = wave_max(nonfin);
+    block_max<2>(ev, lds);
+    const double err = ev[0], nonfin = ev[1];
     int accept = 0, status = S.status, steps = S.steps, rej = S.rejected;
     double tnew = u, dtnew = dt, outflow = S.outflow;
     if (running) {
@@ -1004,7 +1198,8 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
         } else {
             accept = (!A.adapt) || err <= 1.0;
             if (accept) {
-                if (A.expansion) outflow += 0.5 * dt * (A.x[row] + A.xs[row]);
+                // g_0 of the state and of the predictor, held by thread 0
+                if (A.expansion) outflow += 0.5 * dt * (in.x[0] + in.xs[0]);
                 tnew = u + dt;
                 steps += 1;
             } else {
@@ -1025,16 +1220,19 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = lane + 64 * q;
+        const int i = threadIdx.x + 256 * q;
+        nf[q] = 0.0;
         if (i >= n) continue;
-        double v = A.x[row + i];
+        double v = in.x[q];
         if (accept) {
             v = xn[q];
             A.x[row + i] = v;
         }
-        A.fb[row + i] = A.expansion ? g_to_f(v, A.p[i], tnew) : v;
+        nf[q] = A.expansion ? g_to_f(v, A.p[i], tnew) : v;
+        A.fb[row + i] = nf[q];
     }
-    if (lane == 0 && running) {
+    if (A.write_op) write_operand<PER>(A, b, n, nf, lds);
+    if (threadIdx.x == 0 && running) {
         S.t = tnew;
         S.dt = dtnew;
         S.steps = steps;
@@ -1052,7 +1250,7 @@ hipError_t launch_epilogue(const PT *part, int nsplit, long split_stride, int ld
                            const double *ext = nullptr, double eta = 0.0)
 {
     const int n = k.n;
-    const dim3 grid((B + 3) / 4), blk(256);
+    const dim3 grid(B), blk(256);
     StepArgs sa{};
     if (step) sa = *step;
     else sa.mode = kStepNone;
@@ -1060,19 +1258,26 @@ hipError_t launch_epilogue(const PT *part, int nsplit, long split_stride, int ld
     hipLaunchKernelGGL((k_epilogue<PT, P>), grid, blk, 0, s, part, nsplit, split_stride, ld_b, \
                        fscale, rscale, rate, f, k.d_h, k.d_K, k.d_E, k.mass, n, B, project, C, \
                        diag, sa, ext, eta)
-    if (n <= 64) KXG_EPI(1);
-    else if (n <= 128) KXG_EPI(2);
-    else if (n <= 256) KXG_EPI(4);
-    else if (n <= 512) KXG_EPI(8);
-    else KXG_EPI(16);
+    if (n <= 256) KXG_EPI(1);
+    else if (n <= 512) KXG_EPI(2);
+    else KXG_EPI(4);
 #undef KXG_EPI
     return hipGetLastError();
 }
 
+RateArgs rate_args(const kxg_kernel &k, const double *f, int B, double *rate)
+{
+    return RateArgs{k.d_RT, f, k.n, B, rate, (B + kRateT - 1) / kRateT};
+}
+
+int rate_tiles(const kxg_kernel &k, int B)
+{
+    return ((B + kRateT - 1) / kRateT) * ((k.n + kRateT - 1) / kRateT);
+}
+
 hipError_t launch_rate(const kxg_kernel &k, const double *f, int B, double *rate, hipStream_t s)
 {
-    const dim3 grid((B + kRateT - 1) / kRateT, (k.n + kRateT - 1) / kRateT);
-    hipLaunchKernelGGL(k_rate, grid, dim3(256), 0, s, k.d_RT, f, k.n, B, rate);
+    hipLaunchKernelGGL(k_rate, dim3(rate_tiles(k, B)), dim3(256), 0, s, rate_args(k, f, B, rate));
     return hipGetLastError();
 }
 
@@ -1153,18 +1358,74 @@ void free_workspace(Workspace &ws)
     ws = Workspace{};
 }
 
+// Which contraction a call takes: the HBM stream (FP64; FP32 on handles
+// built for tiny batches, so that on one handle the path and the rounding
+// of a row do not depend on how many rows share the call), the LDS-shared
+// 16-bit GEMM for large batches, or the register GEMM.  bpad = rows of the
+// GEMM operand (0 for the stream).
+struct Path {
+    bool stream, lds;
+    int bpad;
+};
+static Path path_of(const kxg_kernel &k, int prec, int B)
+{
+    Path p{false, false, 0};
+    if (prec == KXG_F64 || (prec == KXG_F32 && B <= 4 && k.b_cap <= 4 && k.d_A32)) {
+        p.stream = true;
+        return p;
+    }
+    if ((prec == KXG_BF16X3 || prec == KXG_F16X3) && B >= kLdsMinB) {
+        constexpr int TILE = 4 * KXG_LDS_BBW * 32;
+        p.lds = true;
+        p.bpad = div_up(B, TILE) * TILE;
+        return p;
+    }
+    const int tile = 32 * gemm_bbw(B);
+    p.bpad = div_up(B, tile) * tile;
+    return p;
+}
+
+// GEMM operand of f for the path of (prec, B); a no-op for the stream path.
+kxg_status prep_operands(const kxg_kernel &k, const Workspace &ws, int prec, const double *f,
+                         int B, hipStream_t s)
+{
+    const Path P = path_of(k, prec, B);
+    if (P.stream) return KXG_OK;
+    hipLaunchKernelGGL(k_prep, dim3(P.bpad), dim3(256), 0, s, f, B, k.n, k.geo.nb, P.bpad,
+                       prec == KXG_F16X3 ? 1 : 0, ws.fop, ws.fpar, ws.fscale);
+    KXG_TRY_HIP(hipGetLastError());
+    return KXG_OK;
+}
+
 kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const double *f,
                      int B, double *C, uint32_t flags, double *diag, hipStream_t s,
-                     const StepArgs *step)
+                     const StepArgs *step_in)
 {
     const int n = k.n;
     const Geometry &g = k.geo;
+    // Operand hand-over between stepper calls applies to the GEMM paths only;
+    // they re-enable it below with the layout of their operand.
+    StepArgs sa{};
+    const StepArgs *step = nullptr;
+    if (step_in) {
+        sa = *step_in;
+        sa.write_op = 0;
+        step = &sa;
+    }
+    const bool op_ready = step_in && step_in->op_ready;
+    auto hand_over = [&](int bpad, int f16) {
+        if (!step_in || !step_in->write_op) return;
+        sa.write_op = 1;
+        sa.fop = ws.fop;
+        sa.fpar = ws.fpar;
+        sa.fscale = ws.fscale;
+        sa.nb = g.nb;
+        sa.bpad = bpad;
+        sa.scale16 = f16;
+    };
     // the loss-rate buffer [b_cap][n] sits at the end of the workspace
     double *rate = reinterpret_cast<double *>(static_cast<char *>(ws.part) + ws.part_bytes) -
                    (size_t)ws.b_cap * n;
-    // FP32 takes the stream kernel only on handles built for tiny batches, so
-    // that on any one handle the path (and the rounding) of a row does not
-    // depend on how many rows share the call.
     const bool exact = (flags & (KXG_INTERP_LOG | KXG_STAT_BOSE | KXG_STAT_FERMI)) != 0;
     if (exact) {
         const bool logi = (flags & KXG_INTERP_LOG) != 0;
@@ -1204,9 +1465,9 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
                                             eta));
         return KXG_OK;
     }
-    const bool use_stream = prec == KXG_F64 || (prec == KXG_F32 && B <= 4 && k.b_cap <= 4 && k.d_A32);
+    const Path P = path_of(k, prec, B);
     const int project = (flags & KXG_PROJECT) ? 1 : 0;
-    if (use_stream) {
+    if (P.stream) {
         const int ns = stream_splits(n);
         const long n2 = (long)n * n;
         const bool dbl = prec == KXG_F64;
@@ -1241,27 +1502,31 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         return KXG_OK;
     }
     const bool f16 = prec == KXG_F16X3;
-    if ((prec == KXG_BF16X3 || prec == KXG_F16X3) && B >= kLdsMinB) {
+    if (P.lds) {
         // large batch: 16-bit GEMM with the A operand shared through LDS
         constexpr int BBW = KXG_LDS_BBW, IBW = KXG_LDS_IBW, TILE = 4 * BBW * 32;
-        const int bpad = div_up(B, TILE) * TILE;
+        const int bpad = P.bpad;
         const int nbt = bpad / TILE, nit = div_up(g.nib, IBW);
         const int splits = k.lds_splits;
-        hipLaunchKernelGGL(k_prep, dim3(bpad), dim3(256), 0, s, f, B, n, g.nb, bpad, f16 ? 1 : 0,
-                           ws.fop, ws.fpar, ws.fscale);
+        if (!op_ready)
+            hipLaunchKernelGGL(k_prep, dim3(bpad), dim3(256), 0, s, f, B, n, g.nb, bpad, f16 ? 1 : 0,
+                               ws.fop, ws.fpar, ws.fscale);
+        hand_over(bpad, f16 ? 1 : 0);
         float *part = static_cast<float *>(ws.part);
+        const dim3 grid(nbt * nit * splits);
+        const int nrate = rate_tiles(k, B);
+        const RateArgs ra = rate_args(k, f, B, rate);
         profile_mark_begin(s);
         if (f16)
-            hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, true>), dim3(nbt * nit * splits), dim3(256), 0, s,
+            hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, true>), grid, dim3(256), 0, s,
                                k.d_Gh, ws.fop, k.d_pairs, g.npairs, g.nib, bpad, g.ipad, nbt, nit,
-                               splits, g.dksteps, part);
+                               splits, g.dksteps, part, nrate, ra);
         else
-            hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, false>), dim3(nbt * nit * splits), dim3(256), 0, s,
+            hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, false>), grid, dim3(256), 0, s,
                                k.d_Gbf, ws.fop, k.d_pairs, g.npairs, g.nib, bpad, g.ipad, nbt, nit,
-                               splits, g.dksteps, part);
+                               splits, g.dksteps, part, nrate, ra);
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
-        KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
         KXG_TRY_HIP(launch_epilogue<float>(part, splits, (long)bpad * g.ipad, g.ipad,
                                            f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr, rate,
                                            f, k, B, project, C, diag, step, s));
@@ -1270,20 +1535,25 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     // GEMM path
     const int bbw = gemm_bbw(B);
     const int tile = 32 * bbw;
-    const int bpad = div_up(B, tile) * tile;
+    const int bpad = P.bpad;
     const int nbt = bpad / tile;
     const int splits = k.gemm_splits;
     const int nwg = nbt * g.nib * splits;
-    hipLaunchKernelGGL(k_prep, dim3(bpad), dim3(256), 0, s, f, B, n, g.nb, bpad, f16 ? 1 : 0,
-                       ws.fop, ws.fpar, ws.fscale);
+    if (!op_ready)
+        hipLaunchKernelGGL(k_prep, dim3(bpad), dim3(256), 0, s, f, B, n, g.nb, bpad, f16 ? 1 : 0,
+                           ws.fop, ws.fpar, ws.fscale);
+    hand_over(bpad, f16 ? 1 : 0);
     float *part = static_cast<float *>(ws.part);
+    const dim3 grid(nwg);
+    const int nrate = rate_tiles(k, B);
+    const RateArgs ra = rate_args(k, f, B, rate);
     profile_mark_begin(s);
 #define KXG_GEMM_F32(W)                                                                  \
-    hipLaunchKernelGGL(k_gemm_f32<W>, dim3(nwg), dim3(256), 0, s, k.d_G32, ws.fop, ws.fpar, \
-                       k.d_pairs, g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part)
+    hipLaunchKernelGGL((k_gemm_f32<W, KXG_F32_SS, KXG_F32_NST>), grid, dim3(256), 0, s, k.d_G32, ws.fop, ws.fpar, \
+                       k.d_pairs, g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part, nrate, ra)
 #define KXG_GEMM_X3(W, H, GP)                                                              \
-    hipLaunchKernelGGL((k_gemm_x3<W, H>), dim3(nwg), dim3(256), 0, s, GP, ws.fop, k.d_pairs, \
-                       g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part)
+    hipLaunchKernelGGL((k_gemm_x3<W, H>), grid, dim3(256), 0, s, GP, ws.fop, k.d_pairs, \
+                       g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part, nrate, ra)
     if (prec == KXG_F32) {
         if (bbw == 1) KXG_GEMM_F32(1); else if (bbw == 2) KXG_GEMM_F32(2); else KXG_GEMM_F32(4);
     } else if (prec == KXG_BF16X3) {
@@ -1299,7 +1569,6 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
 #undef KXG_GEMM_X3
     profile_mark_end(s);
     KXG_TRY_HIP(hipGetLastError());
-    KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
     KXG_TRY_HIP(launch_epilogue<float>(part, splits, (long)bpad * g.ipad, g.ipad,
                                        f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr, rate, f,
                                        k, B, project, C, diag, step, s));

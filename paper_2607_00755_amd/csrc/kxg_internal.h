@@ -95,6 +95,8 @@ struct StepArgs;
 kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const double *f,
                      int B, double *C, uint32_t flags, double *diag, hipStream_t s,
                      const StepArgs *step = nullptr);
+kxg_status prep_operands(const kxg_kernel &k, const Workspace &ws, int prec, const double *f,
+                         int B, hipStream_t s);
 kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws);
 void free_workspace(Workspace &ws);
 hipError_t launch_moments(const kxg_kernel &k, const double *f, int B, double *out,

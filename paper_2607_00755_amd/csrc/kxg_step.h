@@ -19,7 +19,7 @@ struct SlotDev {
 };
 
 // Stepper update applied by the evaluation epilogue to the operator output
-// of every slot (one wave per slot), instead of writing C.
+// of every slot (one workgroup per slot), instead of writing C.
 enum StepMode { kStepNone = 0, kStepRK4 = 1, kStepHeunPred = 2, kStepHeunCorr = 3 };
 struct StepArgs {
     SlotDev *sl;
@@ -30,6 +30,11 @@ struct StepArgs {
     const double *p, *dp;
     int mode, stage, expansion, adapt;
     double rtol, safety, fac_lo, fac_hi, dt_min;
+    // GEMM operand of the next operator call, written by the epilogue from
+    // the new f (write_op) instead of by a separate pass; op_ready: the
+    // operand of this call was written that way (or by an explicit pass).
+    float *fop, *fpar, *fscale;
+    int nb, bpad, scale16, write_op, op_ready;
 };
 
 // f on the physical grid from the comoving state g = a^3 p^3 f at u = ln a.
