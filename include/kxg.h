@@ -110,6 +110,21 @@ int32_t kxg_kernel_n(const kxg_kernel *k);
  * admission by memory footprint.  0 if the precision was not built. */
 size_t kxg_kernel_bytes(const kxg_kernel *k, int32_t prec);
 
+/* Shape of the contraction a handle runs (for reporting work and bytes).
+ * The block-packed operand of the batched FP32 path has pair blocks of
+ * 32 rows i x 16 x 16 (k, m) (off-diagonal ones carrying both orderings);
+ * the blocks that the kinematic cuts (App. B) leave all zero are dropped. */
+typedef struct {
+    int32_t n;
+    int64_t packed_blocks;    /* (i-block, pair) blocks of the full packing   */
+    int64_t nonzero_blocks;   /* blocks kept in the FP32 operand (0 if no FP32) */
+    int32_t gemm_units;       /* FP32 GEMM work units (K ranges) per batch tile */
+    int32_t max_slots;        /* most K partials of an i-block                  */
+} kxg_kernel_info;
+
+/* Fill *out for handle k.  Errors: KXG_EINVAL (null argument). */
+kxg_status kxg_kernel_stats(const kxg_kernel *k, kxg_kernel_info *out);
+
 /* Copy the FP64 tensors to host memory: A_host [n][n][n] (m fastest),
  * R_host [n][n].  Either may be NULL.  Synchronous. */
 kxg_status kxg_kernel_export(const kxg_kernel *k, double *A_host, double *R_host);

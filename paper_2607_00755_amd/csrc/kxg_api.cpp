@@ -151,7 +151,8 @@ static void release(kxg_kernel *k)
 {
     if (!k) return;
     void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_A32,
-                    k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs, k->d_JL, k->d_invdK};
+                    k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs, k->d_JL, k->d_invdK,
+                    k->d_pairs_c, k->d_cib, k->d_units, k->d_nslot};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     free_workspace(k->ws);
@@ -176,6 +177,107 @@ struct kxg_stepper {
     int g_batch = -1;
     hipStream_t g_stream = nullptr;
 };
+
+// FP32 GEMM over non-zero blocks only.  The kinematic cuts leave whole
+// 32 x 16 x 16 blocks of the packed operand at zero (about a quarter at
+// n = 256, most of them at large i); they are dropped from the operand and
+// from the K loop, which is exact.  The remaining blocks of each i-block are
+// cut into work units of about equal length (in super-steps of kF32SS dk
+// steps), so that one GEMM launch at the handle's largest batch has about
+// KXG_GEMM_WG_TARGET workgroups; the partial of unit j of an i-block goes to
+// K slot j.  The units depend on the handle only, so the reduction order of
+// a row does not depend on the batch.
+static kxg_status build_compact_f32(kxg_kernel *k, int b_cap, hipStream_t s)
+{
+    const Geometry &g = k->geo;
+    const size_t nflags = (size_t)g.nib * g.npairs;
+    unsigned char *d_flags = nullptr;
+    kxg_status st = dalloc(&d_flags, nflags);
+    if (st != KXG_OK) return st;
+    std::vector<unsigned char> flags(nflags);
+    hipError_t e = launch_block_nz(*k, d_flags, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), d_flags, nflags, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_flags);
+    if (e != hipSuccess) { set_error("kxg_kernel_build: %s", hipGetErrorString(e)); return KXG_EHIP; }
+    std::vector<int> pairs_c, cib, cnt(g.nib, 0), first(g.nib, 0);
+    for (int ib = 0; ib < g.nib; ++ib) {
+        first[ib] = (int)cib.size();
+        int q = 0;
+        for (int kb = 0; kb < g.nb; ++kb)
+            for (int mb = kb; mb < g.nb; ++mb, ++q)
+                if (flags[(size_t)ib * g.npairs + q]) {
+                    pairs_c.push_back(kb);
+                    pairs_c.push_back(mb);
+                    cib.push_back(ib);
+                    ++cnt[ib];
+                }
+    }
+    k->ncomp = (long)cib.size();
+    // work units
+    constexpr int pps = kBlk / kF32SS;               // super-steps per block
+    const int bbw = b_cap <= 32 ? 1 : (b_cap <= 64 ? 2 : 4);
+    const int nbt = div_up(b_cap, 32 * bbw);
+    const long total = k->ncomp * pps;
+    // units in all: one launch of at most KXG_GEMM_WG_TARGET workgroups
+    // (a second round of workgroups would double the time of its CUs), and
+    // at least 4 super-steps a wave
+    int target = std::max(1, KXG_GEMM_WG_TARGET / nbt);
+    target = (int)std::max<long>(1, std::min<long>(target, total / (4 * kWaves)));
+    // share them out in proportion to each i-block's blocks (largest
+    // remainders), at least one per non-empty i-block
+    std::vector<int> nu(g.nib, 0);
+    {
+        int given = 0;
+        std::vector<std::pair<double, int>> rem;
+        for (int ib = 0; ib < g.nib; ++ib) {
+            if (cnt[ib] == 0) continue;
+            const double share = (double)target * cnt[ib] * pps / (double)total;
+            nu[ib] = std::max(1, (int)share);
+            given += nu[ib];
+            rem.push_back({share - (int)share, ib});
+        }
+        std::sort(rem.begin(), rem.end(), [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
+            return a.first > b.first || (a.first == b.first && a.second < b.second);
+        });
+        for (size_t q = 0; q < rem.size() && given < target; ++q, ++given) ++nu[rem[q].second];
+    }
+    std::vector<int> units, nslot(g.nib, 0);
+    for (int ib = 0; ib < g.nib; ++ib) {
+        const long len = (long)cnt[ib] * pps, base = (long)first[ib] * pps;
+        if (len == 0) continue;
+        const int nu_ib = (int)std::min<long>(nu[ib], len);
+        for (int j = 0; j < nu_ib; ++j) {
+            units.push_back(ib);
+            units.push_back(j);
+            units.push_back((int)(base + len * j / nu_ib));
+            units.push_back((int)(base + len * (j + 1) / nu_ib));
+        }
+        nslot[ib] = nu_ib;
+    }
+    k->nunits = (int)(units.size() / 4);
+    k->maxslots = 0;
+    for (int v : nslot) k->maxslots = std::max(k->maxslots, v);
+    const size_t gsz = (size_t)std::max<long>(1, k->ncomp) * kBlk * 512;
+    st = dalloc(&k->d_G32, gsz);
+    if (st == KXG_OK) st = dalloc(&k->d_pairs_c, std::max<size_t>(2, pairs_c.size()));
+    if (st == KXG_OK) st = dalloc(&k->d_cib, std::max<size_t>(1, cib.size()));
+    if (st == KXG_OK) st = dalloc(&k->d_units, std::max<size_t>(4, units.size()));
+    if (st == KXG_OK) st = dalloc(&k->d_nslot, (size_t)g.nib);
+    if (st != KXG_OK) return st;
+    e = hipSuccess;
+    if (!pairs_c.empty())
+        e = hipMemcpy(k->d_pairs_c, pairs_c.data(), pairs_c.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !cib.empty())
+        e = hipMemcpy(k->d_cib, cib.data(), cib.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !units.empty())
+        e = hipMemcpy(k->d_units, units.data(), units.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(k->d_nslot, nslot.data(), nslot.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_pack_f32(*k, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { set_error("kxg_kernel_build: %s", hipGetErrorString(e)); return KXG_EHIP; }
+    return KXG_OK;
+}
 
 extern "C" {
 
@@ -232,6 +334,7 @@ kxg_status kxg_gauss_legendre(int32_t n, double *x, double *w)
     gauss_legendre(n, x, w);
     return KXG_OK;
 }
+
 
 kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_cap,
                             void *stream, kxg_kernel **out)
@@ -321,7 +424,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     KXG_ALLOC(k->d_A64, n3);
     KXG_ALLOC(k->d_RT, n2);
     KXG_ALLOC(k->d_pairs, 2 * (size_t)g.npairs);
-    if (want32) { KXG_ALLOC(k->d_A32, n3); KXG_ALLOC(k->d_G32, packed); }
+    if (want32) { KXG_ALLOC(k->d_A32, n3); }
     if (wantbf) { KXG_ALLOC(k->d_Gbf, 2 * packed); }
     if (wanth) { KXG_ALLOC(k->d_Gh, 2 * packed); KXG_ALLOC(k->d_hrow, (size_t)g.ipad); }
     if (want_jl) { KXG_ALLOC(k->d_JL, n3); KXG_ALLOC(k->d_invdK, (size_t)n); }
@@ -377,10 +480,15 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
         release(k);
         return KXG_EHIP;
     }
+    if (want32) {
+        st = build_compact_f32(k, b_cap, s);
+        if (st != KXG_OK) { release(k); return st; }
+    }
     st = alloc_workspace(*k, b_cap, k->ws);
     if (st != KXG_OK) { release(k); return st; }
     k->bytes[KXG_F64] = (n3 + n2) * sizeof(double) + (want_jl ? n3 * sizeof(uint16_t) : 0);
-    if (want32) k->bytes[KXG_F32] = (n3 + packed) * sizeof(float) + n2 * sizeof(double);
+    if (want32)
+        k->bytes[KXG_F32] = (n3 + (size_t)k->ncomp * kBlk * 512) * sizeof(float) + n2 * sizeof(double);
     if (wantbf) k->bytes[KXG_BF16X3] = 2 * packed * sizeof(uint16_t) + n2 * sizeof(double);
     if (wanth) k->bytes[KXG_F16X3] = 2 * packed * sizeof(uint16_t) + n2 * sizeof(double);
     *out = k;
@@ -401,6 +509,18 @@ size_t kxg_kernel_bytes(const kxg_kernel *k, int32_t prec)
     for (int q = 1; q < 4; ++q)
         if (k->bytes[q]) tot += k->bytes[q] - (size_t)k->n * k->n * sizeof(double);
     return tot;
+}
+
+kxg_status kxg_kernel_stats(const kxg_kernel *k, kxg_kernel_info *out)
+{
+    g_err[0] = 0;
+    if (!k || !out) { set_error("kxg_kernel_stats: null argument"); return KXG_EINVAL; }
+    out->n = k->n;
+    out->packed_blocks = (int64_t)k->geo.nib * k->geo.npairs;
+    out->nonzero_blocks = k->d_G32 ? k->ncomp : 0;
+    out->gemm_units = k->nunits;
+    out->max_slots = k->maxslots;
+    return KXG_OK;
 }
 
 kxg_status kxg_kernel_export(const kxg_kernel *k, double *A_host, double *R_host)

@@ -207,25 +207,45 @@ __device__ double packed_value(const double *__restrict__ A, int n, int i, int k
     return v;
 }
 
-// FP32 GEMM operand, ordered as the 32x32x2 MFMA consumes it:
-// [ib][pair][dk][half][lane][4]; lane l holds row i = ib*32 + l%32 and
-// K index 2t + l/32 of row dk of the block, t = 4*half + r.
-__global__ void k_pack_f32(int n, int npairs, int nib, const int *__restrict__ pairs,
-                           const double *__restrict__ A, float *__restrict__ G)
+// Non-zero flag of every (i-block, pair) block of the packed operand: 32
+// rows i x the 16 x 16 (k, m) block and its transpose.  Grid (pair, i-block).
+__global__ __launch_bounds__(256) void k_block_nz(int n, int npairs, const int *__restrict__ pairs,
+                                                  const double *__restrict__ A,
+                                                  unsigned char *__restrict__ flags)
 {
-    const long total = (long)nib * npairs * kBlk * 2 * 64 * 4;
+    const int pr = blockIdx.x, ib = blockIdx.y;
+    const int kb = pairs[2 * pr], mb = pairs[2 * pr + 1];
+    int any = 0;
+    for (int e = threadIdx.x; e < kIBlk * kBlk * kBlk; e += 256) {
+        const int i = ib * kIBlk + e / (kBlk * kBlk);
+        const int dk = (e / kBlk) % kBlk, dm = e % kBlk;
+        if (packed_value(A, n, i, kb, mb, dk, dm) != 0.0) any = 1;
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) flags[(long)ib * npairs + pr] = (unsigned char)(any != 0);
+}
+
+// FP32 GEMM operand, ordered as the 32x32x2 MFMA consumes it, over the
+// compacted blocks: [block c][dk][half][lane][4]; block c is pair
+// (kb, mb) = pairs_c[c] of i-block cib[c]; lane l holds row
+// i = cib*32 + l%32 and K index 2t + l/32 of row dk of the block,
+// t = 4*half + r.
+__global__ void k_pack_f32(int n, long ncomp, const int *__restrict__ pairs_c,
+                           const int *__restrict__ cib, const double *__restrict__ A,
+                           float *__restrict__ G)
+{
+    const long total = ncomp * kBlk * 2 * 64 * 4;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (long)gridDim.x * blockDim.x) {
         long t = idx;
         const int r = (int)(t % 4); t /= 4;
         const int lane = (int)(t % 64); t /= 64;
         const int half = (int)(t % 2); t /= 2;
-        const int dk = (int)(t % kBlk); t /= kBlk;
-        const int pr = (int)(t % npairs);
-        const int ib = (int)(t / npairs);
-        const int i = ib * kIBlk + (lane & 31);
+        const int dk = (int)(t % kBlk);
+        const long c = t / kBlk;
+        const int i = cib[c] * kIBlk + (lane & 31);
         const int dm = 2 * (4 * half + r) + (lane >> 5);
-        G[idx] = (float)packed_value(A, n, i, pairs[2 * pr], pairs[2 * pr + 1], dk, dm);
+        G[idx] = (float)packed_value(A, n, i, pairs_c[2 * c], pairs_c[2 * c + 1], dk, dm);
     }
 }
 
@@ -356,6 +376,23 @@ hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, hipStream_t s)
+{
+    const Geometry &g = k.geo;
+    hipLaunchKernelGGL(k_block_nz, dim3(g.npairs, g.nib), dim3(256), 0, s, k.n, g.npairs,
+                       k.d_pairs, k.d_A64, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s)
+{
+    const long tot = k.ncomp * kBlk * 2 * 64 * 4;
+    if (tot > 0)
+        hipLaunchKernelGGL(k_pack_f32, dim3(grid_for(tot)), dim3(256), 0, s, k.n, k.ncomp,
+                           k.d_pairs_c, k.d_cib, k.d_A64, k.d_G32);
+    return hipGetLastError();
+}
+
 hipError_t launch_derive(kxg_kernel &k, hipStream_t s)
 {
     const Geometry &g = k.geo;
@@ -363,11 +400,6 @@ hipError_t launch_derive(kxg_kernel &k, hipStream_t s)
     if (k.d_A32) {
         hipLaunchKernelGGL(k_to_f32, dim3(grid_for(dense)), dim3(256), 0, s, dense, k.d_A64,
                            k.d_A32);
-    }
-    if (k.d_G32) {
-        const long tot = (long)g.nib * g.npairs * kBlk * 2 * 64 * 4;
-        hipLaunchKernelGGL(k_pack_f32, dim3(grid_for(tot)), dim3(256), 0, s, k.n, g.npairs,
-                           g.nib, k.d_pairs, k.d_A64, k.d_G32);
     }
     if (k.d_Gbf) {
         const long tot = (long)g.nib * g.npairs * kBlk * 64 * 8;

@@ -33,9 +33,6 @@ inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 #define KXG_STREAM_NT 1
 #endif
 // shape of the LDS-shared 16-bit GEMM: b-blocks and i-blocks per wave
-#ifndef KXG_F32_SS
-#define KXG_F32_SS 4         // dk steps per register stage of the FP32 GEMM
-#endif
 #ifndef KXG_F32_NST
 #define KXG_F32_NST 2        // register stages of the FP32 GEMM
 #endif
@@ -408,9 +405,10 @@ __device__ void store_tile(floatx16 (&acc)[BBW], float *lds, float *__restrict__
     }
 }
 
-// FP32 GEMM on v_mfma_f32_32x32x2f32.  Workgroup = (batch tile of BBW*32
-// distributions, i-block of 32 rows, K split); its 4 waves take 4
-// consecutive sub-ranges of the split's dk steps.  Per dk step (one row k of a
+// FP32 GEMM on v_mfma_f32_32x32x2f32 over the non-zero blocks of the packed
+// operand.  Workgroup = (batch tile of BBW*32 distributions, work unit =
+// i-block of 32 rows and a range of its blocks); its 4 waves take 4
+// consecutive sub-ranges of the unit's dk steps.  Per dk step (one row k of a
 // (kb, mb) block, 16 K values) a wave issues 8*BBW MFMAs; the A operand
 // (F2 = f_k f_m) is one multiply per MFMA, the B operand (packed tensor)
 // comes straight from memory in MFMA order.
@@ -429,30 +427,29 @@ struct F32Stage {
     float4 fm[BBW][2];         // f_m of the (kb, mb) block in parity order
 };
 
-template <int BBW, int SS = 2, int NST = 2>
+template <int BBW, int SS = kF32SS, int NST = 2>
 __global__ __launch_bounds__(256, 2) void k_gemm_f32(
     const float *__restrict__ G, const float *__restrict__ fop, const float *__restrict__ fpar,
-    const int *__restrict__ pairs, int npairs, int bpad, int ipad, int nbt, int splits,
-    long dksteps, float *__restrict__ part, int nrate, RateArgs rargs)
+    const int *__restrict__ pairs, const int *__restrict__ units, int bpad, int ipad, int nbt,
+    float *__restrict__ part, int nrate, RateArgs rargs)
 {
     static_assert(SS == 2 || SS == 4, "super-step of 2 or 4 dk steps");
     static_assert(NST == 2 || NST == 3, "2 or 3 register stages");
     typedef float fkvec __attribute__((ext_vector_type(SS)));
     constexpr int PPS = kBlk / SS;                 // super-steps per (kb, mb) pair
     __shared__ __align__(16) float lds[3 * BBW * 16 * 64];
-    int L = xcd_logical(blockIdx.x, gridDim.x);
-    const int bt = L % nbt;
-    L /= nbt;
-    const int sp = L % splits;
-    const int ib = L / splits;
+    static_assert(SS == kF32SS, "work units are counted in super-steps of kF32SS dk steps");
+    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int bt = L % nbt, u = L / nbt;
+    // work unit: i-block, K slot and range of (compacted) super-steps
+    const int ib = units[4 * u], sp = units[4 * u + 1];
+    const long ub = units[4 * u + 2], ue = units[4 * u + 3];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int r = lane & 31, hb = lane >> 5;
-    const long w = (long)sp * kWaves + wave, nw = (long)splits * kWaves;
-    const long nss = dksteps / SS;                 // super-steps (dksteps is a multiple of 16)
-    const long s0 = w * nss / nw, s1 = (w + 1) * nss / nw;
+    const long s0 = ub + (ue - ub) * wave / kWaves, s1 = ub + (ue - ub) * (wave + 1) / kWaves;
     const int brow0 = bt * BBW * 32;
-    const float *Gi = G + (long)ib * npairs * kBlk * 512;
+    const float *Gi = G;
     const float *fkb = fop + (long)(brow0 + r) * kBlk;
     const float *fmb = fpar + ((long)(brow0 + r) * 2 + hb) * 8;
     const long bstride = (long)bpad * kBlk;        // one 16-block of the grid, all rows
@@ -896,7 +893,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
 // order, so the result of a distribution does not depend on B.
 template <typename PT, int PER>
 __global__ __launch_bounds__(256) void k_epilogue(
-    const PT *__restrict__ part, int nsplit, long split_stride, int ld_b,
+    const PT *__restrict__ part, int nsplit, const int *__restrict__ nslot, long split_stride, int ld_b,
     const float *__restrict__ fscale, const float *__restrict__ rscale,
     const double *__restrict__ rate, const double *__restrict__ f,
     const double *__restrict__ h, const double *__restrict__ K, const double *__restrict__ E,
@@ -959,12 +956,13 @@ __global__ __launch_bounds__(256) void k_epilogue(
                 // split partials: 16 loads in flight, added in split order
                 const PT *pp = part + (long)b * ld_b + i;
                 const double rt = rate[(long)b * n + i];
+                const int ns = nslot ? nslot[i / kIBlk] : nsplit;   // K slots of this row
                 double g = 0.0;
-                for (int sp0 = 0; sp0 < nsplit; sp0 += 16) {
+                for (int sp0 = 0; sp0 < ns; sp0 += 16) {
                     PT v[16];
 #pragma unroll
                     for (int u = 0; u < 16; ++u)
-                        v[u] = (sp0 + u < nsplit) ? pp[(long)(sp0 + u) * split_stride] : (PT)0;
+                        v[u] = (sp0 + u < ns) ? pp[(long)(sp0 + u) * split_stride] : (PT)0;
 #pragma unroll
                     for (int u = 0; u < 16; ++u) g += (double)v[u];
                 }
@@ -1243,7 +1241,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
 }
 
 template <typename PT>
-hipError_t launch_epilogue(const PT *part, int nsplit, long split_stride, int ld_b,
+hipError_t launch_epilogue(const PT *part, int nsplit, const int *nslot, long split_stride, int ld_b,
                            const float *fscale, const float *rscale, const double *rate,
                            const double *f, const kxg_kernel &k, int B, int project, double *C,
                            double *diag, const StepArgs *step, hipStream_t s,
@@ -1255,7 +1253,7 @@ hipError_t launch_epilogue(const PT *part, int nsplit, long split_stride, int ld
     if (step) sa = *step;
     else sa.mode = kStepNone;
 #define KXG_EPI(P)                                                                             \
-    hipLaunchKernelGGL((k_epilogue<PT, P>), grid, blk, 0, s, part, nsplit, split_stride, ld_b, \
+    hipLaunchKernelGGL((k_epilogue<PT, P>), grid, blk, 0, s, part, nsplit, nslot, split_stride, ld_b, \
                        fscale, rscale, rate, f, k.d_h, k.d_K, k.d_E, k.mass, n, B, project, C, \
                        diag, sa, ext, eta)
     if (n <= 256) KXG_EPI(1);
@@ -1326,7 +1324,7 @@ kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws)
     size_t need = (size_t)stream_splits(n) * b_cap * n * sizeof(double);
     if (k.d_JL) need = (size_t)stream_splits(n) * b_cap * 4 * n * sizeof(double);
     if (k.d_G32 || k.d_Gbf || k.d_Gh) {
-        const size_t g = (size_t)k.gemm_splits * bpad * k.geo.ipad * sizeof(float);
+        const size_t g = (size_t)std::max(k.gemm_splits, k.maxslots) * bpad * k.geo.ipad * sizeof(float);
         if (g > need) need = g;
     }
     if ((k.d_Gbf || k.d_Gh) && b_cap >= kLdsMinB) {
@@ -1460,7 +1458,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
 #undef KXG_SX
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
-        KXG_TRY_HIP(launch_epilogue<double>(ext, nsplit, 0, 0, nullptr, nullptr, rate, f, k, B,
+        KXG_TRY_HIP(launch_epilogue<double>(ext, nsplit, nullptr, 0, 0, nullptr, nullptr, rate, f, k, B,
                                             (flags & KXG_PROJECT) ? 1 : 0, C, diag, step, s, ext,
                                             eta));
         return KXG_OK;
@@ -1497,7 +1495,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
         KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
-        KXG_TRY_HIP(launch_epilogue<double>(part, nsplit, (long)B * n, n, nullptr, nullptr, rate,
+        KXG_TRY_HIP(launch_epilogue<double>(part, nsplit, nullptr, (long)B * n, n, nullptr, nullptr, rate,
                                             f, k, B, project, C, diag, step, s));
         return KXG_OK;
     }
@@ -1527,7 +1525,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
                                splits, g.dksteps, part, nrate, ra);
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
-        KXG_TRY_HIP(launch_epilogue<float>(part, splits, (long)bpad * g.ipad, g.ipad,
+        KXG_TRY_HIP(launch_epilogue<float>(part, splits, nullptr, (long)bpad * g.ipad, g.ipad,
                                            f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr, rate,
                                            f, k, B, project, C, diag, step, s));
         return KXG_OK;
@@ -1549,8 +1547,8 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     const RateArgs ra = rate_args(k, f, B, rate);
     profile_mark_begin(s);
 #define KXG_GEMM_F32(W)                                                                  \
-    hipLaunchKernelGGL((k_gemm_f32<W, KXG_F32_SS, KXG_F32_NST>), grid, dim3(256), 0, s, k.d_G32, ws.fop, ws.fpar, \
-                       k.d_pairs, g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part, nrate, ra)
+    hipLaunchKernelGGL((k_gemm_f32<W, kF32SS, KXG_F32_NST>), dim3(nbt * k.nunits), dim3(256), 0, s, \
+                       k.d_G32, ws.fop, ws.fpar, k.d_pairs_c, k.d_units, bpad, g.ipad, nbt, part, nrate, ra)
 #define KXG_GEMM_X3(W, H, GP)                                                              \
     hipLaunchKernelGGL((k_gemm_x3<W, H>), grid, dim3(256), 0, s, GP, ws.fop, k.d_pairs, \
                        g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part, nrate, ra)
@@ -1569,7 +1567,9 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
 #undef KXG_GEMM_X3
     profile_mark_end(s);
     KXG_TRY_HIP(hipGetLastError());
-    KXG_TRY_HIP(launch_epilogue<float>(part, splits, (long)bpad * g.ipad, g.ipad,
+    const bool f32 = prec == KXG_F32;
+    KXG_TRY_HIP(launch_epilogue<float>(part, f32 ? k.maxslots : splits, f32 ? k.d_nslot : nullptr,
+                                       (long)bpad * g.ipad, g.ipad,
                                        f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr, rate, f,
                                        k, B, project, C, diag, step, s));
     return KXG_OK;

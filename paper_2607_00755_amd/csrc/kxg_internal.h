@@ -28,6 +28,7 @@ constexpr int kIBlk = 32;            // output rows (i) per MFMA tile
 constexpr int kBRows = 32;           // distributions per MFMA tile
 constexpr int kWaves = 4;            // waves per GEMM workgroup (split K)
 constexpr int kLdsMinB = 512;        // batches from this size use the LDS-shared 16-bit GEMM
+constexpr int kF32SS = 4;            // dk steps per super-step of the FP32 GEMM (work units)
 
 // Geometry of the block-packed GEMM operand: the (k,m) plane is cut into
 // 16x16 blocks; only blocks with kb <= mb are stored (off-diagonal blocks hold
@@ -71,6 +72,15 @@ struct kxg_kernel {
     uint16_t *d_Gh = nullptr;    // packed GEMM operand, FP16 hi/lo (row-scaled)
     float *d_hrow = nullptr;     // [ipad] FP16 row scales (powers of two)
     int *d_pairs = nullptr;      // [npairs][2] (kb, mb)
+    // FP32 GEMM over the non-zero (i-block, pair) blocks only: the pairs of
+    // each i-block whose 32 x 16 x 16 block of A (both orderings) has a
+    // non-zero, i-block by i-block; G32 holds these blocks in that order.
+    int *d_pairs_c = nullptr;    // [ncomp][2] (kb, mb)
+    int *d_cib = nullptr;        // [ncomp] i-block of each compacted pair
+    int *d_units = nullptr;      // [nunits][4] (i-block, slot, first, end super-step)
+    int *d_nslot = nullptr;      // [nib] K slots (partials) of each i-block
+    long ncomp = 0;              // non-zero (i-block, pair) blocks
+    int nunits = 0, maxslots = 0;
     uint16_t *d_JL = nullptr;    // [n][n][n] interpolation bracket j_L (0xFFFF: cut)
     double *d_invdK = nullptr;   // [n] 1 / (K_{j+1} - K_j) (0 for the last point)
     kxg::Geometry geo;
@@ -87,6 +97,8 @@ hipError_t launch_build_A(const kxg_kernel &k, const double *d_xmu, const double
                           hipStream_t s);
 hipError_t launch_build_R(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_derive(kxg_kernel &k, hipStream_t s);
+hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, hipStream_t s);
+hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s);
 
 struct StepArgs;

@@ -37,7 +37,7 @@ EXPORTED = [
     "kxg_gauss_legendre", "kxg_stepper_create", "kxg_stepper_free", "kxg_stepper_set",
     "kxg_stepper_release", "kxg_stepper_advance", "kxg_stepper_set_dt",
     "kxg_stepper_query", "kxg_stepper_get", "kxg_stepper_save", "kxg_stepper_load",
-    "kxg_last_error", "kxg_profile_begin", "kxg_profile_end",
+    "kxg_last_error", "kxg_profile_begin", "kxg_profile_end", "kxg_kernel_stats",
 ]
 
 
@@ -52,6 +52,12 @@ class Grid(ctypes.Structure):
                 ("dp", ctypes.POINTER(ctypes.c_double)), ("mass", ctypes.c_double),
                 ("g_dof", ctypes.c_double), ("m2", ctypes.c_double),
                 ("n_mu", ctypes.c_int32), ("quad", ctypes.c_int32)]
+
+
+class KernelInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("packed_blocks", ctypes.c_int64),
+                ("nonzero_blocks", ctypes.c_int64), ("gemm_units", ctypes.c_int32),
+                ("max_slots", ctypes.c_int32)]
 
 
 class StepperParams(ctypes.Structure):
@@ -97,6 +103,7 @@ def lib():
         L.kxg_kernel_bytes.argtypes = [_vp, ctypes.c_int32]
         L.kxg_kernel_bytes.restype = ctypes.c_size_t
         L.kxg_kernel_export.argtypes = [_vp, _dp, _dp]
+        L.kxg_kernel_stats.argtypes = [_vp, ctypes.POINTER(KernelInfo)]
         L.kxg_kernel_grid.argtypes = [_vp, _dp, _dp, _dp, _dp]
         L.kxg_eval.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctypes.c_uint32,
                                _vp, _vp]
@@ -202,6 +209,14 @@ class Kernel:
 
     def bytes(self, prec: int = -1) -> int:
         return int(lib().kxg_kernel_bytes(self._h, prec))
+
+    def stats(self) -> dict:
+        """kxg_kernel_stats: blocks of the packed operand, kept blocks, units."""
+        info = KernelInfo()
+        _check(lib().kxg_kernel_stats(self._h, ctypes.byref(info)))
+        return {"n": info.n, "packed_blocks": info.packed_blocks,
+                "nonzero_blocks": info.nonzero_blocks, "gemm_units": info.gemm_units,
+                "max_slots": info.max_slots}
 
     def export(self):
         n = self.n

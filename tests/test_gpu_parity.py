@@ -485,3 +485,24 @@ def test_expansion_conserves_comoving_number_on_device(dev):
         if q["status"] != 0:
             break
     assert q["status"] == 1
+
+
+def test_zero_block_skipping_matches_oracle_tensor(dev):
+    """The FP32 operand keeps exactly the (i-block, pair) blocks of the
+    packed tensor that hold a non-zero weight (blocks of 32 rows i x 16 x 16
+    (k, m), both orderings), counted here from the oracle's tensor."""
+    for n in (40, 96):
+        p = inputs.log_grid(n, 1e-3, 20.0)
+        k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=64)
+        st = k.stats()
+        A = oracle.Operator(p).A != 0.0
+        nb, nib = (n + 15) // 16, (n + 31) // 32
+        sym = A | A.transpose(0, 2, 1)
+        kept = 0
+        for ib in range(nib):
+            for kb in range(nb):
+                for mb in range(kb, nb):
+                    kept += bool(sym[ib * 32:(ib + 1) * 32, kb * 16:(kb + 1) * 16,
+                                     mb * 16:(mb + 1) * 16].any())
+        assert st["packed_blocks"] == nib * nb * (nb + 1) // 2
+        assert st["nonzero_blocks"] == kept < st["packed_blocks"]
