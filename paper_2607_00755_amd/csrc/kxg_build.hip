@@ -196,14 +196,21 @@ __global__ void k_to_f32(long count, const double *__restrict__ src, float *__re
 
 // Value of the block-packed operand for output row i and pair (kb <= mb),
 // block-local (dk, dm): off-diagonal blocks carry both orderings of (k,m).
-__device__ double packed_value(const double *__restrict__ A, int n, int i, int kb, int mb,
-                               int dk, int dm)
+// The loss term is folded in: f_i sum_m R_im f_m = sum_{k,m} delta_ik R_im
+// f_k f_m, so the operand holds A'_ikm = A_ikm - delta_ik R_im and the GEMM
+// yields gain - loss directly (eq. discrete_collision_operator).
+__device__ double packed_value(const double *__restrict__ A, const double *__restrict__ RT, int n,
+                               int i, int kb, int mb, int dk, int dm)
 {
     const int k = kb * kBlk + dk, m = mb * kBlk + dm;
     if (i >= n || k >= n || m >= n) return 0.0;
     const long row = (long)i * n * n;
     double v = A[row + (long)k * n + m];
-    if (kb != mb) v += A[row + (long)m * n + k];
+    if (k == i) v -= RT[(long)m * n + i];
+    if (kb != mb) {
+        v += A[row + (long)m * n + k];
+        if (m == i) v -= RT[(long)k * n + i];
+    }
     return v;
 }
 
@@ -211,6 +218,7 @@ __device__ double packed_value(const double *__restrict__ A, int n, int i, int k
 // rows i x the 16 x 16 (k, m) block and its transpose.  Grid (pair, i-block).
 __global__ __launch_bounds__(256) void k_block_nz(int n, int npairs, const int *__restrict__ pairs,
                                                   const double *__restrict__ A,
+                                                  const double *__restrict__ RT,
                                                   unsigned char *__restrict__ flags)
 {
     const int pr = blockIdx.x, ib = blockIdx.y;
@@ -219,7 +227,7 @@ __global__ __launch_bounds__(256) void k_block_nz(int n, int npairs, const int *
     for (int e = threadIdx.x; e < kIBlk * kBlk * kBlk; e += 256) {
         const int i = ib * kIBlk + e / (kBlk * kBlk);
         const int dk = (e / kBlk) % kBlk, dm = e % kBlk;
-        if (packed_value(A, n, i, kb, mb, dk, dm) != 0.0) any = 1;
+        if (packed_value(A, RT, n, i, kb, mb, dk, dm) != 0.0) any = 1;
     }
     any = __syncthreads_or(any);
     if (threadIdx.x == 0) flags[(long)ib * npairs + pr] = (unsigned char)(any != 0);
@@ -232,7 +240,7 @@ __global__ __launch_bounds__(256) void k_block_nz(int n, int npairs, const int *
 // t = 4*half + r.
 __global__ void k_pack_f32(int n, long ncomp, const int *__restrict__ pairs_c,
                            const int *__restrict__ cib, const double *__restrict__ A,
-                           float *__restrict__ G)
+                           const double *__restrict__ RT, float *__restrict__ G)
 {
     const long total = ncomp * kBlk * 2 * 64 * 4;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -245,7 +253,7 @@ __global__ void k_pack_f32(int n, long ncomp, const int *__restrict__ pairs_c,
         const long c = t / kBlk;
         const int i = cib[c] * kIBlk + (lane & 31);
         const int dm = 2 * (4 * half + r) + (lane >> 5);
-        G[idx] = (float)packed_value(A, n, i, pairs_c[2 * c], pairs_c[2 * c + 1], dk, dm);
+        G[idx] = (float)packed_value(A, RT, n, i, pairs_c[2 * c], pairs_c[2 * c + 1], dk, dm);
     }
 }
 
@@ -263,7 +271,8 @@ __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32
 // lane l holds row i = ib*32 + l%32 and the 8 consecutive K indices
 // 8*(l/32) + j of row dk of the block.  hi = bf16(v), lo = bf16(v - hi).
 __global__ void k_pack_bf16(int n, int npairs, int nib, const int *__restrict__ pairs,
-                            const double *__restrict__ A, uint16_t *__restrict__ G)
+                            const double *__restrict__ A, const double *__restrict__ RT,
+                            uint16_t *__restrict__ G)
 {
     const long total = (long)nib * npairs * kBlk * 64 * 8;   // hi/lo written together
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -276,7 +285,7 @@ __global__ void k_pack_bf16(int n, int npairs, int nib, const int *__restrict__ 
         const int ib = (int)(t / npairs);
         const int i = ib * kIBlk + (lane & 31);
         const int dm = 8 * (lane >> 5) + j;
-        const double v = packed_value(A, n, i, pairs[2 * pr], pairs[2 * pr + 1], dk, dm);
+        const double v = packed_value(A, RT, n, i, pairs[2 * pr], pairs[2 * pr + 1], dk, dm);
         const uint16_t hi = bf16_rne((float)v);
         const uint16_t lo = bf16_rne((float)(v - (double)bf16_to_f32(hi)));
         const long base = ((((long)ib * npairs + pr) * kBlk + dk) * 2) * 64 * 8;
@@ -286,26 +295,33 @@ __global__ void k_pack_bf16(int n, int npairs, int nib, const int *__restrict__ 
 }
 
 // Power-of-two scale per output row for the FP16 operand: the largest
-// packed entry of row i (bounded by twice the row maximum of A) lands in
-// [2^13, 2^14].  One workgroup per row.
+// packed entry of row i (bounded by twice the row maximum of A plus twice
+// that of R, which is folded into the operand) lands in [2^13, 2^14].  One
+// workgroup per row.
 __global__ __launch_bounds__(256) void k_row_scale(int n, int ipad, const double *__restrict__ A,
+                                                   const double *__restrict__ RT,
                                                    float *__restrict__ scale)
 {
-    __shared__ double red[256];
+    __shared__ double red[2][256];
     const int i = blockIdx.x;
-    double mx = 0.0;
+    double ma = 0.0, mr = 0.0;
     if (i < n) {
         const double *row = A + (long)i * n * n;
-        for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) mx = fmax(mx, fabs(row[e]));
+        for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) ma = fmax(ma, fabs(row[e]));
+        for (int j = threadIdx.x; j < n; j += blockDim.x) mr = fmax(mr, fabs(RT[(long)j * n + i]));
     }
-    red[threadIdx.x] = mx;
+    red[0][threadIdx.x] = ma;
+    red[1][threadIdx.x] = mr;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double top = 2.0 * red[0];
+        const double top = 2.0 * (red[0][0] + red[1][0]);
         float sc = 1.0f;
         if (top > 0.0) {
             const int e = 14 - (int)ceil(log2(top));
@@ -317,8 +333,8 @@ __global__ __launch_bounds__(256) void k_row_scale(int n, int ipad, const double
 
 // FP16 hi/lo operand (same order as the BF16 one) of the row-scaled tensor.
 __global__ void k_pack_f16(int n, int npairs, int nib, const int *__restrict__ pairs,
-                           const double *__restrict__ A, const float *__restrict__ rs,
-                           uint16_t *__restrict__ G)
+                           const double *__restrict__ A, const double *__restrict__ RT,
+                           const float *__restrict__ rs, uint16_t *__restrict__ G)
 {
     const long total = (long)nib * npairs * kBlk * 64 * 8;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -331,7 +347,7 @@ __global__ void k_pack_f16(int n, int npairs, int nib, const int *__restrict__ p
         const int ib = (int)(t / npairs);
         const int i = ib * kIBlk + (lane & 31);
         const int dm = 8 * (lane >> 5) + j;
-        const double v = packed_value(A, n, i, pairs[2 * pr], pairs[2 * pr + 1], dk, dm) *
+        const double v = packed_value(A, RT, n, i, pairs[2 * pr], pairs[2 * pr + 1], dk, dm) *
                          (double)rs[i];
         const _Float16 hi = (_Float16)(float)v;
         const _Float16 lo = (_Float16)(float)(v - (double)(float)hi);
@@ -380,7 +396,7 @@ hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, hipStream_
 {
     const Geometry &g = k.geo;
     hipLaunchKernelGGL(k_block_nz, dim3(g.npairs, g.nib), dim3(256), 0, s, k.n, g.npairs,
-                       k.d_pairs, k.d_A64, flags);
+                       k.d_pairs, k.d_A64, k.d_RT, flags);
     return hipGetLastError();
 }
 
@@ -389,7 +405,7 @@ hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s)
     const long tot = k.ncomp * kBlk * 2 * 64 * 4;
     if (tot > 0)
         hipLaunchKernelGGL(k_pack_f32, dim3(grid_for(tot)), dim3(256), 0, s, k.n, k.ncomp,
-                           k.d_pairs_c, k.d_cib, k.d_A64, k.d_G32);
+                           k.d_pairs_c, k.d_cib, k.d_A64, k.d_RT, k.d_G32);
     return hipGetLastError();
 }
 
@@ -404,14 +420,14 @@ hipError_t launch_derive(kxg_kernel &k, hipStream_t s)
     if (k.d_Gbf) {
         const long tot = (long)g.nib * g.npairs * kBlk * 64 * 8;
         hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(tot)), dim3(256), 0, s, k.n, g.npairs,
-                           g.nib, k.d_pairs, k.d_A64, k.d_Gbf);
+                           g.nib, k.d_pairs, k.d_A64, k.d_RT, k.d_Gbf);
     }
     if (k.d_Gh) {
         hipLaunchKernelGGL(k_row_scale, dim3(g.ipad), dim3(256), 0, s, k.n, g.ipad, k.d_A64,
-                           k.d_hrow);
+                           k.d_RT, k.d_hrow);
         const long tot = (long)g.nib * g.npairs * kBlk * 64 * 8;
         hipLaunchKernelGGL(k_pack_f16, dim3(grid_for(tot)), dim3(256), 0, s, k.n, g.npairs,
-                           g.nib, k.d_pairs, k.d_A64, k.d_hrow, k.d_Gh);
+                           g.nib, k.d_pairs, k.d_A64, k.d_RT, k.d_hrow, k.d_Gh);
     }
     return hipGetLastError();
 }

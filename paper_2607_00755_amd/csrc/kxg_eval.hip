@@ -360,13 +360,6 @@ __device__ void rate_tile(const RateArgs &ra, int tile, double *red)
     __syncthreads();
 }
 
-// The tiles of a GEMM workgroup: g, g + ngemm, ... (done in its prologue,
-// while the first loads of its own operands are in flight).
-__device__ void rate_tiles_of(const RateArgs &ra, int ntiles, int g, int ngemm, double *red)
-{
-    for (int t = g; t < ntiles; t += ngemm) rate_tile(ra, t, red);
-}
-
 __global__ __launch_bounds__(256) void k_rate(RateArgs ra)
 {
     __shared__ double red[3 * 4 * 64];
@@ -375,33 +368,41 @@ __global__ __launch_bounds__(256) void k_rate(RateArgs ra)
 
 // Reduce the 4 waves' accumulators of a workgroup (fixed order 0+1+2+3) and
 // store the FP32 partial of this K split.  32x32 MFMA result layout: register
-// e of lane l holds row 8*(e/4) + 4*(l/32) + e%4, column l%32.
+// e of lane l holds row 8*(e/4) + 4*(l/32) + e%4, column l%32.  Every wave
+// parks its accumulators in LDS as [wave][bb][e/4][lane][4]; wave q then sums
+// registers 4q..4q+3 of all four and stores those rows.  `lds` holds
+// 4*BBW*16*64 floats.
 template <int BBW>
 __device__ void store_tile(floatx16 (&acc)[BBW], float *lds, float *__restrict__ part, int sp,
                            int bpad, int ipad, int brow0, int icol0)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (wave > 0) {
+    float4 *l4 = reinterpret_cast<float4 *>(lds);
 #pragma unroll
-        for (int bb = 0; bb < BBW; ++bb)
+    for (int bb = 0; bb < BBW; ++bb)
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                lds[(((wave - 1) * BBW + bb) * 16 + e) * 64 + lane] = acc[bb][e];
-    }
+        for (int g = 0; g < 4; ++g)
+            l4[((wave * BBW + bb) * 4 + g) * 64 + lane] =
+                make_float4(acc[bb][4 * g], acc[bb][4 * g + 1], acc[bb][4 * g + 2], acc[bb][4 * g + 3]);
     __syncthreads();
-    if (wave == 0) {
-        float *dst = part + (long)sp * bpad * ipad;
+    float *dst = part + (long)sp * bpad * ipad;
 #pragma unroll
-        for (int bb = 0; bb < BBW; ++bb)
+    for (int bb = 0; bb < BBW; ++bb) {
+        float4 v = l4[((0 * BBW + bb) * 4 + wave) * 64 + lane];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                float v = acc[bb][e];
-                v += lds[((0 * BBW + bb) * 16 + e) * 64 + lane];
-                v += lds[((1 * BBW + bb) * 16 + e) * 64 + lane];
-                v += lds[((2 * BBW + bb) * 16 + e) * 64 + lane];
-                const int row = brow0 + bb * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                dst[(long)row * ipad + icol0 + (lane & 31)] = v;
-            }
+        for (int w = 1; w < 4; ++w) {
+            const float4 x = l4[((w * BBW + bb) * 4 + wave) * 64 + lane];
+            v.x += x.x;
+            v.y += x.y;
+            v.z += x.z;
+            v.w += x.w;
+        }
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int row = brow0 + bb * 32 + 8 * wave + 4 * (lane >> 5) + c;
+            dst[(long)row * ipad + icol0 + (lane & 31)] = vv[c];
+        }
     }
 }
 
@@ -431,13 +432,13 @@ template <int BBW, int SS = kF32SS, int NST = 2>
 __global__ __launch_bounds__(256, 2) void k_gemm_f32(
     const float *__restrict__ G, const float *__restrict__ fop, const float *__restrict__ fpar,
     const int *__restrict__ pairs, const int *__restrict__ units, int bpad, int ipad, int nbt,
-    float *__restrict__ part, int nrate, RateArgs rargs)
+    float *__restrict__ part)
 {
     static_assert(SS == 2 || SS == 4, "super-step of 2 or 4 dk steps");
     static_assert(NST == 2 || NST == 3, "2 or 3 register stages");
     typedef float fkvec __attribute__((ext_vector_type(SS)));
     constexpr int PPS = kBlk / SS;                 // super-steps per (kb, mb) pair
-    __shared__ __align__(16) float lds[3 * BBW * 16 * 64];
+    __shared__ __align__(16) float lds[4 * BBW * 16 * 64];
     static_assert(SS == kF32SS, "work units are counted in super-steps of kF32SS dk steps");
     const int L = xcd_logical(blockIdx.x, gridDim.x);
     const int bt = L % nbt, u = L / nbt;
@@ -506,8 +507,6 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(
 #pragma unroll
         for (int j = 0; j < NST - 1; ++j) load_stage(s0 + j, st[j]);
     }
-    // loss-rate tiles of this workgroup while those loads are in flight
-    rate_tiles_of(rargs, nrate, blockIdx.x, gridDim.x, reinterpret_cast<double *>(lds));
     long s = s0;
     for (; s + NST <= s1; s += NST) {
 #pragma unroll
@@ -531,11 +530,11 @@ template <int BBW, bool F16>
 __global__ __launch_bounds__(256, 2) void k_gemm_x3(
     const uint16_t *__restrict__ G, const float *__restrict__ fop, const int *__restrict__ pairs,
     int npairs, int bpad, int ipad, int nbt, int splits, long dksteps,
-    float *__restrict__ part, int nrate, RateArgs rargs)
+    float *__restrict__ part)
 {
     typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
     typedef typename std::conditional<F16, _Float16, __bf16>::type op_t;
-    __shared__ __align__(16) float lds[3 * BBW * 16 * 64];
+    __shared__ __align__(16) float lds[4 * BBW * 16 * 64];
     int L = xcd_logical(blockIdx.x, gridDim.x);
     const int bt = L % nbt;
     L /= nbt;
@@ -568,8 +567,6 @@ __global__ __launch_bounds__(256, 2) void k_gemm_x3(
         for (int bb = 0; bb < BBW; ++bb)
             nfk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
     }
-    // loss-rate tiles of this workgroup while the first loads are in flight
-    rate_tiles_of(rargs, nrate, blockIdx.x, gridDim.x, reinterpret_cast<double *>(lds));
     for (long u = u0; u < u1; ++u) {
         const int pr = (int)(u >> 4);
         if (pr != cur_pair) {
@@ -649,7 +646,7 @@ template <int BBW, int IBW, int SS, bool F16>
 __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_gemm_x3_lds(
     const uint16_t *G, const float *__restrict__ fop, const int *__restrict__ pairs,
     int npairs, int nib, int bpad, int ipad, int nbt, int nit, int splits, long dksteps,
-    float *__restrict__ part, int nrate, RateArgs rargs)
+    float *__restrict__ part)
 {
     typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
     typedef typename std::conditional<F16, _Float16, __bf16>::type op_t;
@@ -756,11 +753,10 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
     // Pairs of super-steps with no exit between them (a conditional exit
     // would let the compiler sink the prefetch below it); an odd last one is
     // done after the loop from stage a and slot 0, which then hold it.
-    if (s0 < s1) load_stage(s0, sa);
-    // loss-rate tiles of this workgroup while those loads are in flight
-    // (through the LDS of the ring, which is free until the first stash)
-    rate_tiles_of(rargs, nrate, blockIdx.x, gridDim.x, reinterpret_cast<double *>(&sA[0][0]));
-    if (s0 < s1) stash(0, sa);
+    if (s0 < s1) {
+        load_stage(s0, sa);
+        stash(0, sa);
+    }
     __syncthreads();
     long s = s0;
     // (the tensor pointer is not restrict-qualified: loads through it are
@@ -898,7 +894,7 @@ __global__ __launch_bounds__(256) void k_epilogue(
     const double *__restrict__ rate, const double *__restrict__ f,
     const double *__restrict__ h, const double *__restrict__ K, const double *__restrict__ E,
     double mass, int n, int B, int project, double *__restrict__ C, double *__restrict__ diag,
-    StepArgs step, const double *__restrict__ ext, double eta)
+    StepArgs step, const double *__restrict__ ext, double eta, int folded)
 {
     __shared__ double red[4 * 12];
     const int b = blockIdx.x;
@@ -953,23 +949,32 @@ __global__ __launch_bounds__(256) void k_epilogue(
                 mx[2] = fmax(mx[2], fabs(gq));
                 craw[q] = gq - lq;
             } else {
-                // split partials: 16 loads in flight, added in split order
+                // split partials: up to 32 (FP32) or 16 (FP64) loads in flight,
+                // added in split order.  With `folded` the partials already
+                // hold gain - loss (the loss term is part of the GEMM operand)
+                // and the loss rates, when given, only feed the diagnostics.
+                constexpr int U = sizeof(PT) == 4 ? 32 : 16;
                 const PT *pp = part + (long)b * ld_b + i;
-                const double rt = rate[(long)b * n + i];
+                const double rt = rate ? rate[(long)b * n + i] : 0.0;
                 const int ns = nslot ? nslot[i / kIBlk] : nsplit;   // K slots of this row
                 double g = 0.0;
-                for (int sp0 = 0; sp0 < ns; sp0 += 16) {
-                    PT v[16];
+                for (int sp0 = 0; sp0 < ns; sp0 += U) {
+                    PT v[U];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u)
+                    for (int u = 0; u < U; ++u)
                         v[u] = (sp0 + u < ns) ? pp[(long)(sp0 + u) * split_stride] : (PT)0;
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) g += (double)v[u];
+                    for (int u = 0; u < U; ++u) g += (double)v[u];
                 }
                 if (fscale) g *= inv_s2 / (double)rscale[i];
                 mx[1] = fmax(mx[1], rt);
-                mx[2] = fmax(mx[2], fabs(g));
-                craw[q] = g - x * rt;
+                if (folded) {
+                    mx[2] = fmax(mx[2], fabs(g + x * rt));
+                    craw[q] = g;
+                } else {
+                    mx[2] = fmax(mx[2], fabs(g));
+                    craw[q] = g - x * rt;
+                }
             }
         }
     }
@@ -1245,7 +1250,7 @@ hipError_t launch_epilogue(const PT *part, int nsplit, const int *nslot, long sp
                            const float *fscale, const float *rscale, const double *rate,
                            const double *f, const kxg_kernel &k, int B, int project, double *C,
                            double *diag, const StepArgs *step, hipStream_t s,
-                           const double *ext = nullptr, double eta = 0.0)
+                           const double *ext = nullptr, double eta = 0.0, int folded = 0)
 {
     const int n = k.n;
     const dim3 grid(B), blk(256);
@@ -1255,7 +1260,7 @@ hipError_t launch_epilogue(const PT *part, int nsplit, const int *nslot, long sp
 #define KXG_EPI(P)                                                                             \
     hipLaunchKernelGGL((k_epilogue<PT, P>), grid, blk, 0, s, part, nsplit, nslot, split_stride, ld_b, \
                        fscale, rscale, rate, f, k.d_h, k.d_K, k.d_E, k.mass, n, B, project, C, \
-                       diag, sa, ext, eta)
+                       diag, sa, ext, eta, folded)
     if (n <= 256) KXG_EPI(1);
     else if (n <= 512) KXG_EPI(2);
     else KXG_EPI(4);
@@ -1512,22 +1517,23 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         hand_over(bpad, f16 ? 1 : 0);
         float *part = static_cast<float *>(ws.part);
         const dim3 grid(nbt * nit * splits);
-        const int nrate = rate_tiles(k, B);
-        const RateArgs ra = rate_args(k, f, B, rate);
         profile_mark_begin(s);
         if (f16)
             hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, true>), grid, dim3(256), 0, s,
                                k.d_Gh, ws.fop, k.d_pairs, g.npairs, g.nib, bpad, g.ipad, nbt, nit,
-                               splits, g.dksteps, part, nrate, ra);
+                               splits, g.dksteps, part);
         else
             hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, false>), grid, dim3(256), 0, s,
                                k.d_Gbf, ws.fop, k.d_pairs, g.npairs, g.nib, bpad, g.ipad, nbt, nit,
-                               splits, g.dksteps, part, nrate, ra);
+                               splits, g.dksteps, part);
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
+        // the loss term is folded into the operand; loss rates only for diagnostics
+        if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
         KXG_TRY_HIP(launch_epilogue<float>(part, splits, nullptr, (long)bpad * g.ipad, g.ipad,
-                                           f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr, rate,
-                                           f, k, B, project, C, diag, step, s));
+                                           f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr,
+                                           diag ? rate : nullptr, f, k, B, project, C, diag, step, s,
+                                           nullptr, 0.0, 1));
         return KXG_OK;
     }
     // GEMM path
@@ -1543,15 +1549,13 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     hand_over(bpad, f16 ? 1 : 0);
     float *part = static_cast<float *>(ws.part);
     const dim3 grid(nwg);
-    const int nrate = rate_tiles(k, B);
-    const RateArgs ra = rate_args(k, f, B, rate);
     profile_mark_begin(s);
 #define KXG_GEMM_F32(W)                                                                  \
     hipLaunchKernelGGL((k_gemm_f32<W, kF32SS, KXG_F32_NST>), dim3(nbt * k.nunits), dim3(256), 0, s, \
-                       k.d_G32, ws.fop, ws.fpar, k.d_pairs_c, k.d_units, bpad, g.ipad, nbt, part, nrate, ra)
+                       k.d_G32, ws.fop, ws.fpar, k.d_pairs_c, k.d_units, bpad, g.ipad, nbt, part)
 #define KXG_GEMM_X3(W, H, GP)                                                              \
     hipLaunchKernelGGL((k_gemm_x3<W, H>), grid, dim3(256), 0, s, GP, ws.fop, k.d_pairs, \
-                       g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part, nrate, ra)
+                       g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part)
     if (prec == KXG_F32) {
         if (bbw == 1) KXG_GEMM_F32(1); else if (bbw == 2) KXG_GEMM_F32(2); else KXG_GEMM_F32(4);
     } else if (prec == KXG_BF16X3) {
@@ -1567,11 +1571,14 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
 #undef KXG_GEMM_X3
     profile_mark_end(s);
     KXG_TRY_HIP(hipGetLastError());
+    // the loss term is folded into the operand; loss rates only for diagnostics
+    if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
     const bool f32 = prec == KXG_F32;
     KXG_TRY_HIP(launch_epilogue<float>(part, f32 ? k.maxslots : splits, f32 ? k.d_nslot : nullptr,
                                        (long)bpad * g.ipad, g.ipad,
-                                       f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr, rate, f,
-                                       k, B, project, C, diag, step, s));
+                                       f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr,
+                                       diag ? rate : nullptr, f, k, B, project, C, diag, step, s,
+                                       nullptr, 0.0, 1));
     return KXG_OK;
 }
 
