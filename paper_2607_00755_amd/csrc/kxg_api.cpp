@@ -114,27 +114,7 @@ static void profile_clear()
 }
 
 // Workgroups aimed at per GEMM launch (at the handle's largest batch).
-#ifndef KXG_GEMM_WG_TARGET
-#define KXG_GEMM_WG_TARGET 512
-#endif
-#ifndef KXG_LDS_WG_TARGET
-#define KXG_LDS_WG_TARGET 512
-#endif
-#ifndef KXG_LDS_BBW
-#define KXG_LDS_BBW 2
-#endif
-#ifndef KXG_LDS_IBW
-#define KXG_LDS_IBW 2
-#endif
 
-static int choose_splits(const Geometry &g, int b_cap)
-{
-    const int bbw = b_cap <= 32 ? 1 : (b_cap <= 64 ? 2 : 4);
-    const int tiles = div_up(b_cap, 32 * bbw) * g.nib;
-    int s = div_up(KXG_GEMM_WG_TARGET, tiles);
-    const int cap = (int)std::max<long>(1, g.dksteps / (kWaves * 4));  // >= 4 steps a wave
-    return std::max(1, std::min(s, cap));
-}
 
 template <typename T>
 static kxg_status dalloc(T **ptr, size_t count)
@@ -152,7 +132,8 @@ static void release(kxg_kernel *k)
     if (!k) return;
     void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_A32,
                     k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs, k->d_JL, k->d_invdK,
-                    k->d_pairs_c, k->d_cib, k->d_units, k->d_nslot};
+                    k->d_pairs_c, k->d_cib, k->d_units, k->d_nslot, k->d_pairs16, k->d_cit16,
+                    k->d_units16, k->d_nslot16};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     free_workspace(k->ws);
@@ -178,16 +159,77 @@ struct kxg_stepper {
     hipStream_t g_stream = nullptr;
 };
 
-// FP32 GEMM over non-zero blocks only.  The kinematic cuts leave whole
+// GEMMs over non-zero blocks only.  The kinematic cuts leave whole
 // 32 x 16 x 16 blocks of the packed operand at zero (about a quarter at
-// n = 256, most of them at large i); they are dropped from the operand and
-// from the K loop, which is exact.  The remaining blocks of each i-block are
-// cut into work units of about equal length (in super-steps of kF32SS dk
-// steps), so that one GEMM launch at the handle's largest batch has about
-// KXG_GEMM_WG_TARGET workgroups; the partial of unit j of an i-block goes to
-// K slot j.  The units depend on the handle only, so the reduction order of
-// a row does not depend on the batch.
-static kxg_status build_compact_f32(kxg_kernel *k, int b_cap, hipStream_t s)
+// n = 256, most of them at large i); they are dropped from the operands and
+// from the K loops, which is exact.  The FP32 operand keeps the blocks of
+// each i-block; the 16-bit operand, whose workgroups cover KXG_LDS_IBW
+// i-blocks at once, keeps the union over such a group.  The kept blocks of
+// each group are cut into work units of about equal length (in super-steps
+// of a few dk steps), so that one launch at the handle's largest batch has
+// at most the targeted number of workgroups; the partial of unit j of a
+// group goes to K slot j.  The units depend on the handle only, so the
+// reduction order of a row does not depend on the batch.
+struct Units {
+    std::vector<int> units, nslot;   // [u][4] = (group, slot, first, end); [group]
+    int maxslots = 0;
+};
+
+static Units make_units(const std::vector<int> &cnt, const std::vector<int> &first, int pps,
+                        int nbt, int wg_target)
+{
+    Units U;
+    const int ng = (int)cnt.size();
+    long total = 0;
+    for (int c : cnt) total += (long)c * pps;
+    U.nslot.assign(ng, 0);
+    if (total == 0) return U;
+    // units in all: one launch of at most wg_target workgroups (a second
+    // round of workgroups would double the time of its CUs), and at least
+    // 4 super-steps a wave
+    int target = std::max(1, wg_target / nbt);
+    target = (int)std::max<long>(1, std::min<long>(target, total / (4 * kWaves)));
+    // shared out in proportion to each group's blocks (largest remainders),
+    // at least one per non-empty group
+    std::vector<int> nu(ng, 0);
+    int given = 0;
+    std::vector<std::pair<double, int>> rem;
+    for (int q = 0; q < ng; ++q) {
+        if (cnt[q] == 0) continue;
+        const double share = (double)target * cnt[q] * pps / (double)total;
+        nu[q] = std::max(1, (int)share);
+        given += nu[q];
+        rem.push_back({share - (int)share, q});
+    }
+    std::sort(rem.begin(), rem.end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+        return x.first > y.first || (x.first == y.first && x.second < y.second);
+    });
+    for (size_t j = 0; j < rem.size() && given < target; ++j, ++given) ++nu[rem[j].second];
+    for (int q = 0; q < ng; ++q) {
+        const long len = (long)cnt[q] * pps, base = (long)first[q] * pps;
+        if (len == 0) continue;
+        const int m = (int)std::min<long>(nu[q], len);
+        for (int j = 0; j < m; ++j) {
+            U.units.push_back(q);
+            U.units.push_back(j);
+            U.units.push_back((int)(base + len * j / m));
+            U.units.push_back((int)(base + len * (j + 1) / m));
+        }
+        U.nslot[q] = m;
+        U.maxslots = std::max(U.maxslots, m);
+    }
+    return U;
+}
+
+template <typename T>
+static hipError_t h2d(T *dst, const std::vector<T> &src)
+{
+    if (src.empty()) return hipSuccess;
+    return hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want32, bool wantbf, bool wanth,
+                                hipStream_t s)
 {
     const Geometry &g = k->geo;
     const size_t nflags = (size_t)g.nib * g.npairs;
@@ -200,80 +242,73 @@ static kxg_status build_compact_f32(kxg_kernel *k, int b_cap, hipStream_t s)
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(d_flags);
     if (e != hipSuccess) { set_error("kxg_kernel_build: %s", hipGetErrorString(e)); return KXG_EHIP; }
-    std::vector<int> pairs_c, cib, cnt(g.nib, 0), first(g.nib, 0);
-    for (int ib = 0; ib < g.nib; ++ib) {
-        first[ib] = (int)cib.size();
-        int q = 0;
-        for (int kb = 0; kb < g.nb; ++kb)
-            for (int mb = kb; mb < g.nb; ++mb, ++q)
-                if (flags[(size_t)ib * g.npairs + q]) {
+    // kept pairs of a group of i-blocks [ib0, ib0 + w)
+    auto compact = [&](int w, std::vector<int> &pairs_c, std::vector<int> &cgrp, std::vector<int> &cnt,
+                       std::vector<int> &first) {
+        const int ng = div_up(g.nib, w);
+        cnt.assign(ng, 0);
+        first.assign(ng, 0);
+        for (int q = 0; q < ng; ++q) {
+            first[q] = (int)cgrp.size();
+            int pr = 0;
+            for (int kb = 0; kb < g.nb; ++kb)
+                for (int mb = kb; mb < g.nb; ++mb, ++pr) {
+                    bool any = false;
+                    for (int ib = q * w; ib < std::min(g.nib, (q + 1) * w); ++ib)
+                        any = any || flags[(size_t)ib * g.npairs + pr];
+                    if (!any) continue;
                     pairs_c.push_back(kb);
                     pairs_c.push_back(mb);
-                    cib.push_back(ib);
-                    ++cnt[ib];
+                    cgrp.push_back(q);
+                    ++cnt[q];
                 }
-    }
-    k->ncomp = (long)cib.size();
-    // work units
-    constexpr int pps = kBlk / kF32SS;               // super-steps per block
-    const int bbw = b_cap <= 32 ? 1 : (b_cap <= 64 ? 2 : 4);
-    const int nbt = div_up(b_cap, 32 * bbw);
-    const long total = k->ncomp * pps;
-    // units in all: one launch of at most KXG_GEMM_WG_TARGET workgroups
-    // (a second round of workgroups would double the time of its CUs), and
-    // at least 4 super-steps a wave
-    int target = std::max(1, KXG_GEMM_WG_TARGET / nbt);
-    target = (int)std::max<long>(1, std::min<long>(target, total / (4 * kWaves)));
-    // share them out in proportion to each i-block's blocks (largest
-    // remainders), at least one per non-empty i-block
-    std::vector<int> nu(g.nib, 0);
-    {
-        int given = 0;
-        std::vector<std::pair<double, int>> rem;
-        for (int ib = 0; ib < g.nib; ++ib) {
-            if (cnt[ib] == 0) continue;
-            const double share = (double)target * cnt[ib] * pps / (double)total;
-            nu[ib] = std::max(1, (int)share);
-            given += nu[ib];
-            rem.push_back({share - (int)share, ib});
         }
-        std::sort(rem.begin(), rem.end(), [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
-            return a.first > b.first || (a.first == b.first && a.second < b.second);
-        });
-        for (size_t q = 0; q < rem.size() && given < target; ++q, ++given) ++nu[rem[q].second];
+    };
+    if (want32) {
+        std::vector<int> pairs_c, cib, cnt, first;
+        compact(1, pairs_c, cib, cnt, first);
+        k->ncomp = (long)cib.size();
+        const int bbw = b_cap <= 32 ? 1 : (b_cap <= 64 ? 2 : 4);
+        const Units U = make_units(cnt, first, kBlk / kF32SS, div_up(b_cap, 32 * bbw), KXG_GEMM_WG_TARGET);
+        k->nunits = (int)(U.units.size() / 4);
+        k->maxslots = U.maxslots;
+        st = dalloc(&k->d_G32, (size_t)std::max<long>(1, k->ncomp) * kBlk * 512);
+        if (st == KXG_OK) st = dalloc(&k->d_pairs_c, std::max<size_t>(2, pairs_c.size()));
+        if (st == KXG_OK) st = dalloc(&k->d_cib, std::max<size_t>(1, cib.size()));
+        if (st == KXG_OK) st = dalloc(&k->d_units, std::max<size_t>(4, U.units.size()));
+        if (st == KXG_OK) st = dalloc(&k->d_nslot, (size_t)g.nib);
+        if (st != KXG_OK) return st;
+        e = h2d(k->d_pairs_c, pairs_c);
+        if (e == hipSuccess) e = h2d(k->d_cib, cib);
+        if (e == hipSuccess) e = h2d(k->d_units, U.units);
+        if (e == hipSuccess) e = h2d(k->d_nslot, U.nslot);
+        if (e == hipSuccess) e = launch_pack_f32(*k, s);
     }
-    std::vector<int> units, nslot(g.nib, 0);
-    for (int ib = 0; ib < g.nib; ++ib) {
-        const long len = (long)cnt[ib] * pps, base = (long)first[ib] * pps;
-        if (len == 0) continue;
-        const int nu_ib = (int)std::min<long>(nu[ib], len);
-        for (int j = 0; j < nu_ib; ++j) {
-            units.push_back(ib);
-            units.push_back(j);
-            units.push_back((int)(base + len * j / nu_ib));
-            units.push_back((int)(base + len * (j + 1) / nu_ib));
-        }
-        nslot[ib] = nu_ib;
+    if (e == hipSuccess && (wantbf || wanth)) {
+        constexpr int w = KXG_LDS_IBW;
+        std::vector<int> pairs_c, cit, cnt, first;
+        compact(w, pairs_c, cit, cnt, first);
+        k->ncomp16 = (long)cit.size();
+        const Units U = make_units(cnt, first, kBlk / KXG_LDS_SS, div_up(b_cap, 4 * KXG_LDS_BBW * 32),
+                                   KXG_LDS_WG_TARGET);
+        k->nunits16 = (int)(U.units.size() / 4);
+        k->maxslots16 = U.maxslots;
+        std::vector<int> nslot_ib(g.nib, 0);
+        for (int ib = 0; ib < g.nib; ++ib) nslot_ib[ib] = U.nslot[ib / w];
+        const size_t gsz = (size_t)std::max<long>(1, k->ncomp16) * w * kBlk * 1024;
+        if (wantbf) st = dalloc(&k->d_Gbf, gsz);
+        if (st == KXG_OK && wanth) st = dalloc(&k->d_Gh, gsz);
+        if (st == KXG_OK) st = dalloc(&k->d_pairs16, std::max<size_t>(2, pairs_c.size()));
+        if (st == KXG_OK) st = dalloc(&k->d_cit16, std::max<size_t>(1, cit.size()));
+        if (st == KXG_OK) st = dalloc(&k->d_units16, std::max<size_t>(4, U.units.size()));
+        if (st == KXG_OK) st = dalloc(&k->d_nslot16, (size_t)g.nib);
+        if (st != KXG_OK) return st;
+        e = h2d(k->d_pairs16, pairs_c);
+        if (e == hipSuccess) e = h2d(k->d_cit16, cit);
+        if (e == hipSuccess) e = h2d(k->d_units16, U.units);
+        if (e == hipSuccess) e = h2d(k->d_nslot16, nslot_ib);
+        if (e == hipSuccess) e = launch_pack_16(*k, w, s);
     }
-    k->nunits = (int)(units.size() / 4);
-    k->maxslots = 0;
-    for (int v : nslot) k->maxslots = std::max(k->maxslots, v);
-    const size_t gsz = (size_t)std::max<long>(1, k->ncomp) * kBlk * 512;
-    st = dalloc(&k->d_G32, gsz);
-    if (st == KXG_OK) st = dalloc(&k->d_pairs_c, std::max<size_t>(2, pairs_c.size()));
-    if (st == KXG_OK) st = dalloc(&k->d_cib, std::max<size_t>(1, cib.size()));
-    if (st == KXG_OK) st = dalloc(&k->d_units, std::max<size_t>(4, units.size()));
-    if (st == KXG_OK) st = dalloc(&k->d_nslot, (size_t)g.nib);
-    if (st != KXG_OK) return st;
-    e = hipSuccess;
-    if (!pairs_c.empty())
-        e = hipMemcpy(k->d_pairs_c, pairs_c.data(), pairs_c.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !cib.empty())
-        e = hipMemcpy(k->d_cib, cib.data(), cib.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !units.empty())
-        e = hipMemcpy(k->d_units, units.data(), units.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(k->d_nslot, nslot.data(), nslot.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_pack_f32(*k, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { set_error("kxg_kernel_build: %s", hipGetErrorString(e)); return KXG_EHIP; }
     return KXG_OK;
@@ -400,19 +435,11 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     g.nib = div_up(n, kIBlk);
     g.ipad = g.nib * kIBlk;
     g.dksteps = (long)g.npairs * kBlk;
-    k->gemm_splits = choose_splits(g, b_cap);
-    {
-        // LDS-shared 16-bit GEMM (tiles of 4*KXG_LDS_BBW*32 x KXG_LDS_IBW*32)
-        const int tiles = div_up(b_cap, 4 * KXG_LDS_BBW * 32) * div_up(g.nib, KXG_LDS_IBW);
-        const int cap = (int)std::max<long>(1, g.dksteps / 8);
-        k->lds_splits = std::max(1, std::min(div_up(KXG_LDS_WG_TARGET, tiles), cap));
-    }
 
     const size_t n3 = (size_t)n * n * n, n2 = (size_t)n * n;
     const bool want32 = prec_mask & KXG_PREC_BIT(KXG_F32);
     const bool wantbf = prec_mask & KXG_PREC_BIT(KXG_BF16X3);
     const bool wanth = prec_mask & KXG_PREC_BIT(KXG_F16X3);
-    const size_t packed = (size_t)g.nib * g.npairs * kBlk * 512;   // elements per copy
     kxg_status st = KXG_OK;
 #define KXG_ALLOC(ptr, cnt) \
     if (st == KXG_OK) st = dalloc(&(ptr), (cnt))
@@ -425,8 +452,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     KXG_ALLOC(k->d_RT, n2);
     KXG_ALLOC(k->d_pairs, 2 * (size_t)g.npairs);
     if (want32) { KXG_ALLOC(k->d_A32, n3); }
-    if (wantbf) { KXG_ALLOC(k->d_Gbf, 2 * packed); }
-    if (wanth) { KXG_ALLOC(k->d_Gh, 2 * packed); KXG_ALLOC(k->d_hrow, (size_t)g.ipad); }
+    if (wanth) { KXG_ALLOC(k->d_hrow, (size_t)g.ipad); }
     if (want_jl) { KXG_ALLOC(k->d_JL, n3); KXG_ALLOC(k->d_invdK, (size_t)n); }
     double *d_xmu = nullptr, *d_wmu = nullptr;
     if (k->nmu > 0) { KXG_ALLOC(d_xmu, (size_t)k->nmu); KXG_ALLOC(d_wmu, (size_t)k->nmu); }
@@ -480,8 +506,8 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
         release(k);
         return KXG_EHIP;
     }
-    if (want32) {
-        st = build_compact_f32(k, b_cap, s);
+    if (want32 || wantbf || wanth) {
+        st = build_compact(k, b_cap, want32, wantbf, wanth, s);
         if (st != KXG_OK) { release(k); return st; }
     }
     st = alloc_workspace(*k, b_cap, k->ws);
@@ -489,8 +515,9 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     k->bytes[KXG_F64] = (n3 + n2) * sizeof(double) + (want_jl ? n3 * sizeof(uint16_t) : 0);
     if (want32)
         k->bytes[KXG_F32] = (n3 + (size_t)k->ncomp * kBlk * 512) * sizeof(float) + n2 * sizeof(double);
-    if (wantbf) k->bytes[KXG_BF16X3] = 2 * packed * sizeof(uint16_t) + n2 * sizeof(double);
-    if (wanth) k->bytes[KXG_F16X3] = 2 * packed * sizeof(uint16_t) + n2 * sizeof(double);
+    const size_t packed16 = (size_t)k->ncomp16 * KXG_LDS_IBW * kBlk * 1024;   // hi + lo values
+    if (wantbf) k->bytes[KXG_BF16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
+    if (wanth) k->bytes[KXG_F16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
     *out = k;
     return KXG_OK;
 }

@@ -267,28 +267,42 @@ __device__ inline uint16_t bf16_rne(float x)
 
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// BF16 hi/lo operand for the 32x32x16 MFMA: [ib][pair][dk][hilo][lane][8];
-// lane l holds row i = ib*32 + l%32 and the 8 consecutive K indices
-// 8*(l/32) + j of row dk of the block.  hi = bf16(v), lo = bf16(v - hi).
-__global__ void k_pack_bf16(int n, int npairs, int nib, const int *__restrict__ pairs,
-                            const double *__restrict__ A, const double *__restrict__ RT,
-                            uint16_t *__restrict__ G)
+// 16-bit hi/lo operands for the 32x32x16 MFMA over the kept blocks of a
+// group of ibw i-blocks: [block c][i-block of the group][dk][hi|lo][lane][8];
+// block c is pair pairs16[c] of group cit[c]; lane l holds row
+// i = (cit*ibw + g)*32 + l%32 and the 8 consecutive K indices 8*(l/32) + j
+// of row dk of the block.  BF16: hi = bf16(v), lo = bf16(v - hi); FP16 (row
+// scale rs): the same of v * rs[i] in FP16.
+template <bool F16>
+__global__ void k_pack_16(int n, long ncomp, int ibw, const int *__restrict__ pairs16,
+                          const int *__restrict__ cit, const double *__restrict__ A,
+                          const double *__restrict__ RT, const float *__restrict__ rs,
+                          uint16_t *__restrict__ G)
 {
-    const long total = (long)nib * npairs * kBlk * 64 * 8;   // hi/lo written together
+    const long total = ncomp * ibw * kBlk * 64 * 8;          // hi/lo written together
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (long)gridDim.x * blockDim.x) {
         long t = idx;
         const int j = (int)(t % 8); t /= 8;
         const int lane = (int)(t % 64); t /= 64;
         const int dk = (int)(t % kBlk); t /= kBlk;
-        const int pr = (int)(t % npairs);
-        const int ib = (int)(t / npairs);
-        const int i = ib * kIBlk + (lane & 31);
+        const int gi = (int)(t % ibw);
+        const long c = t / ibw;
+        const int i = (cit[c] * ibw + gi) * kIBlk + (lane & 31);
         const int dm = 8 * (lane >> 5) + j;
-        const double v = packed_value(A, RT, n, i, pairs[2 * pr], pairs[2 * pr + 1], dk, dm);
-        const uint16_t hi = bf16_rne((float)v);
-        const uint16_t lo = bf16_rne((float)(v - (double)bf16_to_f32(hi)));
-        const long base = ((((long)ib * npairs + pr) * kBlk + dk) * 2) * 64 * 8;
+        const double v = packed_value(A, RT, n, i, pairs16[2 * c], pairs16[2 * c + 1], dk, dm);
+        uint16_t hi, lo;
+        if constexpr (F16) {
+            const double vs = i < n ? v * (double)rs[i] : 0.0;
+            const _Float16 h = (_Float16)(float)vs;
+            const _Float16 l = (_Float16)(float)(vs - (double)(float)h);
+            hi = __builtin_bit_cast(uint16_t, h);
+            lo = __builtin_bit_cast(uint16_t, l);
+        } else {
+            hi = bf16_rne((float)v);
+            lo = bf16_rne((float)(v - (double)bf16_to_f32(hi)));
+        }
+        const long base = (((c * ibw + gi) * kBlk + dk) * 2) * 64 * 8;
         G[base + (long)lane * 8 + j] = hi;
         G[base + 64 * 8 + (long)lane * 8 + j] = lo;
     }
@@ -328,32 +342,6 @@ __global__ __launch_bounds__(256) void k_row_scale(int n, int ipad, const double
             sc = (float)ldexp(1.0, e);
         }
         scale[i] = sc;
-    }
-}
-
-// FP16 hi/lo operand (same order as the BF16 one) of the row-scaled tensor.
-__global__ void k_pack_f16(int n, int npairs, int nib, const int *__restrict__ pairs,
-                           const double *__restrict__ A, const double *__restrict__ RT,
-                           const float *__restrict__ rs, uint16_t *__restrict__ G)
-{
-    const long total = (long)nib * npairs * kBlk * 64 * 8;
-    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (long)gridDim.x * blockDim.x) {
-        long t = idx;
-        const int j = (int)(t % 8); t /= 8;
-        const int lane = (int)(t % 64); t /= 64;
-        const int dk = (int)(t % kBlk); t /= kBlk;
-        const int pr = (int)(t % npairs);
-        const int ib = (int)(t / npairs);
-        const int i = ib * kIBlk + (lane & 31);
-        const int dm = 8 * (lane >> 5) + j;
-        const double v = packed_value(A, RT, n, i, pairs[2 * pr], pairs[2 * pr + 1], dk, dm) *
-                         (double)rs[i];
-        const _Float16 hi = (_Float16)(float)v;
-        const _Float16 lo = (_Float16)(float)(v - (double)(float)hi);
-        const long base = ((((long)ib * npairs + pr) * kBlk + dk) * 2) * 64 * 8;
-        G[base + (long)lane * 8 + j] = __builtin_bit_cast(uint16_t, hi);
-        G[base + 64 * 8 + (long)lane * 8 + j] = __builtin_bit_cast(uint16_t, lo);
     }
 }
 
@@ -409,6 +397,19 @@ hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_pack_16(const kxg_kernel &k, int ibw, hipStream_t s)
+{
+    const long tot = k.ncomp16 * ibw * kBlk * 64 * 8;
+    if (tot <= 0) return hipSuccess;
+    if (k.d_Gbf)
+        hipLaunchKernelGGL(k_pack_16<false>, dim3(grid_for(tot)), dim3(256), 0, s, k.n, k.ncomp16,
+                           ibw, k.d_pairs16, k.d_cit16, k.d_A64, k.d_RT, k.d_hrow, k.d_Gbf);
+    if (k.d_Gh)
+        hipLaunchKernelGGL(k_pack_16<true>, dim3(grid_for(tot)), dim3(256), 0, s, k.n, k.ncomp16,
+                           ibw, k.d_pairs16, k.d_cit16, k.d_A64, k.d_RT, k.d_hrow, k.d_Gh);
+    return hipGetLastError();
+}
+
 hipError_t launch_derive(kxg_kernel &k, hipStream_t s)
 {
     const Geometry &g = k.geo;
@@ -417,18 +418,9 @@ hipError_t launch_derive(kxg_kernel &k, hipStream_t s)
         hipLaunchKernelGGL(k_to_f32, dim3(grid_for(dense)), dim3(256), 0, s, dense, k.d_A64,
                            k.d_A32);
     }
-    if (k.d_Gbf) {
-        const long tot = (long)g.nib * g.npairs * kBlk * 64 * 8;
-        hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(tot)), dim3(256), 0, s, k.n, g.npairs,
-                           g.nib, k.d_pairs, k.d_A64, k.d_RT, k.d_Gbf);
-    }
-    if (k.d_Gh) {
+    if (k.d_hrow)
         hipLaunchKernelGGL(k_row_scale, dim3(g.ipad), dim3(256), 0, s, k.n, g.ipad, k.d_A64,
                            k.d_RT, k.d_hrow);
-        const long tot = (long)g.nib * g.npairs * kBlk * 64 * 8;
-        hipLaunchKernelGGL(k_pack_f16, dim3(grid_for(tot)), dim3(256), 0, s, k.n, g.npairs,
-                           g.nib, k.d_pairs, k.d_A64, k.d_RT, k.d_hrow, k.d_Gh);
-    }
     return hipGetLastError();
 }
 

@@ -36,15 +36,6 @@ inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 #ifndef KXG_F32_NST
 #define KXG_F32_NST 2        // register stages of the FP32 GEMM
 #endif
-#ifndef KXG_LDS_SS
-#define KXG_LDS_SS 4         // dk steps per LDS stage of the 16-bit GEMM
-#endif
-#ifndef KXG_LDS_BBW
-#define KXG_LDS_BBW 2
-#endif
-#ifndef KXG_LDS_IBW
-#define KXG_LDS_IBW 2
-#endif
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Remap so that consecutive logical indices share an XCD: workgroups
@@ -523,105 +514,6 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(
     store_tile<BBW>(acc, lds, part, sp, bpad, ipad, brow0, ib * kIBlk);
 }
 
-// 16-bit x3 GEMM on v_mfma_f32_32x32x16_{bf16,f16}: per dk step one MFMA
-// K-step of 16; F2 is formed in FP32 and split into hi + lo; the packed
-// tensor arrives pre-split.  gain ~ A_hi F2_hi + A_hi F2_lo + A_lo F2_hi.
-template <int BBW, bool F16>
-__global__ __launch_bounds__(256, 2) void k_gemm_x3(
-    const uint16_t *__restrict__ G, const float *__restrict__ fop, const int *__restrict__ pairs,
-    int npairs, int bpad, int ipad, int nbt, int splits, long dksteps,
-    float *__restrict__ part)
-{
-    typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
-    typedef typename std::conditional<F16, _Float16, __bf16>::type op_t;
-    __shared__ __align__(16) float lds[4 * BBW * 16 * 64];
-    int L = xcd_logical(blockIdx.x, gridDim.x);
-    const int bt = L % nbt;
-    L /= nbt;
-    const int sp = L % splits;
-    const int ib = L / splits;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r = lane & 31, hb = lane >> 5;
-    const long w = (long)sp * kWaves + wave, nw = (long)splits * kWaves;
-    const long u0 = w * dksteps / nw, u1 = (w + 1) * dksteps / nw;
-    const int brow0 = bt * BBW * 32;
-    const uint16_t *Gi = G + (long)ib * npairs * kBlk * 1024;
-
-    floatx16 acc[BBW];
-#pragma unroll
-    for (int bb = 0; bb < BBW; ++bb)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[bb][e] = 0.0f;
-
-    float fm[BBW][8];
-    int cur_pair = -1;
-    uint4 nh = make_uint4(0, 0, 0, 0), nl = nh;
-    float nfk[BBW];
-    if (u0 < u1) {
-        const int pr = (int)(u0 >> 4), dk = (int)(u0 & 15);
-        const uint16_t *gp = Gi + u0 * 1024;
-        nh = reinterpret_cast<const uint4 *>(gp)[lane];
-        nl = reinterpret_cast<const uint4 *>(gp + 512)[lane];
-        const int kb = pairs[2 * pr];
-#pragma unroll
-        for (int bb = 0; bb < BBW; ++bb)
-            nfk[bb] = fop[((long)kb * bpad + brow0 + bb * 32 + r) * kBlk + dk];
-    }
-    for (long u = u0; u < u1; ++u) {
-        const int pr = (int)(u >> 4);
-        if (pr != cur_pair) {
-            cur_pair = pr;
-            const int mb = pairs[2 * pr + 1];
-#pragma unroll
-            for (int bb = 0; bb < BBW; ++bb) {
-                const float4 *src = reinterpret_cast<const float4 *>(
-                    fop + ((long)mb * bpad + brow0 + bb * 32 + r) * kBlk + 8 * hb);
-                const float4 x0 = src[0], x1 = src[1];
-                fm[bb][0] = x0.x; fm[bb][1] = x0.y; fm[bb][2] = x0.z; fm[bb][3] = x0.w;
-                fm[bb][4] = x1.x; fm[bb][5] = x1.y; fm[bb][6] = x1.z; fm[bb][7] = x1.w;
-            }
-        }
-        const uint4 ah = nh, al = nl;
-        float fk[BBW];
-#pragma unroll
-        for (int bb = 0; bb < BBW; ++bb) fk[bb] = nfk[bb];
-        if (u + 1 < u1) {
-            const long un = u + 1;
-            const int prn = (int)(un >> 4), dkn = (int)(un & 15);
-            const uint16_t *gp = Gi + un * 1024;
-            nh = reinterpret_cast<const uint4 *>(gp)[lane];
-            nl = reinterpret_cast<const uint4 *>(gp + 512)[lane];
-            const int kbn = pairs[2 * prn];
-#pragma unroll
-            for (int bb = 0; bb < BBW; ++bb)
-                nfk[bb] = fop[((long)kbn * bpad + brow0 + bb * 32 + r) * kBlk + dkn];
-        }
-        const opx8 Ah = __builtin_bit_cast(opx8, ah);
-        const opx8 Al = __builtin_bit_cast(opx8, al);
-#pragma unroll
-        for (int bb = 0; bb < BBW; ++bb) {
-            opx8 ph, pl;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float pv = fk[bb] * fm[bb][j];
-                const op_t h = (op_t)pv;
-                ph[j] = h;
-                pl[j] = (op_t)(pv - (float)h);
-            }
-            if constexpr (F16) {
-                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(pl, Ah, acc[bb], 0, 0, 0);
-                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ph, Al, acc[bb], 0, 0, 0);
-                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ph, Ah, acc[bb], 0, 0, 0);
-            } else {
-                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, Ah, acc[bb], 0, 0, 0);
-                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, Al, acc[bb], 0, 0, 0);
-                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, Ah, acc[bb], 0, 0, 0);
-            }
-        }
-    }
-    store_tile<BBW>(acc, lds, part, sp, bpad, ipad, brow0, ib * kIBlk);
-}
-
 // 16-bit x3 GEMM for large batches, the packed tensor shared through LDS.
 // A workgroup's 4 waves work on the same K split and the same IBW i-blocks;
 // wave w takes the BBW b-blocks [w*BBW, (w+1)*BBW) of the workgroup's
@@ -645,7 +537,7 @@ struct X3Stage {
 template <int BBW, int IBW, int SS, bool F16>
 __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_gemm_x3_lds(
     const uint16_t *G, const float *__restrict__ fop, const int *__restrict__ pairs,
-    int npairs, int nib, int bpad, int ipad, int nbt, int nit, int splits, long dksteps,
+    const int *__restrict__ units, int nib, int bpad, int ipad, int nbt,
     float *__restrict__ part)
 {
     typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
@@ -658,29 +550,27 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
     static_assert(NV % 256 == 0, "a super-step must split evenly over 256 threads");
     typedef X3Stage<BBW, SS, NQ> Stage;
     __shared__ u32x4 sA[2][NV];
-    int L = xcd_logical(blockIdx.x, gridDim.x);
-    const int bt = L % nbt;
-    L /= nbt;
-    const int sp = L % splits;
-    const int it = L / splits;
+    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int bt = L % nbt, u = L / nbt;
+    // work unit: group of IBW i-blocks, K slot and range of (compacted) super-steps
+    const int it = units[4 * u], sp = units[4 * u + 1];
+    const long s0 = units[4 * u + 2], s1 = units[4 * u + 3];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int r = lane & 31, hb = lane >> 5;
-    const long nss = dksteps / SS;
-    const long s0 = (long)sp * nss / splits, s1 = (long)(sp + 1) * nss / splits;
     const int brow0 = bt * (4 * BBW * 32) + wave * (BBW * 32);
     const int ib0 = it * IBW;
     const long bstride = (long)bpad * kBlk;
     const float *fkb = fop + (long)(brow0 + r) * kBlk;
     const float *fmb = fop + (long)(brow0 + r) * kBlk + 8 * hb;
     // loader role: vector q = threadIdx.x + 256 c of a super-step belongs to
-    // i-block q / VPS (clamped to the last one; such rows are never stored)
+    // i-block q / VPS of the group; block c of the compacted operand holds
+    // IBW * 16 * 128 vectors
     const u32x4 *qsrc[NQ];
 #pragma unroll
     for (int c = 0; c < NQ; ++c) {
         const int q = threadIdx.x + 256 * c;
-        const int ibq = min(ib0 + q / VPS, nib - 1);
-        qsrc[c] = reinterpret_cast<const u32x4 *>(G) + (long)ibq * npairs * kBlk * 128 + (q % VPS);
+        qsrc[c] = reinterpret_cast<const u32x4 *>(G) + (long)(q / VPS) * kBlk * 128 + (q % VPS);
     }
 
     floatx16 acc[BBW][IBW];
@@ -694,8 +584,9 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
     Stage sa, sb;
     auto load_stage = [&](long s, Stage &x) {
         s = s < s1 ? s : s1 - 1;
+        const long cb = s / PPS, d0 = (s % PPS) * SS;   // block, first dk step
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) x.gv[c] = qsrc[c][s * VPS];
+        for (int c = 0; c < NQ; ++c) x.gv[c] = qsrc[c][(cb * IBW * kBlk + d0) * 128];
         const int pr = (int)(s / PPS);
         const int kb = pairs[2 * pr], mb = pairs[2 * pr + 1];
         const int dk = (int)(s % PPS) * SS;
@@ -1325,27 +1216,21 @@ int gemm_bbw(int B) { return B <= 32 ? 1 : (B <= 64 ? 2 : 4); }
 kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws)
 {
     const int n = k.n;
-    const int bpad = div_up(b_cap, 128) * 128;
+    // rows of the GEMM operands: a multiple of both batch tilings
+    constexpr int tile16 = 4 * KXG_LDS_BBW * 32;
+    const int bpad = div_up(div_up(b_cap, 128) * 128, tile16) * tile16;
     size_t need = (size_t)stream_splits(n) * b_cap * n * sizeof(double);
     if (k.d_JL) need = (size_t)stream_splits(n) * b_cap * 4 * n * sizeof(double);
-    if (k.d_G32 || k.d_Gbf || k.d_Gh) {
-        const size_t g = (size_t)std::max(k.gemm_splits, k.maxslots) * bpad * k.geo.ipad * sizeof(float);
-        if (g > need) need = g;
-    }
-    if ((k.d_Gbf || k.d_Gh) && b_cap >= kLdsMinB) {
-        const size_t bl = (size_t)div_up(b_cap, 512) * 512;
-        const size_t g = (size_t)k.lds_splits * bl * k.geo.ipad * sizeof(float);
-        if (g > need) need = g;
-    }
+    const size_t slots = (size_t)std::max(k.d_G32 ? k.maxslots : 0, (k.d_Gbf || k.d_Gh) ? k.maxslots16 : 0);
+    need = std::max(need, slots * bpad * k.geo.ipad * sizeof(float));
     need += (size_t)b_cap * n * sizeof(double);      // loss rates
     ws.part_bytes = need;
     ws.bpad_cap = bpad;
     ws.b_cap = b_cap;
     if (hipMalloc(&ws.part, need) != hipSuccess) { set_error("workspace: out of memory"); return KXG_ENOMEM; }
-    const int bpad_l = div_up(b_cap, 512) * 512;
-    const size_t fb = (size_t)k.geo.nb * (bpad_l > bpad ? bpad_l : bpad) * kBlk * sizeof(float);
+    const size_t fb = (size_t)k.geo.nb * bpad * kBlk * sizeof(float);
     if (hipMalloc((void **)&ws.fop, fb) != hipSuccess || hipMalloc((void **)&ws.fpar, fb) != hipSuccess ||
-        hipMalloc((void **)&ws.fscale, (bpad_l > bpad ? bpad_l : bpad) * sizeof(float)) != hipSuccess) {
+        hipMalloc((void **)&ws.fscale, bpad * sizeof(float)) != hipSuccess) {
         set_error("workspace: out of memory");
         return KXG_ENOMEM;
     }
@@ -1377,7 +1262,7 @@ static Path path_of(const kxg_kernel &k, int prec, int B)
         p.stream = true;
         return p;
     }
-    if ((prec == KXG_BF16X3 || prec == KXG_F16X3) && B >= kLdsMinB) {
+    if (prec == KXG_BF16X3 || prec == KXG_F16X3) {
         constexpr int TILE = 4 * KXG_LDS_BBW * 32;
         p.lds = true;
         p.bpad = div_up(B, TILE) * TILE;
@@ -1506,79 +1391,55 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     }
     const bool f16 = prec == KXG_F16X3;
     if (P.lds) {
-        // large batch: 16-bit GEMM with the A operand shared through LDS
+        // 16-bit GEMM, the packed tensor shared through LDS
         constexpr int BBW = KXG_LDS_BBW, IBW = KXG_LDS_IBW, TILE = 4 * BBW * 32;
         const int bpad = P.bpad;
-        const int nbt = bpad / TILE, nit = div_up(g.nib, IBW);
-        const int splits = k.lds_splits;
+        const int nbt = bpad / TILE;
         if (!op_ready)
             hipLaunchKernelGGL(k_prep, dim3(bpad), dim3(256), 0, s, f, B, n, g.nb, bpad, f16 ? 1 : 0,
                                ws.fop, ws.fpar, ws.fscale);
         hand_over(bpad, f16 ? 1 : 0);
         float *part = static_cast<float *>(ws.part);
-        const dim3 grid(nbt * nit * splits);
+        const dim3 grid(nbt * k.nunits16);
         profile_mark_begin(s);
         if (f16)
             hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, true>), grid, dim3(256), 0, s,
-                               k.d_Gh, ws.fop, k.d_pairs, g.npairs, g.nib, bpad, g.ipad, nbt, nit,
-                               splits, g.dksteps, part);
+                               k.d_Gh, ws.fop, k.d_pairs16, k.d_units16, g.nib, bpad, g.ipad, nbt, part);
         else
             hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, false>), grid, dim3(256), 0, s,
-                               k.d_Gbf, ws.fop, k.d_pairs, g.npairs, g.nib, bpad, g.ipad, nbt, nit,
-                               splits, g.dksteps, part);
+                               k.d_Gbf, ws.fop, k.d_pairs16, k.d_units16, g.nib, bpad, g.ipad, nbt, part);
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
         // the loss term is folded into the operand; loss rates only for diagnostics
         if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
-        KXG_TRY_HIP(launch_epilogue<float>(part, splits, nullptr, (long)bpad * g.ipad, g.ipad,
+        KXG_TRY_HIP(launch_epilogue<float>(part, k.maxslots16, k.d_nslot16, (long)bpad * g.ipad, g.ipad,
                                            f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr,
                                            diag ? rate : nullptr, f, k, B, project, C, diag, step, s,
                                            nullptr, 0.0, 1));
         return KXG_OK;
     }
-    // GEMM path
+    // FP32 GEMM
     const int bbw = gemm_bbw(B);
-    const int tile = 32 * bbw;
     const int bpad = P.bpad;
-    const int nbt = bpad / tile;
-    const int splits = k.gemm_splits;
-    const int nwg = nbt * g.nib * splits;
+    const int nbt = bpad / (32 * bbw);
     if (!op_ready)
-        hipLaunchKernelGGL(k_prep, dim3(bpad), dim3(256), 0, s, f, B, n, g.nb, bpad, f16 ? 1 : 0,
+        hipLaunchKernelGGL(k_prep, dim3(bpad), dim3(256), 0, s, f, B, n, g.nb, bpad, 0,
                            ws.fop, ws.fpar, ws.fscale);
-    hand_over(bpad, f16 ? 1 : 0);
+    hand_over(bpad, 0);
     float *part = static_cast<float *>(ws.part);
-    const dim3 grid(nwg);
     profile_mark_begin(s);
 #define KXG_GEMM_F32(W)                                                                  \
     hipLaunchKernelGGL((k_gemm_f32<W, kF32SS, KXG_F32_NST>), dim3(nbt * k.nunits), dim3(256), 0, s, \
                        k.d_G32, ws.fop, ws.fpar, k.d_pairs_c, k.d_units, bpad, g.ipad, nbt, part)
-#define KXG_GEMM_X3(W, H, GP)                                                              \
-    hipLaunchKernelGGL((k_gemm_x3<W, H>), grid, dim3(256), 0, s, GP, ws.fop, k.d_pairs, \
-                       g.npairs, bpad, g.ipad, nbt, splits, g.dksteps, part)
-    if (prec == KXG_F32) {
-        if (bbw == 1) KXG_GEMM_F32(1); else if (bbw == 2) KXG_GEMM_F32(2); else KXG_GEMM_F32(4);
-    } else if (prec == KXG_BF16X3) {
-        if (bbw == 1) KXG_GEMM_X3(1, false, k.d_Gbf);
-        else if (bbw == 2) KXG_GEMM_X3(2, false, k.d_Gbf);
-        else KXG_GEMM_X3(4, false, k.d_Gbf);
-    } else {
-        if (bbw == 1) KXG_GEMM_X3(1, true, k.d_Gh);
-        else if (bbw == 2) KXG_GEMM_X3(2, true, k.d_Gh);
-        else KXG_GEMM_X3(4, true, k.d_Gh);
-    }
+    if (bbw == 1) KXG_GEMM_F32(1); else if (bbw == 2) KXG_GEMM_F32(2); else KXG_GEMM_F32(4);
 #undef KXG_GEMM_F32
-#undef KXG_GEMM_X3
     profile_mark_end(s);
     KXG_TRY_HIP(hipGetLastError());
     // the loss term is folded into the operand; loss rates only for diagnostics
     if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
-    const bool f32 = prec == KXG_F32;
-    KXG_TRY_HIP(launch_epilogue<float>(part, f32 ? k.maxslots : splits, f32 ? k.d_nslot : nullptr,
-                                       (long)bpad * g.ipad, g.ipad,
-                                       f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr,
-                                       diag ? rate : nullptr, f, k, B, project, C, diag, step, s,
-                                       nullptr, 0.0, 1));
+    KXG_TRY_HIP(launch_epilogue<float>(part, k.maxslots, k.d_nslot, (long)bpad * g.ipad, g.ipad,
+                                       nullptr, nullptr, diag ? rate : nullptr, f, k, B, project, C,
+                                       diag, step, s, nullptr, 0.0, 1));
     return KXG_OK;
 }
 

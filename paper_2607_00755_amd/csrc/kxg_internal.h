@@ -27,8 +27,24 @@ constexpr int kBlk = 16;             // (k,m) block edge of the packed GEMM layo
 constexpr int kIBlk = 32;            // output rows (i) per MFMA tile
 constexpr int kBRows = 32;           // distributions per MFMA tile
 constexpr int kWaves = 4;            // waves per GEMM workgroup (split K)
-constexpr int kLdsMinB = 512;        // batches from this size use the LDS-shared 16-bit GEMM
 constexpr int kF32SS = 4;            // dk steps per super-step of the FP32 GEMM (work units)
+
+// Tuning of the GEMM launches (overridable at build time).
+#ifndef KXG_GEMM_WG_TARGET
+#define KXG_GEMM_WG_TARGET 512   // workgroups of one FP32 GEMM launch at the handle's largest batch
+#endif
+#ifndef KXG_LDS_WG_TARGET
+#define KXG_LDS_WG_TARGET 512   // workgroups of one 16-bit GEMM launch at the handle's largest batch
+#endif
+#ifndef KXG_LDS_SS
+#define KXG_LDS_SS 4   // dk steps per LDS stage of the 16-bit GEMM
+#endif
+#ifndef KXG_LDS_BBW
+#define KXG_LDS_BBW 1   // 32-row batch blocks per wave of the 16-bit GEMM
+#endif
+#ifndef KXG_LDS_IBW
+#define KXG_LDS_IBW 4   // i-blocks per workgroup of the 16-bit GEMM
+#endif
 
 // Geometry of the block-packed GEMM operand: the (k,m) plane is cut into
 // 16x16 blocks; only blocks with kb <= mb are stored (off-diagonal blocks hold
@@ -81,11 +97,15 @@ struct kxg_kernel {
     int *d_nslot = nullptr;      // [nib] K slots (partials) of each i-block
     long ncomp = 0;              // non-zero (i-block, pair) blocks
     int nunits = 0, maxslots = 0;
+    // the same for the 16-bit operands, per group of KXG_LDS_IBW i-blocks
+    // (union of their non-zero pairs); Gbf/Gh hold [block][i-block of the
+    // group][dk][hi|lo][lane][8]
+    int *d_pairs16 = nullptr, *d_cit16 = nullptr, *d_units16 = nullptr, *d_nslot16 = nullptr;
+    long ncomp16 = 0;
+    int nunits16 = 0, maxslots16 = 0;
     uint16_t *d_JL = nullptr;    // [n][n][n] interpolation bracket j_L (0xFFFF: cut)
     double *d_invdK = nullptr;   // [n] 1 / (K_{j+1} - K_j) (0 for the last point)
     kxg::Geometry geo;
-    int gemm_splits = 8;         // workgroup splits of K (fixed per handle)
-    int lds_splits = 8;          // K splits of the LDS-shared 16-bit GEMM
     size_t bytes[4] = {0, 0, 0, 0};
     kxg::Workspace ws;
 };
@@ -99,6 +119,7 @@ hipError_t launch_build_R(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_derive(kxg_kernel &k, hipStream_t s);
 hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, hipStream_t s);
 hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s);
+hipError_t launch_pack_16(const kxg_kernel &k, int ibw, hipStream_t s);
 hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s);
 
 struct StepArgs;
