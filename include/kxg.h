@@ -120,6 +120,9 @@ typedef struct {
     int64_t nonzero_blocks;   /* blocks kept in the FP32 operand (0 if no FP32) */
     int32_t gemm_units;       /* FP32 GEMM work units (K ranges) per batch tile */
     int32_t max_slots;        /* most K partials of an i-block                  */
+    int64_t blocks16;         /* (i-block, pair) blocks the 16-bit GEMM runs over:
+                                 the union of the non-zero pairs of each group of
+                                 i-blocks a workgroup covers (0 if no 16-bit) */
 } kxg_kernel_info;
 
 /* Fill *out for handle k.  Errors: KXG_EINVAL (null argument). */

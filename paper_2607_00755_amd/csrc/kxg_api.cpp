@@ -547,6 +547,7 @@ kxg_status kxg_kernel_stats(const kxg_kernel *k, kxg_kernel_info *out)
     out->nonzero_blocks = k->d_G32 ? k->ncomp : 0;
     out->gemm_units = k->nunits;
     out->max_slots = k->maxslots;
+    out->blocks16 = (k->d_Gbf || k->d_Gh) ? k->ncomp16 * KXG_LDS_IBW : 0;
     return KXG_OK;
 }
 

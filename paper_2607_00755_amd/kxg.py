@@ -57,7 +57,7 @@ class Grid(ctypes.Structure):
 class KernelInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("packed_blocks", ctypes.c_int64),
                 ("nonzero_blocks", ctypes.c_int64), ("gemm_units", ctypes.c_int32),
-                ("max_slots", ctypes.c_int32)]
+                ("max_slots", ctypes.c_int32), ("blocks16", ctypes.c_int64)]
 
 
 class StepperParams(ctypes.Structure):
@@ -216,7 +216,7 @@ class Kernel:
         _check(lib().kxg_kernel_stats(self._h, ctypes.byref(info)))
         return {"n": info.n, "packed_blocks": info.packed_blocks,
                 "nonzero_blocks": info.nonzero_blocks, "gemm_units": info.gemm_units,
-                "max_slots": info.max_slots}
+                "max_slots": info.max_slots, "blocks16": info.blocks16}
 
     def export(self):
         n = self.n
