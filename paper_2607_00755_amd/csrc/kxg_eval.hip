@@ -33,6 +33,12 @@ inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 #define KXG_STREAM_NT 1
 #endif
 // shape of the LDS-shared 16-bit GEMM: b-blocks and i-blocks per wave
+#ifndef KXG_EPI_U
+#define KXG_EPI_U 32         // FP32 split partials in flight per thread in the epilogue
+#endif
+#ifndef KXG_EPI_MINB
+#define KXG_EPI_MINB 1       // epilogue workgroups per CU the register budget must allow
+#endif
 #ifndef KXG_F32_NST
 #define KXG_F32_NST 2        // register stages of the FP32 GEMM
 #endif
@@ -730,6 +736,33 @@ __device__ void block_max(double (&v)[NV], double *lds)
     __syncthreads();
 }
 
+// Reductions over the threads of one distribution in the epilogue: a wave
+// (TPB = 64) or the whole workgroup (TPB = 256, through `lds`).
+template <int NV, int TPB>
+__device__ void grp_sum(double (&v)[NV], double *lds)
+{
+    if constexpr (TPB == 64) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+    } else {
+        block_sum<NV>(v, lds);
+    }
+}
+
+template <int NV, int TPB>
+__device__ void grp_max(double (&v)[NV], double *lds)
+{
+    if constexpr (TPB == 64) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = wave_max(v[j]);
+    } else {
+        block_max<NV>(v, lds);
+    }
+}
+
+template <int TPB>
+__device__ inline int epi_tl() { return (int)threadIdx.x % TPB; }
+
 // Stepper inputs of one slot, loaded at the start of the epilogue so that
 // their latency overlaps that of the split partials.
 template <int PER>
@@ -737,13 +770,13 @@ struct StepIn {
     double x[PER], acc[PER], xs[PER], nx[PER];
 };
 
-template <int PER>
+template <int PER, int TPB>
 __device__ void load_step_inputs(const StepArgs &A, int b, int n, StepIn<PER> &in)
 {
     const long row = (long)b * n;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x + 256 * q;
+        const int i = epi_tl<TPB>() + TPB * q;
         in.x[q] = in.acc[q] = in.xs[q] = in.nx[q] = 0.0;
         if (i >= n) continue;
         if (A.mode == kStepRK4) {
@@ -761,12 +794,12 @@ __device__ void load_step_inputs(const StepArgs &A, int b, int n, StepIn<PER> &i
     }
 }
 
-template <int PER>
+template <int PER, int TPB>
 __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)[PER],
                             const StepIn<PER> &in, double *lds);
 
-// FP64 epilogue, one 256-thread workgroup per distribution, PER grid points
-// per thread (element i = thread + 256 q), App. C:
+// FP64 epilogue, TPB threads per distribution (a wave, or the whole 256-thread
+// workgroup), PER grid points per thread (element i = t + TPB q), App. C:
 //   gain = sum of the split partials (fixed order; FP16 scales undone),
 //   C_raw = gain - f * rate,
 //   xi_i = |f_i|/f_max above 1e-12, and the 2x2 system for the correction
@@ -776,10 +809,10 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
 //   and the diagnostics of eqs. app_epsilon_definition and
 //   app_projection_relative_correction.
 // All loads of a thread (partials, rates, stepper state) are issued before
-// the first reduction; the block reductions add the four waves in a fixed
-// order, so the result of a distribution does not depend on B.
-template <typename PT, int PER>
-__global__ __launch_bounds__(256) void k_epilogue(
+// the first reduction; the reductions add in a fixed order, so the result
+// of a distribution does not depend on B.
+template <typename PT, int PER, bool EXT, int TPB>
+__global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
     const PT *__restrict__ part, int nsplit, const int *__restrict__ nslot, long split_stride, int ld_b,
     const float *__restrict__ fscale, const float *__restrict__ rscale,
     const double *__restrict__ rate, const double *__restrict__ f,
@@ -788,14 +821,17 @@ __global__ __launch_bounds__(256) void k_epilogue(
     StepArgs step, const double *__restrict__ ext, double eta, int folded)
 {
     __shared__ double red[4 * 12];
-    const int b = blockIdx.x;
+    const int b = blockIdx.x * (256 / TPB) + (int)threadIdx.x / TPB;
+    if constexpr (TPB == 64) {
+        if (b >= B) return;                    // whole wave; no barriers with TPB = 64
+    }
     const double *fb = f + (long)b * n;
     StepIn<PER> in;
-    load_step_inputs<PER>(step, b, n, in);
+    load_step_inputs<PER, TPB>(step, b, n, in);
     double hv[PER], kv[PER], ev[PER];          // grid constants, loaded up front
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x + 256 * q;
+        const int i = epi_tl<TPB>() + TPB * q;
         hv[q] = i < n ? h[i] : 0.0;
         kv[q] = i < n ? K[i] : 0.0;
         ev[q] = i < n ? E[i] : 0.0;
@@ -809,7 +845,7 @@ __global__ __launch_bounds__(256) void k_epilogue(
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x + 256 * q;
+        const int i = epi_tl<TPB>() + TPB * q;
         fv[q] = 0.0;
         craw[q] = 0.0;
         if (i < n) {
@@ -818,7 +854,7 @@ __global__ __launch_bounds__(256) void k_epilogue(
             if (!isfinite(x)) mx[3] = fmax(mx[3], 1.0);
             else if (x < 0.0) mx[3] = fmax(mx[3], 0.5);
             mx[0] = fmax(mx[0], fabs(x));
-            if (ext) {
+            if constexpr (EXT) {
                 // exact form: four split sums per row, layout [split][B][4][n]
                 double a4[4] = {0.0, 0.0, 0.0, 0.0};
                 for (int sp0 = 0; sp0 < nsplit; sp0 += 4) {
@@ -839,43 +875,64 @@ __global__ __launch_bounds__(256) void k_epilogue(
                 mx[1] = fmax(mx[1], a4[1]);
                 mx[2] = fmax(mx[2], fabs(gq));
                 craw[q] = gq - lq;
-            } else {
-                // split partials: up to 32 (FP32) or 16 (FP64) loads in flight,
-                // added in split order.  With `folded` the partials already
-                // hold gain - loss (the loss term is part of the GEMM operand)
-                // and the loss rates, when given, only feed the diagnostics.
-                constexpr int U = sizeof(PT) == 4 ? 32 : 16;
-                const PT *pp = part + (long)b * ld_b + i;
-                const double rt = rate ? rate[(long)b * n + i] : 0.0;
-                const int ns = nslot ? nslot[i / kIBlk] : nsplit;   // K slots of this row
-                double g = 0.0;
-                for (int sp0 = 0; sp0 < ns; sp0 += U) {
-                    PT v[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        v[u] = (sp0 + u < ns) ? pp[(long)(sp0 + u) * split_stride] : (PT)0;
-#pragma unroll
-                    for (int u = 0; u < U; ++u) g += (double)v[u];
-                }
-                if (fscale) g *= inv_s2 / (double)rscale[i];
-                mx[1] = fmax(mx[1], rt);
-                if (folded) {
-                    mx[2] = fmax(mx[2], fabs(g + x * rt));
-                    craw[q] = g;
-                } else {
-                    mx[2] = fmax(mx[2], fabs(g));
-                    craw[q] = g - x * rt;
-                }
             }
         }
     }
-    block_max<4>(mx, red);
+    if constexpr (!EXT) {
+        // split partials: up to 32 (FP32) or 16 (FP64) loads per thread in
+        // flight over all its grid points, each row's added in split order.
+        // With `folded` the partials already hold gain - loss (the loss term
+        // is part of the GEMM operand) and the loss rates, when given, only
+        // feed the diagnostics.
+        constexpr int U = (sizeof(PT) == 4 ? KXG_EPI_U : 16) / PER > 0 ? (sizeof(PT) == 4 ? KXG_EPI_U : 16) / PER : 1;
+        int ns[PER], nsmax = 0;
+        double g[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = epi_tl<TPB>() + TPB * q;
+            ns[q] = i < n ? (nslot ? nslot[i / kIBlk] : nsplit) : 0;   // K slots of this row
+            nsmax = ns[q] > nsmax ? ns[q] : nsmax;
+            g[q] = 0.0;
+        }
+        for (int sp0 = 0; sp0 < nsmax; sp0 += U) {
+            PT v[PER][U];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const PT *pp = part + (long)b * ld_b + epi_tl<TPB>() + TPB * q;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    v[q][u] = (sp0 + u < ns[q]) ? pp[(long)(sp0 + u) * split_stride] : (PT)0;
+            }
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+#pragma unroll
+                for (int u = 0; u < U; ++u) g[q] += (double)v[q][u];
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = epi_tl<TPB>() + TPB * q;
+            if (i >= n) continue;
+            double gq = g[q];
+            if (fscale) gq *= inv_s2 / (double)rscale[i];
+            const double rt = rate ? rate[(long)b * n + i] : 0.0;
+            const double x = fv[q];
+            mx[1] = fmax(mx[1], rt);
+            if (folded) {
+                mx[2] = fmax(mx[2], fabs(gq + x * rt));
+                craw[q] = gq;
+            } else {
+                mx[2] = fmax(mx[2], fabs(gq));
+                craw[q] = gq - x * rt;
+            }
+        }
+    }
+    grp_max<4, TPB>(mx, red);
     const double fmaxv = mx[0];
     // s0, s1, b00, b01, b11, sum h|C|, sum hE|C|, sum hEC, number
     double sm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x + 256 * q;
+        const int i = epi_tl<TPB>() + TPB * q;
         xi[q] = 0.0;
         if (i < n) {
             const double hi = hv[q], ki = kv[q], ei = ev[q];
@@ -892,7 +949,7 @@ __global__ __launch_bounds__(256) void k_epilogue(
             sm[8] += hi * fv[q];
         }
     }
-    block_sum<9>(sm, red);
+    grp_sum<9, TPB>(sm, red);
     const double s0 = sm[0], s1 = sm[1], b00 = sm[2], b01 = sm[3], b11 = sm[4];
     const double an = sm[5], ae = sm[6], se = sm[7], num = sm[8];
     double al = 0.0, be = 0.0;
@@ -906,7 +963,7 @@ __global__ __launch_bounds__(256) void k_epilogue(
     double out[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x + 256 * q;
+        const int i = epi_tl<TPB>() + TPB * q;
         out[q] = 0.0;
         if (i < n) {
             const double hi = hv[q], ei = ev[q];
@@ -923,18 +980,18 @@ __global__ __launch_bounds__(256) void k_epilogue(
         }
     }
     if (step.mode != kStepNone) {
-        step_update<PER>(step, b, n, out, in, red);
+        step_update<PER, TPB>(step, b, n, out, in, red);
         return;
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x + 256 * q;
+        const int i = epi_tl<TPB>() + TPB * q;
         if (i < n) C[(long)b * n + i] = out[q];
     }
     if (diag) {
-        block_sum<6>(tt, red);
-        block_max<1>(bad, red);
-        if (threadIdx.x == 0) {
+        grp_sum<6, TPB>(tt, red);
+        grp_max<1, TPB>(bad, red);
+        if (epi_tl<TPB>() == 0) {
             double *d = diag + (long)b * KXG_NDIAG;
             d[0] = al - be * mass;
             d[1] = be;
@@ -961,7 +1018,7 @@ __global__ __launch_bounds__(256) void k_epilogue(
 // i = thread + 256 q), in the layouts and with the FP16 scaling of k_prep;
 // the padding (grid points n.. and rows beyond the batch) keeps the zeros
 // written by k_prep at the start of the run.
-template <int PER>
+template <int PER, int TPB>
 __device__ void write_operand(const StepArgs &A, int b, int n, const double (&nf)[PER],
                               double *lds)
 {
@@ -970,14 +1027,14 @@ __device__ void write_operand(const StepArgs &A, int b, int n, const double (&nf
         double m[1] = {0.0};
 #pragma unroll
         for (int q = 0; q < PER; ++q)
-            if ((int)threadIdx.x + 256 * q < n) m[0] = fmax(m[0], fabs(nf[q]));
-        block_max<1>(m, lds);
+            if ((int)epi_tl<TPB>() + TPB * q < n) m[0] = fmax(m[0], fabs(nf[q]));
+        grp_max<1, TPB>(m, lds);
         if (m[0] > 0.0 && isfinite(m[0])) sc = (float)ldexp(1.0, 7 - (int)ceil(log2(m[0])));
-        if (threadIdx.x == 0) A.fscale[b] = sc;
+        if (epi_tl<TPB>() == 0) A.fscale[b] = sc;
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x + 256 * q;
+        const int i = epi_tl<TPB>() + TPB * q;
         if (i >= n) continue;
         const float x = (float)nf[q] * sc;
         const int blk = i / kBlk, d = i % kBlk;
@@ -994,7 +1051,7 @@ __device__ void write_operand(const StepArgs &A, int b, int n, const double (&nf
 // dt *= clamp(safety err^-1/2, fac_lo, fac_hi), clipped to end at t_end.
 // Every thread reaches the same decision (block reductions); thread 0
 // writes the slot record.
-template <int PER>
+template <int PER, int TPB>
 __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)[PER],
                             const StepIn<PER> &in, double *lds)
 {
@@ -1008,7 +1065,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
         double bad[1] = {0.0};
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int i = threadIdx.x + 256 * q;
+            const int i = epi_tl<TPB>() + TPB * q;
             nf[q] = 0.0;
             if (i >= n) continue;
             const double xv = in.x[q];
@@ -1027,10 +1084,10 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
             A.fb[row + i] = v;
             nf[q] = v;
         }
-        if (A.write_op) write_operand<PER>(A, b, n, nf, lds);
+        if (A.write_op) write_operand<PER, TPB>(A, b, n, nf, lds);
         if (A.stage == 4) {
-            block_max<1>(bad, lds);
-            if (threadIdx.x == 0 && running) {
+            grp_max<1, TPB>(bad, lds);
+            if (epi_tl<TPB>() == 0 && running) {
                 S.t = u + dt;
                 S.steps += 1;
                 if (bad[0] > 0.0) S.status = -1;
@@ -1044,7 +1101,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
     if (A.mode == kStepHeunPred) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int i = threadIdx.x + 256 * q;
+            const int i = epi_tl<TPB>() + TPB * q;
             nf[q] = 0.0;
             if (i >= n) continue;
             const double xv = in.x[q];
@@ -1061,7 +1118,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
             nf[q] = A.expansion ? g_to_f(v, A.p[i], u + dt) : v;
             A.fb[row + i] = nf[q];
         }
-        if (A.write_op) write_operand<PER>(A, b, n, nf, lds);
+        if (A.write_op) write_operand<PER, TPB>(A, b, n, nf, lds);
         return;
     }
     // Heun corrector and control
@@ -1069,7 +1126,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
     double ev[2] = {0.0, 0.0};              // err, non-finite flag
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x + 256 * q;
+        const int i = epi_tl<TPB>() + TPB * q;
         xn[q] = 0.0;
         if (i >= n || !running) continue;
         const double xsv = in.xs[q];
@@ -1082,7 +1139,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
         if (!isfinite(v)) ev[1] = 1.0;
         ev[0] = fmax(ev[0], isfinite(e) ? e : 1e300);
     }
-    block_max<2>(ev, lds);
+    grp_max<2, TPB>(ev, lds);
     const double err = ev[0], nonfin = ev[1];
     int accept = 0, status = S.status, steps = S.steps, rej = S.rejected;
     double tnew = u, dtnew = dt, outflow = S.outflow;
@@ -1114,7 +1171,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int i = threadIdx.x + 256 * q;
+        const int i = epi_tl<TPB>() + TPB * q;
         nf[q] = 0.0;
         if (i >= n) continue;
         double v = in.x[q];
@@ -1125,8 +1182,8 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
         nf[q] = A.expansion ? g_to_f(v, A.p[i], tnew) : v;
         A.fb[row + i] = nf[q];
     }
-    if (A.write_op) write_operand<PER>(A, b, n, nf, lds);
-    if (threadIdx.x == 0 && running) {
+    if (A.write_op) write_operand<PER, TPB>(A, b, n, nf, lds);
+    if (epi_tl<TPB>() == 0 && running) {
         S.t = tnew;
         S.dt = dtnew;
         S.steps = steps;
@@ -1144,17 +1201,29 @@ hipError_t launch_epilogue(const PT *part, int nsplit, const int *nslot, long sp
                            const double *ext = nullptr, double eta = 0.0, int folded = 0)
 {
     const int n = k.n;
-    const dim3 grid(B), blk(256);
+    // threads per distribution: a wave for handles built for large batches
+    // (more distributions in flight), else the whole workgroup; fixed per
+    // handle, so a row's reduction order does not depend on B
+    const int tpb = k.b_cap >= 2048 ? 64 : 256;
+    const dim3 grid(tpb == 64 ? (B + 3) / 4 : B), blk(256);
     StepArgs sa{};
     if (step) sa = *step;
     else sa.mode = kStepNone;
-#define KXG_EPI(P)                                                                             \
-    hipLaunchKernelGGL((k_epilogue<PT, P>), grid, blk, 0, s, part, nsplit, nslot, split_stride, ld_b, \
+#define KXG_EPI1(P, X, T)                                                                      \
+    hipLaunchKernelGGL((k_epilogue<PT, P, X, T>), grid, blk, 0, s, part, nsplit, nslot, split_stride, ld_b, \
                        fscale, rscale, rate, f, k.d_h, k.d_K, k.d_E, k.mass, n, B, project, C, \
                        diag, sa, ext, eta, folded)
-    if (n <= 256) KXG_EPI(1);
-    else if (n <= 512) KXG_EPI(2);
-    else KXG_EPI(4);
+#define KXG_EPI(P, T) if (ext) KXG_EPI1(P, true, T); else KXG_EPI1(P, false, T)
+    if (tpb == 256) {
+        if (n <= 256) KXG_EPI(1, 256);
+        else if (n <= 512) KXG_EPI(2, 256);
+        else KXG_EPI(4, 256);
+    } else {
+        if (n <= 256) KXG_EPI(4, 64);
+        else if (n <= 512) KXG_EPI(8, 64);
+        else KXG_EPI(16, 64);
+    }
+#undef KXG_EPI1
 #undef KXG_EPI
     return hipGetLastError();
 }
