@@ -237,20 +237,27 @@ def main():
     st = kxg.Stepper(ker, kind=kxg.RK4, prec=kxg.F32, b_cap=B)
     for b, s in enumerate(w.solves):
         st.set(b, f0[b], lam=s.lam, t_end=1e30, h_i=1.0)
-    st.advance(args.warmup)
-    torch.cuda.synchronize()
-    kxg.profile_begin(4 * args.steps + 8)
+    # the timed steps run as they do in production: on a stream of their own,
+    # each step one replay of the captured iteration (HIP graph)
+    run_stream = torch.cuda.Stream()
+    st.advance(args.warmup, stream=run_stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st.advance(args.steps)
+    st.advance(args.steps, stream=run_stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gemm_ms, gemm_n = kxg.profile_end()
     ms_step = 1e3 * wall / args.steps
     value = 4 * B / (wall / args.steps)
     q = st.query()
     bad = sum(1 for x in q[:B] if x["status"] < 0)
     log("batched f32 RK4: %.3f ms/step, %.3e C-evals/s, %d failed slots" % (ms_step, value, bad))
+    # GEMM launch times for the roofline: a further run of the same steps
+    # with timing events around every GEMM launch (direct launches)
+    prof_steps = min(args.steps, 100)
+    kxg.profile_begin(4 * prof_steps + 8)
+    st.advance(prof_steps, stream=run_stream)
+    torch.cuda.synchronize()
+    gemm_ms, gemm_n = kxg.profile_end()
     gemm_avg_ms = gemm_ms / max(gemm_n, 1)
     # executed MFMA work: the kept 32 x 16 x 16 blocks of the packed operand
     # (blocks the kinematic cuts leave all zero are skipped), all B rows
@@ -313,14 +320,16 @@ def main():
             st4 = kxg.Stepper(k4, kind=kxg.RK4, prec=prec, b_cap=4096)
             for b, s in enumerate(w4.solves):
                 st4.set(b, f4[b], lam=s.lam, t_end=1e30, h_i=1.0)
-            st4.advance(3)
+            st4.advance(3, stream=run_stream)
             torch.cuda.synchronize()
             steps4 = 20
-            kxg.profile_begin(4 * steps4 + 8)
             t0 = time.perf_counter()
-            st4.advance(steps4)
+            st4.advance(steps4, stream=run_stream)
             torch.cuda.synchronize()
             wl = (time.perf_counter() - t0) / steps4
+            kxg.profile_begin(4 * 5 + 8)
+            st4.advance(5, stream=run_stream)
+            torch.cuda.synchronize()
             g_ms, g_n = kxg.profile_end()
             g_us = 1e3 * g_ms / max(g_n, 1)
             # executed MFMA work per GEMM: 3 products over the kept blocks

@@ -33,6 +33,9 @@ inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 #define KXG_STREAM_NT 1
 #endif
 // shape of the LDS-shared 16-bit GEMM: b-blocks and i-blocks per wave
+#ifndef KXG_EPI_WAVE_BCAP
+#define KXG_EPI_WAVE_BCAP 2048   // handles from this b_cap get a wave per distribution in the epilogue
+#endif
 #ifndef KXG_EPI_U
 #define KXG_EPI_U 32         // FP32 split partials in flight per thread in the epilogue
 #endif
@@ -57,16 +60,32 @@ __device__ inline int xcd_logical(int bid, int nwg)
 // Stream gain: grid (split, i, group of BT distributions).  Each workgroup
 // reads a contiguous chunk of row i of the dense tensor once and forms
 // sum A[i][k][m] f_k f_m for its BT distributions, f taken from LDS; the
-// (k, m) position of each element is tracked incrementally.
+// (k, m) position of each element is tracked incrementally.  With RT given,
+// the split-0 workgroups also subtract the loss f_i sum_m R_im f_m (FP64),
+// so the partials sum to gain - loss.
 template <typename T, int VEC, int BT>
 __global__ __launch_bounds__(256) void k_stream(const T *__restrict__ A,
                                                 const double *__restrict__ f, int n, int B,
-                                                int chunk, double *__restrict__ part)
+                                                int chunk, double *__restrict__ part,
+                                                const double *__restrict__ RT)
 {
     extern __shared__ double smem_d[];
     T *fs = reinterpret_cast<T *>(smem_d);
     __shared__ double red[4][BT];
+    __shared__ double redl[4][BT];
     const int split = blockIdx.x, i = blockIdx.y, b0 = blockIdx.z * BT;
+    const bool loss = RT && split == 0;
+    double lsum[BT];
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) lsum[bb] = 0.0;
+    if (loss) {
+        for (int m = threadIdx.x; m < n; m += 256) {
+            const double r = RT[(long)m * n + i];
+#pragma unroll
+            for (int bb = 0; bb < BT; ++bb)
+                if (b0 + bb < B) lsum[bb] += r * f[(long)(b0 + bb) * n + m];
+        }
+    }
     for (int q = threadIdx.x; q < BT * n; q += 256) {
         const int bb = q / n, m = q - bb * n;
         fs[q] = (b0 + bb < B) ? (T)f[(long)(b0 + bb) * n + m] : (T)0;
@@ -135,11 +154,20 @@ __global__ __launch_bounds__(256) void k_stream(const T *__restrict__ A,
         double v = (double)acc[bb];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
         if (lane == 0) red[wave][bb] = v;
+        if (loss) {
+            double l = lsum[bb];
+            for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+            if (lane == 0) redl[wave][bb] = l;
+        }
     }
     __syncthreads();
     if (threadIdx.x < BT && b0 + (int)threadIdx.x < B) {
         const int bb = threadIdx.x;
-        const double v = ((red[0][bb] + red[1][bb]) + red[2][bb]) + red[3][bb];
+        double v = ((red[0][bb] + red[1][bb]) + red[2][bb]) + red[3][bb];
+        if (loss) {
+            const double rate = ((redl[0][bb] + redl[1][bb]) + redl[2][bb]) + redl[3][bb];
+            v -= f[(long)(b0 + bb) * n + i] * rate;
+        }
         part[((long)split * B + b0 + bb) * n + i] = v;
     }
 }
@@ -926,7 +954,16 @@ __global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
             }
         }
     }
-    grp_max<4, TPB>(mx, red);
+    // without diagnostics only f_max and the five projection sums are
+    // reduced (the reductions of single values are the same either way)
+    const bool lean = diag == nullptr;
+    if (lean) {
+        double m1[1] = {mx[0]};
+        grp_max<1, TPB>(m1, red);
+        mx[0] = m1[0];
+    } else {
+        grp_max<4, TPB>(mx, red);
+    }
     const double fmaxv = mx[0];
     // s0, s1, b00, b01, b11, sum h|C|, sum hE|C|, sum hEC, number
     double sm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -949,7 +986,14 @@ __global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
             sm[8] += hi * fv[q];
         }
     }
-    grp_sum<9, TPB>(sm, red);
+    if (lean) {
+        double s5[5] = {sm[0], sm[1], sm[2], sm[3], sm[4]};
+        grp_sum<5, TPB>(s5, red);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) sm[j] = s5[j];
+    } else {
+        grp_sum<9, TPB>(sm, red);
+    }
     const double s0 = sm[0], s1 = sm[1], b00 = sm[2], b01 = sm[3], b11 = sm[4];
     const double an = sm[5], ae = sm[6], se = sm[7], num = sm[8];
     double al = 0.0, be = 0.0;
@@ -1204,7 +1248,7 @@ hipError_t launch_epilogue(const PT *part, int nsplit, const int *nslot, long sp
     // threads per distribution: a wave for handles built for large batches
     // (more distributions in flight), else the whole workgroup; fixed per
     // handle, so a row's reduction order does not depend on B
-    const int tpb = k.b_cap >= 2048 ? 64 : 256;
+    const int tpb = k.b_cap >= KXG_EPI_WAVE_BCAP ? 64 : 256;
     const dim3 grid(tpb == 64 ? (B + 3) / 4 : B), blk(256);
     StepArgs sa{};
     if (step) sa = *step;
@@ -1441,7 +1485,8 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         profile_mark_begin(s);
 #define KXG_ST(T, V, BTV) \
     hipLaunchKernelGGL((k_stream<T, V, BTV>), grid, dim3(256), shm, s, \
-                       reinterpret_cast<const T *>(dbl ? (const void *)k.d_A64 : (const void *)k.d_A32), f, n, B, chunk, part)
+                       reinterpret_cast<const T *>(dbl ? (const void *)k.d_A64 : (const void *)k.d_A32), f, n, B, chunk, part, \
+                       k.d_RT)
 #define KXG_ST2(T, V) \
     if (BT == 1) KXG_ST(T, V, 1); else if (BT == 2) KXG_ST(T, V, 2); else KXG_ST(T, V, 4)
         if (dbl) {
@@ -1453,9 +1498,11 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
 #undef KXG_ST
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
-        KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
-        KXG_TRY_HIP(launch_epilogue<double>(part, nsplit, nullptr, (long)B * n, n, nullptr, nullptr, rate,
-                                            f, k, B, project, C, diag, step, s));
+        // the split-0 partials carry the loss term; loss rates only for diagnostics
+        if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
+        KXG_TRY_HIP(launch_epilogue<double>(part, nsplit, nullptr, (long)B * n, n, nullptr, nullptr,
+                                            diag ? rate : nullptr, f, k, B, project, C, diag, step, s,
+                                            nullptr, 0.0, 1));
         return KXG_OK;
     }
     const bool f16 = prec == KXG_F16X3;
