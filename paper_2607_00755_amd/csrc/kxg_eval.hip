@@ -488,16 +488,21 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(
 
     F32Stage<BBW, SS> st[NST];
 
+    // (kb, mb) of the next stage to load, read one stage ahead so that the
+    // scalar load is not waited for right before the vector loads it feeds
+    const int2 *pairs2 = reinterpret_cast<const int2 *>(pairs);
+    auto pair_of = [&](long s) { return pairs2[(s < s1 ? s : s1 - 1) / PPS]; };
+    int2 pnext = pair_of(s0);
     auto load_stage = [&](long s, F32Stage<BBW, SS> &x) {
         s = s < s1 ? s : s1 - 1;
+        const int kb = pnext.x, mb = pnext.y;
+        pnext = pair_of(s + 1);
         const float4 *gp = reinterpret_cast<const float4 *>(Gi + s * (SS * 512));
 #pragma unroll
         for (int d = 0; d < SS; ++d) {
             x.g[2 * d] = gp[d * 128 + lane];
             x.g[2 * d + 1] = gp[d * 128 + 64 + lane];
         }
-        const int pr = (int)(s / PPS);
-        const int kb = pairs[2 * pr], mb = pairs[2 * pr + 1];
         const int dk = (int)(s % PPS) * SS;
 #pragma unroll
         for (int bb = 0; bb < BBW; ++bb) {
@@ -509,18 +514,33 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(
             x.fm[bb][1] = src[1];
         }
     };
+    // F2 operand of step q = 8 d + t of a stage: f_k (dk step d) times f_m
+    // (t-th value of this lane's half of the block)
+    auto f2 = [&](const F32Stage<BBW, SS> &x, int q, int bb) {
+        const int d = q >> 3, t = q & 7;
+        return x.fk[bb][d] * x.fm[bb][t >> 2][t & 3];
+    };
+    // The products of step q + 1 are formed before the MFMAs of step q (the
+    // scheduler may not move them across), so a product never takes the
+    // register that an MFMA in flight is reading.
     auto compute = [&](const F32Stage<BBW, SS> &x) {
+        float pv[2][BBW];
 #pragma unroll
-        for (int d = 0; d < SS; ++d) {
-            const float bv[8] = {x.g[2 * d].x, x.g[2 * d].y, x.g[2 * d].z, x.g[2 * d].w,
-                                 x.g[2 * d + 1].x, x.g[2 * d + 1].y, x.g[2 * d + 1].z, x.g[2 * d + 1].w};
+        for (int bb = 0; bb < BBW; ++bb) pv[0][bb] = f2(x, 0, bb);
 #pragma unroll
-            for (int t = 0; t < 8; ++t)
+        for (int q = 0; q < SS * 8; ++q) {
+            const int d = q >> 3, t = q & 7;
+            const float4 gv = x.g[2 * d + (t >> 2)];
+            const float bv = (t & 3) == 0 ? gv.x : (t & 3) == 1 ? gv.y : (t & 3) == 2 ? gv.z : gv.w;
+            if (q + 1 < SS * 8) {
 #pragma unroll
-                for (int bb = 0; bb < BBW; ++bb) {
-                    const float fm = x.fm[bb][t >> 2][t & 3];
-                    acc[bb] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.fk[bb][d] * fm, bv[t], acc[bb], 0, 0, 0);
-                }
+                for (int bb = 0; bb < BBW; ++bb) pv[(q + 1) & 1][bb] = f2(x, q + 1, bb);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int bb = 0; bb < BBW; ++bb)
+                acc[bb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[q & 1][bb], bv, acc[bb], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
     };
 

@@ -27,7 +27,10 @@ constexpr int kBlk = 16;             // (k,m) block edge of the packed GEMM layo
 constexpr int kIBlk = 32;            // output rows (i) per MFMA tile
 constexpr int kBRows = 32;           // distributions per MFMA tile
 constexpr int kWaves = 4;            // waves per GEMM workgroup (split K)
-constexpr int kF32SS = 4;            // dk steps per super-step of the FP32 GEMM (work units)
+#ifndef KXG_F32_SS
+#define KXG_F32_SS 4   // dk steps per super-step of the FP32 GEMM (work units)
+#endif
+constexpr int kF32SS = KXG_F32_SS;
 
 // Tuning of the GEMM launches (overridable at build time).
 #ifndef KXG_GEMM_WG_TARGET
