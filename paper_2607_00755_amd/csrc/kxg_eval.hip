@@ -816,12 +816,22 @@ __device__ inline int epi_tl() { return (int)threadIdx.x % TPB; }
 template <int PER>
 struct StepIn {
     double x[PER], acc[PER], xs[PER], nx[PER];
+    double lam, hi, dt, t;      // the slot's control values (stepper modes only)
+    int status;
 };
 
 template <int PER, int TPB>
 __device__ void load_step_inputs(const StepArgs &A, int b, int n, StepIn<PER> &in)
 {
     const long row = (long)b * n;
+    if (A.mode != kStepNone) {
+        const SlotDev &S = A.sl[b];
+        in.lam = S.lam;
+        in.hi = S.hi_scale;
+        in.dt = S.dt;
+        in.t = S.t;
+        in.status = S.status;
+    }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int i = epi_tl<TPB>() + TPB * q;
@@ -869,23 +879,71 @@ __global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
     StepArgs step, const double *__restrict__ ext, double eta, int folded)
 {
     __shared__ double red[4 * 12];
-    const int b = blockIdx.x * (256 / TPB) + (int)threadIdx.x / TPB;
+    // one distribution per workgroup (TPB = 256) or per wave (TPB = 64)
+    const int b = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / TPB) + (int)threadIdx.x / TPB);
     if constexpr (TPB == 64) {
         if (b >= B) return;                    // whole wave; no barriers with TPB = 64
     }
     const double *fb = f + (long)b * n;
     StepIn<PER> in;
     load_step_inputs<PER, TPB>(step, b, n, in);
-    double hv[PER], kv[PER], ev[PER];          // grid constants, loaded up front
+    // Every load of a thread (grid constants, f, the split partials below)
+    // is issued before the first of them is used: rows past n read row 0
+    // and drop the value, so no load sits behind a branch and a wait.
+    double hv[PER], kv[PER], ev[PER], fv[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int i = epi_tl<TPB>() + TPB * q;
-        hv[q] = i < n ? h[i] : 0.0;
-        kv[q] = i < n ? K[i] : 0.0;
-        ev[q] = i < n ? E[i] : 0.0;
+        const int ic = i < n ? i : 0;
+        const double hx = h[ic], kx = K[ic], ex = E[ic], fx = fb[ic];
+        hv[q] = i < n ? hx : 0.0;
+        kv[q] = i < n ? kx : 0.0;
+        ev[q] = i < n ? ex : 0.0;
+        fv[q] = i < n ? fx : 0.0;
     }
-    double fv[PER], craw[PER], xi[PER];
+    double craw[PER], xi[PER];
     double mx[4] = {0.0, 0.0, 0.0, 0.0};      // f_max, largest rate, largest |gain|, input flag
+    double g[PER] = {};
+    if constexpr (!EXT) {
+        // split partials: up to 32 (FP32) or 16 (FP64) loads per thread in
+        // flight over all its grid points, each row's added in split order.
+        // With `folded` the partials already hold gain - loss (the loss term
+        // is part of the GEMM operand) and the loss rates, when given, only
+        // feed the diagnostics.
+        // Slots up to nsplit (the largest count) are read for every row,
+        // unconditionally (past nsplit the last slot again); slots past the
+        // row's own count, read from the allocated workspace, are dropped in
+        // the sum.
+        constexpr int U = (sizeof(PT) == 4 ? KXG_EPI_U : 16) / PER > 0 ? (sizeof(PT) == 4 ? KXG_EPI_U : 16) / PER : 1;
+        int ns[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = epi_tl<TPB>() + TPB * q;
+            const int nq = nslot ? nslot[(i < n ? i : 0) / kIBlk] : nsplit;   // K slots of this row
+            ns[q] = i < n ? nq : 0;
+        }
+        for (int sp0 = 0; sp0 < nsplit; sp0 += U) {
+            PT v[PER][U];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int i = epi_tl<TPB>() + TPB * q;
+                const PT *pp = part + (long)b * ld_b + (i < n ? i : 0);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int sp = sp0 + u < nsplit ? sp0 + u : nsplit - 1;   // no branch
+                    v[q][u] = pp[(long)sp * split_stride];
+                }
+            }
+            // the row counts are used only below, so that no wait for them
+            // is placed ahead of the loads
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (sp0 + u < ns[q]) g[q] += (double)v[q][u];
+        }
+    }
     double inv_s2 = 1.0;
     if (fscale) {
         const double sc = fscale[b];
@@ -894,11 +952,9 @@ __global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int i = epi_tl<TPB>() + TPB * q;
-        fv[q] = 0.0;
         craw[q] = 0.0;
         if (i < n) {
-            const double x = fb[i];
-            fv[q] = x;
+            const double x = fv[q];
             if (!isfinite(x)) mx[3] = fmax(mx[3], 1.0);
             else if (x < 0.0) mx[3] = fmax(mx[3], 0.5);
             mx[0] = fmax(mx[0], fabs(x));
@@ -927,35 +983,6 @@ __global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
         }
     }
     if constexpr (!EXT) {
-        // split partials: up to 32 (FP32) or 16 (FP64) loads per thread in
-        // flight over all its grid points, each row's added in split order.
-        // With `folded` the partials already hold gain - loss (the loss term
-        // is part of the GEMM operand) and the loss rates, when given, only
-        // feed the diagnostics.
-        constexpr int U = (sizeof(PT) == 4 ? KXG_EPI_U : 16) / PER > 0 ? (sizeof(PT) == 4 ? KXG_EPI_U : 16) / PER : 1;
-        int ns[PER], nsmax = 0;
-        double g[PER];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int i = epi_tl<TPB>() + TPB * q;
-            ns[q] = i < n ? (nslot ? nslot[i / kIBlk] : nsplit) : 0;   // K slots of this row
-            nsmax = ns[q] > nsmax ? ns[q] : nsmax;
-            g[q] = 0.0;
-        }
-        for (int sp0 = 0; sp0 < nsmax; sp0 += U) {
-            PT v[PER][U];
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const PT *pp = part + (long)b * ld_b + epi_tl<TPB>() + TPB * q;
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    v[q][u] = (sp0 + u < ns[q]) ? pp[(long)(sp0 + u) * split_stride] : (PT)0;
-            }
-#pragma unroll
-            for (int q = 0; q < PER; ++q)
-#pragma unroll
-                for (int u = 0; u < U; ++u) g[q] += (double)v[q][u];
-        }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int i = epi_tl<TPB>() + TPB * q;
@@ -1120,12 +1147,12 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
                             const StepIn<PER> &in, double *lds)
 {
     SlotDev &S = A.sl[b];
-    const int running = S.status == 0;
+    const int running = in.status == 0;
     const long row = (long)b * n;
-    const double dt = S.dt, u = S.t;
+    const double dt = in.dt, u = in.t;
     double nf[PER];                            // the next operator input
     if (A.mode == kStepRK4) {
-        const double lam = S.lam / S.hi_scale;
+        const double lam = in.lam / in.hi;
         double bad[1] = {0.0};
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -1175,7 +1202,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
                 nf[q] = A.expansion ? g_to_f(xv, A.p[i], u) : xv;
                 continue;
             }
-            const double k = rhs_u(A.expansion, xv, in.nx[q], out[q], A.p[i], A.dp[i], S.lam, S.hi_scale, u);
+            const double k = rhs_u(A.expansion, xv, in.nx[q], out[q], A.p[i], A.dp[i], in.lam, in.hi, u);
             A.acc[row + i] = k;
             const double v = xv + dt * k;
             A.xs[row + i] = v;
@@ -1194,7 +1221,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
         xn[q] = 0.0;
         if (i >= n || !running) continue;
         const double xsv = in.xs[q];
-        const double k2 = rhs_u(A.expansion, xsv, in.nx[q], out[q], A.p[i], A.dp[i], S.lam, S.hi_scale, u + dt);
+        const double k2 = rhs_u(A.expansion, xsv, in.nx[q], out[q], A.p[i], A.dp[i], in.lam, in.hi, u + dt);
         const double x0 = in.x[q];
         const double v = x0 + 0.5 * dt * (in.acc[q] + k2);
         xn[q] = v;
