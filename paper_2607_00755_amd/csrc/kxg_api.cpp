@@ -153,8 +153,10 @@ struct kxg_stepper {
     Workspace ws;
     std::vector<char> used;
     int b_hi = 0;
-    // one captured iteration (HIP graph) for the current batch bucket
+    // captured iterations (HIP graphs) for the current batch bucket: one,
+    // and kGraphIters in a row (fewer graph launches on long advances)
     hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec_n = nullptr;
     int g_batch = -1;
     hipStream_t g_stream = nullptr;
 };
@@ -673,6 +675,7 @@ void kxg_stepper_free(kxg_stepper *s)
 {
     if (!s) return;
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->gexec_n) (void)hipGraphExecDestroy(s->gexec_n);
     void *ptrs[] = {s->d_slots, s->d_x, s->d_fb, s->d_acc, s->d_xs, s->d_dt};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -773,31 +776,42 @@ static kxg_status enqueue_iteration(kxg_stepper *s, int B, hipStream_t st)
 
 // Capture one iteration over `batch` slots on stream st into an executable
 // graph (re-captured only when the batch bucket or the stream changes).
-static bool ensure_graph(kxg_stepper *s, int batch, hipStream_t st)
+constexpr int kGraphIters = 8;
+
+// Capture `iters` iterations of the stepper on `st` into an executable graph
+// (null if capture or instantiation fails).
+static hipGraphExec_t capture_iterations(kxg_stepper *s, int batch, int iters, hipStream_t st)
 {
-    if (s->gexec && s->g_batch == batch && s->g_stream == st) return true;
-    if (s->gexec) {
-        (void)hipGraphExecDestroy(s->gexec);
-        s->gexec = nullptr;
-    }
-    s->g_batch = -1;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
-    const kxg_status r = enqueue_iteration(s, batch, st);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    kxg_status r = KXG_OK;
+    for (int it = 0; it < iters && r == KXG_OK; ++it) r = enqueue_iteration(s, batch, st);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &graph);
     if (r != KXG_OK || e != hipSuccess || !graph) {
         if (graph) (void)hipGraphDestroy(graph);
         (void)hipGetLastError();
-        return false;
+        return nullptr;
     }
     hipGraphExec_t exec = nullptr;
     const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess || !exec) {
         (void)hipGetLastError();
-        return false;
+        return nullptr;
     }
-    s->gexec = exec;
+    return exec;
+}
+
+static bool ensure_graph(kxg_stepper *s, int batch, hipStream_t st)
+{
+    if (s->gexec && s->g_batch == batch && s->g_stream == st) return true;
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->gexec_n) (void)hipGraphExecDestroy(s->gexec_n);
+    s->gexec = s->gexec_n = nullptr;
+    s->g_batch = -1;
+    s->gexec = capture_iterations(s, batch, 1, st);
+    if (!s->gexec) return false;
+    s->gexec_n = capture_iterations(s, batch, kGraphIters, st);   // optional
     s->g_batch = batch;
     s->g_stream = st;
     return true;
@@ -818,7 +832,10 @@ kxg_status kxg_stepper_advance(kxg_stepper *s, int32_t n_iter, void *stream)
     if (st != nullptr && !g_prof.on && ensure_graph(s, bucket, st)) {
         kxg_status r = prep_operands(*s->k, s->ws, s->prm.prec, s->d_fb, bucket, st);
         if (r != KXG_OK) return r;
-        for (int it = 0; it < n_iter; ++it) KXG_TRY_HIP(hipGraphLaunch(s->gexec, st));
+        int it = 0;
+        if (s->gexec_n)
+            for (; it + kGraphIters <= n_iter; it += kGraphIters) KXG_TRY_HIP(hipGraphLaunch(s->gexec_n, st));
+        for (; it < n_iter; ++it) KXG_TRY_HIP(hipGraphLaunch(s->gexec, st));
         return KXG_OK;
     }
     kxg_status r0 = prep_operands(*s->k, s->ws, s->prm.prec, s->d_fb, B, st);
