@@ -50,20 +50,33 @@ def parse():
     return ap.parse_args()
 
 
-def counted_traffic(profile_md, source):
-    """HBM bytes per launch from a committed counter summary, if it was taken
-    on the current kernel source (sha1 recorded in the summary), else None."""
+def kernel_source_sha1(sources):
+    """sha1 over the kernel's source files, concatenated in the given order."""
     import hashlib
+    h = hashlib.sha1()
+    for src in sources:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return h.hexdigest()
+
+
+GEMM_F32_SOURCES = ("paper_2607_00755_amd/csrc/kxg_gemm_f32.hip",
+                    "paper_2607_00755_amd/csrc/kxg_device.h",
+                    "paper_2607_00755_amd/csrc/kxg_internal.h")
+
+
+def counted_traffic(profile_md, sources):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel sources (sha1 recorded in the summary), else None."""
     try:
         text = open(os.path.join(ROOT, "profiles", profile_md)).read()
-        sha = hashlib.sha1(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+        sha = kernel_source_sha1(sources)
     except OSError:
         return None
     fields = {}
     for line in text.splitlines():
         if ":" in line and line.split(":")[0].strip() in ("kernel_source_sha1", "traffic_bytes_per_launch"):
             k, v = line.split(":", 1)
-            fields[k.strip()] = v.strip().strip("`")
+            fields[k.strip()] = v.split()[0].strip("`")   # first token; a remark may follow
     if fields.get("kernel_source_sha1") != sha or "traffic_bytes_per_launch" not in fields:
         return None
     return int(float(fields["traffic_bytes_per_launch"]))
@@ -91,15 +104,14 @@ def single_paths(args, dev):
     k = kxg.Kernel(p, precs=(kxg.F64,), b_cap=1)
     f = torch.tensor(inputs.draw_solves(1)[0].f0(p)[None, :], device=dev)
     C = torch.empty_like(f)
-    d = torch.empty((1, kxg.NDIAG), dtype=torch.float64, device=dev)
     for _ in range(3):
-        k.eval(f, prec=kxg.F64, out=C, diag=d)
+        k.eval(f, prec=kxg.F64, out=C, diagnostics=False)
     torch.cuda.synchronize()
     reps = 100
     kxg.profile_begin(reps + 2)
     t0 = time.perf_counter()
     for _ in range(reps):
-        k.eval(f, prec=kxg.F64, out=C, diag=d)
+        k.eval(f, prec=kxg.F64, out=C, diagnostics=False)
     torch.cuda.synchronize()
     wl = (time.perf_counter() - t0) / reps
     ms, cnt = kxg.profile_end()
@@ -221,7 +233,7 @@ def main():
         f = torch.tensor(inputs.draw_solves(1)[0].f0(p)[None, :], device=dev)
         C = torch.empty_like(f)
         for _ in range(50):
-            k.eval(f, prec=kxg.F64, out=C)
+            k.eval(f, prec=kxg.F64, out=C, diagnostics=False)
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": "stream384", "evals": 50}), flush=True)
         return
@@ -268,8 +280,7 @@ def main():
     achieved = flops_exec / (gemm_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["f32"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4),
-                "traffic": counted_traffic("gemm_f32_n256_b512.md",
-                                           "paper_2607_00755_amd/csrc/kxg_eval.hip"),
+                "traffic": counted_traffic("gemm_f32_n256_b512.md", GEMM_F32_SOURCES),
                 "kernel": "k_gemm_f32<4>", "avg_launch_us": round(gemm_avg_ms * 1e3, 2),
                 "launches": gemm_n, "flops_per_launch": flops_exec,
                 "packed_flops_per_launch": flops_packed,
@@ -285,17 +296,17 @@ def main():
         torch.cuda.synchronize()
         args.no_extras, args.no_cpu_baseline, args.serve_requests = True, True, 0
     # ---------------- plain FP64 single distribution ----------------
+    # (projected C, no diagnostics: the same output as the batched step)
     f1 = f0[:1].contiguous()
     C1 = torch.empty_like(f1)
-    d1 = torch.empty((1, kxg.NDIAG), dtype=torch.float64, device=dev)
     for _ in range(5):
-        ker.eval(f1, prec=kxg.F64, out=C1, diag=d1)
+        ker.eval(f1, prec=kxg.F64, out=C1, diagnostics=False)
     torch.cuda.synchronize()
     reps = 200
     kxg.profile_begin(reps + 2)
     t0 = time.perf_counter()
     for _ in range(reps):
-        ker.eval(f1, prec=kxg.F64, out=C1, diag=d1)
+        ker.eval(f1, prec=kxg.F64, out=C1, diagnostics=False)
     torch.cuda.synchronize()
     plain_wall = (time.perf_counter() - t0) / reps
     s_ms, s_n = kxg.profile_end()

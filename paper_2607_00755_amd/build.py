@@ -25,6 +25,7 @@ UNITS = {
     "kxg_api.cpp": ["-x", "hip"],
     "kxg_build.hip": ["-ffp-contract=off"],
     "kxg_eval.hip": [],
+    "kxg_gemm_f32.hip": [],
     "kxg_step.hip": [],
 }
 

@@ -124,6 +124,11 @@ hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, hipStream_
 hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_pack_16(const kxg_kernel &k, int ibw, hipStream_t s);
 hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s);
+// FP32 GEMM over the kept blocks: nwg = batch tiles x work units, bbw
+// 32-row b-blocks per wave (1, 2 or 4)
+hipError_t launch_gemm_f32(int bbw, int nwg, const float *G, const float *fop, const float *fpar,
+                           const int *pairs, const int *units, int bpad, int ipad, int nbt, float *part,
+                           hipStream_t s);
 
 struct StepArgs;
 // Evaluate C[f] for B rows; with `step` the epilogue applies that stepper

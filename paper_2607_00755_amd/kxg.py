@@ -231,23 +231,25 @@ class Kernel:
         return dict(zip(("dp", "E", "K", "h"), out))
 
     def eval(self, f, prec: int = F64, project: bool = True, out=None, diag=None, stream=None,
-             log_interp: bool = False, eta: int = 0):
+             log_interp: bool = False, eta: int = 0, diagnostics: bool = True):
         """C[f] for f of shape [B, n] (device float64).  Returns (C, diag).
         log_interp / eta (+1 Bose-Einstein, -1 Fermi-Dirac) select the exact
-        form of the operator (handle built with brackets=True)."""
+        form of the operator (handle built with brackets=True).  With
+        diagnostics=False no diagnostics are computed and diag is None."""
         import torch
         if f.dim() == 1:
             f = f.view(1, -1)
         B = f.shape[0]
         if out is None:
             out = torch.empty_like(f)
-        if diag is None:
+        if diag is None and diagnostics:
             diag = torch.empty((B, NDIAG), dtype=torch.float64, device=f.device)
         flags = (PROJECT if project else 0) | (INTERP_LOG if log_interp else 0)
         flags |= STAT_BOSE if eta > 0 else (STAT_FERMI if eta < 0 else 0)
         _check(lib().kxg_eval(self._h, int(prec), _dev_ptr(f, B * self.n, "f"), B,
                               _dev_ptr(out, B * self.n, "C"), flags,
-                              _dev_ptr(diag, B * NDIAG, "diag"), _stream_ptr(stream)))
+                              _dev_ptr(diag, B * NDIAG, "diag") if diag is not None else None,
+                              _stream_ptr(stream)))
         return out, diag
 
     def moments(self, f, out=None, stream=None):

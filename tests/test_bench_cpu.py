@@ -1,0 +1,43 @@
+"""Host-side checks of bench.py: the JSON contract fields it computes without
+a GPU (counter lookup, --gpus guard)."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_counted_traffic_matches_current_sources(tmp_path, monkeypatch):
+    """The committed counter summary is used only while the GEMM sources are
+    the ones it was taken on."""
+    sha = bench.kernel_source_sha1(bench.GEMM_F32_SOURCES)
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "x.md").write_text("kernel_source_sha1: `%s`  (a remark)\ntraffic_bytes_per_launch: 123\n" % sha)
+    (prof / "y.md").write_text("kernel_source_sha1: `%s`\ntraffic_bytes_per_launch: 123\n" % ("0" * 40))
+    src = tmp_path / "paper_2607_00755_amd" / "csrc"
+    src.mkdir(parents=True)
+    for s in bench.GEMM_F32_SOURCES:
+        (tmp_path / s).write_bytes(open(os.path.join(ROOT, s), "rb").read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.counted_traffic("x.md", bench.GEMM_F32_SOURCES) == 123
+    assert bench.counted_traffic("y.md", bench.GEMM_F32_SOURCES) is None
+    assert bench.counted_traffic("missing.md", bench.GEMM_F32_SOURCES) is None
+    # a changed kernel source invalidates the summary
+    (tmp_path / bench.GEMM_F32_SOURCES[0]).write_bytes(b"changed")
+    assert bench.counted_traffic("x.md", bench.GEMM_F32_SOURCES) is None
+
+
+def test_committed_gemm_profile_is_parseable():
+    text = open(os.path.join(ROOT, "profiles", "gemm_f32_n256_b512.md")).read()
+    assert "kernel_source_sha1:" in text and "traffic_bytes_per_launch:" in text
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)

@@ -337,6 +337,52 @@ def test_graph_replay_matches_eager(dev, kind, prec, B):
         assert [x["steps"] for x in q0[:B]] == [x["steps"] for x in q1[:B]]
 
 
+@pytest.mark.parametrize("kind,prec", [(kxg.RK4, kxg.F32), (kxg.HEUN, kxg.F64)])
+def test_multi_iteration_graph_matches_eager(dev, kind, prec):
+    """Long advances on a side stream replay a graph of eight captured
+    iterations (then single ones for the rest); the state after 8 + 11
+    iterations must equal that of the same iterations launched eagerly."""
+    B = 24
+    p = inputs.log_grid(40, 1e-3, 20.0)
+    f0 = batch(p, B, seed=21)
+    k = kxg.Kernel(p, precs=(prec,), b_cap=32)
+    exp = kxg.EXP_RADIATION if kind == kxg.HEUN else kxg.EXP_NONE
+    steppers = [kxg.Stepper(k, kind=kind, prec=prec, b_cap=32, expansion=exp) for _ in range(2)]
+    side = torch.cuda.Stream()
+    for st in steppers:
+        for b in range(B):
+            st.set(b, torch.tensor(f0[b], device=dev), lam=1.5, t_end=1e3, h_i=0.0)
+    torch.cuda.synchronize()
+    out = [torch.empty(40, dtype=torch.float64, device=dev) for _ in range(2)]
+    for n_iter in (8, 11):
+        steppers[0].advance(n_iter, stream=side)
+        side.synchronize()
+        steppers[1].advance(n_iter)
+        torch.cuda.synchronize()
+        for b in range(B):
+            steppers[0].get(b, out=out[0], stream=side)
+            side.synchronize()
+            steppers[1].get(b, out=out[1])
+            torch.cuda.synchronize()
+            assert torch.equal(out[0], out[1]), (n_iter, b)
+        q0, q1 = steppers[0].query(stream=side), steppers[1].query()
+        assert [x["steps"] for x in q0[:B]] == [x["steps"] for x in q1[:B]]
+        assert [x["t"] for x in q0[:B]] == [x["t"] for x in q1[:B]]
+
+
+@pytest.mark.parametrize("prec", ALL)
+def test_eval_without_diagnostics_same_C(dev, prec):
+    """With no diagnostics buffer the operator output is bitwise the same."""
+    p = inputs.log_grid(64, 1e-3, 20.0)
+    f = torch.tensor(batch(p, 5, seed=4), device=dev)
+    k = kxg.Kernel(p, precs=(prec,), b_cap=8)
+    C1, d1 = k.eval(f, prec=prec)
+    C2, d2 = k.eval(f, prec=prec, diagnostics=False)
+    torch.cuda.synchronize()
+    assert d2 is None and d1 is not None
+    assert torch.equal(C1, C2)
+
+
 @pytest.mark.parametrize("prec", [kxg.BF16X3, kxg.F16X3])
 def test_eval_16bit_large_batch_lds_path(dev, prec):
     """B >= 512 takes the LDS-shared GEMM: ragged batch (600 -> 1024 rows) and
