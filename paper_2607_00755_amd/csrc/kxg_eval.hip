@@ -20,6 +20,9 @@
 namespace kxg {
 namespace {
 
+typedef float floatx8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x8 __attribute__((ext_vector_type(8)));
+
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
 #ifndef KXG_STREAM_UNROLL
@@ -475,15 +478,26 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
             }
 #pragma unroll
             for (int bb = 0; bb < BBW; ++bb) {
-                const float fmv[8] = {x.fm[bb][0].x, x.fm[bb][0].y, x.fm[bb][0].z, x.fm[bb][0].w,
-                                      x.fm[bb][1].x, x.fm[bb][1].y, x.fm[bb][1].z, x.fm[bb][1].w};
+                // F2 = f_k f_m for this lane's 8 K values, split hi + lo as
+                // whole vectors (conversions two values per instruction).
+                // BF16: hi is the product with its low 16 bits cleared (exact
+                // in BF16, no conversion), lo = product - hi is exact in FP32
+                // and rounded to BF16; FP16: hi rounded, lo = product - hi.
+                const float4 m0 = x.fm[bb][0], m1 = x.fm[bb][1];
+                const floatx8 fmv = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+                const floatx8 pv = x.fk[bb][d] * fmv;
                 opx8 ph, pl;
+                if constexpr (F16) {
+                    ph = __builtin_convertvector(pv, opx8);
+                    pl = __builtin_convertvector(pv - __builtin_convertvector(ph, floatx8), opx8);
+                } else {
+                    const u32x8 bits = __builtin_bit_cast(u32x8, pv);
+                    const u32x8 hb = bits & 0xFFFF0000u;
+                    u32x4 hw;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const float pv = x.fk[bb][d] * fmv[j];
-                    const op_t h = (op_t)pv;
-                    ph[j] = h;
-                    pl[j] = (op_t)(pv - (float)h);
+                    for (int j = 0; j < 4; ++j) hw[j] = (bits[2 * j] >> 16) | hb[2 * j + 1];
+                    ph = __builtin_bit_cast(opx8, hw);
+                    pl = __builtin_convertvector(pv - __builtin_bit_cast(floatx8, hb), opx8);
                 }
                 // three products, smallest first
 #pragma unroll
