@@ -428,12 +428,13 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
     const float *fmb = fop + (long)(brow0 + r) * kBlk + 8 * hb;
     // loader role: vector q = threadIdx.x + 256 c of a super-step belongs to
     // i-block q / VPS of the group; block c of the compacted operand holds
-    // IBW * 16 * 128 vectors
-    const u32x4 *qsrc[NQ];
+    // IBW * 16 * 128 vectors.  The lane offsets are 32-bit and added to a
+    // uniform base per stage (scalar base, no 64-bit address arithmetic).
+    int qoff[NQ];
 #pragma unroll
     for (int c = 0; c < NQ; ++c) {
         const int q = threadIdx.x + 256 * c;
-        qsrc[c] = reinterpret_cast<const u32x4 *>(G) + (long)(q / VPS) * kBlk * 128 + (q % VPS);
+        qoff[c] = (q / VPS) * kBlk * 128 + (q % VPS);
     }
 
     floatx16 acc[BBW][IBW];
@@ -448,8 +449,9 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
     auto load_stage = [&](long s, Stage &x) {
         s = s < s1 ? s : s1 - 1;
         const long cb = s / PPS, d0 = (s % PPS) * SS;   // block, first dk step
+        const u32x4 *Gs = reinterpret_cast<const u32x4 *>(G) + (cb * IBW * kBlk + d0) * 128;
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) x.gv[c] = qsrc[c][(cb * IBW * kBlk + d0) * 128];
+        for (int c = 0; c < NQ; ++c) x.gv[c] = Gs[qoff[c]];
         const int pr = (int)(s / PPS);
         const int kb = pairs[2 * pr], mb = pairs[2 * pr + 1];
         const int dk = (int)(s % PPS) * SS;
