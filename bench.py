@@ -61,7 +61,7 @@ def kernel_source_sha1(sources):
 
 GEMM_F32_SOURCES = ("paper_2607_00755_amd/csrc/kxg_gemm_f32.hip",
                     "paper_2607_00755_amd/csrc/kxg_device.h",
-                    "paper_2607_00755_amd/csrc/kxg_internal.h")
+                    "paper_2607_00755_amd/csrc/kxg_geom.h")
 
 
 def counted_traffic(profile_md, sources):

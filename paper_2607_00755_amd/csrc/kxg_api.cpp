@@ -130,7 +130,7 @@ static kxg_status dalloc(T **ptr, size_t count)
 static void release(kxg_kernel *k)
 {
     if (!k) return;
-    void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_A32,
+    void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_R, k->d_A32,
                     k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs, k->d_JL, k->d_invdK,
                     k->d_pairs_c, k->d_cib, k->d_units, k->d_nslot, k->d_pairs16, k->d_cit16,
                     k->d_units16, k->d_nslot16};
@@ -452,6 +452,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     KXG_ALLOC(k->d_h, n);
     KXG_ALLOC(k->d_A64, n3);
     KXG_ALLOC(k->d_RT, n2);
+    KXG_ALLOC(k->d_R, n2);
     KXG_ALLOC(k->d_pairs, 2 * (size_t)g.npairs);
     if (want32) { KXG_ALLOC(k->d_A32, n3); }
     if (wanth) { KXG_ALLOC(k->d_hrow, (size_t)g.ipad); }

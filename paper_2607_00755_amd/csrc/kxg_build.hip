@@ -355,6 +355,17 @@ inline int grid_for(long work, int block = 256, int cap = 1 << 20)
 
 }  // namespace
 
+// R in row order (R[i][j]) from its transpose, for the row-wise loss of the
+// single-distribution stream.
+__global__ __launch_bounds__(256) void k_transpose(int n, const double *__restrict__ RT,
+                                                   double *__restrict__ R)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long)n * n) return;
+    const int i = (int)(t / n), j = (int)(t % n);
+    R[t] = RT[(long)j * n + i];
+}
+
 hipError_t launch_build_A(const kxg_kernel &k, const double *d_xmu, const double *d_wmu,
                           hipStream_t s)
 {
@@ -370,6 +381,7 @@ hipError_t launch_build_R(const kxg_kernel &k, hipStream_t s)
     const long total = (long)k.n * k.n;
     hipLaunchKernelGGL(k_build_R, dim3(grid_for(total, 64)), dim3(64), 0, s, k.n, k.d_K,
                        k.d_A64, k.d_RT);
+    hipLaunchKernelGGL(k_transpose, dim3(grid_for(total)), dim3(256), 0, s, k.n, k.d_RT, k.d_R);
     return hipGetLastError();
 }
 

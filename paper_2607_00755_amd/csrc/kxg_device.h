@@ -1,7 +1,9 @@
 // Device helpers shared by the GEMM translation units.
 #pragma once
 
-#include "kxg_internal.h"
+#include <hip/hip_runtime.h>
+
+#include "kxg_geom.h"
 
 namespace kxg {
 

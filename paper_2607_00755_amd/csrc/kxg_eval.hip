@@ -13,6 +13,7 @@
 //     workgroups (and over the 4 waves of each); partials are reduced in FP64
 //     by the epilogue in a fixed order, independent of the batch size.
 #include "kxg_device.h"
+#include "kxg_internal.h"
 #include "kxg_step.h"
 
 #include <type_traits>
@@ -46,27 +47,27 @@ inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 // Stream gain: grid (split, i, group of BT distributions).  Each workgroup
 // reads a contiguous chunk of row i of the dense tensor once and forms
 // sum A[i][k][m] f_k f_m for its BT distributions, f taken from LDS; the
-// (k, m) position of each element is tracked incrementally.  With RT given,
-// the split-0 workgroups also subtract the loss f_i sum_m R_im f_m (FP64),
-// so the partials sum to gain - loss.
+// (k, m) position of each element is tracked incrementally.  With R given
+// (row order), the split-0 workgroups also subtract the loss
+// f_i sum_m R_im f_m (FP64), so the partials sum to gain - loss.
 template <typename T, int VEC, int BT>
 __global__ __launch_bounds__(256) void k_stream(const T *__restrict__ A,
                                                 const double *__restrict__ f, int n, int B,
                                                 int chunk, double *__restrict__ part,
-                                                const double *__restrict__ RT)
+                                                const double *__restrict__ R)
 {
     extern __shared__ double smem_d[];
     T *fs = reinterpret_cast<T *>(smem_d);
     __shared__ double red[4][BT];
     __shared__ double redl[4][BT];
     const int split = blockIdx.x, i = blockIdx.y, b0 = blockIdx.z * BT;
-    const bool loss = RT && split == 0;
+    const bool loss = R && split == 0;
     double lsum[BT];
 #pragma unroll
     for (int bb = 0; bb < BT; ++bb) lsum[bb] = 0.0;
     if (loss) {
         for (int m = threadIdx.x; m < n; m += 256) {
-            const double r = RT[(long)m * n + i];
+            const double r = R[(long)i * n + m];
 #pragma unroll
             for (int bb = 0; bb < BT; ++bb)
                 if (b0 + bb < B) lsum[bb] += r * f[(long)(b0 + bb) * n + m];
@@ -404,7 +405,6 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
     float *__restrict__ part)
 {
     typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
-    typedef typename std::conditional<F16, _Float16, __bf16>::type op_t;
     typedef float fkvec __attribute__((ext_vector_type(SS)));
     constexpr int VPS = SS * 128;                  // 16-byte vectors per i-block and super-step
     constexpr int NV = IBW * VPS;                  // per super-step
@@ -1355,7 +1355,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
 #define KXG_ST(T, V, BTV) \
     hipLaunchKernelGGL((k_stream<T, V, BTV>), grid, dim3(256), shm, s, \
                        reinterpret_cast<const T *>(dbl ? (const void *)k.d_A64 : (const void *)k.d_A32), f, n, B, chunk, part, \
-                       k.d_RT)
+                       k.d_R)
 #define KXG_ST2(T, V) \
     if (BT == 1) KXG_ST(T, V, 1); else if (BT == 2) KXG_ST(T, V, 2); else KXG_ST(T, V, 4)
         if (dbl) {

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/kxg.h"
+#include "kxg_geom.h"
 
 namespace kxg {
 
@@ -23,14 +24,6 @@ void set_error(const char *fmt, ...);
     } while (0)
 
 constexpr int kMaxN = 1024;          // largest grid
-constexpr int kBlk = 16;             // (k,m) block edge of the packed GEMM layout
-constexpr int kIBlk = 32;            // output rows (i) per MFMA tile
-constexpr int kBRows = 32;           // distributions per MFMA tile
-constexpr int kWaves = 4;            // waves per GEMM workgroup (split K)
-#ifndef KXG_F32_SS
-#define KXG_F32_SS 4   // dk steps per super-step of the FP32 GEMM (work units)
-#endif
-constexpr int kF32SS = KXG_F32_SS;
 
 // Tuning of the GEMM launches (overridable at build time).
 #ifndef KXG_GEMM_WG_TARGET
@@ -85,6 +78,7 @@ struct kxg_kernel {
     double *d_p = nullptr, *d_dp = nullptr, *d_E = nullptr, *d_K = nullptr, *d_h = nullptr;
     double *d_A64 = nullptr;     // [n][n][n] FP64 master, m fastest
     double *d_RT = nullptr;      // [n][n] R transposed: RT[j][i] = R[i][j]
+    double *d_R = nullptr;       // [n][n] R in row order
     float *d_A32 = nullptr;      // [n][n][n] FP32 copy (single-f stream)
     float *d_G32 = nullptr;      // packed GEMM operand, FP32
     uint16_t *d_Gbf = nullptr;   // packed GEMM operand, BF16 hi/lo
