@@ -42,6 +42,13 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=800,
                     help="measured serving requests (after --serve-warm warm-up ones); 0 = skip")
     ap.add_argument("--serve-warm", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-check", type=int, default=8,
+                    help="measured requests re-run alone and compared with their result in the mix")
+    ap.add_argument("--serve-sweep", default="",
+                    help="comma-separated arrival rates of a saturation sweep (e.g. 5,10,20,50); empty = none")
+    ap.add_argument("--serve-sweep-requests", type=int, default=120,
+                    help="measured requests per sweep rate (after a fifth as many warm-up ones)")
     ap.add_argument("--profile-run", nargs="?", const="gemm", default=None,
                     choices=("gemm", "stream384"),
                     help="short run for profilers: 'gemm' = the timed RK4 steps, the plain "
@@ -80,6 +87,49 @@ def counted_traffic(profile_md, sources):
     if fields.get("kernel_source_sha1") != sha or "traffic_bytes_per_launch" not in fields:
         return None
     return int(float(fields["traffic_bytes_per_launch"]))
+
+
+def serving_alone_check(serving, reqs, done, warm, count):
+    """Re-run `count` measured requests alone (fresh server, same path) and
+    compare their final state with the one they reached in the mix."""
+    import numpy as np
+    from paper_2607_00755_amd import inputs, kxg
+    mixed = {r.rid: r for r in done if r.rid >= warm and r.status == 1}
+    ids = sorted(mixed)
+    sample = ids[::max(1, len(ids) // count)][:count]
+    worst, same_steps = 0.0, True
+    for rid in sample:
+        one = reqs[rid]
+        alone = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16, keep_results=True)
+        solo = alone.run([inputs.Solve(one.lam, one.p_low, one.p_high, one.ratio, n=one.n,
+                                       t_end=one.t_end, arrival=0.0)])[0]
+        a, b = solo.result, mixed[rid].result
+        worst = max(worst, float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+        same_steps = same_steps and solo.steps == mixed[rid].steps
+        del alone
+    return {"requests": len(sample), "max_rel_diff": worst, "same_steps": same_steps}
+
+
+def serving_sweep(serving, args):
+    """Arrival-rate sweep of the serving loop: p50/p99 latency and solves/s
+    per rate (the rate where p99 runs away is the sustainable limit)."""
+    from paper_2607_00755_amd import inputs, kxg
+    out = []
+    nr = args.serve_sweep_requests
+    nw = max(1, nr // 5)
+    for rate in [float(x) for x in args.serve_sweep.split(",") if x.strip()]:
+        reqs = inputs.serving_requests(nw + nr, rate=rate)
+        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16)
+        t0 = time.perf_counter()
+        done = srv.run(reqs)
+        st = srv.stats(done, warm=nw)
+        out.append({"rate_req_per_s": rate, "requests": nr, "p50_s": round(st["p50_s"], 3),
+                    "p99_s": round(st["p99_s"], 3), "solves_per_s": round(st["solves_per_s"], 2),
+                    "completed": st["completed"], "wall_s": round(time.perf_counter() - t0, 1)})
+        log("serving sweep %.1f req/s: p50 %.3f s p99 %.3f s, %.2f solves/s" %
+            (rate, st["p50_s"], st["p99_s"], st["solves_per_s"]))
+        del srv
+    return out
 
 
 def packed_k(n):
@@ -363,19 +413,27 @@ def main():
     serve = None
     if args.serve_requests > 0:
         from paper_2607_00755_amd import serving
-        reqs = inputs.serving_requests(args.serve_warm + args.serve_requests)
-        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16)
+        reqs = inputs.serving_requests(args.serve_warm + args.serve_requests, rate=args.serve_rate)
+        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16, keep_results=args.serve_check > 0)
         t0 = time.perf_counter()
         done = srv.run(reqs)
         el = time.perf_counter() - t0
         serve = srv.stats(done, warm=args.serve_warm)
         serve.update({"requests": args.serve_requests, "warmup_requests": args.serve_warm,
-                      "rate_req_per_s": 200.0, "wall_s": round(el, 2), "prec": "f32",
+                      "rate_req_per_s": args.serve_rate, "wall_s": round(el, 2), "prec": "f32",
                       "stepper": "adaptive Heun in ln a, rtol 1e-6, radiation drift"})
         serve["mean_batch"] = {str(k): round(v, 1) for k, v in serve["mean_batch"].items()}
         log("serving: p50 %.3f s p99 %.3f s, %.2f solves/s" %
             (serve["p50_s"], serve["p99_s"], serve["solves_per_s"]))
         del srv
+        if args.serve_check > 0:
+            serve["alone_check"] = serving_alone_check(serving, reqs, done, args.serve_warm, args.serve_check)
+            log("serving: %d requests re-run alone, max rel diff %.2e, same steps %s" %
+                (serve["alone_check"]["requests"], serve["alone_check"]["max_rel_diff"],
+                 serve["alone_check"]["same_steps"]))
+        done = None
+        if args.serve_sweep:
+            extras["serving_sweep"] = serving_sweep(serving, args)
 
     # ---------------- CPU oracle baseline ----------------
     cpu = None

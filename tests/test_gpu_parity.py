@@ -154,6 +154,49 @@ def test_batch_invariance_bitwise(dev):
             assert np.array_equal(part.cpu().numpy(), full[sel]), (prec, len(sel))
 
 
+@pytest.mark.parametrize("n", [40, 200])
+def test_single_distribution_stream_bitwise(dev, n):
+    """The FP64 stream path evaluates one distribution (one per pass) and
+    three (grouped passes); the result and the diagnostics of a row must
+    not depend on that, over many calls in a row."""
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    f0 = batch(p, 3, seed=31)
+    k = kxg.Kernel(p, precs=(kxg.F64,), b_cap=8)
+    f3 = torch.tensor(f0, device=dev)
+    for rnd in range(25):
+        scale = 1.0 + 0.1 * rnd
+        C3, d3 = k.eval(f3 * scale, prec=kxg.F64)
+        b = rnd % 3
+        C1, d1 = k.eval((f3[b:b + 1] * scale).contiguous(), prec=kxg.F64)
+        torch.cuda.synchronize()
+        assert torch.equal(C1[0], C3[b]), (rnd, b)
+        assert torch.equal(d1[0], d3[b]), (rnd, b)
+    C, _ = k.eval(f3[:1].contiguous(), prec=kxg.F64)
+    assert rel(C.cpu().numpy(), oracle_C(oracle.Operator(p), f0[:1], True)) <= TOL[kxg.F64]
+
+
+def test_single_slot_fp64_stepper_matches_batched_slot(dev):
+    """A one-slot FP64 stepper follows the same trajectory, bit for bit, as
+    the same solve in a three-slot stepper."""
+    n = 48
+    p = inputs.log_grid(n, 1e-2, 10.0)
+    f0 = batch(p, 3, seed=5)
+    k = kxg.Kernel(p, precs=(kxg.F64,), b_cap=4)
+    one = kxg.Stepper(k, kind=kxg.RK4, prec=kxg.F64, b_cap=1)
+    three = kxg.Stepper(k, kind=kxg.RK4, prec=kxg.F64, b_cap=3)
+    one.set(0, torch.tensor(f0[1], device=dev), lam=1.0, t_end=1e9, h_i=1.0)
+    for b in range(3):
+        three.set(b, torch.tensor(f0[b], device=dev), lam=1.0, t_end=1e9, h_i=1.0)
+    side = torch.cuda.Stream()
+    one.advance(12, stream=side)
+    three.advance(12, stream=side)
+    side.synchronize()
+    a = one.get(0, stream=side)
+    c = three.get(1, stream=side)
+    side.synchronize()
+    assert torch.equal(a, c)
+
+
 def test_edge_cases(dev):
     p = inputs.log_grid(16, 1e-2, 5.0)
     k = kxg.Kernel(p, precs=(kxg.F64, kxg.F32), b_cap=9)
