@@ -370,6 +370,25 @@ def main():
     extras["batched_vs_plain_fp64"] = round(value / plain, 1)
     log("plain fp64 N=256: %.1f us/eval (stream kernel %.1f us, %.0f GB/s)" %
         (1e6 * plain_wall, stream_us, bytes_stream / (stream_us * 1e-6) / 1e9))
+    if not args.no_extras:
+        # the same evaluation with the 134 MB tensor evicted from the 256 MB
+        # MALL first (a 1 GiB buffer written between evaluations)
+        scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        cold = []
+        for r in range(20):
+            scratch.fill_(float(r))
+            kxg.profile_begin(2)
+            ker.eval(f1, prec=kxg.F64, out=C1, diagnostics=False)
+            torch.cuda.synchronize()
+            c_ms, c_n = kxg.profile_end()
+            cold.append(1e3 * c_ms / max(c_n, 1))
+        del scratch
+        cold_us = sorted(cold)[len(cold) // 2]
+        extras["plain_fp64"]["cold_stream_kernel_us"] = round(cold_us, 2)
+        extras["plain_fp64"]["cold_stream_GBps"] = round(bytes_stream / (cold_us * 1e-6) / 1e9, 1)
+        extras["plain_fp64"]["cold_hbm_frac"] = round(bytes_stream / (cold_us * 1e-6) / 1e9 / HBM_PEAK, 4)
+        log("plain fp64 N=256 cold: stream kernel %.1f us (median of 20), %.0f GB/s" %
+            (cold_us, bytes_stream / (cold_us * 1e-6) / 1e9))
 
     if not args.no_extras:
         # ---------------- 16-bit split at B = 4096: RK4 steps ----------------

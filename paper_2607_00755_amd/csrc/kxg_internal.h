@@ -33,10 +33,10 @@ constexpr int kMaxN = 1024;          // largest grid
 #define KXG_LDS_WG_TARGET 512   // workgroups of one 16-bit GEMM launch at the handle's largest batch
 #endif
 #ifndef KXG_LDS_SS
-#define KXG_LDS_SS 4   // dk steps per LDS stage of the 16-bit GEMM
+#define KXG_LDS_SS 2   // dk steps per LDS stage of the 16-bit GEMM
 #endif
 #ifndef KXG_LDS_BBW
-#define KXG_LDS_BBW 1   // 32-row batch blocks per wave of the 16-bit GEMM
+#define KXG_LDS_BBW 2   // 32-row batch blocks per wave of the 16-bit GEMM
 #endif
 #ifndef KXG_LDS_IBW
 #define KXG_LDS_IBW 4   // i-blocks per workgroup of the 16-bit GEMM
