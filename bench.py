@@ -472,6 +472,25 @@ def main():
                "sample": "%d evaluations of one N=256 distribution (FP64 A/R contraction + "
                          "projection) in %.1f s" % (cnt, el)}
         log("cpu oracle: %.2f C-evals/s on %d threads" % (cnt / el, threads))
+        if not args.no_extras:
+            # further rows: one thread at N = 256, all threads at N = 32, 128, 384
+            rows = []
+            for nn, th, secs in ((256, 1, 3.0), (32, threads, 1.5), (128, threads, 1.5), (384, threads, 3.0)):
+                oracle.set_threads(th)
+                pp = inputs.log_grid(nn, 1e-3, 20.0)
+                o2 = oracle.Operator(pp)
+                fx = inputs.draw_solves(1)[0].f0(pp)
+                o2.collision(fx, project=True)
+                c2, t1 = 0, time.perf_counter()
+                while time.perf_counter() - t1 < secs:
+                    o2.collision(fx, project=True)
+                    c2 += 1
+                e2 = time.perf_counter() - t1
+                rows.append({"n": nn, "threads": th, "C_evals_per_s": round(c2 / e2, 2), "evals": c2})
+                del o2
+            oracle.set_threads(threads)
+            extras["cpu_oracle_rows"] = rows
+            log("cpu oracle rows: %s" % rows)
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "C-evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
