@@ -515,6 +515,32 @@ def test_batched_fp32_rk4_subsample(dev):
         assert rel(st.get(b).cpu().numpy(), ref) <= TOL[kxg.F32], b
 
 
+def test_batched_fp32_rk4_2000_steps_subsample(dev):
+    """The full batched FP32 run (N=256, B=512, 2000 RK4 steps as graph
+    replays on a side stream): 8 seeded solves within 1e-5 of the FP64
+    oracle at the end."""
+    w = inputs.batched_fp32_n256(512)
+    p = w.grid()
+    f0 = w.f0()
+    k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=512)
+    st = kxg.Stepper(k, kind=kxg.RK4, prec=kxg.F32, b_cap=512)
+    ft = torch.tensor(f0, device=dev)
+    for b, s in enumerate(w.solves):
+        st.set(b, ft[b], lam=s.lam, t_end=1e30, h_i=1.0)
+    side = torch.cuda.Stream()
+    st.advance(2000, stream=side)
+    side.synchronize()
+    q = st.query(stream=side)
+    op = oracle.Operator(p)
+    for b in np.linspace(0, 511, 8).astype(int):
+        assert q[b]["steps"] == 2000
+        s = w.solves[b]
+        dt = 0.1 / (s.lam * op.gamma0(f0[b]))
+        ref = op.rk4(f0[b], s.lam, dt, 2000)
+        got = st.get(int(b), stream=side).cpu().numpy()
+        assert rel(got, ref) <= TOL[kxg.F32], (b, rel(got, ref))
+
+
 @pytest.mark.parametrize("prec", [kxg.BF16X3, kxg.F16X3])
 def test_mixed_precision_2000_steps_subsample(dev, prec):
     """N=256, B=4096 16-bit split contraction with FP64 projection and state:
