@@ -50,10 +50,12 @@ def parse():
     ap.add_argument("--serve-sweep-requests", type=int, default=120,
                     help="measured requests per sweep rate (after a fifth as many warm-up ones)")
     ap.add_argument("--profile-run", nargs="?", const="gemm", default=None,
-                    choices=("gemm", "stream384"),
+                    choices=("gemm", "stream384", "x3"),
                     help="short run for profilers: 'gemm' = the timed RK4 steps, the plain "
                          "FP64 path and a 1 GiB device copy (the calibration kernel); "
-                         "'stream384' = 50 plain FP64 evaluations at N = 384 and the copy")
+                         "'stream384' = 50 plain FP64 evaluations at N = 384 and the copy; "
+                         "'x3' = --steps 16-bit RK4 steps (BF16x3, then FP16x3) at N = 256, "
+                         "B = 4096 and the copy")
     return ap.parse_args()
 
 
@@ -286,6 +288,27 @@ def main():
             k.eval(f, prec=kxg.F64, out=C, diagnostics=False)
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": "stream384", "evals": 50}), flush=True)
+        return
+    if args.profile_run == "x3":
+        # the 16-bit workload: N = 256, B = 4096 RK4 steps in BF16x3 and FP16x3
+        # (graph replays on a side stream), then the calibration copy
+        w4 = inputs.mixed_n256(4096)
+        p4 = w4.grid()
+        f4 = torch.tensor(w4.f0(), device=dev)
+        k4 = kxg.Kernel(p4, precs=(kxg.BF16X3, kxg.F16X3), b_cap=4096)
+        side = torch.cuda.Stream()
+        for prec in (kxg.BF16X3, kxg.F16X3):
+            st4 = kxg.Stepper(k4, kind=kxg.RK4, prec=prec, b_cap=4096)
+            for b, s in enumerate(w4.solves):
+                st4.set(b, f4[b], lam=s.lam, t_end=1e30, h_i=1.0)
+            st4.advance(args.steps, stream=side)
+            side.synchronize()
+            del st4
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": "x3", "steps": args.steps}), flush=True)
         return
 
     # ---------------- batched FP32 RK4 (the timed step) ----------------

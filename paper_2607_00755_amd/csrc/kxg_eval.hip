@@ -1,17 +1,22 @@
 // Evaluation of C[f] = gain - loss for a batch of distributions
 // (Sec. 4.1 eq. discrete_collision_operator of arXiv 2607.00755, linear
-// interpolation form), with the FP64 epilogue: loss term, two-moment
-// projection (App. C) and diagnostics.
+// interpolation form), with the FP64 epilogue: split-K reduction, two-moment
+// projection (App. C), diagnostics and the stepper's stage update.
 //
-// gain paths
+// contraction paths (each yields gain - loss in its partials)
 //   * stream: one pass over the dense tensor A[i][k][m] per group of up to
-//     4 distributions, f staged in LDS; HBM-bound (single distribution).
-//   * GEMM: gain[b][i] = sum_K F2[b][K] A'[i][K] with K = (k,m) over the
-//     block-packed (k <= m) tensor, F2[b][(k,m)] = f_bk f_bm formed in
-//     registers, on the MFMA units (FP32 32x32x2, or BF16/FP16 32x32x16 with a
-//     hi+lo split of A' and of F2: hi*hi + hi*lo + lo*hi).  K is split over
-//     workgroups (and over the 4 waves of each); partials are reduced in FP64
-//     by the epilogue in a fixed order, independent of the batch size.
+//     4 distributions, f staged in LDS, the loss row f_i sum_m R_im f_m added
+//     by the first K split of each row; HBM-bound (single distribution).
+//   * GEMM: C[b][i] = sum_K F2[b][K] A'[i][K] with K = (k,m) over the
+//     block-packed (k <= m) tensor with the loss folded in
+//     (A' = A - delta_ik R_im), F2[b][(k,m)] = f_bk f_bm formed in registers,
+//     on the MFMA units (FP32 32x32x2 in kxg_gemm_f32.hip, or BF16/FP16
+//     32x32x16 here with a hi+lo split of A' and of F2: hi*hi + hi*lo +
+//     lo*hi).  K is split over workgroups (and over the 4 waves of each);
+//     partials are reduced in FP64 by the epilogue in a fixed order,
+//     independent of the batch size.
+//   * exact forms (log interpolation, quantum statistics): k_stream_x.
+// The loss rates R f (k_rate) are computed only for the diagnostics.
 #include "kxg_device.h"
 #include "kxg_internal.h"
 #include "kxg_step.h"
