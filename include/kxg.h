@@ -249,7 +249,12 @@ kxg_status kxg_stepper_release(kxg_stepper *s, int32_t slot, void *stream);
 
 /* Advance every running slot by n_iter iterations (RK4: steps; Heun:
  * attempted steps, two operator calls each).  Slots that reach t_end,
- * max_steps or fail stop by themselves on the device.  Asynchronous. */
+ * max_steps or fail stop by themselves on the device.  On a non-default
+ * stream the iterations replay HIP graphs captured on first use (eight
+ * iterations per replay, then single ones for the rest; recaptured when the
+ * batch bucket or the stream changes); on the default stream, or while a
+ * profile is open, they are launched directly.  Same results either way.
+ * Asynchronous. */
 kxg_status kxg_stepper_advance(kxg_stepper *s, int32_t n_iter, void *stream);
 
 /* Set the next dt of every slot from host memory dt_host [b_cap] (replay of
