@@ -482,7 +482,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        threads = oracle.max_threads()
         op = oracle.Operator(p)
         fb = w.f0()[0]
         op.collision(fb, project=True)

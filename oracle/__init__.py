@@ -64,7 +64,14 @@ def _f64(a) -> np.ndarray:
 
 
 def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (timing only)."""
     os.environ["OMP_NUM_THREADS"] = str(n)
+    lib().or_set_threads(ctypes.c_int(int(n)))
+
+
+def max_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(lib().or_max_threads())
 
 
 class Grid:

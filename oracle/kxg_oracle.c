@@ -19,6 +19,7 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -605,3 +606,10 @@ int or_heun(int n, const double *A, const double *R, const double *p,
     free(xn); free(f); free(c); free(tmp);
     return acc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Thread count of the OpenMP loops (timing of the oracle only).            */
+/* ------------------------------------------------------------------------ */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+int or_max_threads(void) { return omp_get_max_threads(); }

@@ -1,6 +1,8 @@
 """Host-side checks of bench.py: the JSON contract fields it computes without
 a GPU (counter lookup, --gpus guard)."""
 import json
+
+import numpy as np
 import os
 import subprocess
 import sys
@@ -41,3 +43,20 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_oracle_thread_control_takes_effect():
+    """The CPU baseline rows time the oracle at a given thread count; the
+    count must reach the OpenMP runtime even after it has started."""
+    import oracle
+    from paper_2607_00755_amd import inputs
+    before = oracle.max_threads()
+    op = oracle.Operator(inputs.log_grid(12, 1e-2, 5.0))
+    op.collision(np.ones(12))          # OpenMP runtime started
+    try:
+        oracle.set_threads(1)
+        assert oracle.max_threads() == 1
+        oracle.set_threads(2)
+        assert oracle.max_threads() == 2
+    finally:
+        oracle.set_threads(before)
