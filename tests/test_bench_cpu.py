@@ -1,11 +1,11 @@
 """Host-side checks of bench.py: the JSON contract fields it computes without
 a GPU (counter lookup, --gpus guard)."""
 import json
-
-import numpy as np
 import os
 import subprocess
 import sys
+
+import numpy as np
 
 import bench
 
