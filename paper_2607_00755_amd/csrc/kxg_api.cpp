@@ -132,8 +132,8 @@ static void release(kxg_kernel *k)
     if (!k) return;
     void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_R, k->d_A32,
                     k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs, k->d_JL, k->d_invdK,
-                    k->d_pairs_c, k->d_cib, k->d_units, k->d_nslot, k->d_pairs16, k->d_cit16,
-                    k->d_units16, k->d_nslot16};
+                    k->d_pairs_c, k->d_cib, k->d_units, k->d_pairs16, k->d_cit16,
+                    k->d_units16};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     free_workspace(k->ws);
@@ -230,6 +230,16 @@ static hipError_t h2d(T *dst, const std::vector<T> &src)
     return hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
+// Slot counts of the i-blocks, packed for the epilogue (16 bits each).
+static SlotCounts pack_slot_counts(const std::vector<int> &per_ib)
+{
+    SlotCounts c;
+    c.per_block = 1;
+    for (size_t ib = 0; ib < per_ib.size() && ib < 32; ++ib)
+        c.w[ib / 4] |= (uint64_t)(per_ib[ib] & 0xFFFF) << (16 * (ib % 4));
+    return c;
+}
+
 static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want32, bool wantbf, bool wanth,
                                 hipStream_t s)
 {
@@ -278,12 +288,11 @@ static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want32, bool want
         if (st == KXG_OK) st = dalloc(&k->d_pairs_c, std::max<size_t>(2, pairs_c.size()));
         if (st == KXG_OK) st = dalloc(&k->d_cib, std::max<size_t>(1, cib.size()));
         if (st == KXG_OK) st = dalloc(&k->d_units, std::max<size_t>(4, U.units.size()));
-        if (st == KXG_OK) st = dalloc(&k->d_nslot, (size_t)g.nib);
         if (st != KXG_OK) return st;
         e = h2d(k->d_pairs_c, pairs_c);
         if (e == hipSuccess) e = h2d(k->d_cib, cib);
         if (e == hipSuccess) e = h2d(k->d_units, U.units);
-        if (e == hipSuccess) e = h2d(k->d_nslot, U.nslot);
+        k->nslot = pack_slot_counts(U.nslot);
         if (e == hipSuccess) e = launch_pack_f32(*k, s);
     }
     if (e == hipSuccess && (wantbf || wanth)) {
@@ -303,12 +312,11 @@ static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want32, bool want
         if (st == KXG_OK) st = dalloc(&k->d_pairs16, std::max<size_t>(2, pairs_c.size()));
         if (st == KXG_OK) st = dalloc(&k->d_cit16, std::max<size_t>(1, cit.size()));
         if (st == KXG_OK) st = dalloc(&k->d_units16, std::max<size_t>(4, U.units.size()));
-        if (st == KXG_OK) st = dalloc(&k->d_nslot16, (size_t)g.nib);
         if (st != KXG_OK) return st;
         e = h2d(k->d_pairs16, pairs_c);
         if (e == hipSuccess) e = h2d(k->d_cit16, cit);
         if (e == hipSuccess) e = h2d(k->d_units16, U.units);
-        if (e == hipSuccess) e = h2d(k->d_nslot16, nslot_ib);
+        k->nslot16 = pack_slot_counts(nslot_ib);
         if (e == hipSuccess) e = launch_pack_16(*k, w, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);

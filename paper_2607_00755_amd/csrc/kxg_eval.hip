@@ -640,6 +640,25 @@ __device__ inline int epi_tl() { return (int)threadIdx.x % TPB; }
 
 // Stepper inputs of one slot, loaded at the start of the epilogue so that
 // their latency overlaps that of the split partials.
+// K slots of i-block ib (wave-uniform) from the packed counts; 0 past 32.
+// The words pass through readfirstlane so that the selection stays among
+// scalar registers (an indexed load of the argument block would be a
+// memory access the partial loads must wait behind).
+__device__ inline int slot_count(const SlotCounts &c, int ib)
+{
+    const int j = ib >> 2;
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const uint32_t l = __builtin_amdgcn_readfirstlane((uint32_t)c.w[t]);
+        const uint32_t h = __builtin_amdgcn_readfirstlane((uint32_t)(c.w[t] >> 32));
+        lo = j == t ? l : lo;
+        hi = j == t ? h : hi;
+    }
+    const uint64_t w = ((uint64_t)hi << 32) | lo;
+    return ib < 32 ? (int)((w >> (16 * (ib & 3))) & 0xFFFF) : 0;
+}
+
 template <int PER>
 struct StepIn {
     double x[PER], acc[PER], xs[PER], nx[PER];
@@ -698,7 +717,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
 // of a distribution does not depend on B.
 template <typename PT, int PER, bool EXT, int TPB>
 __global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
-    const PT *__restrict__ part, int nsplit, const int *__restrict__ nslot, long split_stride, int ld_b,
+    const PT *__restrict__ part, int nsplit, SlotCounts nsc, long split_stride, int ld_b,
     const float *__restrict__ fscale, const float *__restrict__ rscale,
     const double *__restrict__ rate, const double *__restrict__ f,
     const double *__restrict__ h, const double *__restrict__ K, const double *__restrict__ E,
@@ -746,7 +765,15 @@ __global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int i = epi_tl<TPB>() + TPB * q;
-            const int nq = nslot ? nslot[(i < n ? i : 0) / kIBlk] : nsplit;   // K slots of this row
+            // K slots of this row: the 64 rows of a wave span the i-block of
+            // its first row and the next one
+            int nq = nsplit;
+            if (nsc.per_block) {
+                const int ib0 = __builtin_amdgcn_readfirstlane((epi_tl<TPB>() + TPB * q) / kIBlk);
+                const int c0 = __builtin_amdgcn_readfirstlane(slot_count(nsc, ib0));
+                const int c1 = __builtin_amdgcn_readfirstlane(slot_count(nsc, ib0 + 1));
+                nq = i / kIBlk == ib0 ? c0 : c1;
+            }
             ns[q] = i < n ? nq : 0;
         }
         for (int sp0 = 0; sp0 < nsplit; sp0 += U) {
@@ -1112,7 +1139,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
 }
 
 template <typename PT>
-hipError_t launch_epilogue(const PT *part, int nsplit, const int *nslot, long split_stride, int ld_b,
+hipError_t launch_epilogue(const PT *part, int nsplit, const SlotCounts &nsc, long split_stride, int ld_b,
                            const float *fscale, const float *rscale, const double *rate,
                            const double *f, const kxg_kernel &k, int B, int project, double *C,
                            double *diag, const StepArgs *step, hipStream_t s,
@@ -1128,7 +1155,7 @@ hipError_t launch_epilogue(const PT *part, int nsplit, const int *nslot, long sp
     if (step) sa = *step;
     else sa.mode = kStepNone;
 #define KXG_EPI1(P, X, T)                                                                      \
-    hipLaunchKernelGGL((k_epilogue<PT, P, X, T>), grid, blk, 0, s, part, nsplit, nslot, split_stride, ld_b, \
+    hipLaunchKernelGGL((k_epilogue<PT, P, X, T>), grid, blk, 0, s, part, nsplit, nsc, split_stride, ld_b, \
                        fscale, rscale, rate, f, k.d_h, k.d_K, k.d_E, k.mass, n, B, project, C, \
                        diag, sa, ext, eta, folded)
 #define KXG_EPI(P, T) if (ext) KXG_EPI1(P, true, T); else KXG_EPI1(P, false, T)
@@ -1335,7 +1362,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
 #undef KXG_SX
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
-        KXG_TRY_HIP(launch_epilogue<double>(ext, nsplit, nullptr, 0, 0, nullptr, nullptr, rate, f, k, B,
+        KXG_TRY_HIP(launch_epilogue<double>(ext, nsplit, SlotCounts{}, 0, 0, nullptr, nullptr, rate, f, k, B,
                                             (flags & KXG_PROJECT) ? 1 : 0, C, diag, step, s, ext,
                                             eta));
         return KXG_OK;
@@ -1374,7 +1401,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         KXG_TRY_HIP(hipGetLastError());
         // the split-0 partials carry the loss term; loss rates only for diagnostics
         if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
-        KXG_TRY_HIP(launch_epilogue<double>(part, nsplit, nullptr, (long)B * n, n, nullptr, nullptr,
+        KXG_TRY_HIP(launch_epilogue<double>(part, nsplit, SlotCounts{}, (long)B * n, n, nullptr, nullptr,
                                             diag ? rate : nullptr, f, k, B, project, C, diag, step, s,
                                             nullptr, 0.0, 1));
         return KXG_OK;
@@ -1402,7 +1429,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         KXG_TRY_HIP(hipGetLastError());
         // the loss term is folded into the operand; loss rates only for diagnostics
         if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
-        KXG_TRY_HIP(launch_epilogue<float>(part, k.maxslots16, k.d_nslot16, (long)bpad * g.ipad, g.ipad,
+        KXG_TRY_HIP(launch_epilogue<float>(part, k.maxslots16, k.nslot16, (long)bpad * g.ipad, g.ipad,
                                            f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr,
                                            diag ? rate : nullptr, f, k, B, project, C, diag, step, s,
                                            nullptr, 0.0, 1));
@@ -1424,7 +1451,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     KXG_TRY_HIP(hipGetLastError());
     // the loss term is folded into the operand; loss rates only for diagnostics
     if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
-    KXG_TRY_HIP(launch_epilogue<float>(part, k.maxslots, k.d_nslot, (long)bpad * g.ipad, g.ipad,
+    KXG_TRY_HIP(launch_epilogue<float>(part, k.maxslots, k.nslot, (long)bpad * g.ipad, g.ipad,
                                        nullptr, nullptr, diag ? rate : nullptr, f, k, B, project, C,
                                        diag, step, s, nullptr, 0.0, 1));
     return KXG_OK;

@@ -55,6 +55,14 @@ struct Geometry {
     long dksteps = 0;  // npairs * 16
 };
 
+// K-slot (split partial) counts of the i-blocks, 16 bits each for up to 32
+// i-blocks (n <= 1024), handed to the epilogue by value so that no load
+// of a table delays the loads of the partials.
+struct SlotCounts {
+    uint64_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int per_block = 0;          // 0: every row has the call's nsplit slots
+};
+
 // Per-handle (or per-stepper) evaluation workspace.
 struct Workspace {
     void *part = nullptr;       // split partial gains
@@ -91,13 +99,14 @@ struct kxg_kernel {
     int *d_pairs_c = nullptr;    // [ncomp][2] (kb, mb)
     int *d_cib = nullptr;        // [ncomp] i-block of each compacted pair
     int *d_units = nullptr;      // [nunits][4] (i-block, slot, first, end super-step)
-    int *d_nslot = nullptr;      // [nib] K slots (partials) of each i-block
+    kxg::SlotCounts nslot;       // K slots (partials) of each i-block
     long ncomp = 0;              // non-zero (i-block, pair) blocks
     int nunits = 0, maxslots = 0;
     // the same for the 16-bit operands, per group of KXG_LDS_IBW i-blocks
     // (union of their non-zero pairs); Gbf/Gh hold [block][i-block of the
     // group][dk][hi|lo][lane][8]
-    int *d_pairs16 = nullptr, *d_cit16 = nullptr, *d_units16 = nullptr, *d_nslot16 = nullptr;
+    int *d_pairs16 = nullptr, *d_cit16 = nullptr, *d_units16 = nullptr;
+    kxg::SlotCounts nslot16;
     long ncomp16 = 0;
     int nunits16 = 0, maxslots16 = 0;
     uint16_t *d_JL = nullptr;    // [n][n][n] interpolation bracket j_L (0xFFFF: cut)
