@@ -444,7 +444,29 @@ def main():
                 "blocks": blocks16}
             log("%s B=4096 RK4: %.3f ms/step, gemm %.1f us" % (name, 1e3 * wl, g_us))
             del st4
-        del k4
+        # split ablations: error of 256 rows against the FP64 path, GEMM time at B = 4096
+        k64 = kxg.Kernel(p, precs=(kxg.F64,), b_cap=256)
+        rows = f4[:256].contiguous()
+        ref, _ = k64.eval(rows, prec=kxg.F64, diagnostics=False)
+        abl = {}
+        for prec, name in ((kxg.BF16X3, "bf16"), (kxg.F16X3, "f16")):
+            for split, sname in ((3, "x3"), (2, "f_only_split"), (1, "no_split")):
+                C, _ = k4.eval(rows, prec=prec, diagnostics=False, split=split)
+                err = ((C - ref).abs().max(dim=1).values / ref.abs().max(dim=1).values).max().item()
+                C4 = torch.empty_like(f4)
+                k4.eval(f4, prec=prec, out=C4, diagnostics=False, split=split)
+                torch.cuda.synchronize()
+                kxg.profile_begin(8)
+                for _ in range(5):
+                    k4.eval(f4, prec=prec, out=C4, diagnostics=False, split=split)
+                torch.cuda.synchronize()
+                a_ms, a_n = kxg.profile_end()
+                abl["%s_%s" % (name, sname)] = {"max_rel_err": float("%.3g" % err),
+                                                "gemm_us": round(1e3 * a_ms / max(a_n, 1), 1)}
+                del C4
+        extras["split_ablation_b4096"] = abl
+        log("split ablations: %s" % abl)
+        del k4, k64
 
     if not args.no_extras:
         # ---------------- single-distribution paths ----------------

@@ -145,6 +145,10 @@ kxg_status kxg_kernel_grid(const kxg_kernel *k, double *dp, double *E,
                               1e-300) instead of linear interpolation of f    */
 #define KXG_STAT_BOSE 4u   /* Bose-Einstein factors (eq. Lambda_quantum, eta=+1) */
 #define KXG_STAT_FERMI 8u  /* Fermi-Dirac factors (eq. Lambda_quantum, eta=-1)   */
+#define KXG_SPLIT_F_ONLY 16u /* ablation, 16-bit precisions: A not split, only
+                                F2 split (products hi*hi + lo*hi)              */
+#define KXG_SPLIT_NONE 32u   /* ablation, 16-bit precisions: no split at all
+                                (the product hi*hi alone)                      */
 #define KXG_NDIAG 12       /* diagnostics per distribution, see kxg_eval     */
 
 /* Evaluate C[f] for B distributions (Sec. 4.1 eq. discrete_collision_
@@ -168,8 +172,11 @@ kxg_status kxg_kernel_grid(const kxg_kernel *k, double *dp, double *E,
  *          11 number moment sum_i h_i f_i.
  *  1 <= B <= b_cap of the handle.  Calls on one handle share its workspace:
  *  serialise them on one stream.  Asynchronous.
- * Errors: KXG_EINVAL (bad flags, both statistics), KXG_EUNSUPPORTED
- * (precision or bracket table not built, exact form at 16-bit), KXG_EHIP. */
+ * KXG_SPLIT_F_ONLY / KXG_SPLIT_NONE drop products of the hi+lo split of the
+ * 16-bit contraction (accuracy ablations; 16-bit precisions only).
+ * Errors: KXG_EINVAL (bad flags, both statistics, both ablations, an
+ * ablation at FP64/FP32), KXG_EUNSUPPORTED (precision or bracket table not
+ * built, exact form at 16-bit), KXG_EHIP. */
 kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev,
                     int32_t B, double *C_dev, uint32_t flags, double *diag_dev,
                     void *stream);

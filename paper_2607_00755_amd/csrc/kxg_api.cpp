@@ -605,7 +605,9 @@ kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev, int3
     g_err[0] = 0;
     if (!k || !f_dev || !C_dev) { set_error("kxg_eval: null handle or buffer"); return KXG_EINVAL; }
     if (B < 1 || B > k->b_cap) { set_error("kxg_eval: B=%d outside [1, b_cap=%d]", B, k->b_cap); return KXG_EINVAL; }
-    if (flags & ~(KXG_PROJECT | KXG_INTERP_LOG | KXG_STAT_BOSE | KXG_STAT_FERMI)) { set_error("kxg_eval: unknown flags 0x%x", flags); return KXG_EINVAL; }
+    if (flags & ~(KXG_PROJECT | KXG_INTERP_LOG | KXG_STAT_BOSE | KXG_STAT_FERMI | KXG_SPLIT_F_ONLY | KXG_SPLIT_NONE)) { set_error("kxg_eval: unknown flags 0x%x", flags); return KXG_EINVAL; }
+    if ((flags & KXG_SPLIT_F_ONLY) && (flags & KXG_SPLIT_NONE)) { set_error("kxg_eval: two split ablations together"); return KXG_EINVAL; }
+    if ((flags & (KXG_SPLIT_F_ONLY | KXG_SPLIT_NONE)) && prec != KXG_BF16X3 && prec != KXG_F16X3) { set_error("kxg_eval: split ablations apply to the 16-bit precisions only"); return KXG_EINVAL; }
     if ((flags & KXG_STAT_BOSE) && (flags & KXG_STAT_FERMI)) { set_error("kxg_eval: Bose and Fermi statistics together"); return KXG_EINVAL; }
     kxg_status st = check_prec(k, prec);
     if (st != KXG_OK) return st;

@@ -403,7 +403,7 @@ struct X3Stage {
     float4 fm[BBW][2];         // f_m (the 8 values of this lane's K half)
 };
 
-template <int BBW, int IBW, int SS, bool F16>
+template <int BBW, int IBW, int SS, bool F16, int SPLIT = 3>
 __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_gemm_x3_lds(
     const uint16_t *G, const float *__restrict__ fop, const int *__restrict__ pairs,
     const int *__restrict__ units, int nib, int bpad, int ipad, int nbt,
@@ -506,11 +506,17 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
                     ph = __builtin_bit_cast(opx8, hw);
                     pl = __builtin_convertvector(pv - __builtin_bit_cast(floatx8, hb), opx8);
                 }
-                // three products, smallest first
+                // three products, smallest first (SPLIT = 2: lo*hi, hi*hi
+                // only, A not split; SPLIT = 1: hi*hi alone)
 #pragma unroll
                 for (int t = 0; t < 3; ++t)
 #pragma unroll
                     for (int ib = 0; ib < IBW; ++ib) {
+                        if constexpr (SPLIT == 1) {
+                            if (t != 2) continue;
+                        } else if constexpr (SPLIT == 2) {
+                            if (t == 1) continue;
+                        }
                         const opx8 &av = t == 0 ? pl : ph;
                         const opx8 &bv = t == 1 ? Al[ib] : Ah[ib];
                         if constexpr (F16)
@@ -1418,13 +1424,19 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         hand_over(bpad, f16 ? 1 : 0);
         float *part = static_cast<float *>(ws.part);
         const dim3 grid(nbt * k.nunits16);
+        // products of the hi+lo split: 3 (production), 2 or 1 (ablations)
+        const int split = (flags & KXG_SPLIT_NONE) ? 1 : ((flags & KXG_SPLIT_F_ONLY) ? 2 : 3);
         profile_mark_begin(s);
-        if (f16)
-            hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, true>), grid, dim3(256), 0, s,
-                               k.d_Gh, ws.fop, k.d_pairs16, k.d_units16, g.nib, bpad, g.ipad, nbt, part);
-        else
-            hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, false>), grid, dim3(256), 0, s,
-                               k.d_Gbf, ws.fop, k.d_pairs16, k.d_units16, g.nib, bpad, g.ipad, nbt, part);
+#define KXG_X3(F, S)                                                                              \
+    hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, F, S>), grid, dim3(256), 0, s,          \
+                       F ? k.d_Gh : k.d_Gbf, ws.fop, k.d_pairs16, k.d_units16, g.nib, bpad, g.ipad, \
+                       nbt, part)
+        if (f16) {
+            if (split == 3) KXG_X3(true, 3); else if (split == 2) KXG_X3(true, 2); else KXG_X3(true, 1);
+        } else {
+            if (split == 3) KXG_X3(false, 3); else if (split == 2) KXG_X3(false, 2); else KXG_X3(false, 1);
+        }
+#undef KXG_X3
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
         // the loss term is folded into the operand; loss rates only for diagnostics

@@ -26,6 +26,8 @@ PROJECT = 1
 INTERP_LOG = 2
 STAT_BOSE = 4
 STAT_FERMI = 8
+SPLIT_F_ONLY = 16
+SPLIT_NONE = 32
 WITH_BRACKETS = 1 << 8
 NDIAG = 12
 RK4, HEUN = 0, 1
@@ -231,11 +233,13 @@ class Kernel:
         return dict(zip(("dp", "E", "K", "h"), out))
 
     def eval(self, f, prec: int = F64, project: bool = True, out=None, diag=None, stream=None,
-             log_interp: bool = False, eta: int = 0, diagnostics: bool = True):
+             log_interp: bool = False, eta: int = 0, diagnostics: bool = True, split: int = 3):
         """C[f] for f of shape [B, n] (device float64).  Returns (C, diag).
         log_interp / eta (+1 Bose-Einstein, -1 Fermi-Dirac) select the exact
         form of the operator (handle built with brackets=True).  With
-        diagnostics=False no diagnostics are computed and diag is None."""
+        diagnostics=False no diagnostics are computed and diag is None.
+        split (16-bit precisions): 3 products of the hi+lo split (default), 2
+        (F2 split only) or 1 (no split), the latter two as ablations."""
         import torch
         if f.dim() == 1:
             f = f.view(1, -1)
@@ -246,6 +250,7 @@ class Kernel:
             diag = torch.empty((B, NDIAG), dtype=torch.float64, device=f.device)
         flags = (PROJECT if project else 0) | (INTERP_LOG if log_interp else 0)
         flags |= STAT_BOSE if eta > 0 else (STAT_FERMI if eta < 0 else 0)
+        flags |= {3: 0, 2: SPLIT_F_ONLY, 1: SPLIT_NONE}[split]
         _check(lib().kxg_eval(self._h, int(prec), _dev_ptr(f, B * self.n, "f"), B,
                               _dev_ptr(out, B * self.n, "C"), flags,
                               _dev_ptr(diag, B * NDIAG, "diag") if diag is not None else None,

@@ -427,6 +427,33 @@ def test_eval_without_diagnostics_same_C(dev, prec):
 
 
 @pytest.mark.parametrize("prec", [kxg.BF16X3, kxg.F16X3])
+def test_split_ablations_lose_accuracy(dev, prec):
+    """The hi+lo split is what brings the 16-bit contraction to 1e-3: with
+    the A split dropped (F2 split only) or no split at all, the error
+    against the oracle is orders of magnitude larger; the ablations are
+    refused at FP64/FP32 and together."""
+    n, B = 64, 40
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    f0 = batch(p, B, seed=17)
+    k = kxg.Kernel(p, precs=(kxg.F32, prec), b_cap=64)
+    ref = oracle_C(oracle.Operator(p), f0, True)
+    f = torch.tensor(f0, device=dev)
+    err = {}
+    for split in (3, 2, 1):
+        C, _ = k.eval(f, prec=prec, split=split)
+        torch.cuda.synchronize()
+        err[split] = rel(C.cpu().numpy(), ref)
+    assert err[3] <= TOL[prec], err
+    assert err[2] > 20 * err[3] and err[1] > 20 * err[3], err
+    with pytest.raises(kxg.KxgError):
+        k.eval(f, prec=kxg.F32, split=2)
+    out = torch.empty_like(f)
+    st = kxg.lib().kxg_eval(k._h, int(prec), f.data_ptr(), B, out.data_ptr(),
+                            kxg.SPLIT_F_ONLY | kxg.SPLIT_NONE, None, None)
+    assert st == kxg.EINVAL
+
+
+@pytest.mark.parametrize("prec", [kxg.BF16X3, kxg.F16X3])
 def test_eval_16bit_large_batch_lds_path(dev, prec):
     """B >= 512 takes the LDS-shared GEMM: ragged batch (600 -> 1024 rows) and
     a ragged i-tile (n = 80: 3 blocks of 32 in tiles of 2)."""
