@@ -174,6 +174,26 @@ def single_paths(args, dev):
                               "bytes_per_launch": 8 * n ** 3}
     log("plain fp64 N=384 stream: %.1f us, %.0f GB/s" % (us, gbps))
     del k
+    # HBM stream, N = 416 FP32 (A32 is 288 MB, also beyond the Infinity Cache)
+    n = 416
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=1)
+    f = torch.tensor(inputs.draw_solves(1)[0].f0(p)[None, :], device=dev)
+    C = torch.empty_like(f)
+    for _ in range(3):
+        k.eval(f, prec=kxg.F32, out=C, diagnostics=False)
+    torch.cuda.synchronize()
+    kxg.profile_begin(reps + 2)
+    for _ in range(reps):
+        k.eval(f, prec=kxg.F32, out=C, diagnostics=False)
+    torch.cuda.synchronize()
+    ms, cnt = kxg.profile_end()
+    us = 1e3 * ms / max(cnt, 1)
+    gbps = 4.0 * n ** 3 / (us * 1e-6) / 1e9
+    out["plain_fp32_n416"] = {"stream_kernel_us": round(us, 2), "stream_GBps": round(gbps, 1),
+                              "hbm_frac": round(gbps / HBM_PEAK, 4), "bytes_per_launch": 4 * n ** 3}
+    log("plain fp32 N=416 stream: %.1f us, %.0f GB/s" % (us, gbps))
+    del k
     # N = 32 FP64, RK4, 100 steps on a side stream (captured graph)
     w = inputs.single_fp64_n32()
     p = w.grid()
