@@ -321,6 +321,7 @@ def main():
             st4 = kxg.Stepper(k4, kind=kxg.RK4, prec=prec, b_cap=4096)
             for b, s in enumerate(w4.solves):
                 st4.set(b, f4[b], lam=s.lam, t_end=1e30, h_i=1.0)
+            torch.cuda.synchronize()       # sets on the default stream, steps on side
             st4.advance(args.steps, stream=side)
             side.synchronize()
             del st4
@@ -342,6 +343,7 @@ def main():
     st = kxg.Stepper(ker, kind=kxg.RK4, prec=kxg.F32, b_cap=B)
     for b, s in enumerate(w.solves):
         st.set(b, f0[b], lam=s.lam, t_end=1e30, h_i=1.0)
+    torch.cuda.synchronize()               # sets on the default stream, steps on run_stream
     # the timed steps run as they do in production: on a stream of their own,
     # each step one replay of the captured iteration (HIP graph)
     run_stream = torch.cuda.Stream()
@@ -443,6 +445,7 @@ def main():
             st4 = kxg.Stepper(k4, kind=kxg.RK4, prec=prec, b_cap=4096)
             for b, s in enumerate(w4.solves):
                 st4.set(b, f4[b], lam=s.lam, t_end=1e30, h_i=1.0)
+            torch.cuda.synchronize()       # sets on the default stream, steps on run_stream
             st4.advance(3, stream=run_stream)
             torch.cuda.synchronize()
             steps4 = 20

@@ -27,6 +27,10 @@
  *    been enqueued and kxg_last_error() gives a message (thread-local).
  *  - Work is enqueued asynchronously on the stream; device faults surface as
  *    KXG_EHIP on a later call that synchronises.
+ *  - The library orders nothing across streams: calls on one handle that are
+ *    issued on different streams (say kxg_stepper_set on the default stream,
+ *    then kxg_stepper_advance on a non-blocking one) race unless the caller
+ *    orders them (a synchronisation or an event wait in between).
  */
 #ifndef KXG_H
 #define KXG_H

@@ -785,8 +785,9 @@ static kxg_status enqueue_iteration(kxg_stepper *s, int B, hipStream_t st)
     return eval_impl(k, s->ws, P.prec, s->d_fb, B, nullptr, flags, nullptr, st, &a);
 }
 
-// Capture one iteration over `batch` slots on stream st into an executable
-// graph (re-captured only when the batch bucket or the stream changes).
+// Iterations per replay of the long graph; the remainder of an advance call
+// replays the one-iteration graph.  Both are captured over the current batch
+// bucket and re-captured when the bucket or the stream changes.
 constexpr int kGraphIters = 8;
 
 // Capture `iters` iterations of the stepper on `st` into an executable graph

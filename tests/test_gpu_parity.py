@@ -221,6 +221,34 @@ def test_edge_cases(dev):
     assert torch.isfinite(C[[0, 1, 2, 3, 5, 7, 8]]).all()
 
 
+def test_largest_grid(dev):
+    """n = 1024, the largest grid (32 i-blocks: every word of the packed
+    slot counts in use): the FP32 and BF16x3 GEMMs agree with the FP64
+    stream to their tolerances, the projection conserves number and energy,
+    and n = 1025 is refused."""
+    n, B = 1024, 6
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    f = torch.tensor(batch(p, B, seed=23), device=dev)
+    k = kxg.Kernel(p, precs=(kxg.F64, kxg.F32, kxg.BF16X3), b_cap=8)
+    C64, _ = k.eval(f, prec=kxg.F64)
+    C32, _ = k.eval(f, prec=kxg.F32)
+    C16, _ = k.eval(f, prec=kxg.BF16X3)
+    torch.cuda.synchronize()
+    ref = C64.cpu().numpy()
+    for C, prec in ((C32, kxg.F32), (C16, kxg.BF16X3)):
+        got = C.cpu().numpy()
+        for b in range(B):
+            assert rel(got[b], ref[b]) <= TOL[prec], (prec, b)
+    g = k.grid()
+    h, E = g["h"], g["E"]
+    for b in range(B):
+        assert abs(np.sum(h * ref[b])) <= 1e-12 * np.sum(h * np.abs(ref[b]))
+        assert abs(np.sum(h * E * ref[b])) <= 1e-12 * np.sum(h * E * np.abs(ref[b]))
+    with pytest.raises(kxg.KxgError) as ei:
+        kxg.Kernel(inputs.log_grid(n + 1, 1e-3, 20.0), precs=(kxg.F64,), b_cap=1)
+    assert ei.value.status == kxg.EINVAL
+
+
 def test_moments(dev):
     p = inputs.log_grid(50, 1e-3, 20.0)
     f0 = batch(p, 5)
@@ -554,6 +582,7 @@ def test_batched_fp32_rk4_2000_steps_subsample(dev):
     ft = torch.tensor(f0, device=dev)
     for b, s in enumerate(w.solves):
         st.set(b, ft[b], lam=s.lam, t_end=1e30, h_i=1.0)
+    torch.cuda.synchronize()               # the sets ran on the default stream
     side = torch.cuda.Stream()
     st.advance(2000, stream=side)
     side.synchronize()
@@ -582,20 +611,23 @@ def test_mixed_precision_2000_steps_subsample(dev, prec):
     ft = torch.tensor(f0, device=dev)
     for b, s in enumerate(w.solves):
         st.set(b, ft[b], lam=s.lam, t_end=1e30, h_i=1.0)
+    torch.cuda.synchronize()               # the sets ran on the default stream
     picks = np.linspace(0, 4095, 4).astype(int)
     out = torch.empty(256, dtype=torch.float64, device=dev)
+    side = torch.cuda.Stream()             # graph replays, as the benchmark runs them
     m_prev = None
     for block in range(4):
-        st.advance(1)
+        st.advance(1, stream=side)
+        side.synchronize()
         fs = torch.stack([st.get(int(b), out=out).clone() for b in picks])
         m = k.moments(fs).cpu().numpy()
         if m_prev is not None:
             assert np.max(np.abs(m[:, :2] - m_prev[:, :2]) / np.abs(m_prev[:, :2])) <= 1e-12
         m_prev = m
-    st.advance(2000 - 4)
-    torch.cuda.synchronize()
+    st.advance(2000 - 4, stream=side)
+    side.synchronize()
     q = st.query()
-    assert all(q[b]["steps"] == 2000 for b in picks)
+    assert all(q[b]["steps"] == 2000 for b in picks), [(int(b), q[b]["steps"], q[b]["status"]) for b in picks]
     op = oracle.Operator(p)
     for b in picks:
         s = w.solves[b]
