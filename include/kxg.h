@@ -103,7 +103,9 @@ typedef struct kxg_kernel kxg_kernel;
 kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask,
                             int32_t b_cap, void *stream, kxg_kernel **out);
 
-/* Release a kernel handle and all its device memory (NULL is a no-op). */
+/* Release a kernel handle and all its device memory (NULL is a no-op).
+ * Free every stepper created on the handle first.  The release waits for
+ * the device (hipFree), so work already enqueued with it completes. */
 void kxg_kernel_free(kxg_kernel *k);
 
 /* Grid size n of a handle. */
@@ -247,6 +249,8 @@ typedef struct kxg_stepper kxg_stepper;
  * Errors: KXG_EINVAL, KXG_EUNSUPPORTED, KXG_ENOMEM, KXG_EHIP. */
 kxg_status kxg_stepper_create(const kxg_kernel *k, const kxg_stepper_params *params,
                               kxg_stepper **out);
+/* Release a stepper, its captured graphs and its device memory (NULL is a
+ * no-op); waits for the device like kxg_kernel_free. */
 void kxg_stepper_free(kxg_stepper *s);
 
 /* Load slot `slot` with the distribution f0_dev (device [n] FP64) and its

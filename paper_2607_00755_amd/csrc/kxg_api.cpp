@@ -113,9 +113,6 @@ static void profile_clear()
     g_prof = Profile{};
 }
 
-// Workgroups aimed at per GEMM launch (at the handle's largest batch).
-
-
 template <typename T>
 static kxg_status dalloc(T **ptr, size_t count)
 {

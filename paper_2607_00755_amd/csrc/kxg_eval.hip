@@ -1228,7 +1228,27 @@ int stream_splits(int n)
     return s;
 }
 
-int gemm_bbw(int B) { return B <= 32 ? 1 : (B <= 64 ? 2 : 4); }
+// 32-row batch blocks per wave of the FP32 GEMM for a call of B rows: the
+// width that minimises width x (workgroups per CU), the MFMA time of the
+// busiest CU.  On a tie a narrower tile wins while the launch stays within
+// two workgroups per CU (two waves per SIMD hide each other's latencies),
+// else the wider one (more MFMAs per operand load).  The work units are
+// fixed per handle and a row's partials do not depend on the width, so
+// neither does any result.
+int gemm_bbw(int nunits, int B)
+{
+    int best = 4;
+    long tbest = -1;
+    for (int w = 4; w >= 1; w >>= 1) {
+        const long wgs = (long)nunits * div_up(B, 32 * w);
+        const long t = w * ((wgs + 255) / 256);
+        if (tbest < 0 || t < tbest || (t == tbest && wgs <= 512)) {
+            tbest = t;
+            best = w;
+        }
+    }
+    return best;
+}
 
 }  // namespace
 
@@ -1288,7 +1308,7 @@ static Path path_of(const kxg_kernel &k, int prec, int B)
         p.bpad = div_up(B, TILE) * TILE;
         return p;
     }
-    const int tile = 32 * gemm_bbw(B);
+    const int tile = 32 * gemm_bbw(k.nunits, B);
     p.bpad = div_up(B, tile) * tile;
     return p;
 }
@@ -1448,7 +1468,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         return KXG_OK;
     }
     // FP32 GEMM
-    const int bbw = gemm_bbw(B);
+    const int bbw = gemm_bbw(k.nunits, B);
     const int bpad = P.bpad;
     const int nbt = bpad / (32 * bbw);
     if (!op_ready)

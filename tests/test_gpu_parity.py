@@ -154,6 +154,36 @@ def test_batch_invariance_bitwise(dev):
             assert np.array_equal(part.cpu().numpy(), full[sel]), (prec, len(sel))
 
 
+def test_gemm_width_invariance_bitwise(dev):
+    """The FP32 GEMM runs a call of B rows with one, two or four 32-row batch
+    blocks per wave, whichever keeps the busiest CU shortest for that B.  At
+    N=256 on a b_cap=512 handle the calls below take all three widths; every
+    row must come out bitwise the same as in the full batch."""
+    w = inputs.batched_fp32_n256(512)
+    p = w.grid()
+    f0 = torch.tensor(w.f0(), device=dev)
+    k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=512)
+    units = k.stats()["gemm_units"]
+
+    def width(B):                      # the launch rule, restated
+        best, tb = 4, None
+        for wd in (4, 2, 1):
+            wgs = units * -(-B // (32 * wd))
+            t = wd * -(-wgs // 256)
+            if tb is None or t < tb or (t == tb and wgs <= 512):
+                best, tb = wd, t
+        return best
+
+    sels = [list(range(512)), list(range(0, 512, 2)), list(range(100, 196)), [511, 3, 250],
+            list(range(17, 317))]
+    assert {width(len(s)) for s in sels} == {1, 2, 4}, [(len(s), width(len(s))) for s in sels]
+    full, _ = k.eval(f0, prec=kxg.F32)
+    full = full.cpu().numpy()
+    for sel in sels:
+        part, _ = k.eval(f0[sel].contiguous(), prec=kxg.F32)
+        assert np.array_equal(part.cpu().numpy(), full[sel]), (len(sel), width(len(sel)))
+
+
 @pytest.mark.parametrize("n", [40, 200])
 def test_single_distribution_stream_bitwise(dev, n):
     """The FP64 stream path evaluates one distribution (one per pass) and
