@@ -355,6 +355,36 @@ def test_heun_expansion_replay(dev, prec, n):
     assert abs(q["outflow"] - r["outflow"]) <= TOL[prec] * abs(r["outflow"]) + 1e-300
 
 
+def test_heun_drift_fp32_n128_full_replay(dev):
+    """The N=128 FP32 evolution with radiation-era drift at full length: the
+    oracle's FP64 adaptive Heun takes 1e4 accepted steps in u = ln a, the
+    device replays them in FP32 (one step per call, dt from the oracle);
+    state, time and outflow at the end within 1e-5."""
+    w = inputs.single_fp32_n128()
+    p = w.grid()
+    s = w.solves[0]
+    f0 = w.f0()[0]
+    op = oracle.Operator(p)
+    Hi = op.gamma0(f0)
+    r = op.heun(f0 * p ** 3, s.lam, Hi, 0.5 * np.log(2e4), 1e-3, expansion=True, max_steps=10000)
+    nsteps = len(r["dt"])
+    assert nsteps == 10000
+    k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=1)
+    st = kxg.Stepper(k, kind=kxg.HEUN, prec=kxg.F32, b_cap=1, expansion=kxg.EXP_RADIATION,
+                     adapt=False)
+    st.set(0, torch.tensor(f0, device=dev), lam=s.lam, t_end=10.0, dt=r["dt"][0], h_i=Hi)
+    for j in range(nsteps):
+        st.set_dt([r["dt"][j]])
+        st.advance(1)
+    got = st.get(0).cpu().numpy()
+    u = r["u"][-1] + r["dt"][-1]
+    ref = r["x"] / (np.exp(3 * u) * p ** 3)
+    assert rel(got, ref) <= TOL[kxg.F32], rel(got, ref)
+    q = st.query()[0]
+    assert q["steps"] == nsteps and abs(q["t"] - u) <= 1e-12 * u
+    assert abs(q["outflow"] - r["outflow"]) <= TOL[kxg.F32] * abs(r["outflow"]) + 1e-300
+
+
 def test_heun_adaptive_fp64_free_run(dev):
     n = 48
     p = inputs.log_grid(n, 1e-3, 20.0)
