@@ -284,8 +284,9 @@ def paper_timing_curve(dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU "
-              "layout is a design note, not an implementation.", file=sys.stderr)
+        print("bench.py: the hot path runs on one GPU only (--gpus 1); how it would shard "
+              "over several GPUs is described in the design notes, not implemented.",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
