@@ -391,6 +391,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         args.no_extras, args.no_cpu_baseline, args.serve_requests = True, True, 0
+    peaks = None
+    if not args.profile_run:
+        # what this chip sustains (independent MFMA loops on every SIMD, a
+        # plain vector copy), beside the datasheet peaks
+        peaks = kxg.peak_probe()
+        extras["measured_peaks"] = {k: round(v, 1) for k, v in peaks.items()}
+        roofline["measured_peak"] = round(peaks["mfma_f32_tflops"], 1)
+        roofline["frac_of_measured"] = round(achieved / peaks["mfma_f32_tflops"], 4)
+        log("measured peaks: %s" % extras["measured_peaks"])
     # ---------------- plain FP64 single distribution ----------------
     # (projected C, no diagnostics: the same output as the batched step)
     f1 = f0[:1].contiguous()
@@ -465,6 +474,8 @@ def main():
                 "evals_per_s": round(4 * 4096 / wl, 1), "ms_per_rk4_step": round(1e3 * wl, 3),
                 "gemm_us": round(g_us, 1), "mfma_tflops": round(fl / (g_us * 1e-6) / 1e12, 1),
                 "mfma_frac": round(fl / (g_us * 1e-6) / 1e12 / PEAK["bf16"], 4),
+                "mfma_frac_of_measured": (round(fl / (g_us * 1e-6) / 1e12 / peaks["mfma_bf16_tflops"], 4)
+                                          if peaks else None),
                 "blocks": blocks16}
             log("%s B=4096 RK4: %.3f ms/step, gemm %.1f us" % (name, 1e3 * wl, g_us))
             del st4
@@ -495,6 +506,10 @@ def main():
     if not args.no_extras:
         # ---------------- single-distribution paths ----------------
         extras.update(single_paths(args, dev))
+        if peaks:
+            for key in ("plain_fp64_n384", "plain_fp32_n416"):
+                if key in extras:
+                    extras[key]["frac_of_measured_read"] = round(extras[key]["stream_GBps"] / peaks["read_GBps"], 4)
         extras["paper_timing_workload_be_log"] = paper_timing_curve(dev)
 
     # ---------------- serving loop (continuous batching) ----------------

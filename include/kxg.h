@@ -302,6 +302,19 @@ kxg_status kxg_stepper_load(kxg_stepper *s, int32_t slot, const void *buf, size_
 kxg_status kxg_profile_begin(int32_t capacity);
 kxg_status kxg_profile_end(double *total_ms, int32_t *launches);
 
+/* Device self-calibration, for reporting roofline fractions against what
+ * this chip sustains beside its datasheet peaks (not an operation of the
+ * method).  out [4] (host): out[0] FP32 matrix-core rate in TFLOP/s, from a
+ * loop of independent v_mfma_f32_32x32x2f32 on every SIMD; out[1] the same
+ * for v_mfma_f32_32x32x16_bf16; out[2] device-memory read bandwidth in GB/s
+ * (a 16-byte-vector read of 1 GiB, the access pattern of the stream
+ * kernels); out[3] copy bandwidth in GB/s (512 MiB copied, bytes read plus
+ * bytes written).  Each is the best of three timed launches (HIP events on
+ * `stream`) after one untimed launch.  Allocates and frees 1 GiB plus 8 MiB
+ * of device memory; synchronises the stream.  Errors: KXG_EINVAL (null
+ * out), KXG_ENOMEM, KXG_EHIP. */
+kxg_status kxg_peak_probe(double *out, void *stream);
+
 /* Thread-local message of the last error ("" if none). */
 const char *kxg_last_error(void);
 

@@ -366,6 +366,60 @@ kxg_status kxg_profile_end(double *total_ms, int32_t *launches)
     return KXG_OK;
 }
 
+kxg_status kxg_peak_probe(double *out, void *stream)
+{
+    // out[0..3]: FP32 and BF16 MFMA TFLOP/s, read and copy GB/s
+    g_err[0] = 0;
+    if (!out) { set_error("kxg_peak_probe: null output"); return KXG_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    constexpr int kWg = 1024, kIters = 4096;          // four waves per SIMD on 256 CUs
+    constexpr int kReadWg = 8192;                      // 128 KiB of the 1 GiB read each
+    constexpr long kVec = (512L << 20) / 16;           // 512 MiB in 16-byte vectors
+    float *sink = nullptr;
+    char *buf = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    kxg_status rs = dalloc(&sink, (size_t)kReadWg * 256);
+    if (rs == KXG_OK) rs = dalloc(&buf, (size_t)2 * kVec * 16);
+    if (rs != KXG_OK) {
+        if (sink) (void)hipFree(sink);
+        return rs;
+    }
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // best of three timed launches after one untimed one
+    auto best_ms = [&](auto &&launch) {
+        float best = 0.0f;
+        for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+            e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0 && (best == 0.0f || ms < best)) best = ms;
+        }
+        return (double)best;
+    };
+    const double waves = (double)kWg * 4 * kIters * 4;  // MFMAs per launch
+    const double f32 = best_ms([&] { return launch_peak_mfma(0, kWg, kIters, sink, st); });
+    const double b16 = best_ms([&] { return launch_peak_mfma(1, kWg, kIters, sink, st); });
+    const double cp = best_ms([&] { return launch_copy16(buf, buf + kVec * 16, kVec, st); });
+    const double rd = best_ms([&] { return launch_read16(buf, 2 * kVec, sink, kReadWg, st); });
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    (void)hipFree(buf);
+    if (e != hipSuccess || f32 <= 0.0 || b16 <= 0.0 || cp <= 0.0 || rd <= 0.0) {
+        set_error("kxg_peak_probe: %s", hipGetErrorString(e));
+        return KXG_EHIP;
+    }
+    out[0] = waves * 4096.0 / (f32 * 1e-3) / 1e12;
+    out[1] = waves * 32768.0 / (b16 * 1e-3) / 1e12;
+    out[2] = 2.0 * kVec * 16 / (rd * 1e-3) / 1e9;
+    out[3] = 2.0 * kVec * 16 / (cp * 1e-3) / 1e9;
+    return KXG_OK;
+}
+
 kxg_status kxg_gauss_legendre(int32_t n, double *x, double *w)
 {
     g_err[0] = 0;

@@ -127,6 +127,10 @@ hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, hipStream_
 hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_pack_16(const kxg_kernel &k, int ibw, hipStream_t s);
 hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s);
+// device self-calibration (kxg_probe.hip)
+hipError_t launch_peak_mfma(int bf16, int nwg, int iters, float *sink, hipStream_t s);
+hipError_t launch_copy16(const void *src, void *dst, long nvec, hipStream_t s);
+hipError_t launch_read16(const void *src, long nvec, float *sink, int nwg, hipStream_t s);
 // FP32 GEMM over the kept blocks: nwg = batch tiles x work units, bbw
 // 32-row b-blocks per wave (1, 2 or 4)
 hipError_t launch_gemm_f32(int bbw, int nwg, const float *G, const float *fop, const float *fpar,

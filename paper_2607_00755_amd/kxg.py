@@ -40,6 +40,7 @@ EXPORTED = [
     "kxg_stepper_release", "kxg_stepper_advance", "kxg_stepper_set_dt",
     "kxg_stepper_query", "kxg_stepper_get", "kxg_stepper_save", "kxg_stepper_load",
     "kxg_last_error", "kxg_profile_begin", "kxg_profile_end", "kxg_kernel_stats",
+    "kxg_peak_probe",
 ]
 
 
@@ -96,6 +97,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libkxg.so not built: run paper_2607_00755_amd/build.py "
                               "(or __graft_entry__.build())")
+        # torch first: its HIP runtime is then the one libkxg binds to, so
+        # that torch's streams and allocations and the library's calls share
+        # one runtime whichever of the two the caller touches first
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         L.kxg_kernel_build.argtypes = [ctypes.POINTER(Grid), ctypes.c_uint32, ctypes.c_int32,
                                        _vp, ctypes.POINTER(_vp)]
@@ -124,6 +129,7 @@ def lib():
         L.kxg_stepper_load.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
         L.kxg_profile_begin.argtypes = [ctypes.c_int32]
         L.kxg_profile_end.argtypes = [_dp, ctypes.POINTER(ctypes.c_int32)]
+        L.kxg_peak_probe.argtypes = [_dp, _vp]
         L.kxg_last_error.argtypes = []
         L.kxg_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -169,6 +175,16 @@ def profile_end():
     cnt = ctypes.c_int32(0)
     _check(lib().kxg_profile_end(ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+def peak_probe(stream=None) -> dict:
+    """kxg_peak_probe: sustained FP32 and BF16 MFMA rates (TFLOP/s), the
+    device-memory read bandwidth and the copy bandwidth (GB/s, read +
+    written) of this device."""
+    out = np.zeros(4)
+    _check(lib().kxg_peak_probe(out.ctypes.data_as(_dp), _stream_ptr(stream)))
+    return {"mfma_f32_tflops": float(out[0]), "mfma_bf16_tflops": float(out[1]),
+            "read_GBps": float(out[2]), "copy_GBps": float(out[3])}
 
 
 def gauss_legendre(n: int):

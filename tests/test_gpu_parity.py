@@ -739,6 +739,15 @@ def test_expansion_conserves_comoving_number_on_device(dev):
     assert q["status"] == 1
 
 
+def test_peak_probe_is_plausible(dev):
+    """The self-calibration reports rates below the datasheet peaks (FP32 and
+    BF16 MFMA 157.3 and 2500 TFLOP/s, HBM 8000 GB/s) and not far under them."""
+    pk = kxg.peak_probe()
+    for key, peak in (("mfma_f32_tflops", 157.3), ("mfma_bf16_tflops", 2500.0), ("read_GBps", 8000.0),
+                      ("copy_GBps", 8000.0)):
+        assert 0.3 * peak < pk[key] < 1.1 * peak, (key, pk[key])
+
+
 def test_zero_block_skipping_matches_oracle_tensor(dev):
     """The FP32 operand keeps exactly the (i-block, pair) blocks of the
     packed tensor that hold a non-zero weight (blocks of 32 rows i x 16 x 16
