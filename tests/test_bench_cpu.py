@@ -1,6 +1,5 @@
 """Host-side checks of bench.py: the JSON contract fields it computes without
 a GPU (counter lookup, --gpus guard)."""
-import json
 import os
 import subprocess
 import sys

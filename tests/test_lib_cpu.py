@@ -2,7 +2,6 @@
 exports every entry point that include/kxg.h declares, computes its
 Gauss-Legendre rule correctly, and rejects bad arguments before any device
 work."""
-import ctypes
 import os
 import re
 

@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from paper_2607_00755_amd import inputs, kxg, serving
+from paper_2607_00755_amd import inputs, serving
 
 
 def small_requests(count, rate=400.0, seed=31, ns=(32, 48)):
