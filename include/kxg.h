@@ -52,8 +52,11 @@ typedef enum {
     KXG_ENUMERIC = 6       /* non-finite values met */
 } kxg_status;
 
-/* Precision of the contraction sum_{n,m} A f f (the loss term, the
- * projection and all state updates are FP64 in every case). */
+/* Precision of the contraction sum_{n,m} A f f.  The projection, the
+ * reduction of the split partials and all state updates are FP64 in every
+ * case; the loss term f_i sum_j R_ij f_j is folded into the operand of the
+ * GEMM paths (so it takes the contraction's precision there) and is summed
+ * in FP64 on the stream paths. */
 typedef enum {
     KXG_F64 = 0,     /* FP64 stream over the dense kernel tensor          */
     KXG_F32 = 1,     /* FP32: stream if b_cap <= 4, else MFMA GEMM        */
