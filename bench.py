@@ -526,6 +526,7 @@ def main():
                       "rate_req_per_s": args.serve_rate, "wall_s": round(el, 2), "prec": "f32",
                       "stepper": "adaptive Heun in ln a, rtol 1e-6, radiation drift"})
         serve["mean_batch"] = {str(k): round(v, 1) for k, v in serve["mean_batch"].items()}
+        serve["per_n"] = {k: {q: round(v, 3) for q, v in d.items()} for k, d in serve["per_n"].items()}
         log("serving: p50 %.3f s p99 %.3f s, %.2f solves/s" %
             (serve["p50_s"], serve["p99_s"], serve["solves_per_s"]))
         del srv

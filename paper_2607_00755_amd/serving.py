@@ -246,4 +246,10 @@ class Server:
             "solves_per_s": len(ok) / span if span and span > 0 else float("nan"),
             "mean_steps": float(np.mean([r.steps for r in ok])) if ok else float("nan"),
             "mean_batch": {n: g.batch_sum / max(g.iters, 1) for n, g in self.groups.items()},
+            "per_n": {str(n): {"completed": len(rs),
+                               "p50_s": float(np.percentile([r.latency for r in rs], 50)),
+                               "p99_s": float(np.percentile([r.latency for r in rs], 99)),
+                               "mean_steps": float(np.mean([r.steps for r in rs]))}
+                      for n in sorted({r.solve.n for r in ok})
+                      for rs in [[r for r in ok if r.solve.n == n]]},
         }

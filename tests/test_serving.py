@@ -33,6 +33,25 @@ def test_admission_refuses_when_budget_too_small():
     assert srv.refused == 3 and srv.used_bytes == 0
 
 
+def test_stats_per_grid_size():
+    """Latency percentiles overall and per grid size, warm-up and failed
+    requests left out (host logic only)."""
+    srv = serving.Server()
+    done = []
+    for rid, (n, lat, st) in enumerate([(64, 1.0, 1), (64, 3.0, 1), (128, 2.0, 1), (128, 9.0, -1),
+                                        (64, 100.0, 1)]):
+        r = serving.Request(rid, inputs.Solve(1.0, 0.1, 2.0, 0.5, n=n), arrival=0.0)
+        r.finished, r.status, r.steps = lat, st, 10 * (rid + 1)
+        done.append(r)
+    s = srv.stats(done, warm=0)
+    assert s["completed"] == 4 and s["failed"] == 1
+    assert s["per_n"]["64"]["completed"] == 3 and s["per_n"]["128"]["completed"] == 1
+    assert s["per_n"]["64"]["p50_s"] == 3.0 and s["per_n"]["128"]["p99_s"] == 2.0
+    assert s["per_n"]["64"]["mean_steps"] == (10 + 20 + 50) / 3
+    w = srv.stats(done, warm=4)
+    assert w["completed"] == 1 and set(w["per_n"]) == {"64"}
+
+
 @pytest.mark.gpu
 def test_serving_overlap_and_mix_invariance():
     reqs = small_requests(14)
