@@ -173,7 +173,8 @@ class Operator:
              atol: Optional[float] = None, safety: float = 0.9, fmin: float = 0.2,
              fmax: float = 5.0, max_steps: int = 10000, replay_dt=None, u0: float = 0.0):
         """Adaptive (or replayed) Heun in u.  Returns dict with the final state,
-        accepted (u, dt), outflow and rejection count."""
+        accepted (u, dt), outflow, rejection count and the log of attempts
+        (dt, error estimate, accepted) in the order they were made."""
         x = _f64(x0).copy()
         if atol is None:
             atol = 1e-12 * float(np.max(np.abs(x)))
@@ -183,6 +184,10 @@ class Operator:
         rd = None if replay_dt is None else _f64(replay_dt)
         outflow = ctypes.c_double(0.0)
         nrej = ctypes.c_int(0)
+        att_cap = 4 * cap + 64
+        att_dt, att_err = np.empty(att_cap), np.empty(att_cap)
+        att_ok = np.empty(att_cap, dtype=np.int32)
+        natt = ctypes.c_int(0)
         nacc = lib().or_heun(
             ctypes.c_int(self.n), _p(self.A), _p(self.R), _p(self.grid.p),
             _p(self.grid.dp_override), ctypes.c_double(self.mass), _p(x),
@@ -191,9 +196,14 @@ class Operator:
             ctypes.c_double(u_end), ctypes.c_double(dt0), ctypes.c_double(rtol),
             ctypes.c_double(atol), ctypes.c_double(safety), ctypes.c_double(fmin),
             ctypes.c_double(fmax), ctypes.c_int(max_steps), ctypes.c_int(nrep), _p(rd),
-            _p(acc_u), _p(acc_dt), ctypes.byref(outflow), ctypes.byref(nrej))
+            _p(acc_u), _p(acc_dt), ctypes.byref(outflow), ctypes.byref(nrej),
+            ctypes.c_int(att_cap), _p(att_dt), _p(att_err), att_ok.ctypes.data_as(_ip),
+            ctypes.byref(natt))
+        na = min(natt.value, att_cap)
         return {"x": x, "u": acc_u[:nacc], "dt": acc_dt[:nacc],
-                "outflow": outflow.value, "rejected": nrej.value}
+                "outflow": outflow.value, "rejected": nrej.value,
+                "attempts": {"dt": att_dt[:na], "err": att_err[:na],
+                             "accepted": att_ok[:na].astype(bool)}}
 
     def gamma0(self, f) -> float:
         """Largest loss rate max_i sum_j R_ij f_j (the initial scattering rate)."""

@@ -12,9 +12,16 @@
  * Jacobian of the reduced kernel, linear vs. log interpolation, the drift
  * discretisation) are stated at the routine that takes them.
  *
- * Parity pins: every routine here is pinned by the CPU tests against the
- * paper's printed numbers, closed forms, invariants or brute force (see the
- * test files named in each comment).  Nothing here is "parity unpinned".
+ * Parity pins: every routine here is checked by the CPU tests
+ * (tests/test_oracle_pins.py, tests/test_golden_cpu.py) against the paper's
+ * printed numbers, closed forms, invariants, brute force or an independent
+ * integration.  The adaptive Heun controller is pinned by its accuracy
+ * against a fine fixed-step RK4 solution (error within rtol and falling in
+ * proportion to it, step count growing as rtol^-1/2, rejections until the
+ * estimate falls to one), the Hubble factor of the expanding-universe
+ * right-hand side by the a^-1 scaling of its collision increment.  Its
+ * step-size law (safety 0.9, exponent 1/2, clamps [0.2, 5]) is a reading
+ * the paper leaves open; the tests check it only against its own statement.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -540,14 +547,17 @@ static double rhs_u(int n, const double *A, const double *R, const double *p,
 /* attempted step.  With nreplay > 0 the steps are not adapted: dt_k is     */
 /* taken from replay_dt and always accepted.  Records accepted (u_k, dt_k). */
 /* Returns the number of accepted steps; *outflow accumulates the drift     */
-/* outflow (trapezoid in u, consistent with the Heun update).              */
+/* outflow (trapezoid in u, consistent with the Heun update).  With att_dt  */
+/* given, the first att_cap attempts are logged (dt, err, accepted) and    */
+/* *n_att receives the number of attempts made.                            */
 /* ------------------------------------------------------------------------ */
 int or_heun(int n, const double *A, const double *R, const double *p,
             const double *dp_override, double mass, double *x, int expansion,
             int project, double lambda, double Hi, double u0, double u_end,
             double dt0, double rtol, double atol, double safety, double fmin,
             double fmax, int max_steps, int nreplay, const double *replay_dt,
-            double *acc_u, double *acc_dt, double *outflow, int *nrejected)
+            double *acc_u, double *acc_dt, double *outflow, int *nrejected,
+            int att_cap, double *att_dt, double *att_err, int *att_ok, int *n_att)
 {
     double *dp = malloc(sizeof(double) * n), *E = malloc(sizeof(double) * n);
     double *K = malloc(sizeof(double) * n), *h = malloc(sizeof(double) * n);
@@ -557,7 +567,7 @@ int or_heun(int n, const double *A, const double *R, const double *p,
     double *tmp = malloc(sizeof(double) * n);
     or_grid(n, p, mass, dp_override, dp, E, K, h);
     double u = u0, dt = dt0;
-    int acc = 0, rej = 0;
+    int acc = 0, rej = 0, natt = 0;
     double out = 0.0;
     int limit = nreplay > 0 ? nreplay : max_steps;
     while (acc < limit) {
@@ -583,6 +593,12 @@ int or_heun(int n, const double *A, const double *R, const double *p,
             if (e > err)
                 err = e;
         }
+        if (att_dt && natt < att_cap) {
+            att_dt[natt] = dt;
+            att_err[natt] = err;
+            att_ok[natt] = (nreplay > 0 || err <= 1.0);
+        }
+        ++natt;
         if (nreplay > 0 || err <= 1.0) {
             if (acc_u) acc_u[acc] = u;
             if (acc_dt) acc_dt[acc] = dt;
@@ -602,6 +618,7 @@ int or_heun(int n, const double *A, const double *R, const double *p,
     }
     if (outflow) *outflow = out;
     if (nrejected) *nrejected = rej;
+    if (n_att) *n_att = natt;
     free(dp); free(E); free(K); free(h); free(k1); free(k2); free(xs);
     free(xn); free(f); free(c); free(tmp);
     return acc;

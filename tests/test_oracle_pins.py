@@ -358,6 +358,89 @@ def test_expansion_heun_conserves_comoving_number():
 
 
 # --------------------------------------------------------------------------
+# Adaptive Heun controller (Sec. 4.2: Euler predictor, trapezoid corrector,
+# their difference as the error estimate).  Started from a first step of
+# half the interval, the controller must reject until the estimate falls
+# to one; the end state, against a fine fixed-step RK4 solution of the same
+# equation (dx/du = lambda C / H_i without expansion), must be within rtol
+# and must improve in proportion to rtol; a second-order method needs
+# about sqrt(100) = 10 times the steps for a 100 times tighter rtol.
+def test_heun_controller_rejects_and_meets_tolerance():
+    w = inputs.single_fp64_n32()
+    p = w.grid()
+    op = oracle.Operator(p, quad=oracle.GL)
+    f0 = w.f0()[0]
+    Hi = op.gamma0(f0)
+    u_end = 2.0
+    ref = op.rk4(f0, 1.0 / Hi, u_end / 4000, 4000)
+    ref2 = op.rk4(f0, 1.0 / Hi, u_end / 2000, 2000)
+    assert np.max(np.abs(ref - ref2)) <= 1e-12 * np.max(np.abs(ref))
+    errs, steps = {}, {}
+    for rtol in (1e-4, 1e-6):
+        r = op.heun(f0, 1.0, Hi, u_end, 1.0, expansion=False, rtol=rtol, max_steps=100000)
+        a = r["attempts"]
+        assert r["rejected"] >= 3 and not a["accepted"][0]
+        assert np.all(a["err"][a["accepted"]] <= 1.0)
+        assert np.all(a["err"][~a["accepted"]] > 1.0)
+        assert a["accepted"].sum() == len(r["dt"]) and (~a["accepted"]).sum() == r["rejected"]
+        assert np.allclose(a["dt"][a["accepted"]], r["dt"], rtol=0, atol=0)
+        assert abs(r["u"][-1] + r["dt"][-1] - u_end) <= 1e-13
+        errs[rtol] = np.max(np.abs(r["x"] - ref)) / np.max(np.abs(ref))
+        steps[rtol] = len(r["dt"])
+        assert errs[rtol] <= rtol, (rtol, errs[rtol])
+    assert errs[1e-6] <= errs[1e-4] / 30.0, errs
+    assert 5.0 <= steps[1e-6] / steps[1e-4] <= 20.0, steps
+
+
+def test_heun_step_size_law():
+    """The step-size law both implementations take (the paper does not state
+    one): dt_next = dt * clamp(0.9 err^-1/2, 0.2, 5), cut short only where
+    the step would pass u_end.  A consistency check of that reading against
+    the oracle's attempt log, not an independent pin: its accuracy is
+    pinned by the test above."""
+    w = inputs.single_fp64_n32()
+    p = w.grid()
+    op = oracle.Operator(p, quad=oracle.GL)
+    f0 = w.f0()[0]
+    Hi = op.gamma0(f0)
+    r = op.heun(f0, 1.0, Hi, 2.0, 1.0, expansion=False, rtol=1e-5, max_steps=100000)
+    a = r["attempts"]
+    want = a["dt"][:-1] * np.clip(0.9 / np.sqrt(a["err"][:-1]), 0.2, 5.0)
+    got = a["dt"][1:]
+    free = got < want * (1 - 1e-12)            # shortened to end at u_end
+    assert free.sum() <= 1
+    assert np.allclose(got[~free], want[~free], rtol=1e-14, atol=0)
+
+
+# --------------------------------------------------------------------------
+# Hubble rate in the collision term of eq. numerical_evolution_loga: with
+# g = a^3 p^3 f, the collision part of dg/du is a^3 p^3 lambda C[f] / H.
+# For the same g, f scales as a^-3, so C[f] as a^-6, while a^3/H = a^5/H_i
+# in the radiation era (H = H_i a^-2): the collision increment of one tiny
+# step started at u = 1 is e^-1 times the one started at u = 0.  At u = 0
+# (a = 1) it is dt p^3 lambda C[f] / H_i to first order in dt.
+def test_expansion_collision_term_scales_with_hubble_rate():
+    w = inputs.single_fp64_n32()
+    p = w.grid()
+    op = oracle.Operator(p, quad=oracle.GL)
+    f0 = w.f0()[0]
+    Hi = op.gamma0(f0)
+    g0 = f0 * p ** 3
+    dt = 1e-7
+
+    def collision_increment(u0, lam):
+        step = lambda l: op.heun(g0, l, Hi, 0.0, 0.0, expansion=True, replay_dt=[dt], u0=u0)["x"]
+        return step(lam) - step(0.0)
+
+    d0 = collision_increment(0.0, 2.0)
+    d1 = collision_increment(1.0, 2.0)
+    scale = np.max(np.abs(d0))
+    assert np.max(np.abs(d1 - np.exp(-1.0) * d0)) <= 1e-6 * scale
+    C = op.collision(f0, project=True)[0]
+    assert np.max(np.abs(d0 - dt * 2.0 * p ** 3 * C / Hi)) <= 1e-5 * scale
+
+
+# --------------------------------------------------------------------------
 # P14: on the paper's two-bump input with N_mu = 18 the projection changes C
 # by less than one per cent of max|C_raw| (App. C, pointwise figure).
 @pytest.mark.parametrize("n", [96, 256])
