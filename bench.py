@@ -43,12 +43,15 @@ def parse():
                     help="measured serving requests (after --serve-warm warm-up ones); 0 = skip")
     ap.add_argument("--serve-warm", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-check", type=int, default=8,
+    ap.add_argument("--serve-check", type=int, default=32,
                     help="measured requests re-run alone and compared with their result in the mix")
-    ap.add_argument("--serve-sweep", default="",
-                    help="comma-separated arrival rates of a saturation sweep (e.g. 5,10,20,50); empty = none")
-    ap.add_argument("--serve-sweep-requests", type=int, default=120,
+    ap.add_argument("--serve-sweep", default="20,30,40,50,60",
+                    help="comma-separated arrival rates of a saturation sweep; empty = none")
+    ap.add_argument("--serve-sweep-requests", type=int, default=400,
                     help="measured requests per sweep rate (after a fifth as many warm-up ones)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the oracle's 16-solve subsamples in full (minutes) instead of "
+                         "extrapolating from a bounded part of each")
     ap.add_argument("--profile-run", nargs="?", const="gemm", default=None,
                     choices=("gemm", "stream384", "x3"),
                     help="short run for profilers: 'gemm' = the timed RK4 steps, the plain "
@@ -112,11 +115,26 @@ def serving_alone_check(serving, reqs, done, warm, count):
     return {"requests": len(sample), "max_rel_diff": worst, "same_steps": same_steps}
 
 
+def sustainable(rows):
+    """The sweep row of the highest rate that is still served: completed
+    solves/s >= 0.9 x the offered rate and p99 <= 2 x the p99 of the lowest
+    rate (rows in increasing rate); None if even the lowest is not."""
+    best = None
+    if rows:
+        p99_0 = rows[0]["p99_s"]
+        for r in rows:
+            if r["solves_per_s"] >= 0.9 * r["rate_req_per_s"] and r["p99_s"] <= 2.0 * p99_0:
+                best = r
+    return best
+
+
 def serving_sweep(serving, args):
     """Arrival-rate sweep of the serving loop: p50/p99 latency and solves/s
-    per rate (the rate where p99 runs away is the sustainable limit)."""
+    per rate.  The largest sustainable rate is the highest one that the loop
+    still completes at (solves/s >= 0.9 x offered) without p99 running away
+    (<= 2 x the p99 of the lowest rate, the nearly unloaded latency)."""
     from paper_2607_00755_amd import inputs, kxg
-    out = []
+    rows = []
     nr = args.serve_sweep_requests
     nw = max(1, nr // 5)
     for rate in [float(x) for x in args.serve_sweep.split(",") if x.strip()]:
@@ -125,13 +143,18 @@ def serving_sweep(serving, args):
         t0 = time.perf_counter()
         done = srv.run(reqs)
         st = srv.stats(done, warm=nw)
-        out.append({"rate_req_per_s": rate, "requests": nr, "p50_s": round(st["p50_s"], 3),
-                    "p99_s": round(st["p99_s"], 3), "solves_per_s": round(st["solves_per_s"], 2),
-                    "completed": st["completed"], "wall_s": round(time.perf_counter() - t0, 1)})
+        rows.append({"rate_req_per_s": rate, "requests": nr, "p50_s": round(st["p50_s"], 3),
+                     "p99_s": round(st["p99_s"], 3), "solves_per_s": round(st["solves_per_s"], 2),
+                     "completed": st["completed"], "truncated": st["truncated"],
+                     "failed": st["failed"], "wall_s": round(time.perf_counter() - t0, 1)})
         log("serving sweep %.1f req/s: p50 %.3f s p99 %.3f s, %.2f solves/s" %
             (rate, st["p50_s"], st["p99_s"], st["solves_per_s"]))
         del srv
-    return out
+    best = sustainable(rows)
+    return {"rates": rows, "requests_per_rate": nr, "warmup_per_rate": nw,
+            "max_sustainable_rate_req_per_s": None if best is None else best["rate_req_per_s"],
+            "max_sustainable_solves_per_s": None if best is None else best["solves_per_s"],
+            "rule": "highest rate with solves/s >= 0.9 x offered and p99 <= 2 x p99 at the lowest rate"}
 
 
 def packed_k(n):
@@ -245,6 +268,70 @@ def single_paths(args, dev):
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_config_rows(full):
+    """Wall time of the FP64 CPU oracle on the workloads' own inputs: the
+    N = 32 single solve in full (one evaluation plus 100 RK4 steps), the
+    N = 128 expanding solve (adaptive Heun until 1e4 accepted steps) and the
+    seeded 16-solve subsample of the N = 256 batches (2000 RK4 steps each;
+    the oracle is FP64 whatever precision the device path uses, so the FP32
+    and 16-bit batches share it).  Without `full` the last two are timed on a
+    bounded part (1000 of the 1e4 steps; 20 of the 2000 steps) and scaled up
+    by the step ratio (the cost per step is the same throughout)."""
+    import oracle
+    from paper_2607_00755_amd import inputs
+    rows = []
+    w = inputs.single_fp64_n32()
+    p = w.grid()
+    f0 = w.f0()[0]
+    t0 = time.perf_counter()
+    op = oracle.Operator(p)
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    op.collision(f0, project=True)
+    op.rk4(f0, 1.0, 0.1 / op.gamma0(f0), 100)
+    rows.append({"workload": w.name, "work": "1 evaluation + 100 RK4 steps", "build_s": round(tb, 4),
+                 "wall_s": round(time.perf_counter() - t0, 4), "extrapolated": False})
+    w = inputs.single_fp32_n128()
+    p = w.grid()
+    f0 = w.f0()[0]
+    s0 = w.solves[0]
+    op = oracle.Operator(p)
+    steps = 10000 if full else 1000
+    t0 = time.perf_counter()
+    r = op.heun(f0 * p ** 3, s0.lam, op.gamma0(f0), 0.5 * np.log(2e4), 1e-3, expansion=True,
+                max_steps=steps)
+    el = time.perf_counter() - t0
+    done = len(r["dt"])
+    rows.append({"workload": w.name, "work": "adaptive Heun in ln a, 1e4 accepted steps",
+                 "measured_steps": done, "measured_s": round(el, 3),
+                 "wall_s": round(el * 10000 / max(done, 1), 2), "extrapolated": done != 10000})
+    w = inputs.batched_fp32_n256(512)
+    p = w.grid()
+    op = oracle.Operator(p)
+    picks = np.linspace(0, 511, 16).astype(int)
+    f0 = w.f0()
+    steps = 2000 if full else 20
+    t0 = time.perf_counter()
+    for b in picks:
+        sv = w.solves[b]
+        op.rk4(f0[b], sv.lam, 0.1 / (sv.lam * op.gamma0(f0[b])), steps)
+    el = time.perf_counter() - t0
+    rows.append({"workload": "n256 batches, 16-solve subsample", "work": "16 solves x 2000 RK4 steps",
+                 "measured_steps": steps, "measured_s": round(el, 3),
+                 "wall_s": round(el * 2000 / steps, 1), "extrapolated": steps != 2000})
+    return rows
+
+
 def paper_timing_curve(dev):
     """The paper's own timing workload (Sec. 5, Fig. run_time): one full-grid
     evaluation of the contact operator for the two-bump input of
@@ -320,8 +407,7 @@ def main():
         side = torch.cuda.Stream()
         for prec in (kxg.BF16X3, kxg.F16X3):
             st4 = kxg.Stepper(k4, kind=kxg.RK4, prec=prec, b_cap=4096)
-            for b, s in enumerate(w4.solves):
-                st4.set(b, f4[b], lam=s.lam, t_end=1e30, h_i=1.0)
+            st4.set_many(0, f4, lam=[s.lam for s in w4.solves], t_end=1e30, h_i=1.0)
             torch.cuda.synchronize()       # sets on the default stream, steps on side
             st4.advance(args.steps, stream=side)
             side.synchronize()
@@ -342,8 +428,7 @@ def main():
     ker = kxg.Kernel(p, precs=(kxg.F64, kxg.F32), b_cap=B)
     log("kernel build N=%d: %.3f s" % (n, time.time() - t0))
     st = kxg.Stepper(ker, kind=kxg.RK4, prec=kxg.F32, b_cap=B)
-    for b, s in enumerate(w.solves):
-        st.set(b, f0[b], lam=s.lam, t_end=1e30, h_i=1.0)
+    st.set_many(0, f0, lam=[s.lam for s in w.solves], t_end=1e30, h_i=1.0)
     torch.cuda.synchronize()               # sets on the default stream, steps on run_stream
     # the timed steps run as they do in production: on a stream of their own,
     # each step one replay of the captured iteration (HIP graph)
@@ -367,18 +452,26 @@ def main():
     torch.cuda.synchronize()
     gemm_ms, gemm_n = kxg.profile_end()
     gemm_avg_ms = gemm_ms / max(gemm_n, 1)
-    # executed MFMA work: the kept 32 x 16 x 16 blocks of the packed operand
-    # (blocks the kinematic cuts leave all zero are skipped), all B rows
+    # algorithmic work of one launch: 2 flops per distribution and non-zero
+    # entry of the symmetric (k <= m) packing of A' = A - delta_ik R_im (gain
+    # and loss in one contraction); the MFMAs execute the kept 32 x 16 x 16
+    # blocks, zeros inside them included
     info = ker.stats()
+    flops_alg = 2.0 * B * info["nnz_packed"]
     flops_exec = 2.0 * B * 32 * 256 * info["nonzero_blocks"]
     flops_packed = 2.0 * B * n * packed_k(n)
     flops_dense = 2.0 * B * n * n * n
-    achieved = flops_exec / (gemm_avg_ms * 1e-3) / 1e12
+    achieved = flops_alg / (gemm_avg_ms * 1e-3) / 1e12
+    achieved_exec = flops_exec / (gemm_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["f32"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4),
                 "traffic": counted_traffic("gemm_f32_n256_b512.md", GEMM_F32_SOURCES),
                 "kernel": "k_gemm_f32<4>", "avg_launch_us": round(gemm_avg_ms * 1e3, 2),
-                "launches": gemm_n, "flops_per_launch": flops_exec,
+                "launches": gemm_n, "flops_per_launch": flops_alg,
+                "nnz_packed": info["nnz_packed"],
+                "executed_flops_per_launch": flops_exec,
+                "executed_tflops": round(achieved_exec, 2),
+                "executed_frac": round(achieved_exec / PEAK["f32"], 4),
                 "packed_flops_per_launch": flops_packed,
                 "dense_equiv_flops_per_launch": flops_dense,
                 "blocks_kept": "%d of %d" % (info["nonzero_blocks"], info["packed_blocks"])}
@@ -399,6 +492,7 @@ def main():
         extras["measured_peaks"] = {k: round(v, 1) for k, v in peaks.items()}
         roofline["measured_peak"] = round(peaks["mfma_f32_tflops"], 1)
         roofline["frac_of_measured"] = round(achieved / peaks["mfma_f32_tflops"], 4)
+        roofline["executed_frac_of_measured"] = round(achieved_exec / peaks["mfma_f32_tflops"], 4)
         log("measured peaks: %s" % extras["measured_peaks"])
     # ---------------- plain FP64 single distribution ----------------
     # (projected C, no diagnostics: the same output as the batched step)
@@ -450,11 +544,12 @@ def main():
         w4 = inputs.mixed_n256(4096)
         f4 = torch.tensor(w4.f0(), device=dev)
         k4 = kxg.Kernel(p, precs=(kxg.BF16X3, kxg.F16X3), b_cap=4096)
-        blocks16 = k4.stats()["blocks16"]
+        info4 = k4.stats()
+        blocks16 = info4["blocks16"]
+        lams4 = [s.lam for s in w4.solves]
         for prec, name in ((kxg.BF16X3, "bf16x3"), (kxg.F16X3, "f16x3")):
             st4 = kxg.Stepper(k4, kind=kxg.RK4, prec=prec, b_cap=4096)
-            for b, s in enumerate(w4.solves):
-                st4.set(b, f4[b], lam=s.lam, t_end=1e30, h_i=1.0)
+            st4.set_many(0, f4, lam=lams4, t_end=1e30, h_i=1.0)
             torch.cuda.synchronize()       # sets on the default stream, steps on run_stream
             st4.advance(3, stream=run_stream)
             torch.cuda.synchronize()
@@ -468,14 +563,19 @@ def main():
             torch.cuda.synchronize()
             g_ms, g_n = kxg.profile_end()
             g_us = 1e3 * g_ms / max(g_n, 1)
-            # executed MFMA work per GEMM: 3 products over the kept blocks
+            # algorithmic work per GEMM: one product over the non-zero packed
+            # entries; executed: the three split products over the kept blocks
+            fa = 2.0 * 4096 * info4["nnz_packed"]
             fl = 3 * 2.0 * 4096 * 32 * 256 * blocks16
             extras[name + "_b4096"] = {
                 "evals_per_s": round(4 * 4096 / wl, 1), "ms_per_rk4_step": round(1e3 * wl, 3),
-                "gemm_us": round(g_us, 1), "mfma_tflops": round(fl / (g_us * 1e-6) / 1e12, 1),
-                "mfma_frac": round(fl / (g_us * 1e-6) / 1e12 / PEAK["bf16"], 4),
-                "mfma_frac_of_measured": (round(fl / (g_us * 1e-6) / 1e12 / peaks["mfma_bf16_tflops"], 4)
-                                          if peaks else None),
+                "gemm_us": round(g_us, 1),
+                "alg_tflops": round(fa / (g_us * 1e-6) / 1e12, 1),
+                "alg_frac": round(fa / (g_us * 1e-6) / 1e12 / PEAK["bf16"], 4),
+                "executed_mfma_tflops": round(fl / (g_us * 1e-6) / 1e12, 1),
+                "executed_mfma_frac": round(fl / (g_us * 1e-6) / 1e12 / PEAK["bf16"], 4),
+                "executed_frac_of_measured": (round(fl / (g_us * 1e-6) / 1e12 / peaks["mfma_bf16_tflops"], 4)
+                                              if peaks else None),
                 "blocks": blocks16}
             log("%s B=4096 RK4: %.3f ms/step, gemm %.1f us" % (name, 1e3 * wl, g_us))
             del st4
@@ -524,7 +624,9 @@ def main():
         serve = srv.stats(done, warm=args.serve_warm)
         serve.update({"requests": args.serve_requests, "warmup_requests": args.serve_warm,
                       "rate_req_per_s": args.serve_rate, "wall_s": round(el, 2), "prec": "f32",
-                      "stepper": "adaptive Heun in ln a, rtol 1e-6, radiation drift"})
+                      "stepper": "adaptive Heun in ln a, rtol 1e-6, radiation drift",
+                      "regime": "overload: the offered rate exceeds what the device completes, "
+                                "so p50/p99 grow with the number of requests (see serving_sweep)"})
         serve["mean_batch"] = {str(k): round(v, 1) for k, v in serve["mean_batch"].items()}
         serve["per_n"] = {k: {q: round(v, 3) for q, v in d.items()} for k, d in serve["per_n"].items()}
         log("serving: p50 %.3f s p99 %.3f s, %.2f solves/s" %
@@ -538,6 +640,8 @@ def main():
         done = None
         if args.serve_sweep:
             extras["serving_sweep"] = serving_sweep(serving, args)
+            log("serving: largest sustainable rate %s req/s" %
+                extras["serving_sweep"]["max_sustainable_rate_req_per_s"])
 
     # ---------------- CPU oracle baseline ----------------
     cpu = None
@@ -555,8 +659,9 @@ def main():
         el = time.perf_counter() - t0
         cpu = {"value": round(cnt / el, 2), "unit": "C-evals/s", "cores": threads, "kind": "oracle",
                "sample": "%d evaluations of one N=256 distribution (FP64 A/R contraction + "
-                         "projection) in %.1f s" % (cnt, el)}
-        log("cpu oracle: %.2f C-evals/s on %d threads" % (cnt / el, threads))
+                         "projection) in %.1f s" % (cnt, el),
+               "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+        log("cpu oracle: %.2f C-evals/s on %d threads (%s)" % (cnt / el, threads, cpu["cpu_model"]))
         if not args.no_extras:
             # further rows: one thread at N = 256, all threads at N = 32, 128, 384
             rows = []
@@ -576,6 +681,8 @@ def main():
             oracle.set_threads(threads)
             extras["cpu_oracle_rows"] = rows
             log("cpu oracle rows: %s" % rows)
+            extras["cpu_oracle_workloads"] = cpu_config_rows(args.cpu_full)
+            log("cpu oracle workloads: %s" % extras["cpu_oracle_workloads"])
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "C-evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),

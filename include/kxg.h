@@ -69,6 +69,14 @@ typedef enum {
  * bracket table j_L[i][n][m] (2 bytes per entry) that the exact-form
  * evaluations (KXG_INTERP_LOG, KXG_STAT_BOSE, KXG_STAT_FERMI) stream. */
 #define KXG_WITH_BRACKETS (1u << 8)
+/* Extra bit of kxg_kernel_build's prec_mask: a lean handle keeps only the
+ * tensors its evaluations read.  The dense FP64 tensor is released after
+ * the build unless KXG_F64 is in the mask (FP64 evaluations and
+ * kxg_kernel_export of A then return KXG_EUNSUPPORTED); the dense FP32 copy
+ * is built only for handles with b_cap <= 4 (the single-distribution
+ * stream) or with the bracket table.  Meant for callers that admit work by
+ * memory footprint. */
+#define KXG_LEAN (1u << 9)
 
 /* Angular integral of the reduced kernel (App. B). */
 typedef enum {
@@ -114,9 +122,10 @@ void kxg_kernel_free(kxg_kernel *k);
 /* Grid size n of a handle. */
 int32_t kxg_kernel_n(const kxg_kernel *k);
 
-/* Device bytes held for precision prec (the tensors an evaluation at that
- * precision reads), or for all of the handle if prec < 0.  Used for
- * admission by memory footprint.  0 if the precision was not built. */
+/* Device bytes of the tensors an evaluation at precision prec reads (0 if
+ * the precision was not built), or, for prec < 0, every device byte the
+ * handle holds (tensors, tables and workspace).  Used for admission by
+ * memory footprint. */
 size_t kxg_kernel_bytes(const kxg_kernel *k, int32_t prec);
 
 /* Shape of the contraction a handle runs (for reporting work and bytes).
@@ -132,6 +141,11 @@ typedef struct {
     int64_t blocks16;         /* (i-block, pair) blocks the 16-bit GEMM runs over:
                                  the union of the non-zero pairs of each group of
                                  i-blocks a workgroup covers (0 if no 16-bit) */
+    int64_t nnz_packed;       /* non-zero entries (i, k <= m) of the symmetric
+                                 packing of A'[i,k,m] = A[i,k,m] - delta_ik R[i,m]
+                                 (A'_ikm + A'_imk for k < m): the contraction's own
+                                 work is 2 flops per entry and distribution (0 on
+                                 handles without a GEMM precision) */
 } kxg_kernel_info;
 
 /* Fill *out for handle k.  Errors: KXG_EINVAL (null argument). */
@@ -240,8 +254,9 @@ typedef struct {
     double h_i;         /* the H_i (or rate0) in use                           */
     int32_t steps;      /* accepted steps                                      */
     int32_t rejected;   /* rejected Heun attempts                              */
-    int32_t status;     /* 0 running, 1 finished, -1 non-finite, -2 dt underflow,
-                           -3 free slot                                        */
+    int32_t status;     /* 0 running, 1 reached t_end, 2 stopped at max_steps
+                           before t_end, -1 non-finite, -2 dt underflow (Heun:
+                           the next step would be below dt_min), -3 free slot */
     int32_t pad;
 } kxg_slot_state;
 
@@ -260,6 +275,22 @@ void kxg_stepper_free(kxg_stepper *s);
  * solve parameters; the slot becomes active.  Asynchronous on stream. */
 kxg_status kxg_stepper_set(kxg_stepper *s, int32_t slot, const double *f0_dev,
                            const kxg_solve_params *sp, void *stream);
+
+/* Load `count` consecutive slots [slot0, slot0 + count) at once, slot
+ * slot0 + j from row j of f0_dev (device [count][n] FP64) with the solve
+ * parameters sp_host[j] (host [count], read before the call returns); one
+ * launch for all of them.  The records travel through a pinned staging
+ * buffer of the stepper: a call waits until the copy of the previous call
+ * has left it.  Errors: KXG_EINVAL (null argument, slots out of range, bad
+ * parameters of any solve; nothing is enqueued then), KXG_EHIP.
+ * Asynchronous on stream. */
+kxg_status kxg_stepper_set_many(kxg_stepper *s, int32_t slot0, int32_t count,
+                                const double *f0_dev, const kxg_solve_params *sp_host,
+                                void *stream);
+
+/* Device bytes the stepper holds (slot records, state vectors, workspace),
+ * for admission by memory footprint; 0 for NULL. */
+size_t kxg_stepper_bytes(const kxg_stepper *s);
 
 /* Free a slot: it stops being advanced, its state is zeroed and it counts
  * as empty.  Asynchronous on stream. */

@@ -156,6 +156,11 @@ struct kxg_stepper {
     hipGraphExec_t gexec_n = nullptr;
     int g_batch = -1;
     hipStream_t g_stream = nullptr;
+    // staging of slot records for kxg_stepper_set_many: pinned host buffer,
+    // its device copy, and an event that marks the end of the last copy
+    SlotDev *h_init = nullptr;
+    SlotDev *d_init = nullptr;
+    hipEvent_t init_evt = nullptr;
 };
 
 // GEMMs over non-zero blocks only.  The kinematic cuts leave whole
@@ -243,14 +248,24 @@ static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want32, bool want
     const Geometry &g = k->geo;
     const size_t nflags = (size_t)g.nib * g.npairs;
     unsigned char *d_flags = nullptr;
+    unsigned int *d_nnz = nullptr;
     kxg_status st = dalloc(&d_flags, nflags);
-    if (st != KXG_OK) return st;
+    if (st == KXG_OK) st = dalloc(&d_nnz, nflags);
+    if (st != KXG_OK) {
+        if (d_flags) (void)hipFree(d_flags);
+        return st;
+    }
     std::vector<unsigned char> flags(nflags);
-    hipError_t e = launch_block_nz(*k, d_flags, s);
+    std::vector<unsigned int> nnz(nflags);
+    hipError_t e = launch_block_nz(*k, d_flags, d_nnz, s);
     if (e == hipSuccess) e = hipMemcpyAsync(flags.data(), d_flags, nflags, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(nnz.data(), d_nnz, nflags * sizeof(unsigned int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(d_flags);
+    (void)hipFree(d_nnz);
     if (e != hipSuccess) { set_error("kxg_kernel_build: %s", hipGetErrorString(e)); return KXG_EHIP; }
+    k->nnz_packed = 0;
+    for (unsigned int c : nnz) k->nnz_packed += c;
     // kept pairs of a group of i-blocks [ib0, ib0 + w)
     auto compact = [&](int w, std::vector<int> &pairs_c, std::vector<int> &cgrp, std::vector<int> &cnt,
                        std::vector<int> &first) {
@@ -454,7 +469,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     if (grid->quad != KXG_QUAD_GL && grid->quad != KXG_QUAD_EXACT) { set_error("kxg_kernel_build: bad quad %d", grid->quad); return KXG_EINVAL; }
     if (grid->quad == KXG_QUAD_GL && (grid->n_mu < 1 || grid->n_mu > 4096)) { set_error("kxg_kernel_build: n_mu=%d outside [1, 4096]", grid->n_mu); return KXG_EINVAL; }
     if (b_cap < 1 || b_cap > (1 << 20)) { set_error("kxg_kernel_build: b_cap=%d outside [1, 2^20]", b_cap); return KXG_EINVAL; }
-    if (prec_mask & ~(0xFu | KXG_WITH_BRACKETS)) { set_error("kxg_kernel_build: unknown precision bits 0x%x", prec_mask); return KXG_EINVAL; }
+    if (prec_mask & ~(0xFu | KXG_WITH_BRACKETS | KXG_LEAN)) { set_error("kxg_kernel_build: unknown precision bits 0x%x", prec_mask); return KXG_EINVAL; }
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     kxg_kernel *k = new (std::nothrow) kxg_kernel;
@@ -466,8 +481,12 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     k->quad = grid->quad;
     k->nmu = grid->quad == KXG_QUAD_GL ? grid->n_mu : 0;
     k->b_cap = b_cap;
-    k->prec_mask = (prec_mask & 0xFu) | KXG_PREC_BIT(KXG_F64);
     const bool want_jl = (prec_mask & KXG_WITH_BRACKETS) != 0;
+    // lean handles keep the dense FP64 tensor only when FP64 evaluations are
+    // asked for, and the dense FP32 copy only where an evaluation streams it
+    const bool lean = (prec_mask & KXG_LEAN) != 0;
+    const bool keep64 = !lean || (prec_mask & KXG_PREC_BIT(KXG_F64));
+    k->prec_mask = (prec_mask & 0xFu) | (keep64 ? KXG_PREC_BIT(KXG_F64) : 0u);
     k->p.assign(grid->p, grid->p + n);
     k->dp.resize(n);
     k->E.resize(n);
@@ -513,7 +532,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     KXG_ALLOC(k->d_RT, n2);
     KXG_ALLOC(k->d_R, n2);
     KXG_ALLOC(k->d_pairs, 2 * (size_t)g.npairs);
-    if (want32) { KXG_ALLOC(k->d_A32, n3); }
+    if (want32 && (!lean || b_cap <= 4 || want_jl)) { KXG_ALLOC(k->d_A32, n3); }
     if (wanth) { KXG_ALLOC(k->d_hrow, (size_t)g.ipad); }
     if (want_jl) { KXG_ALLOC(k->d_JL, n3); KXG_ALLOC(k->d_invdK, (size_t)n); }
     double *d_xmu = nullptr, *d_wmu = nullptr;
@@ -572,14 +591,29 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
         st = build_compact(k, b_cap, want32, wantbf, wanth, s);
         if (st != KXG_OK) { release(k); return st; }
     }
+    if (!keep64) {
+        (void)hipFree(k->d_A64);
+        k->d_A64 = nullptr;
+    }
     st = alloc_workspace(*k, b_cap, k->ws);
     if (st != KXG_OK) { release(k); return st; }
-    k->bytes[KXG_F64] = (n3 + n2) * sizeof(double) + (want_jl ? n3 * sizeof(uint16_t) : 0);
+    // tensors an evaluation at each precision reads
+    const size_t jl = want_jl ? n3 * sizeof(uint16_t) : 0;
+    if (keep64) k->bytes[KXG_F64] = (n3 + n2) * sizeof(double) + jl;
     if (want32)
-        k->bytes[KXG_F32] = (n3 + (size_t)k->ncomp * kBlk * 512) * sizeof(float) + n2 * sizeof(double);
+        k->bytes[KXG_F32] = ((k->d_A32 ? n3 : 0) + (size_t)k->ncomp * kBlk * 512) * sizeof(float) +
+                            n2 * sizeof(double) + (k->d_A32 ? jl : 0);
     const size_t packed16 = (size_t)k->ncomp16 * KXG_LDS_IBW * kBlk * 1024;   // hi + lo values
     if (wantbf) k->bytes[KXG_BF16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
     if (wanth) k->bytes[KXG_F16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
+    // everything the handle holds on the device
+    const size_t fbytes = (size_t)k->geo.nb * k->ws.bpad_cap * kBlk * sizeof(float);
+    k->held = 5 * (size_t)n * sizeof(double) + 2 * n2 * sizeof(double) + 2 * (size_t)g.npairs * sizeof(int) +
+              (k->d_A64 ? n3 * sizeof(double) : 0) + (k->d_A32 ? n3 * sizeof(float) : 0) + jl +
+              (want_jl ? (size_t)n * sizeof(double) : 0) +
+              (size_t)k->ncomp * kBlk * 512 * sizeof(float) + (wantbf ? packed16 * sizeof(uint16_t) : 0) +
+              (wanth ? packed16 * sizeof(uint16_t) + (size_t)g.ipad * sizeof(float) : 0) +
+              k->ws.part_bytes + 2 * fbytes + (size_t)k->ws.bpad_cap * sizeof(float);
     *out = k;
     return KXG_OK;
 }
@@ -592,12 +626,7 @@ size_t kxg_kernel_bytes(const kxg_kernel *k, int32_t prec)
 {
     if (!k) return 0;
     if (prec >= 0 && prec < 4) return k->bytes[prec];
-    size_t tot = k->ws.part_bytes;
-    const size_t n3 = (size_t)k->n * k->n * k->n;
-    tot += (n3 + (size_t)k->n * k->n) * sizeof(double);
-    for (int q = 1; q < 4; ++q)
-        if (k->bytes[q]) tot += k->bytes[q] - (size_t)k->n * k->n * sizeof(double);
-    return tot;
+    return k->held;
 }
 
 kxg_status kxg_kernel_stats(const kxg_kernel *k, kxg_kernel_info *out)
@@ -610,6 +639,7 @@ kxg_status kxg_kernel_stats(const kxg_kernel *k, kxg_kernel_info *out)
     out->gemm_units = k->nunits;
     out->max_slots = k->maxslots;
     out->blocks16 = (k->d_Gbf || k->d_Gh) ? k->ncomp16 * KXG_LDS_IBW : 0;
+    out->nnz_packed = (k->d_G32 || k->d_Gbf || k->d_Gh) ? k->nnz_packed : 0;
     return KXG_OK;
 }
 
@@ -618,6 +648,7 @@ kxg_status kxg_kernel_export(const kxg_kernel *k, double *A_host, double *R_host
     g_err[0] = 0;
     if (!k) { set_error("kxg_kernel_export: null handle"); return KXG_EINVAL; }
     const size_t n = k->n;
+    if (A_host && !k->d_A64) { set_error("kxg_kernel_export: lean handle without the FP64 tensor"); return KXG_EUNSUPPORTED; }
     if (A_host) KXG_TRY_HIP(hipMemcpy(A_host, k->d_A64, n * n * n * sizeof(double), hipMemcpyDeviceToHost));
     if (R_host) {
         std::vector<double> rt(n * n);
@@ -710,6 +741,17 @@ kxg_status kxg_stepper_create(const kxg_kernel *k, const kxg_stepper_params *prm
     if (st == KXG_OK) st = dalloc(&s->d_acc, rows);
     if (st == KXG_OK) st = dalloc(&s->d_xs, rows);
     if (st == KXG_OK) st = dalloc(&s->d_dt, (size_t)prm->b_cap);
+    if (st == KXG_OK) st = dalloc(&s->d_init, (size_t)prm->b_cap);
+    if (st == KXG_OK && hipHostMalloc((void **)&s->h_init, (size_t)prm->b_cap * sizeof(SlotDev)) != hipSuccess) {
+        s->h_init = nullptr;
+        set_error("kxg_stepper_create: pinned host allocation failed");
+        st = KXG_ENOMEM;
+    }
+    if (st == KXG_OK && hipEventCreateWithFlags(&s->init_evt, hipEventDisableTiming) != hipSuccess) {
+        s->init_evt = nullptr;
+        set_error("kxg_stepper_create: hipEventCreate failed");
+        st = KXG_EHIP;
+    }
     if (st == KXG_OK) st = alloc_workspace(*k, prm->b_cap, s->ws);
     if (st == KXG_OK) {
         std::vector<SlotDev> init(prm->b_cap);
@@ -738,7 +780,12 @@ void kxg_stepper_free(kxg_stepper *s)
     if (!s) return;
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
     if (s->gexec_n) (void)hipGraphExecDestroy(s->gexec_n);
-    void *ptrs[] = {s->d_slots, s->d_x, s->d_fb, s->d_acc, s->d_xs, s->d_dt};
+    if (s->init_evt) {
+        (void)hipEventSynchronize(s->init_evt);
+        (void)hipEventDestroy(s->init_evt);
+    }
+    if (s->h_init) (void)hipHostFree(s->h_init);
+    void *ptrs[] = {s->d_slots, s->d_x, s->d_fb, s->d_acc, s->d_xs, s->d_dt, s->d_init};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     free_workspace(s->ws);
@@ -753,18 +800,14 @@ static void update_hi(kxg_stepper *s)
     s->b_hi = hi;
 }
 
-kxg_status kxg_stepper_set(kxg_stepper *s, int32_t slot, const double *f0_dev,
-                           const kxg_solve_params *sp, void *stream)
+static bool solve_params_ok(const kxg_solve_params *sp)
 {
-    g_err[0] = 0;
-    if (!s || !f0_dev || !sp) { set_error("kxg_stepper_set: null argument"); return KXG_EINVAL; }
-    if (slot < 0 || slot >= s->prm.b_cap) { set_error("kxg_stepper_set: slot %d out of range", slot); return KXG_EINVAL; }
-    if (!std::isfinite(sp->lambda) || sp->lambda < 0.0 || !std::isfinite(sp->t_end) || sp->t_end <= 0.0 ||
-        !std::isfinite(sp->dt) || !std::isfinite(sp->h_i)) {
-        set_error("kxg_stepper_set: lambda >= 0, finite dt/h_i and t_end > 0 required");
-        return KXG_EINVAL;
-    }
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    return std::isfinite(sp->lambda) && sp->lambda >= 0.0 && std::isfinite(sp->t_end) &&
+           sp->t_end > 0.0 && std::isfinite(sp->dt) && std::isfinite(sp->h_i);
+}
+
+static SlotDev slot_record(const kxg_solve_params *sp)
+{
     SlotDev init;
     std::memset(&init, 0, sizeof init);
     init.lam = sp->lambda;
@@ -774,12 +817,64 @@ kxg_status kxg_stepper_set(kxg_stepper *s, int32_t slot, const double *f0_dev,
     init.tend = sp->t_end;
     init.maxsteps = sp->max_steps;
     init.status = 0;
+    return init;
+}
+
+kxg_status kxg_stepper_set(kxg_stepper *s, int32_t slot, const double *f0_dev,
+                           const kxg_solve_params *sp, void *stream)
+{
+    g_err[0] = 0;
+    if (!s || !f0_dev || !sp) { set_error("kxg_stepper_set: null argument"); return KXG_EINVAL; }
+    if (slot < 0 || slot >= s->prm.b_cap) { set_error("kxg_stepper_set: slot %d out of range", slot); return KXG_EINVAL; }
+    if (!solve_params_ok(sp)) {
+        set_error("kxg_stepper_set: lambda >= 0, finite dt/h_i and t_end > 0 required");
+        return KXG_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const SlotDev init = slot_record(sp);
     KXG_TRY_HIP(launch_slot_init(slot, init, s->d_slots, st));
     KXG_TRY_HIP(launch_slot_set(s->k->n, s->prm.kind, s->prm.expansion, s->prm.atol_rel, slot,
                                 s->d_slots, f0_dev, s->k->d_p, s->k->d_RT, s->d_x, s->d_fb, st));
     s->used[slot] = 1;
     update_hi(s);
     return KXG_OK;
+}
+
+kxg_status kxg_stepper_set_many(kxg_stepper *s, int32_t slot0, int32_t count,
+                                const double *f0_dev, const kxg_solve_params *sp_host,
+                                void *stream)
+{
+    g_err[0] = 0;
+    if (!s || !f0_dev || !sp_host) { set_error("kxg_stepper_set_many: null argument"); return KXG_EINVAL; }
+    if (count < 1 || slot0 < 0 || slot0 > s->prm.b_cap - count) {
+        set_error("kxg_stepper_set_many: slots [%d, %d) outside [0, %d)", slot0, slot0 + count, s->prm.b_cap);
+        return KXG_EINVAL;
+    }
+    for (int j = 0; j < count; ++j)
+        if (!solve_params_ok(&sp_host[j])) {
+            set_error("kxg_stepper_set_many: solve %d: lambda >= 0, finite dt/h_i and t_end > 0 required", j);
+            return KXG_EINVAL;
+        }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the staging buffer is reused: wait until the previous copy out of it is done
+    KXG_TRY_HIP(hipEventSynchronize(s->init_evt));
+    for (int j = 0; j < count; ++j) s->h_init[j] = slot_record(&sp_host[j]);
+    KXG_TRY_HIP(hipMemcpyAsync(s->d_init, s->h_init, (size_t)count * sizeof(SlotDev), hipMemcpyHostToDevice, st));
+    KXG_TRY_HIP(hipEventRecord(s->init_evt, st));
+    KXG_TRY_HIP(launch_slot_set_many(s->k->n, s->prm.kind, s->prm.expansion, s->prm.atol_rel, slot0, count,
+                                     s->d_init, s->d_slots, f0_dev, s->k->d_p, s->k->d_RT, s->d_x, s->d_fb, st));
+    for (int j = 0; j < count; ++j) s->used[slot0 + j] = 1;
+    update_hi(s);
+    return KXG_OK;
+}
+
+size_t kxg_stepper_bytes(const kxg_stepper *s)
+{
+    if (!s) return 0;
+    const size_t b = (size_t)s->prm.b_cap, n = (size_t)s->k->n;
+    const size_t fbytes = (size_t)s->k->geo.nb * s->ws.bpad_cap * kBlk * sizeof(float);
+    return b * (2 * sizeof(SlotDev) + sizeof(double)) + 4 * b * n * sizeof(double) + s->ws.part_bytes +
+           2 * fbytes + (size_t)s->ws.bpad_cap * sizeof(float);
 }
 
 kxg_status kxg_stepper_release(kxg_stepper *s, int32_t slot, void *stream)

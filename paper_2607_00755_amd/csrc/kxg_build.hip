@@ -215,22 +215,41 @@ __device__ double packed_value(const double *__restrict__ A, const double *__res
 }
 
 // Non-zero flag of every (i-block, pair) block of the packed operand: 32
-// rows i x the 16 x 16 (k, m) block and its transpose.  Grid (pair, i-block).
+// rows i x the 16 x 16 (k, m) block and its transpose.  Also the number of
+// non-zero entries of the symmetric packing restricted to k <= m (inside a
+// diagonal block only dk <= dm, with A'_ikm + A'_imk off the diagonal): the
+// contraction's own work, 2 flops per entry and distribution.  Grid (pair,
+// i-block).
 __global__ __launch_bounds__(256) void k_block_nz(int n, int npairs, const int *__restrict__ pairs,
                                                   const double *__restrict__ A,
                                                   const double *__restrict__ RT,
-                                                  unsigned char *__restrict__ flags)
+                                                  unsigned char *__restrict__ flags,
+                                                  unsigned int *__restrict__ nnz)
 {
+    __shared__ int cnt[4];
     const int pr = blockIdx.x, ib = blockIdx.y;
     const int kb = pairs[2 * pr], mb = pairs[2 * pr + 1];
-    int any = 0;
+    int any = 0, c = 0;
     for (int e = threadIdx.x; e < kIBlk * kBlk * kBlk; e += 256) {
         const int i = ib * kIBlk + e / (kBlk * kBlk);
         const int dk = (e / kBlk) % kBlk, dm = e % kBlk;
-        if (packed_value(A, RT, n, i, kb, mb, dk, dm) != 0.0) any = 1;
+        const double v = packed_value(A, RT, n, i, kb, mb, dk, dm);
+        if (v != 0.0) any = 1;
+        if (kb != mb) {
+            c += v != 0.0;
+        } else if (dk <= dm) {
+            // the symmetric entry of the diagonal block (k <= m)
+            const double w = dk == dm ? v : v + packed_value(A, RT, n, i, kb, mb, dm, dk);
+            c += w != 0.0;
+        }
     }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = c;
     any = __syncthreads_or(any);
-    if (threadIdx.x == 0) flags[(long)ib * npairs + pr] = (unsigned char)(any != 0);
+    if (threadIdx.x == 0) {
+        flags[(long)ib * npairs + pr] = (unsigned char)(any != 0);
+        nnz[(long)ib * npairs + pr] = (unsigned int)(cnt[0] + cnt[1] + cnt[2] + cnt[3]);
+    }
 }
 
 // FP32 GEMM operand, ordered as the 32x32x2 MFMA consumes it, over the
@@ -392,11 +411,12 @@ hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, hipStream_t s)
+hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, unsigned int *nnz,
+                           hipStream_t s)
 {
     const Geometry &g = k.geo;
     hipLaunchKernelGGL(k_block_nz, dim3(g.npairs, g.nib), dim3(256), 0, s, k.n, g.npairs,
-                       k.d_pairs, k.d_A64, k.d_RT, flags);
+                       k.d_pairs, k.d_A64, k.d_RT, flags, nnz);
     return hipGetLastError();
 }
 

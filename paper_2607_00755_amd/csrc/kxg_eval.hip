@@ -1042,8 +1042,8 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
                 S.t = u + dt;
                 S.steps += 1;
                 if (bad[0] > 0.0) S.status = -1;
-                else if (S.t >= S.tend * (1.0 - 1e-14) || (S.maxsteps > 0 && S.steps >= S.maxsteps))
-                    S.status = 1;
+                else if (S.t >= S.tend * (1.0 - 1e-14)) S.status = 1;
+                else if (S.maxsteps > 0 && S.steps >= S.maxsteps) S.status = 2;
                 else if (S.t + dt > S.tend) S.dt = S.tend - S.t;
             }
         }
@@ -1112,8 +1112,10 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
                 fac = fmin(A.fac_hi, fmax(A.fac_lo, fac));
                 dtnew = dt * fac;
             }
-            if (accept && (tnew >= S.tend * (1.0 - 1e-14) || (S.maxsteps > 0 && steps >= S.maxsteps))) {
+            if (accept && tnew >= S.tend * (1.0 - 1e-14)) {
                 status = 1;
+            } else if (accept && S.maxsteps > 0 && steps >= S.maxsteps) {
+                status = 2;                         // step cap before t_end
             } else {
                 if (tnew + dtnew > S.tend) dtnew = S.tend - tnew;
                 if (A.adapt && dtnew < A.dt_min) status = -2;

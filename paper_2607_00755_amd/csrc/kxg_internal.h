@@ -101,6 +101,7 @@ struct kxg_kernel {
     int *d_units = nullptr;      // [nunits][4] (i-block, slot, first, end super-step)
     kxg::SlotCounts nslot;       // K slots (partials) of each i-block
     long ncomp = 0;              // non-zero (i-block, pair) blocks
+    long nnz_packed = 0;         // non-zero entries of the k <= m packing of A' = A - delta_ik R_im
     int nunits = 0, maxslots = 0;
     // the same for the 16-bit operands, per group of KXG_LDS_IBW i-blocks
     // (union of their non-zero pairs); Gbf/Gh hold [block][i-block of the
@@ -113,6 +114,7 @@ struct kxg_kernel {
     double *d_invdK = nullptr;   // [n] 1 / (K_{j+1} - K_j) (0 for the last point)
     kxg::Geometry geo;
     size_t bytes[4] = {0, 0, 0, 0};
+    size_t held = 0;             // device bytes held by the handle
     kxg::Workspace ws;
 };
 
@@ -123,7 +125,8 @@ hipError_t launch_build_A(const kxg_kernel &k, const double *d_xmu, const double
                           hipStream_t s);
 hipError_t launch_build_R(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_derive(kxg_kernel &k, hipStream_t s);
-hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, hipStream_t s);
+hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, unsigned int *nnz,
+                           hipStream_t s);
 hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_pack_16(const kxg_kernel &k, int ibw, hipStream_t s);
 hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s);

@@ -57,6 +57,10 @@ __device__ inline double rhs_u(int expansion, double xi, double next, double c, 
 hipError_t launch_slot_set(int n, int kind, int expansion, double atol_rel, int slot,
                            SlotDev *sl, const double *f0, const double *p, const double *RT,
                            double *x, double *fb, hipStream_t s);
+hipError_t launch_slot_set_many(int n, int kind, int expansion, double atol_rel, int slot0,
+                                int count, const SlotDev *init, SlotDev *sl, const double *f0,
+                                const double *p, const double *RT, double *x, double *fb,
+                                hipStream_t s);
 hipError_t launch_slot_get(int n, int expansion, int slot, const SlotDev *sl, const double *p,
                            const double *x, double *out, hipStream_t s);
 hipError_t launch_slot_refresh(int n, int expansion, int slot, const SlotDev *sl,

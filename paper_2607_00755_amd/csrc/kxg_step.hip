@@ -26,12 +26,11 @@ __device__ void bmax(double (&v)[NV], double *lds)
 
 // Slot load: x from f0 (g = p^3 f at u = 0 when expanding), operator input,
 // h_i from the largest initial loss rate when not given, default dt and atol.
-__global__ __launch_bounds__(256) void k_slot_set(int n, int kind, int expansion, double atol_rel,
-                                                  int slot, SlotDev *__restrict__ sl,
-                                                  const double *__restrict__ f0,
-                                                  const double *__restrict__ p,
-                                                  const double *__restrict__ RT,
-                                                  double *__restrict__ x, double *__restrict__ fb)
+// The slot record already holds the solve parameters.
+__device__ void slot_set(int n, int kind, int expansion, double atol_rel, int slot,
+                         SlotDev *__restrict__ sl, const double *__restrict__ f0,
+                         const double *__restrict__ p, const double *__restrict__ RT,
+                         double *__restrict__ x, double *__restrict__ fb)
 {
     __shared__ double frow[kMaxN];
     __shared__ double lds[8];
@@ -65,6 +64,34 @@ __global__ __launch_bounds__(256) void k_slot_set(int n, int kind, int expansion
         if (!(S.atol > 0.0)) S.atol = 1e-300;
         S.status = 0;
     }
+}
+
+__global__ __launch_bounds__(256) void k_slot_set(int n, int kind, int expansion, double atol_rel,
+                                                  int slot, SlotDev *__restrict__ sl,
+                                                  const double *__restrict__ f0,
+                                                  const double *__restrict__ p,
+                                                  const double *__restrict__ RT,
+                                                  double *__restrict__ x, double *__restrict__ fb)
+{
+    slot_set(n, kind, expansion, atol_rel, slot, sl, f0, p, RT, x, fb);
+}
+
+// Many slots at once: workgroup j copies record init[j] into slot slot0 + j,
+// then loads that slot from row j of f0 [count][n].
+__global__ __launch_bounds__(256) void k_slot_set_many(int n, int kind, int expansion,
+                                                       double atol_rel, int slot0,
+                                                       const SlotDev *__restrict__ init,
+                                                       SlotDev *__restrict__ sl,
+                                                       const double *__restrict__ f0,
+                                                       const double *__restrict__ p,
+                                                       const double *__restrict__ RT,
+                                                       double *__restrict__ x,
+                                                       double *__restrict__ fb)
+{
+    const int j = blockIdx.x;
+    if (threadIdx.x == 0) sl[slot0 + j] = init[j];
+    __syncthreads();
+    slot_set(n, kind, expansion, atol_rel, slot0 + j, sl, f0 + (long)j * n, p, RT, x, fb);
 }
 
 __global__ void k_slot_get(int n, int expansion, int slot, const SlotDev *__restrict__ sl,
@@ -133,6 +160,16 @@ hipError_t launch_slot_set(int n, int kind, int expansion, double atol_rel, int 
 {
     hipLaunchKernelGGL(k_slot_set, dim3(1), dim3(256), 0, s, n, kind, expansion, atol_rel, slot,
                        sl, f0, p, RT, x, fb);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_set_many(int n, int kind, int expansion, double atol_rel, int slot0,
+                                int count, const SlotDev *init, SlotDev *sl, const double *f0,
+                                const double *p, const double *RT, double *x, double *fb,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_slot_set_many, dim3(count), dim3(256), 0, s, n, kind, expansion, atol_rel,
+                       slot0, init, sl, f0, p, RT, x, fb);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ STAT_FERMI = 8
 SPLIT_F_ONLY = 16
 SPLIT_NONE = 32
 WITH_BRACKETS = 1 << 8
+LEAN = 1 << 9
 NDIAG = 12
 RK4, HEUN = 0, 1
 EXP_NONE, EXP_RADIATION = 0, 1
@@ -40,7 +41,7 @@ EXPORTED = [
     "kxg_stepper_release", "kxg_stepper_advance", "kxg_stepper_set_dt",
     "kxg_stepper_query", "kxg_stepper_get", "kxg_stepper_save", "kxg_stepper_load",
     "kxg_last_error", "kxg_profile_begin", "kxg_profile_end", "kxg_kernel_stats",
-    "kxg_peak_probe",
+    "kxg_peak_probe", "kxg_stepper_set_many", "kxg_stepper_bytes",
 ]
 
 
@@ -60,7 +61,8 @@ class Grid(ctypes.Structure):
 class KernelInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("packed_blocks", ctypes.c_int64),
                 ("nonzero_blocks", ctypes.c_int64), ("gemm_units", ctypes.c_int32),
-                ("max_slots", ctypes.c_int32), ("blocks16", ctypes.c_int64)]
+                ("max_slots", ctypes.c_int32), ("blocks16", ctypes.c_int64),
+                ("nnz_packed", ctypes.c_int64)]
 
 
 class StepperParams(ctypes.Structure):
@@ -120,6 +122,10 @@ def lib():
         L.kxg_stepper_free.argtypes = [_vp]
         L.kxg_stepper_free.restype = None
         L.kxg_stepper_set.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.POINTER(SolveParams), _vp]
+        L.kxg_stepper_set_many.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp,
+                                           ctypes.POINTER(SolveParams), _vp]
+        L.kxg_stepper_bytes.argtypes = [_vp]
+        L.kxg_stepper_bytes.restype = ctypes.c_size_t
         L.kxg_stepper_release.argtypes = [_vp, ctypes.c_int32, _vp]
         L.kxg_stepper_advance.argtypes = [_vp, ctypes.c_int32, _vp]
         L.kxg_stepper_set_dt.argtypes = [_vp, _dp, _vp]
@@ -198,7 +204,8 @@ class Kernel:
 
     def __init__(self, p: Sequence[float], precs=(F64,), b_cap: int = 1, mass: float = 1.0,
                  g_dof: float = 1.0, m2: float = 1.0, n_mu: int = 18, quad: int = QUAD_GL,
-                 dp: Optional[Sequence[float]] = None, stream=None, brackets: bool = False):
+                 dp: Optional[Sequence[float]] = None, stream=None, brackets: bool = False,
+                 lean: bool = False):
         self._h = None
         self.p = np.ascontiguousarray(p, dtype=np.float64)
         self.n = len(self.p)
@@ -207,7 +214,7 @@ class Kernel:
         g = Grid(self.n, self.p.ctypes.data_as(_dp),
                  None if self._dp is None else self._dp.ctypes.data_as(_dp),
                  float(mass), float(g_dof), float(m2), int(n_mu), int(quad))
-        mask = WITH_BRACKETS if brackets else 0
+        mask = (WITH_BRACKETS if brackets else 0) | (LEAN if lean else 0)
         for q in precs:
             mask |= 1 << int(q)
         h = _vp()
@@ -234,7 +241,8 @@ class Kernel:
         _check(lib().kxg_kernel_stats(self._h, ctypes.byref(info)))
         return {"n": info.n, "packed_blocks": info.packed_blocks,
                 "nonzero_blocks": info.nonzero_blocks, "gemm_units": info.gemm_units,
-                "max_slots": info.max_slots, "blocks16": info.blocks16}
+                "max_slots": info.max_slots, "blocks16": info.blocks16,
+                "nnz_packed": info.nnz_packed}
 
     def export(self):
         n = self.n
@@ -322,6 +330,26 @@ class Stepper:
         sp = SolveParams(float(lam), float(h_i), float(dt), float(t_end), int(max_steps))
         _check(lib().kxg_stepper_set(self._h, int(slot), _dev_ptr(f0, self.n, "f0"),
                                      ctypes.byref(sp), _stream_ptr(stream)))
+
+    def set_many(self, slot0: int, f0, lam, t_end, dt=0.0, h_i=0.0, max_steps=0, stream=None):
+        """Load slots slot0 .. slot0 + len(f0) - 1 in one call (f0: device
+        [count, n] float64; the other arguments are scalars or one value per
+        slot)."""
+        count = f0.shape[0] if f0.dim() == 2 else 1
+        per = lambda v: np.broadcast_to(np.asarray(v, dtype=np.float64), (count,))
+        lam_, te_, dt_, hi_ = per(lam), per(t_end), per(dt), per(h_i)
+        ms_ = np.broadcast_to(np.asarray(max_steps, dtype=np.int64), (count,))
+        arr = (SolveParams * count)()
+        for j in range(count):
+            arr[j] = SolveParams(float(lam_[j]), float(hi_[j]), float(dt_[j]), float(te_[j]),
+                                 int(ms_[j]))
+        _check(lib().kxg_stepper_set_many(self._h, int(slot0), int(count),
+                                          _dev_ptr(f0, count * self.n, "f0"), arr,
+                                          _stream_ptr(stream)))
+
+    def bytes(self) -> int:
+        """Device bytes the stepper holds."""
+        return int(lib().kxg_stepper_bytes(self._h))
 
     def release(self, slot: int, stream=None):
         _check(lib().kxg_stepper_release(self._h, int(slot), _stream_ptr(stream)))

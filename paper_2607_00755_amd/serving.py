@@ -13,7 +13,15 @@ grid of its size N.  The loop
 * advances all running slots of an N-group together, so that each iteration
   is one batched evaluation per group, each group on its own stream;
 * retires finished solves, records arrival-to-result latency, and frees the
-  slot for the next arrival.
+  slot for the next arrival;
+* cancels requests on demand (`Server.cancel`): a waiting request is dropped,
+  a running one has its slot released on its group's stream (ordered after
+  the work already enqueued there), and the other solves of the group go on
+  unchanged.
+
+Request status: 1 reached its end time, 2 stopped at the step cap before it
+(reported as truncated, not as completed), -1 non-finite state, -2 step-size
+underflow, -4 refused (does not fit the memory budget), -5 cancelled.
 
 All numerical work runs in libkxg; this module only schedules.
 """
@@ -88,11 +96,15 @@ class Server:
         self.groups: Dict[int, Group] = {}
         self.used_bytes = 0
         self.refused = 0
+        self._cancel: set = set()
+        self._held: Dict[int, int] = {}
 
     # ---------------------------------------------------------------- memory
     def slot_bytes(self, n: int) -> int:
-        # stepper state (x, operator input, k1, x*) + loss-rate row + slot record
-        return 5 * n * 8 + 96
+        # stepper state (x, operator input, k1, x*) + loss-rate row + slot
+        # records; used for the estimate before a group is built (the
+        # stepper's evaluation workspace is charged once it exists)
+        return 5 * n * 8 + 2 * 96 + 8
 
     def group_bytes(self, n: int) -> int:
         g = self.groups.get(n)
@@ -102,18 +114,28 @@ class Server:
 
     def _open_group(self, n: int) -> Optional[Group]:
         p = inputs.log_grid(n, self.pmin, self.pmax)
-        # estimate before building: dense FP64 + FP32 copies + packed operand + state
+        # estimate before building, of the peak during the build: the dense
+        # FP64 tensor (released at the end of a lean build unless FP64 is
+        # served), the packed operand (at most the full packing) and the
+        # slot state; after the build the handle's real holding is charged
         nb = (n + 15) // 16
         packed = ((n + 31) // 32) * nb * (nb + 1) // 2 * 16 * 512 * 4
-        est = 8 * n ** 3 + 4 * n ** 3 + packed + self.b_cap * self.slot_bytes(n)
+        est = 8 * n ** 3 + packed + self.b_cap * self.slot_bytes(n)
+        est = max(est, self._held.get(n, 0))     # what this group held when last built
         if self.used_bytes + est > self.budget:
             return None
         torch = self.torch
         stream = torch.cuda.Stream()
-        ker = kxg.Kernel(p, precs=(self.prec,), b_cap=self.b_cap, stream=stream)
+        ker = kxg.Kernel(p, precs=(self.prec,), b_cap=self.b_cap, stream=stream, lean=True)
         st = kxg.Stepper(ker, kind=kxg.HEUN, prec=self.prec, b_cap=self.b_cap,
                          expansion=kxg.EXP_RADIATION, rtol=self.rtol)
-        real = ker.bytes(-1) + self.b_cap * self.slot_bytes(n)
+        real = ker.bytes(-1) + st.bytes()
+        self._held[n] = real
+        if self.used_bytes + real > self.budget:
+            # the estimate did not include the evaluation workspaces: the
+            # group does not fit after all
+            del st, ker
+            return None
         g = Group(n, ker, st, stream, self.b_cap, free=list(range(self.b_cap)), p=p, bytes=real,
                   event=torch.cuda.Event())
         self.groups[n] = g
@@ -165,6 +187,36 @@ class Server:
             g.free.append(slot)
             done.append(req)
 
+    def cancel(self, rid: int) -> None:
+        """Cancel request `rid` (its index in the list given to run): it is
+        taken out at the next turn of the loop, wherever it is by then."""
+        self._cancel.add(int(rid))
+
+    def _apply_cancellations(self, waiting: List[Request], now: float,
+                             done: List[Request]) -> List[Request]:
+        if not self._cancel:
+            return waiting
+        keep = []
+        for req in waiting:
+            if req.rid in self._cancel:
+                self._cancel.discard(req.rid)
+                req.status, req.finished = -5, now
+                done.append(req)
+            else:
+                keep.append(req)
+        for g in self.groups.values():
+            for slot, req in list(g.slots.items()):
+                if req.rid not in self._cancel:
+                    continue
+                self._cancel.discard(req.rid)
+                # enqueued on the group's stream, after the chunk in flight
+                g.stepper.release(slot, stream=g.stream)
+                del g.slots[slot]
+                g.free.append(slot)
+                req.status, req.finished = -5, now
+                done.append(req)
+        return keep
+
     def run(self, requests: List[inputs.Solve], realtime: bool = True,
             on_tick=None) -> List[Request]:
         """Serve the requests (arrival times in seconds from the start)."""
@@ -180,6 +232,7 @@ class Server:
             while nxt < len(pending) and (pending[nxt].arrival <= now or not realtime):
                 waiting.append(pending[nxt])
                 nxt += 1
+            waiting = self._apply_cancellations(waiting, now, done)
             # admission (FIFO, later requests may pass a blocked one of another N)
             still = []
             for req in waiting:
@@ -234,22 +287,31 @@ class Server:
         return done
 
     def stats(self, done: List[Request], warm: int = 0) -> dict:
-        ok = [r for r in done if r.rid >= warm and r.status == 1]
+        """Latency and throughput over the requests from `warm` on.  Only
+        solves that reached their end time (status 1) count as completed;
+        step-capped ones (2) are truncated, cancelled (-5) and refused (-4)
+        ones are counted apart, everything else is failed."""
+        mine = [r for r in done if r.rid >= warm]
+        ok = [r for r in mine if r.status == 1]
         lat = np.array([r.latency for r in ok]) if ok else np.array([np.nan])
         span = (max(r.finished for r in ok) - min(r.arrival for r in ok)) if ok else float("nan")
         return {
             "completed": len(ok),
-            "failed": sum(1 for r in done if r.rid >= warm and r.status not in (1, -4)),
-            "refused": sum(1 for r in done if r.rid >= warm and r.status == -4),
+            "truncated": sum(1 for r in mine if r.status == 2),
+            "failed": sum(1 for r in mine if r.status not in (1, 2, -4, -5)),
+            "refused": sum(1 for r in mine if r.status == -4),
+            "cancelled": sum(1 for r in mine if r.status == -5),
             "p50_s": float(np.percentile(lat, 50)),
             "p99_s": float(np.percentile(lat, 99)),
             "solves_per_s": len(ok) / span if span and span > 0 else float("nan"),
             "mean_steps": float(np.mean([r.steps for r in ok])) if ok else float("nan"),
+            "max_steps": int(max(r.steps for r in ok)) if ok else 0,
             "mean_batch": {n: g.batch_sum / max(g.iters, 1) for n, g in self.groups.items()},
             "per_n": {str(n): {"completed": len(rs),
                                "p50_s": float(np.percentile([r.latency for r in rs], 50)),
                                "p99_s": float(np.percentile([r.latency for r in rs], 99)),
-                               "mean_steps": float(np.mean([r.steps for r in rs]))}
+                               "mean_steps": float(np.mean([r.steps for r in rs])),
+                               "max_steps": int(max(r.steps for r in rs))}
                       for n in sorted({r.solve.n for r in ok})
                       for rs in [[r for r in ok if r.solve.n == n]]},
         }

@@ -59,3 +59,25 @@ def test_oracle_thread_control_takes_effect():
         assert oracle.max_threads() == 2
     finally:
         oracle.set_threads(before)
+
+
+def test_sustainable_rate_rule():
+    rows = [{"rate_req_per_s": 10.0, "solves_per_s": 9.9, "p99_s": 4.0},
+            {"rate_req_per_s": 20.0, "solves_per_s": 19.5, "p99_s": 5.0},
+            {"rate_req_per_s": 40.0, "solves_per_s": 37.0, "p99_s": 7.9},
+            {"rate_req_per_s": 60.0, "solves_per_s": 45.0, "p99_s": 20.0}]
+    assert bench.sustainable(rows)["rate_req_per_s"] == 40.0
+    rows[2]["p99_s"] = 8.1          # p99 more than twice the unloaded one
+    assert bench.sustainable(rows)["rate_req_per_s"] == 20.0
+    assert bench.sustainable([]) is None
+
+
+def test_cpu_oracle_workload_rows():
+    """Bounded oracle timings of the workloads: config-1 solve in full, the
+    others scaled from a bounded part by the step ratio."""
+    rows = bench.cpu_config_rows(full=False)
+    assert [r["extrapolated"] for r in rows] == [False, True, True]
+    assert rows[1]["measured_steps"] == 1000
+    assert abs(rows[1]["wall_s"] - 10 * rows[1]["measured_s"]) <= 0.02 * rows[1]["wall_s"] + 0.01
+    assert abs(rows[2]["wall_s"] - 100 * rows[2]["measured_s"]) <= 0.1 + 0.01 * rows[2]["wall_s"]
+    assert bench.cpu_model()

@@ -35,21 +35,40 @@ def test_admission_refuses_when_budget_too_small():
 
 def test_stats_per_grid_size():
     """Latency percentiles overall and per grid size, warm-up and failed
-    requests left out (host logic only)."""
+    requests left out; step-capped (2), cancelled (-5) and refused (-4)
+    requests counted apart, not as completed (host logic only)."""
     srv = serving.Server()
     done = []
     for rid, (n, lat, st) in enumerate([(64, 1.0, 1), (64, 3.0, 1), (128, 2.0, 1), (128, 9.0, -1),
-                                        (64, 100.0, 1)]):
+                                        (64, 100.0, 1), (64, 7.0, 2), (128, 4.0, -5),
+                                        (128, 0.0, -4), (64, 5.0, -2)]):
         r = serving.Request(rid, inputs.Solve(1.0, 0.1, 2.0, 0.5, n=n), arrival=0.0)
         r.finished, r.status, r.steps = lat, st, 10 * (rid + 1)
         done.append(r)
     s = srv.stats(done, warm=0)
-    assert s["completed"] == 4 and s["failed"] == 1
+    assert s["completed"] == 4 and s["failed"] == 2
+    assert s["truncated"] == 1 and s["cancelled"] == 1 and s["refused"] == 1
     assert s["per_n"]["64"]["completed"] == 3 and s["per_n"]["128"]["completed"] == 1
     assert s["per_n"]["64"]["p50_s"] == 3.0 and s["per_n"]["128"]["p99_s"] == 2.0
     assert s["per_n"]["64"]["mean_steps"] == (10 + 20 + 50) / 3
+    assert s["per_n"]["64"]["max_steps"] == 50 and s["max_steps"] == 50
     w = srv.stats(done, warm=4)
     assert w["completed"] == 1 and set(w["per_n"]) == {"64"}
+
+
+def test_cancel_waiting_requests():
+    """Cancelled requests that have not been admitted leave the queue with
+    status -5 (host logic only; no group exists)."""
+    srv = serving.Server()
+    waiting = [serving.Request(rid, inputs.Solve(1.0, 0.1, 2.0, 0.5, n=64), arrival=0.0)
+               for rid in range(4)]
+    srv.cancel(1)
+    srv.cancel(3)
+    done = []
+    left = srv._apply_cancellations(waiting, 2.5, done)
+    assert [r.rid for r in left] == [0, 2]
+    assert [(r.rid, r.status, r.finished) for r in done] == [(1, -5, 2.5), (3, -5, 2.5)]
+    assert srv._apply_cancellations(left, 3.0, done) == left
 
 
 @pytest.mark.gpu
@@ -71,3 +90,64 @@ def test_serving_overlap_and_mix_invariance():
         a, b = solo.result, mixed[rid].result
         assert solo.steps == mixed[rid].steps
         assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(b)), rid
+
+
+@pytest.mark.gpu
+def test_serving_cancel_leaves_others_unchanged():
+    """Three requests cancelled while running (or waiting) leave with status
+    -5; every other request ends bit for bit as in a run without the
+    cancellations (same steps, same final state)."""
+    reqs = small_requests(12, seed=37)
+    base = serving.Server(b_cap=16, rtol=1e-4, iters_per_tick=8, keep_results=True)
+    ref = {r.rid: r for r in base.run(reqs, realtime=False)}
+    srv = serving.Server(b_cap=16, rtol=1e-4, iters_per_tick=8, keep_results=True)
+    cancel = (2, 5, 9)
+    ticks = [0]
+
+    def on_tick(ndone, ntotal):
+        ticks[0] += 1
+        if ticks[0] == 3:
+            for rid in cancel:
+                srv.cancel(rid)
+
+    done = {r.rid: r for r in srv.run(reqs, realtime=False, on_tick=on_tick)}
+    assert len(done) == 12
+    assert all(done[rid].status == -5 for rid in cancel), [done[r].status for r in cancel]
+    st = srv.stats(list(done.values()))
+    assert st["cancelled"] == 3 and st["completed"] == 9
+    for rid, r in done.items():
+        if rid in cancel:
+            continue
+        assert r.status == 1 and r.steps == ref[rid].steps, rid
+        assert np.array_equal(r.result, ref[rid].result), rid
+
+
+@pytest.mark.gpu
+def test_served_solves_match_oracle():
+    """Served solves (FP64 contraction, adaptive Heun in ln a with drift,
+    config-5 grid p in [1e-4, 20]) against the oracle's free-running adaptive
+    Heun of the same solve: one request per grid size N = 64 and 128 at the
+    shortest end time of the workload (t_end H_i = 100), run through the
+    serving loop together.  Both sides take the same controller (rtol 1e-6)
+    in FP64, so they agree to rtol level: 1e-5 max-norm, and step counts
+    within 0.1 % (over some 2e4 steps a rounding difference may flip an
+    accept decision now and then)."""
+    import oracle
+    reqs = [inputs.Solve(0.3, 0.12, 2.2, 0.8, n=64, t_end=100.0, arrival=0.0),
+            inputs.Solve(0.02, 0.07, 1.6, 3.0, n=128, t_end=100.0, arrival=0.0)]
+    srv = serving.Server(prec=serving.kxg.F64, b_cap=4, iters_per_tick=64, keep_results=True)
+    done = {r.rid: r for r in srv.run(reqs, realtime=False)}
+    for rid, sv in enumerate(reqs):
+        r = done[rid]
+        assert r.status == 1, r.status
+        p = inputs.log_grid(sv.n, inputs.SERVING_PMIN, inputs.SERVING_PMAX)
+        f0 = sv.f0(p)
+        op = oracle.Operator(p)
+        u_end = serving.u_end_of(sv.t_end)
+        ref = op.heun(f0 * p ** 3, sv.lam, op.gamma0(f0), u_end, 1e-3, expansion=True,
+                      rtol=1e-6, max_steps=200000)
+        assert abs(r.steps - len(ref["dt"])) <= max(2, 1e-3 * len(ref["dt"])), \
+            (sv.n, r.steps, len(ref["dt"]))
+        want = ref["x"] / (np.exp(3 * u_end) * p ** 3)
+        err = float(np.max(np.abs(r.result - want)) / np.max(np.abs(want)))
+        assert err <= 1e-5, (sv.n, err)
