@@ -141,11 +141,14 @@ typedef struct {
     int64_t blocks16;         /* (i-block, pair) blocks the 16-bit GEMM runs over:
                                  the union of the non-zero pairs of each group of
                                  i-blocks a workgroup covers (0 if no 16-bit) */
-    int64_t nnz_packed;       /* non-zero entries (i, k <= m) of the symmetric
-                                 packing of A'[i,k,m] = A[i,k,m] - delta_ik R[i,m]
-                                 (A'_ikm + A'_imk for k < m): the contraction's own
-                                 work is 2 flops per entry and distribution (0 on
-                                 handles without a GEMM precision) */
+    int64_t nnz_packed;       /* entries (i, k <= m) of the symmetric packing of
+                                 A'[i,k,m] = A[i,k,m] - delta_ik R[i,m]
+                                 (A'_ikm + A'_imk for k < m) that carry a weight
+                                 (A[i,k,m], A[i,m,k], or R on k = i or m = i;
+                                 counted by structure, so exact cancellations do
+                                 not move it): the contraction's own work is 2
+                                 flops per entry and distribution (0 on handles
+                                 without a GEMM precision) */
 } kxg_kernel_info;
 
 /* Fill *out for handle k.  Errors: KXG_EINVAL (null argument). */

@@ -214,12 +214,27 @@ __device__ double packed_value(const double *__restrict__ A, const double *__res
     return v;
 }
 
+// Whether entry (k, m) of the symmetric packing has any contributing term:
+// A[i,k,m], A[i,m,k] or a loss weight R[i,.] on the diagonal k = i or m = i.
+// Counting these instead of the non-zero values keeps the count free of
+// accidental cancellations (A - R rounding to exactly zero in one evaluation
+// order and not in another); it depends only on the kinematic cuts.
+__device__ int packed_structural(const double *__restrict__ A, const double *__restrict__ RT,
+                                 int n, int i, int k, int m)
+{
+    if (i >= n || k >= n || m >= n) return 0;
+    const long row = (long)i * n * n;
+    int s = A[row + (long)k * n + m] != 0.0 || A[row + (long)m * n + k] != 0.0;
+    if (k == i) s |= RT[(long)m * n + i] != 0.0;
+    if (m == i) s |= RT[(long)k * n + i] != 0.0;
+    return s;
+}
+
 // Non-zero flag of every (i-block, pair) block of the packed operand: 32
 // rows i x the 16 x 16 (k, m) block and its transpose.  Also the number of
-// non-zero entries of the symmetric packing restricted to k <= m (inside a
-// diagonal block only dk <= dm, with A'_ikm + A'_imk off the diagonal): the
-// contraction's own work, 2 flops per entry and distribution.  Grid (pair,
-// i-block).
+// entries of the symmetric packing restricted to k <= m (inside a diagonal
+// block only dk <= dm) that carry a weight: the contraction's own work, 2
+// flops per entry and distribution.  Grid (pair, i-block).
 __global__ __launch_bounds__(256) void k_block_nz(int n, int npairs, const int *__restrict__ pairs,
                                                   const double *__restrict__ A,
                                                   const double *__restrict__ RT,
@@ -235,13 +250,9 @@ __global__ __launch_bounds__(256) void k_block_nz(int n, int npairs, const int *
         const int dk = (e / kBlk) % kBlk, dm = e % kBlk;
         const double v = packed_value(A, RT, n, i, kb, mb, dk, dm);
         if (v != 0.0) any = 1;
-        if (kb != mb) {
-            c += v != 0.0;
-        } else if (dk <= dm) {
-            // the symmetric entry of the diagonal block (k <= m)
-            const double w = dk == dm ? v : v + packed_value(A, RT, n, i, kb, mb, dm, dk);
-            c += w != 0.0;
-        }
+        // entries (k <= m) with a contributing term (inside a diagonal
+        // block only dk <= dm)
+        if (kb != mb || dk <= dm) c += packed_structural(A, RT, n, i, kb * kBlk + dk, mb * kBlk + dm);
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
     if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = c;

@@ -101,7 +101,7 @@ struct kxg_kernel {
     int *d_units = nullptr;      // [nunits][4] (i-block, slot, first, end super-step)
     kxg::SlotCounts nslot;       // K slots (partials) of each i-block
     long ncomp = 0;              // non-zero (i-block, pair) blocks
-    long nnz_packed = 0;         // non-zero entries of the k <= m packing of A' = A - delta_ik R_im
+    long nnz_packed = 0;         // entries of the k <= m packing of A' = A - delta_ik R_im that carry a weight
     int nunits = 0, maxslots = 0;
     // the same for the 16-bit operands, per group of KXG_LDS_IBW i-blocks
     // (union of their non-zero pairs); Gbf/Gh hold [block][i-block of the

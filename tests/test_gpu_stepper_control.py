@@ -158,16 +158,19 @@ def test_lean_handle(dev):
 
 @pytest.mark.parametrize("n", [48, 100])
 def test_packed_nonzero_count_matches_oracle(dev, n):
-    """nnz of the k <= m packing of A' = A - delta_ik R_im (the contraction's
-    own work per distribution is twice that), from the oracle's A and R."""
+    """Entries (i, k <= m) of the symmetric packing of A' = A - delta_ik R_im
+    that carry a weight (A[i,k,m], A[i,m,k], or R on the diagonal k = i or
+    m = i; the contraction's own work per distribution is twice that), from
+    the oracle's A and R.  Counted by structure, not by value, so that an
+    accidental exact cancellation in one evaluation order cannot move it."""
     p = inputs.log_grid(n, 1e-3, 20.0)
     k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=64)
     op = oracle.Operator(p)
-    Ap = op.A.copy()
+    nzA = op.A != 0.0
     idx = np.arange(n)
-    Ap[idx, idx, :] -= op.R                       # A'[i, i, m] = A[i, i, m] - R[i, m]
-    sym = Ap + np.transpose(Ap, (0, 2, 1))        # both orderings for k < m
-    iu = np.triu_indices(n, 1)
-    want = int(np.count_nonzero(sym[:, iu[0], iu[1]]) +
-               np.count_nonzero(Ap[:, idx, idx]))
+    loss = np.zeros_like(nzA)
+    loss[idx, idx, :] = op.R != 0.0               # k = i carries R[i, m]
+    s = nzA | np.transpose(nzA, (0, 2, 1)) | loss | np.transpose(loss, (0, 2, 1))
+    iu = np.triu_indices(n)
+    want = int(np.count_nonzero(s[:, iu[0], iu[1]]))
     assert k.stats()["nnz_packed"] == want
