@@ -207,6 +207,27 @@ kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev,
                     int32_t B, double *C_dev, uint32_t flags, double *diag_dev,
                     void *stream);
 
+/* Size of the library's static device scratch array (64 MiB per device),
+ * the workspace of kxg_eval_noalloc. */
+#define KXG_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* kxg_eval that allocates nothing: for callers that cannot call hipMalloc
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * device allocation).  Same arguments, results and errors as kxg_eval, bit
+ * for bit; the call's workspace (split partials, loss rates, GEMM operands,
+ * FP16 scales) lives in a static device array of KXG_NOALLOC_SCRATCH_BYTES
+ * that every device the library runs on holds until the process ends,
+ * instead of in the handle's workspace.  The first call on a device looks up
+ * that device's copy of the array (no allocation).  Every call on a device
+ * shares its array: calls that overlap on one device (on several streams,
+ * or from several threads without ordering) race; calls on one stream are
+ * ordered.  The array keeps the last call's contents; nothing in it needs
+ * to start at zero.  Additional error: KXG_EINVAL when the call needs more
+ * scratch than the array holds (the message gives both sizes). */
+kxg_status kxg_eval_noalloc(const kxg_kernel *k, int32_t prec, const double *f_dev,
+                            int32_t B, double *C_dev, uint32_t flags, double *diag_dev,
+                            void *stream);
+
 /* Discrete moments of B distributions (App. B): out_dev [B][3] =
  * { sum h f, sum h E f, -sum_{f>0} h f (ln f - 1) }.  Asynchronous. */
 kxg_status kxg_moments(const kxg_kernel *k, const double *f_dev, int32_t B,

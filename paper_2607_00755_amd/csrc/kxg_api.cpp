@@ -681,10 +681,10 @@ static kxg_status check_prec(const kxg_kernel *k, int32_t prec)
     return KXG_OK;
 }
 
-kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev, int32_t B,
-                    double *C_dev, uint32_t flags, double *diag_dev, void *stream)
+// Argument checks shared by kxg_eval and kxg_eval_noalloc.
+static kxg_status check_eval(const kxg_kernel *k, int32_t prec, const double *f_dev, int32_t B,
+                             double *C_dev, uint32_t flags)
 {
-    g_err[0] = 0;
     if (!k || !f_dev || !C_dev) { set_error("kxg_eval: null handle or buffer"); return KXG_EINVAL; }
     if (B < 1 || B > k->b_cap) { set_error("kxg_eval: B=%d outside [1, b_cap=%d]", B, k->b_cap); return KXG_EINVAL; }
     if (flags & ~(KXG_PROJECT | KXG_INTERP_LOG | KXG_STAT_BOSE | KXG_STAT_FERMI | KXG_SPLIT_F_ONLY | KXG_SPLIT_NONE)) { set_error("kxg_eval: unknown flags 0x%x", flags); return KXG_EINVAL; }
@@ -698,8 +698,27 @@ kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev, int3
         if (prec != KXG_F64 && prec != KXG_F32) { set_error("kxg_eval: exact-form evaluation runs in FP64 or FP32 only"); return KXG_EUNSUPPORTED; }
         if (prec == KXG_F32 && !k->d_A32) { set_error("kxg_eval: FP32 tensor not built"); return KXG_EUNSUPPORTED; }
     }
+    return KXG_OK;
+}
+
+kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev, int32_t B,
+                    double *C_dev, uint32_t flags, double *diag_dev, void *stream)
+{
+    g_err[0] = 0;
+    const kxg_status st = check_eval(k, prec, f_dev, B, C_dev, flags);
+    if (st != KXG_OK) return st;
     return eval_impl(*k, k->ws, prec, f_dev, B, C_dev, flags, diag_dev,
                      static_cast<hipStream_t>(stream));
+}
+
+kxg_status kxg_eval_noalloc(const kxg_kernel *k, int32_t prec, const double *f_dev, int32_t B,
+                            double *C_dev, uint32_t flags, double *diag_dev, void *stream)
+{
+    g_err[0] = 0;
+    const kxg_status st = check_eval(k, prec, f_dev, B, C_dev, flags);
+    if (st != KXG_OK) return st;
+    return eval_noalloc_impl(*k, prec, f_dev, B, C_dev, flags, diag_dev,
+                             static_cast<hipStream_t>(stream));
 }
 
 kxg_status kxg_moments(const kxg_kernel *k, const double *f_dev, int32_t B, double *out_dev,

@@ -21,6 +21,7 @@
 #include "kxg_internal.h"
 #include "kxg_step.h"
 
+#include <mutex>
 #include <type_traits>
 
 namespace kxg {
@@ -1489,6 +1490,99 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
                                        nullptr, nullptr, diag ? rate : nullptr, f, k, B, project, C,
                                        diag, step, s, nullptr, 0.0, 1));
     return KXG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation without allocation: the workspace of one call (split partials,
+// loss rates, GEMM operands and FP16 scales) is carved out of a file-scope
+// device array instead of the handle's workspace.  Each device holds its own
+// copy of the array for the life of the process; host code never passes the
+// array's name to a kernel (that is a host-side stand-in, not a device
+// address) but the address hipGetSymbolAddress returns for the current
+// device, looked up once per device.  Calls that overlap on one device share
+// the array and race.
+static __device__ __align__(256) unsigned char scratch[KXG_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+static kxg_status scratch_of_current_device(unsigned char **out)
+{
+    int dev = 0;
+    KXG_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("kxg_eval_noalloc: device %d beyond the %d supported", dev, kMaxDevices);
+        return KXG_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("kxg_eval_noalloc: hipGetSymbolAddress of the scratch array failed: %s",
+                      hipGetErrorString(e));
+            return KXG_EHIP;
+        }
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return KXG_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bytes of workspace one call of (prec, B, flags) needs, laid out as
+// [partials | loss rates [B][n]] [operand, natural order] [operand, parity
+// order] [FP16 scales]; fills ws with addresses inside `base` (if given).
+static size_t call_workspace(const kxg_kernel &k, int prec, int B, uint32_t flags,
+                             unsigned char *base, Workspace &ws)
+{
+    const int n = k.n;
+    const bool exact = (flags & (KXG_INTERP_LOG | KXG_STAT_BOSE | KXG_STAT_FERMI)) != 0;
+    const Path P = path_of(k, prec, B);
+    size_t part;
+    int bpad = 0;
+    if (exact) {
+        part = (size_t)stream_splits(n) * B * 4 * n * sizeof(double);
+    } else if (P.stream) {
+        part = (size_t)stream_splits(n) * B * n * sizeof(double);
+    } else {
+        bpad = P.bpad;
+        const int slots = P.lds ? k.maxslots16 : k.maxslots;
+        part = (size_t)slots * bpad * k.geo.ipad * sizeof(float);
+    }
+    const size_t rate = (size_t)B * n * sizeof(double);
+    const size_t fb = (size_t)k.geo.nb * bpad * kBlk * sizeof(float);
+    const size_t o_part = 0, o_fop = align256(part + rate), o_fpar = o_fop + align256(fb),
+                 o_fsc = o_fpar + align256(fb), total = o_fsc + align256((size_t)bpad * sizeof(float));
+    ws = Workspace{};
+    ws.part_bytes = part + rate;
+    ws.b_cap = B;
+    ws.bpad_cap = bpad;
+    if (base) {
+        ws.part = base + o_part;
+        ws.fop = bpad ? reinterpret_cast<float *>(base + o_fop) : nullptr;
+        ws.fpar = bpad ? reinterpret_cast<float *>(base + o_fpar) : nullptr;
+        ws.fscale = bpad ? reinterpret_cast<float *>(base + o_fsc) : nullptr;
+    }
+    return total;
+}
+
+kxg_status eval_noalloc_impl(const kxg_kernel &k, int prec, const double *f, int B, double *C,
+                             uint32_t flags, double *diag, hipStream_t s)
+{
+    Workspace ws;
+    const size_t need = call_workspace(k, prec, B, flags, nullptr, ws);
+    if (need > (size_t)KXG_NOALLOC_SCRATCH_BYTES) {
+        set_error("kxg_eval_noalloc: this call needs %zu bytes of scratch, the static array holds %zu "
+                  "(fewer distributions per call, or kxg_eval)", need, (size_t)KXG_NOALLOC_SCRATCH_BYTES);
+        return KXG_EINVAL;
+    }
+    unsigned char *base = nullptr;
+    const kxg_status st = scratch_of_current_device(&base);
+    if (st != KXG_OK) return st;
+    call_workspace(k, prec, B, flags, base, ws);
+    return eval_impl(k, ws, prec, f, B, C, flags, diag, s);
 }
 
 hipError_t launch_moments(const kxg_kernel &k, const double *f, int B, double *out, hipStream_t s)

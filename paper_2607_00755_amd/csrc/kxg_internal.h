@@ -24,6 +24,7 @@ void set_error(const char *fmt, ...);
     } while (0)
 
 constexpr int kMaxN = 1024;          // largest grid
+constexpr int kMaxDevices = 64;      // devices the allocation-free evaluation keeps a scratch address for
 
 // Tuning of the GEMM launches (overridable at build time).
 #ifndef KXG_GEMM_WG_TARGET
@@ -146,6 +147,10 @@ struct StepArgs;
 kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const double *f,
                      int B, double *C, uint32_t flags, double *diag, hipStream_t s,
                      const StepArgs *step = nullptr);
+// kxg_eval with the call's workspace in the library's static device array
+// (no allocation); KXG_EINVAL if the call needs more than that array holds.
+kxg_status eval_noalloc_impl(const kxg_kernel &k, int prec, const double *f, int B, double *C,
+                             uint32_t flags, double *diag, hipStream_t s);
 kxg_status prep_operands(const kxg_kernel &k, const Workspace &ws, int prec, const double *f,
                          int B, hipStream_t s);
 kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws);

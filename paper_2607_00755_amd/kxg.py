@@ -31,6 +31,7 @@ SPLIT_NONE = 32
 WITH_BRACKETS = 1 << 8
 LEAN = 1 << 9
 NDIAG = 12
+NOALLOC_SCRATCH_BYTES = 64 << 20   # the static scratch of kxg_eval_noalloc
 RK4, HEUN = 0, 1
 EXP_NONE, EXP_RADIATION = 0, 1
 
@@ -41,7 +42,7 @@ EXPORTED = [
     "kxg_stepper_release", "kxg_stepper_advance", "kxg_stepper_set_dt",
     "kxg_stepper_query", "kxg_stepper_get", "kxg_stepper_save", "kxg_stepper_load",
     "kxg_last_error", "kxg_profile_begin", "kxg_profile_end", "kxg_kernel_stats",
-    "kxg_peak_probe", "kxg_stepper_set_many", "kxg_stepper_bytes",
+    "kxg_peak_probe", "kxg_stepper_set_many", "kxg_stepper_bytes", "kxg_eval_noalloc",
 ]
 
 
@@ -116,6 +117,8 @@ def lib():
         L.kxg_kernel_grid.argtypes = [_vp, _dp, _dp, _dp, _dp]
         L.kxg_eval.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctypes.c_uint32,
                                _vp, _vp]
+        L.kxg_eval_noalloc.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp,
+                                       ctypes.c_uint32, _vp, _vp]
         L.kxg_moments.argtypes = [_vp, _vp, ctypes.c_int32, _vp, _vp]
         L.kxg_gauss_legendre.argtypes = [ctypes.c_int32, _dp, _dp]
         L.kxg_stepper_create.argtypes = [_vp, ctypes.POINTER(StepperParams), ctypes.POINTER(_vp)]
@@ -264,6 +267,20 @@ class Kernel:
         diagnostics=False no diagnostics are computed and diag is None.
         split (16-bit precisions): 3 products of the hi+lo split (default), 2
         (F2 split only) or 1 (no split), the latter two as ablations."""
+        return self._eval(lib().kxg_eval, f, prec, project, out, diag, stream, log_interp,
+                          eta, diagnostics, split)
+
+    def eval_noalloc(self, f, prec: int = F64, project: bool = True, out=None, diag=None,
+                     stream=None, log_interp: bool = False, eta: int = 0,
+                     diagnostics: bool = True, split: int = 3):
+        """eval through kxg_eval_noalloc: the same result, with the call's
+        workspace in the library's static device array (raises KxgError when
+        the call needs more than that array holds)."""
+        return self._eval(lib().kxg_eval_noalloc, f, prec, project, out, diag, stream,
+                          log_interp, eta, diagnostics, split)
+
+    def _eval(self, entry, f, prec, project, out, diag, stream, log_interp, eta, diagnostics,
+              split):
         import torch
         if f.dim() == 1:
             f = f.view(1, -1)
@@ -275,10 +292,10 @@ class Kernel:
         flags = (PROJECT if project else 0) | (INTERP_LOG if log_interp else 0)
         flags |= STAT_BOSE if eta > 0 else (STAT_FERMI if eta < 0 else 0)
         flags |= {3: 0, 2: SPLIT_F_ONLY, 1: SPLIT_NONE}[split]
-        _check(lib().kxg_eval(self._h, int(prec), _dev_ptr(f, B * self.n, "f"), B,
-                              _dev_ptr(out, B * self.n, "C"), flags,
-                              _dev_ptr(diag, B * NDIAG, "diag") if diag is not None else None,
-                              _stream_ptr(stream)))
+        _check(entry(self._h, int(prec), _dev_ptr(f, B * self.n, "f"), B,
+                     _dev_ptr(out, B * self.n, "C"), flags,
+                     _dev_ptr(diag, B * NDIAG, "diag") if diag is not None else None,
+                     _stream_ptr(stream)))
         return out, diag
 
     def moments(self, f, out=None, stream=None):

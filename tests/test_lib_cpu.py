@@ -57,6 +57,7 @@ def test_build_rejects_bad_arguments(kwargs, msg):
 def test_null_handles_are_rejected():
     L = kxg.lib()
     assert L.kxg_eval(None, 0, None, 1, None, 0, None, None) == kxg.EINVAL
+    assert L.kxg_eval_noalloc(None, 0, None, 1, None, 0, None, None) == kxg.EINVAL
     assert L.kxg_stepper_advance(None, 1, None) == kxg.EINVAL
     assert L.kxg_kernel_bytes(None, 0) == 0
     L.kxg_kernel_free(None)
