@@ -48,6 +48,10 @@ def lib():
         L.or_weight.restype = ctypes.c_double
         L.or_drift.restype = ctypes.c_double
         L.or_heun.restype = ctypes.c_int
+        L.or_deposit.restype = ctypes.c_int
+        L.or_condensate_a3nu.restype = ctypes.c_double
+        L.or_gamma22.restype = ctypes.c_double
+        L.or_freeze_in.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -205,6 +209,54 @@ class Operator:
                 "attempts": {"dt": att_dt[:na], "err": att_err[:na],
                              "accepted": att_ok[:na].astype(bool)}}
 
+    # -- freeze-in sources and the two regimes of the evolution (Sec. 3, 4.2) --
+    def deposit(self, p0: float):
+        """(j, w_j, w_{j+1}): nodes and energy-linear weights sharing the
+        condensate injection at momentum p0 (j = -1 outside the grid)."""
+        return deposit(self.grid, p0)
+
+    def sources(self, u: float, Hi: float, **kw):
+        """Freeze-in source vector S_i(u) in the units of C (see sources())."""
+        return sources(self.grid, u, Hi, **kw)
+
+    def gamma22(self, f, lam: float = 1.0) -> float:
+        """Effective self-scattering rate n<sigma v>: the per-particle loss
+        rate lam (R f)_i averaged over the particles of f."""
+        return float(lib().or_gamma22(ctypes.c_int(self.n), _p(self.R), _p(self.grid.h),
+                                      _p(_f64(f)), ctypes.c_double(lam)))
+
+    def freeze_in(self, x0, lam: float, Hi: float, u_end: float, du: float,
+                  eps_switch: float = 1e-2, N0: float = 0.0, Gamma: float = 0.0,
+                  p0: float = 1.0, kappa: float = 0.0, mh: float = 250.0, Ti: float = 1.0,
+                  dt0: float = 1e-3, project: bool = True, rtol: float = 1e-6,
+                  atol_rel: float = 1e-12, safety: float = 0.9, fmin: float = 0.2,
+                  fmax: float = 5.0, max_steps: int = 100000, replay_dt=None, u0: float = 0.0):
+        """Source-only RK4 on fixed du until Gamma_22/H > eps_switch, then
+        adaptive (or replayed) Heun with the elastic operator (atol =
+        atol_rel max|x| at the switch); state g = a^3 p^3 f.  Returns dict: x, n_src, u_switch, regime-2 accepted
+        (u, dt), outflow, rejected."""
+        x = _f64(x0).copy()
+        nrep = 0 if replay_dt is None else len(replay_dt)
+        cap = max(nrep, max_steps) + 1
+        acc_u, acc_dt = np.empty(cap), np.empty(cap)
+        rd = None if replay_dt is None else _f64(replay_dt)
+        nsrc, usw = ctypes.c_int(0), ctypes.c_double(0.0)
+        outflow, nrej = ctypes.c_double(0.0), ctypes.c_int(0)
+        nacc = lib().or_freeze_in(
+            ctypes.c_int(self.n), _p(self.A), _p(self.R), _p(self.grid.p),
+            _p(self.grid.dp_override), ctypes.c_double(self.mass), _p(x),
+            ctypes.c_int(int(project)), ctypes.c_double(lam), ctypes.c_double(Hi),
+            ctypes.c_double(u0), ctypes.c_double(u_end), ctypes.c_double(du),
+            ctypes.c_double(eps_switch), ctypes.c_double(N0), ctypes.c_double(Gamma),
+            ctypes.c_double(p0), ctypes.c_double(kappa), ctypes.c_double(mh),
+            ctypes.c_double(Ti), ctypes.c_double(dt0), ctypes.c_double(rtol),
+            ctypes.c_double(atol_rel), ctypes.c_double(safety), ctypes.c_double(fmin),
+            ctypes.c_double(fmax), ctypes.c_int(max_steps), ctypes.c_int(nrep), _p(rd),
+            _p(acc_u), _p(acc_dt), ctypes.byref(nsrc), ctypes.byref(usw),
+            ctypes.byref(outflow), ctypes.byref(nrej))
+        return {"x": x, "n_src": nsrc.value, "u_switch": usw.value, "u": acc_u[:nacc],
+                "dt": acc_dt[:nacc], "outflow": outflow.value, "rejected": nrej.value}
+
     def gamma0(self, f) -> float:
         """Largest loss rate max_i sum_j R_ij f_j (the initial scattering rate)."""
         return float(np.max(self.R @ _f64(f)))
@@ -223,6 +275,37 @@ def direct(p, f, mass=1.0, gdof=1.0, m2=1.0, quad=GL, nmu=18, interp=LIN,
                                 ctypes.c_int(interp), ctypes.c_int(int(eta)), _p(f), _p(g),
                                 _p(l), _p(c))
     return c, g, l
+
+
+def deposit(grid: Grid, p0: float):
+    """(j, w_j, w_{j+1}) of the condensate injection at momentum p0."""
+    wl, wr = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    j = lib().or_deposit(ctypes.c_int(grid.n), _p(grid.p), ctypes.c_double(grid.mass),
+                         ctypes.c_double(p0), ctypes.byref(wl), ctypes.byref(wr))
+    return j, wl.value, wr.value
+
+
+def sources(grid: Grid, u: float, Hi: float, N0: float = 0.0, Gamma: float = 0.0,
+            p0: float = 1.0, kappa: float = 0.0, mh: float = 250.0, Ti: float = 1.0):
+    """Freeze-in source vector S_i(u) on a grid, in the units of C: the
+    condensate injection (a^3 nu_Phi = N0 at u = 0, decay rate Gamma, decay
+    momentum p0) and the Higgs decay (amplitude kappa, mass mh, bath
+    temperature Ti at u = 0)."""
+    j, wl, wr = deposit(grid, p0) if N0 > 0.0 else (-1, 0.0, 0.0)
+    S = np.empty(grid.n)
+    lib().or_sources(ctypes.c_int(grid.n), _p(grid.p), _p(grid.h), _p(grid.E),
+                     ctypes.c_double(grid.mass), ctypes.c_double(u), ctypes.c_double(Hi),
+                     ctypes.c_double(N0), ctypes.c_double(Gamma), ctypes.c_int(j),
+                     ctypes.c_double(wl), ctypes.c_double(wr), ctypes.c_double(kappa),
+                     ctypes.c_double(mh), ctypes.c_double(Ti), _p(S))
+    return S
+
+
+def condensate_a3nu(N0: float, Gamma: float, Hi: float, u: float) -> float:
+    """a^3 nu_Phi(u): the solution of the condensate's decay law in the
+    radiation era (code units, nu = (2 pi^2 / g) n)."""
+    return float(lib().or_condensate_a3nu(ctypes.c_double(N0), ctypes.c_double(Gamma),
+                                          ctypes.c_double(Hi), ctypes.c_double(u)))
 
 
 def drift(p, dp, g):

@@ -22,6 +22,14 @@
  * right-hand side by the a^-1 scaling of its collision increment.  Its
  * step-size law (safety 0.9, exponent 1/2, clamps [0.2, 5]) is a reading
  * the paper leaves open; the tests check it only against its own statement.
+ * The freeze-in part (Sec. 3, Sec. 4.2) is pinned by the injection moments
+ * of the condensate (number and energy, exactly), the decay law of the
+ * condensate against a numerical solution, the Higgs-decay rate against
+ * its Bessel-function closed form, Gamma_22 against n sigma <v_rel> of a
+ * non-relativistic Maxwell-Boltzmann gas, conservation of chi number plus
+ * twice the condensate's (fourth order in the source-only step), the switch
+ * at the first state over the threshold, and the second regime against the
+ * pinned Heun of the expanding run.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -621,6 +629,259 @@ int or_heun(int n, const double *A, const double *R, const double *p,
     if (n_att) *n_att = natt;
     free(dp); free(E); free(K); free(h); free(k1); free(k2); free(xs);
     free(xn); free(f); free(c); free(tmp);
+    return acc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Freeze-in sources of the two-source scenario (Sec. 3), in the code's     */
+/* units: f as in the moments sum_i h_i f_i = (2 pi^2 / g) n, so a number   */
+/* density n enters as nu = (2 pi^2 / g) n, and time in units where H at    */
+/* u = ln a = 0 is H_i (radiation era, H = H_i e^{-2u}, t = e^{2u}/(2H_i)). */
+/*                                                                          */
+/* Cold condensate, eq. C_condensate_decay: C = (2 pi^2/g) 2 Gamma n_Phi    */
+/* delta(p - p0)/p0^2, i.e. 2 Gamma nu_Phi particles per unit time and      */
+/* volume at momentum p0.  nu_Phi follows d(nu a^3)/dt = -Gamma nu a^3 (the */
+/* decay law of the condensate, dn/dt + 3Hn = -Gamma n), whose solution in  */
+/* the radiation era is                                                      */
+/*   a^3 nu_Phi(u) = N0 exp(-(Gamma / (2 H_i)) (e^{2u} - 1)),               */
+/* N0 = a^3 nu_Phi at u = 0.                                                 */
+/* Reading of the delta on the grid: the injection is shared between the    */
+/* two nodes that bracket p0 in kinetic energy, with the energy-linear      */
+/* weights of eq. app_interp_weights, w_{j+1} = (K0 - K_j)/(K_{j+1} - K_j), */
+/* w_j = 1 - w_{j+1}, each divided by h_j: then sum_i h_i C_i = 2 Gamma nu  */
+/* and sum_i h_i E_i C_i = E0 2 Gamma nu exactly (E0 = sqrt(p0^2+m^2) =     */
+/* m_Phi/2 for Phi -> chi chi), the two injection moments of Sec. 3.        */
+/* Returns j (or -1 when p0 lies outside the grid) and the two weights.     */
+/* ------------------------------------------------------------------------ */
+int or_deposit(int n, const double *p, double mass, double p0, double *wl,
+               double *wr)
+{
+    double K0 = p0 * p0 / (sqrt(p0 * p0 + mass * mass) + mass);
+    double Kf = p[0] * p[0] / (sqrt(p[0] * p[0] + mass * mass) + mass);
+    double Kl = p[n - 1] * p[n - 1] / (sqrt(p[n - 1] * p[n - 1] + mass * mass) + mass);
+    if (!(K0 >= Kf && K0 <= Kl))
+        return -1;
+    int j = 0;
+    for (int q = 0; q < n - 1; ++q) {
+        double Kq = p[q] * p[q] / (sqrt(p[q] * p[q] + mass * mass) + mass);
+        if (Kq <= K0)
+            j = q;
+    }
+    double Kj = p[j] * p[j] / (sqrt(p[j] * p[j] + mass * mass) + mass);
+    double Kj1 = p[j + 1] * p[j + 1] / (sqrt(p[j + 1] * p[j + 1] + mass * mass) + mass);
+    *wr = (K0 - Kj) / (Kj1 - Kj);
+    *wl = 1.0 - *wr;
+    return j;
+}
+
+double or_condensate_a3nu(double N0, double Gamma, double Hi, double u)
+{
+    return N0 * exp(-(Gamma / (2.0 * Hi)) * (exp(2.0 * u) - 1.0));
+}
+
+/* Higgs decay h -> chi chi in the thermal bath, eq. C_higgs_decay:         */
+/*   C(p) = kappa (T / (E p)) (exp(-E_-/T) - exp(-E_+/T)),                  */
+/*   E_+- = (m_h^2 E +- m_h p sqrt(m_h^2 - 4 m^2)) / (2 m^2),               */
+/* kappa = (lambda_Hchi v)^2 / (8 pi g) in the code's units.  Reading of    */
+/* the bath temperature (the paper does not print T(a)): T = T_i e^{-u},    */
+/* the radiation era with a constant number of relativistic species, the    */
+/* same era as H = H_i e^{-2u}.  The difference of exponentials is taken as */
+/* exp(-E_-/T) (1 - exp(-(E_+ - E_-)/T)) with the second factor by expm1.   */
+static double higgs_source(double p, double E, double mass, double kappa,
+                           double mh, double T)
+{
+    double kh = sqrt(mh * mh - 4.0 * mass * mass);
+    double m2x2 = 2.0 * mass * mass;
+    double Em = (mh * mh * E - mh * p * kh) / m2x2;
+    double dE = 2.0 * mh * p * kh / m2x2;                  /* E_+ - E_- */
+    return kappa * (T / (E * p)) * exp(-Em / T) * (-expm1(-dE / T));
+}
+
+/* Source vector S_i(u) (both channels) in the units of C. */
+void or_sources(int n, const double *p, const double *h, const double *E,
+                double mass, double u, double Hi, double N0, double Gamma,
+                int jdep, double wl, double wr, double kappa, double mh,
+                double Ti, double *S)
+{
+    for (int i = 0; i < n; ++i)
+        S[i] = 0.0;
+    if (kappa > 0.0) {
+        double T = Ti * exp(-u);
+        for (int i = 0; i < n; ++i)
+            S[i] += higgs_source(p[i], E[i], mass, kappa, mh, T);
+    }
+    if (N0 > 0.0 && jdep >= 0) {
+        double nu = exp(-3.0 * u) * or_condensate_a3nu(N0, Gamma, Hi, u);
+        S[jdep] += 2.0 * Gamma * nu * wl / h[jdep];
+        S[jdep + 1] += 2.0 * Gamma * nu * wr / h[jdep + 1];
+    }
+}
+
+/* Effective self-scattering rate Gamma_22 = n <sigma v> (Sec. 4.2): the    */
+/* per-particle loss rate lambda sum_j R_ij f_j averaged over the particles */
+/* of f, lambda sum_i h_i f_i (R f)_i / sum_i h_i f_i (0 for f = 0).        */
+double or_gamma22(int n, const double *R, const double *h, const double *f,
+                  double lambda)
+{
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < n; ++j)
+            r += R[(size_t)i * n + j] * f[j];
+        num += h[i] * f[i] * r;
+        den += h[i] * f[i];
+    }
+    return den > 0.0 ? lambda * num / den : 0.0;
+}
+
+/* Right-hand side of the freeze-in run in u for g = a^3 p^3 f:            */
+/*   dg/du = drift + a^3 p^3 (coll lambda C[f] + S(u)) / H(u),              */
+/* C projected if asked; coll = 0 in the source-only regime.  Returns the   */
+/* outflow rate g_0 of the drift.                                           */
+static double rhs_fi(int n, const double *A, const double *R, const double *p,
+                     const double *dp, const double *h, const double *E,
+                     double mass, const double *x, double u, double lambda,
+                     double Hi, int coll, int project, double N0, double Gamma,
+                     int jdep, double wl, double wr, double kappa, double mh,
+                     double Ti, double *out, double *f, double *c, double *S,
+                     double *tmp)
+{
+    double a3 = exp(3.0 * u);
+    for (int i = 0; i < n; ++i)
+        f[i] = x[i] / (a3 * p[i] * p[i] * p[i]);
+    if (coll)
+        rhs_static(n, A, R, h, E, f, lambda, project, c, tmp);
+    else
+        for (int i = 0; i < n; ++i)
+            c[i] = 0.0;
+    or_sources(n, p, h, E, mass, u, Hi, N0, Gamma, jdep, wl, wr, kappa, mh, Ti, S);
+    double outflow = or_drift(n, p, dp, x, out);
+    double H = Hi * exp(-2.0 * u);
+    for (int i = 0; i < n; ++i)
+        out[i] += a3 * p[i] * p[i] * p[i] * (c[i] + S[i]) / H;
+    return outflow;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The two regimes of Sec. 4.2 for a freeze-in run, from u0 to u_end:       */
+/*  1. source-only: elastic operator off, classical RK4 on fixed steps du   */
+/*     in u (the sources are smooth); before each step the effective rate   */
+/*     Gamma_22 of the current f is compared with H(u);                     */
+/*  2. from the first state with Gamma_22 / H > eps_switch on: the elastic  */
+/*     operator is on and the adaptive Heun of or_heun advances the state   */
+/*     (first step dt0; in replay mode the dt list of this regime), with    */
+/*     atol = atol_rel max_i |x_i| of the state at the switch (a run that   */
+/*     starts from f = 0 has no scale before the sources act).               */
+/* The source-only step is clipped to end at u_end.  Counts: *n_src steps  */
+/* in regime 1, u_switch (u_end if never switched), the accepted regime-2  */
+/* steps (returned; their (u, dt) in acc_u/acc_dt), rejections, outflow    */
+/* (RK4 weights in regime 1, trapezoid in regime 2).  max_steps caps the   */
+/* accepted steps of both regimes together.                                */
+/* ------------------------------------------------------------------------ */
+int or_freeze_in(int n, const double *A, const double *R, const double *p,
+                 const double *dp_override, double mass, double *x, int project,
+                 double lambda, double Hi, double u0, double u_end, double du,
+                 double eps_switch, double N0, double Gamma, double p0,
+                 double kappa, double mh, double Ti, double dt0, double rtol,
+                 double atol_rel, double safety, double fmin, double fmax,
+                 int max_steps, int nreplay, const double *replay_dt,
+                 double *acc_u, double *acc_dt, int *n_src, double *u_switch,
+                 double *outflow, int *nrejected)
+{
+    double *dp = malloc(sizeof(double) * n), *E = malloc(sizeof(double) * n);
+    double *K = malloc(sizeof(double) * n), *h = malloc(sizeof(double) * n);
+    double *k1 = malloc(sizeof(double) * n), *k2 = malloc(sizeof(double) * n);
+    double *k3 = malloc(sizeof(double) * n), *k4 = malloc(sizeof(double) * n);
+    double *y = malloc(sizeof(double) * n), *xn = malloc(sizeof(double) * n);
+    double *f = malloc(sizeof(double) * n), *c = malloc(sizeof(double) * n);
+    double *S = malloc(sizeof(double) * n), *tmp = malloc(sizeof(double) * n);
+    or_grid(n, p, mass, dp_override, dp, E, K, h);
+    double wl = 0.0, wr = 0.0;
+    int jdep = N0 > 0.0 ? or_deposit(n, p, mass, p0, &wl, &wr) : -1;
+    double u = u0, out = 0.0;
+    int steps = 0, nsrc = 0, rej = 0, acc = 0, coll = 0;
+    *u_switch = u_end;
+#define RHS(xx, uu, kk, cc) rhs_fi(n, A, R, p, dp, h, E, mass, xx, uu, lambda, Hi, cc, \
+                                   project, N0, Gamma, jdep, wl, wr, kappa, mh, Ti, kk, \
+                                   f, c, S, tmp)
+    /* regime 1 */
+    while (u < u_end && (max_steps <= 0 || steps < max_steps)) {
+        double a3 = exp(3.0 * u);
+        for (int i = 0; i < n; ++i)
+            f[i] = x[i] / (a3 * p[i] * p[i] * p[i]);
+        double H = Hi * exp(-2.0 * u);
+        if (or_gamma22(n, R, h, f, lambda) / H > eps_switch) {
+            coll = 1;
+            *u_switch = u;
+            break;
+        }
+        double d = u + du > u_end ? u_end - u : du;
+        double o1 = RHS(x, u, k1, 0);
+        for (int i = 0; i < n; ++i) y[i] = x[i] + 0.5 * d * k1[i];
+        double o2 = RHS(y, u + 0.5 * d, k2, 0);
+        for (int i = 0; i < n; ++i) y[i] = x[i] + 0.5 * d * k2[i];
+        double o3 = RHS(y, u + 0.5 * d, k3, 0);
+        for (int i = 0; i < n; ++i) y[i] = x[i] + d * k3[i];
+        double o4 = RHS(y, u + d, k4, 0);
+        for (int i = 0; i < n; ++i)
+            x[i] += d / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+        out += d / 6.0 * (o1 + 2.0 * o2 + 2.0 * o3 + o4);
+        u += d;
+        ++steps;
+        ++nsrc;
+    }
+    /* regime 2: adaptive (or replayed) Heun with the elastic operator */
+    double dt = dt0, atol = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (fabs(x[i]) > atol)
+            atol = fabs(x[i]);
+    atol *= atol_rel;
+    if (!(atol > 0.0))
+        atol = 1e-300;
+    int limit = nreplay > 0 ? nreplay : (max_steps > 0 ? max_steps - steps : 0x7fffffff);
+    while (coll && acc < limit) {
+        if (nreplay > 0) {
+            dt = replay_dt[acc];
+        } else {
+            if (!(u < u_end))
+                break;
+            if (u + dt > u_end)
+                dt = u_end - u;
+        }
+        double o1 = RHS(x, u, k1, 1);
+        for (int i = 0; i < n; ++i) y[i] = x[i] + dt * k1[i];
+        double o2 = RHS(y, u + dt, k2, 1);
+        double err = 0.0;
+        for (int i = 0; i < n; ++i) {
+            xn[i] = x[i] + 0.5 * dt * (k1[i] + k2[i]);
+            double sc = atol + rtol * (fabs(x[i]) > fabs(xn[i]) ? fabs(x[i]) : fabs(xn[i]));
+            double e = fabs(xn[i] - y[i]) / sc;
+            if (e > err)
+                err = e;
+        }
+        if (nreplay > 0 || err <= 1.0) {
+            if (acc_u) acc_u[acc] = u;
+            if (acc_dt) acc_dt[acc] = dt;
+            out += 0.5 * dt * (o1 + o2);
+            u += dt;
+            memcpy(x, xn, sizeof(double) * n);
+            ++acc;
+        } else {
+            ++rej;
+        }
+        if (nreplay == 0) {
+            double fac = err > 0.0 ? safety / sqrt(err) : fmax;
+            if (fac < fmin) fac = fmin;
+            if (fac > fmax) fac = fmax;
+            dt *= fac;
+        }
+    }
+#undef RHS
+    *n_src = nsrc;
+    if (outflow) *outflow = out;
+    if (nrejected) *nrejected = rej;
+    free(dp); free(E); free(K); free(h); free(k1); free(k2); free(k3); free(k4);
+    free(y); free(xn); free(f); free(c); free(S); free(tmp);
     return acc;
 }
 

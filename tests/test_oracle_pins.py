@@ -491,3 +491,152 @@ def test_quantum_operator_dilute_limit_and_statistics_sign():
     assert np.all(gb >= g0) and np.all(gf <= g0) and np.all(lb >= l0) and np.all(lf <= l0)
     # the eta-odd parts are equal and opposite (the eta^2 terms cancel in Lambda)
     assert np.allclose((cb - c0), -(cf - c0), rtol=1e-10, atol=1e-14 * np.max(np.abs(gb)))
+
+
+# --------------------------------------------------------------------------
+# Freeze-in sources of the two-source scenario (Sec. 3) and the two regimes
+# of the evolution (Sec. 4.2).
+def test_condensate_deposit_injects_number_and_energy():
+    """The condensate injects 2 Gamma nu particles per unit time at energy
+    E0 = sqrt(p0^2 + m^2) each (number and energy injection rates
+    C_0 = 2 Gamma n, C_E = 2 E0 Gamma n of Sec. 3): the deposit on the grid
+    must carry exactly both moments, at any p0 inside the grid."""
+    p = inputs.log_grid(40, 1e-3, 20.0)
+    op = oracle.Operator(p)
+    h, E = op.grid.h, op.grid.E
+    Hi, N0, Gam, u = 1.0, 0.7, 0.4, 0.3
+    nu = np.exp(-3 * u) * N0 * np.exp(-(Gam / (2 * Hi)) * (np.exp(2 * u) - 1))
+    for p0 in (2e-3, 0.05, 0.8, float(p[17]), 7.3, 19.9):
+        S = op.sources(u, Hi, N0=N0, Gamma=Gam, p0=p0)
+        assert np.count_nonzero(S) <= 2 and np.all(S >= 0)
+        E0 = np.sqrt(p0 * p0 + 1.0)
+        assert abs(np.sum(h * S) / (2 * Gam * nu) - 1) < 1e-13
+        assert abs(np.sum(h * E * S) / (2 * Gam * nu * E0) - 1) < 1e-13
+        j = int(np.flatnonzero(S)[0])
+        assert p[j] <= p0 * (1 + 1e-12) and (np.count_nonzero(S) == 1 or p0 <= p[j + 1])
+    assert op.deposit(30.0)[0] == -1 and op.deposit(1e-4)[0] == -1
+
+
+def test_condensate_decay_law():
+    """a^3 n_Phi from the closed form against a numerical solution of the
+    decay law dn/dt + 3 H n = -Gamma n written in u = ln a,
+    d(a^3 n)/du = -(Gamma / H(u)) a^3 n, H = H_i e^{-2u}."""
+    from scipy.integrate import solve_ivp
+    Hi, N0 = 2.0, 1.3
+    for Gam in (0.05, 1.0, 6.0):
+        sol = solve_ivp(lambda u, y: -(Gam / (Hi * np.exp(-2 * u))) * y, (0.0, 1.5), [N0],
+                        rtol=1e-12, atol=1e-300, dense_output=True, method="DOP853")
+        for u in (0.1, 0.5, 1.0, 1.5):
+            ref = float(sol.sol(u)[0])
+            got = oracle.condensate_a3nu(N0, Gam, Hi, u)
+            assert abs(got - ref) <= 1e-9 * N0, (Gam, u, got, ref)
+
+
+def test_higgs_source_rate_closed_form():
+    """The number injection of eq. C_higgs_decay, int p^2 C_h dp, has the
+    closed form kappa T sqrt(m_h^2 - 4 m^2) K1(m_h / T) (the thermal average
+    of a decay in a Maxwell-Boltzmann bath); the discrete sum_i h_i S_i
+    matches it to rounding on a grid that covers the source's support (the
+    trapezoid rule in ln p of a smooth integrand that vanishes at both ends
+    converges faster than any power of the spacing)."""
+    from scipy.special import k1
+    kappa, mh = 0.37, 5.0
+    for T in (0.8, 2.0):
+        ref = kappa * T * np.sqrt(mh * mh - 4.0) * k1(mh / T)
+        for n in (100, 400):
+            g = oracle.Grid(inputs.log_grid(n, 1e-6, 200.0))
+            # Ti such that T(u) = Ti e^{-u} equals T at u = 0.3
+            S = oracle.sources(g, 0.3, 1.0, kappa=kappa, mh=mh, Ti=T * np.exp(0.3))
+            assert np.all(S >= 0)
+            assert abs(np.sum(g.h * S) / ref - 1.0) < 1e-12, (T, n)
+
+
+def test_gamma22_is_n_sigma_vrel_nonrelativistic():
+    """Gamma_22 = n <sigma v> (Sec. 4.2): for a non-relativistic
+    Maxwell-Boltzmann f the mean relative speed is sqrt(16 T / (pi m)) and
+    sigma = |M|^2 / (64 pi m^2), n = int d^3p/(2 pi)^3 f; the rate prefactor
+    lambda multiplies it; f -> c f scales it by c."""
+    T, m = 0.004, 1.0
+    p = inputs.log_grid(97, 1e-4, 1.0)
+    f = np.exp(-(np.sqrt(p * p + m * m) - m) / T)
+    op = oracle.Operator(p, quad=oracle.EXACT, m2=1.0, mass=m)
+    n_ref, _ = integrate.quad(lambda q: 4 * np.pi * q * q * np.exp(-(np.sqrt(q * q + 1) - 1) / T)
+                              / (2 * np.pi) ** 3, 0, 1.0, epsabs=0, epsrel=1e-12, limit=200)
+    ref = n_ref * np.sqrt(16 * T / (np.pi * m)) / (64 * np.pi)
+    assert abs(op.gamma22(f) / ref - 1.0) < 1.5e-2
+    assert abs(op.gamma22(f, lam=3.0) / op.gamma22(f) - 3.0) < 1e-13
+    assert abs(op.gamma22(2.5 * f) / op.gamma22(f) - 2.5) < 1e-13
+    assert op.gamma22(np.zeros_like(f)) == 0.0
+
+
+def _freeze_in_setup(n=40):
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    return p, oracle.Operator(p)
+
+
+def test_freeze_in_source_only_conserves_total_number():
+    """Source-only regime: the comoving number of chi, the number drifted out
+    below p_min and twice the condensate's a^3 n_Phi add up to a constant
+    (each decay gives two chi); fixed-step RK4 keeps it to fourth order."""
+    p, op = _freeze_in_setup()
+    V = op.grid.dp / p
+    Hi, N0, Gam, p0 = 1.0, 1.0, 0.6, 0.8
+    x0 = inputs.bump_pair(p, 0.5, 2.0, 1e-3, 5e-4, 0.3, 0.3) * p ** 3
+    inv0 = np.sum(V * x0) + 2 * N0
+    errs = []
+    for du in (0.04, 0.02, 0.01):
+        r = op.freeze_in(x0, 0.0, Hi, 1.2, du, N0=N0, Gamma=Gam, p0=p0)
+        assert r["n_src"] == int(round(1.2 / du)) and len(r["u"]) == 0
+        inv = np.sum(V * r["x"]) + r["outflow"] + 2 * oracle.condensate_a3nu(N0, Gam, Hi, 1.2)
+        errs.append(abs(inv - inv0) / inv0)
+    assert errs[-1] < 1e-9, errs
+    assert 10.0 < errs[0] / errs[1] < 24.0 and 10.0 < errs[1] / errs[2] < 24.0, errs
+
+
+def test_freeze_in_switch_fires_at_threshold():
+    """The elastic operator is switched on at the first step whose state has
+    Gamma_22 / H > eps_switch, and not before."""
+    p, op = _freeze_in_setup()
+    Hi, N0, Gam, p0, du, eps = 1.0, 2.0, 0.5, 0.8, 0.02, 1e-2
+    x0 = np.zeros(len(p))
+    lam = 150.0
+    r = op.freeze_in(x0, lam, Hi, 1.5, du, eps_switch=eps, N0=N0, Gamma=Gam, p0=p0,
+                     max_steps=20000)
+    k = r["n_src"]
+    assert 5 < k < 70 and abs(r["u_switch"] - k * du) < 1e-12 and len(r["u"]) > 0
+
+    def state(steps):
+        s = op.freeze_in(x0, lam, Hi, 1.5, du, eps_switch=eps, N0=N0, Gamma=Gam, p0=p0,
+                         max_steps=steps)
+        assert s["n_src"] == steps and len(s["u"]) == 0
+        u = steps * du
+        return op.gamma22(s["x"] / (np.exp(3 * u) * p ** 3), lam) / (Hi * np.exp(-2 * u))
+
+    assert state(k) > eps >= state(k - 1)
+
+
+def test_freeze_in_regime_two_is_the_heun_of_the_expanding_run():
+    """With the switch at the start and no sources, the second regime is the
+    adaptive Heun of the expanding-universe equation, step for step."""
+    p, op = _freeze_in_setup()
+    f0 = inputs.bump_pair(p, 0.2, 2.0, 1.0, 1.0, 0.3, 0.3)
+    x0 = f0 * p ** 3
+    Hi = op.gamma0(f0)
+    a = op.heun(x0, 3.0, Hi, 0.1, 1e-3, expansion=True, max_steps=4000)
+    b = op.freeze_in(x0, 3.0, Hi, 0.1, 0.01, eps_switch=-1.0, dt0=1e-3, max_steps=4000)
+    assert b["n_src"] == 0 and b["u_switch"] == 0.0
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["dt"], b["dt"])
+
+
+def test_freeze_in_with_collisions_conserves_total_number():
+    """Both regimes with the condensate source: comoving chi number +
+    outflow + 2 a^3 n_Phi stays constant to the integrators' tolerance
+    (the projected elastic operator conserves number)."""
+    p, op = _freeze_in_setup()
+    V = op.grid.dp / p
+    Hi, N0, Gam, p0 = 1.0, 2.0, 0.5, 0.8
+    x0 = np.zeros(len(p))
+    r = op.freeze_in(x0, 150.0, Hi, 1.0, 0.02, N0=N0, Gamma=Gam, p0=p0, max_steps=20000)
+    assert r["n_src"] > 0 and len(r["u"]) > 0 and abs(r["u"][-1] + r["dt"][-1] - 1.0) < 1e-12
+    inv = np.sum(V * r["x"]) + r["outflow"] + 2 * oracle.condensate_a3nu(N0, Gam, Hi, 1.0)
+    assert abs(inv - 2 * N0) < 1e-7 * 2 * N0, inv - 2 * N0
