@@ -259,6 +259,12 @@ typedef struct {
     double safety;      /* dt *= clamp(safety err^-1/2, fac_min, fac_max)       */
     double fac_min, fac_max;
     double dt_min;      /* Heun: a slot whose dt falls below this fails         */
+    int32_t freeze_in;  /* 1: the slots may carry freeze-in sources and start in
+                           the source-only regime (kxg_solve_params src_*,
+                           du_src, eps_switch; Heun with KXG_EXP_RADIATION only).
+                           Every operator call then also forms the FP64 loss
+                           rates R f that the regime switch tests.             */
+    int32_t pad_;
 } kxg_stepper_params;
 
 typedef struct {
@@ -268,7 +274,34 @@ typedef struct {
     double dt;          /* RK4: step in t; Heun: first step (u or t);
                            <= 0 selects 0.1 / (lambda * rate0) for RK4, 1e-3 Heun */
     double t_end;       /* end of t (RK4) or u (Heun)                            */
-    int32_t max_steps;  /* accepted-step cap (<= 0: none)                        */
+    int32_t max_steps;  /* accepted-step cap (<= 0: none), both regimes together */
+    int32_t pad_;
+    /* Freeze-in sources of Sec. 3 (steppers with freeze_in = 1; all zero for
+     * none), in the code's units: densities as nu = (2 pi^2 / g) n, so that
+     * sum_i h_i f_i is the chi density; time in units of 1/h_i (H = h_i e^{-2u},
+     * so h_i must be given, > 0).  Condensate (eq. C_condensate_decay):
+     * 2 Gamma nu_Phi particles per unit time at momentum p0, shared between
+     * the two grid points that bracket p0 in kinetic energy with the
+     * energy-linear weights of eq. app_interp_weights (number and energy
+     * injected exactly), a^3 nu_Phi = src_n0 exp(-(Gamma / 2 h_i)(e^{2u} - 1)).
+     * Higgs decay (eq. C_higgs_decay): kappa (T / E p)(e^{-E_-/T} - e^{-E_+/T}),
+     * E_+- = (m_h^2 E +- m_h p sqrt(m_h^2 - 4 m^2)) / (2 m^2), T = T_i e^{-u}. */
+    double src_n0;      /* a^3 nu_Phi at u = 0 (0: no condensate)                */
+    double src_gamma;   /* condensate decay rate Gamma_Phi                       */
+    double src_p0;      /* momentum of the decay products (inside the grid)      */
+    double src_kappa;   /* Higgs-decay amplitude kappa (0: no Higgs source)      */
+    double src_mh;      /* Higgs mass / particle mass (> 2)                      */
+    double src_ti;      /* bath temperature at u = 0 / particle mass (> 0)       */
+    /* Regimes of Sec. 4.2: du_src > 0 starts the slot in the source-only
+     * regime (elastic operator off, one classical RK4 step of size du_src in u
+     * per iteration); before each such step the slot tests
+     * Gamma_22 / H > eps_switch, with Gamma_22 = lambda sum h f (R f) / sum h f
+     * the mean per-particle loss rate of the current f, and from the first
+     * state over it on runs the adaptive Heun with the elastic operator and
+     * the sources (first step dt, atol = atol_rel max |x| at the switch).
+     * du_src <= 0: the elastic operator is on from the start. */
+    double du_src;
+    double eps_switch;  /* the paper uses 1e-2                                   */
 } kxg_solve_params;
 
 typedef struct {
@@ -281,6 +314,9 @@ typedef struct {
     int32_t status;     /* 0 running, 1 reached t_end, 2 stopped at max_steps
                            before t_end, -1 non-finite, -2 dt underflow (Heun:
                            the next step would be below dt_min), -3 free slot */
+    int32_t phase;      /* 0 source-only regime, 1 elastic operator on          */
+    double u_switch;    /* u at the switch (0 if it started with collisions on) */
+    int32_t n_src;      /* steps taken in the source-only regime (in steps too) */
     int32_t pad;
 } kxg_slot_state;
 

@@ -742,6 +742,10 @@ kxg_status kxg_stepper_create(const kxg_kernel *k, const kxg_stepper_params *prm
     if (prm->expansion != KXG_EXP_NONE && prm->expansion != KXG_EXP_RADIATION) { set_error("kxg_stepper_create: bad expansion"); return KXG_EINVAL; }
     if (prm->expansion == KXG_EXP_RADIATION && prm->kind != KXG_HEUN) { set_error("kxg_stepper_create: expansion needs the Heun stepper"); return KXG_EINVAL; }
     if (prm->b_cap < 1 || prm->b_cap > (1 << 20)) { set_error("kxg_stepper_create: bad b_cap"); return KXG_EINVAL; }
+    if (prm->freeze_in != 0 && (prm->kind != KXG_HEUN || prm->expansion != KXG_EXP_RADIATION)) {
+        set_error("kxg_stepper_create: freeze-in sources need the Heun stepper with expansion");
+        return KXG_EINVAL;
+    }
     if (prm->kind == KXG_HEUN && prm->adapt &&
         !(prm->rtol > 0 && prm->safety > 0 && prm->fac_min > 0 && prm->fac_max >= prm->fac_min)) {
         set_error("kxg_stepper_create: bad Heun controller parameters");
@@ -825,7 +829,35 @@ static bool solve_params_ok(const kxg_solve_params *sp)
            sp->t_end > 0.0 && std::isfinite(sp->dt) && std::isfinite(sp->h_i);
 }
 
-static SlotDev slot_record(const kxg_solve_params *sp)
+static bool has_freeze_in(const kxg_solve_params *sp)
+{
+    return sp->src_n0 != 0.0 || sp->src_kappa != 0.0 || sp->du_src > 0.0;
+}
+
+// Freeze-in fields of a solve (Sec. 3, Sec. 4.2); "" if they are valid for
+// this stepper, else what is wrong.
+static const char *freeze_in_error(const kxg_stepper *s, const kxg_solve_params *sp)
+{
+    if (!has_freeze_in(sp)) return "";
+    if (!s->prm.freeze_in) return "freeze-in fields on a stepper created without freeze_in";
+    const double fin[] = {sp->src_n0, sp->src_gamma, sp->src_p0, sp->src_kappa, sp->src_mh,
+                          sp->src_ti, sp->du_src, sp->eps_switch};
+    for (double v : fin)
+        if (!std::isfinite(v)) return "non-finite freeze-in field";
+    if (!(sp->h_i > 0.0)) return "a freeze-in solve needs h_i > 0 (H at u = 0)";
+    if (sp->src_n0 < 0.0 || sp->src_gamma < 0.0 || sp->src_kappa < 0.0) return "negative source";
+    if (sp->src_n0 > 0.0) {
+        const kxg_kernel &k = *s->k;
+        const double m = k.mass, K0 = sp->src_p0 * sp->src_p0 / (std::sqrt(sp->src_p0 * sp->src_p0 + m * m) + m);
+        if (!(sp->src_p0 > 0.0) || !(K0 >= k.K[0] && K0 <= k.K[k.n - 1]))
+            return "condensate momentum src_p0 outside the grid";
+    }
+    if (sp->src_kappa > 0.0 && !(sp->src_mh > 2.0 * s->k->mass && sp->src_ti > 0.0))
+        return "Higgs source needs src_mh > 2 m and src_ti > 0";
+    return "";
+}
+
+static SlotDev slot_record(const kxg_stepper *s, const kxg_solve_params *sp)
 {
     SlotDev init;
     std::memset(&init, 0, sizeof init);
@@ -836,6 +868,34 @@ static SlotDev slot_record(const kxg_solve_params *sp)
     init.tend = sp->t_end;
     init.maxsteps = sp->max_steps;
     init.status = 0;
+    init.phase = 1;
+    init.jdep = -1;
+    if (s->prm.freeze_in && has_freeze_in(sp)) {
+        const kxg_kernel &k = *s->k;
+        const double m = k.mass;
+        init.src_n0 = sp->src_n0;
+        init.src_gamma = sp->src_gamma;
+        init.src_kappa = sp->src_kappa;
+        init.src_mh = sp->src_mh;
+        init.src_kh = sp->src_kappa > 0.0 ? std::sqrt(sp->src_mh * sp->src_mh - 4.0 * m * m) : 0.0;
+        init.src_ti = sp->src_ti;
+        init.du_src = sp->du_src;
+        init.eps_switch = sp->eps_switch;
+        init.phase = sp->du_src > 0.0 ? 0 : 1;
+        if (sp->src_n0 > 0.0) {
+            // the two grid points that bracket p0 in kinetic energy, with the
+            // energy-linear weights (App. B eq. app_interp_weights), over h
+            const double p0 = sp->src_p0;
+            const double K0 = p0 * p0 / (std::sqrt(p0 * p0 + m * m) + m);
+            int j = 0;
+            for (int q = 0; q < k.n - 1; ++q)
+                if (k.K[q] <= K0) j = q;
+            const double wr = (K0 - k.K[j]) / (k.K[j + 1] - k.K[j]);
+            init.jdep = j;
+            init.wl_h = (1.0 - wr) / k.h[j];
+            init.wr_h = wr / k.h[j + 1];
+        }
+    }
     return init;
 }
 
@@ -849,8 +909,10 @@ kxg_status kxg_stepper_set(kxg_stepper *s, int32_t slot, const double *f0_dev,
         set_error("kxg_stepper_set: lambda >= 0, finite dt/h_i and t_end > 0 required");
         return KXG_EINVAL;
     }
+    const char *fe = freeze_in_error(s, sp);
+    if (*fe) { set_error("kxg_stepper_set: %s", fe); return KXG_EINVAL; }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const SlotDev init = slot_record(sp);
+    const SlotDev init = slot_record(s, sp);
     KXG_TRY_HIP(launch_slot_init(slot, init, s->d_slots, st));
     KXG_TRY_HIP(launch_slot_set(s->k->n, s->prm.kind, s->prm.expansion, s->prm.atol_rel, slot,
                                 s->d_slots, f0_dev, s->k->d_p, s->k->d_RT, s->d_x, s->d_fb, st));
@@ -869,15 +931,18 @@ kxg_status kxg_stepper_set_many(kxg_stepper *s, int32_t slot0, int32_t count,
         set_error("kxg_stepper_set_many: slots [%d, %d) outside [0, %d)", slot0, slot0 + count, s->prm.b_cap);
         return KXG_EINVAL;
     }
-    for (int j = 0; j < count; ++j)
+    for (int j = 0; j < count; ++j) {
         if (!solve_params_ok(&sp_host[j])) {
             set_error("kxg_stepper_set_many: solve %d: lambda >= 0, finite dt/h_i and t_end > 0 required", j);
             return KXG_EINVAL;
         }
+        const char *fe = freeze_in_error(s, &sp_host[j]);
+        if (*fe) { set_error("kxg_stepper_set_many: solve %d: %s", j, fe); return KXG_EINVAL; }
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     // the staging buffer is reused: wait until the previous copy out of it is done
     KXG_TRY_HIP(hipEventSynchronize(s->init_evt));
-    for (int j = 0; j < count; ++j) s->h_init[j] = slot_record(&sp_host[j]);
+    for (int j = 0; j < count; ++j) s->h_init[j] = slot_record(s, &sp_host[j]);
     KXG_TRY_HIP(hipMemcpyAsync(s->d_init, s->h_init, (size_t)count * sizeof(SlotDev), hipMemcpyHostToDevice, st));
     KXG_TRY_HIP(hipEventRecord(s->init_evt, st));
     KXG_TRY_HIP(launch_slot_set_many(s->k->n, s->prm.kind, s->prm.expansion, s->prm.atol_rel, slot0, count,
@@ -930,6 +995,9 @@ static kxg_status enqueue_iteration(kxg_stepper *s, int B, hipStream_t st)
     a.fac_lo = P.fac_min;
     a.fac_hi = P.fac_max;
     a.dt_min = P.dt_min;
+    a.freeze_in = P.freeze_in;
+    a.atol_rel = P.atol_rel;
+    a.mass = k.mass;
     // every operator call of the iteration takes its GEMM operand from the
     // epilogue of the call before (the first from kxg_stepper_advance)
     a.write_op = 1;
@@ -1051,6 +1119,9 @@ kxg_status kxg_stepper_query(kxg_stepper *s, kxg_slot_state *out, void *stream)
         out[b].steps = h[b].steps;
         out[b].rejected = h[b].rejected;
         out[b].status = s->used[b] ? h[b].status : -3;
+        out[b].phase = h[b].phase;
+        out[b].u_switch = h[b].u_switch;
+        out[b].n_src = h[b].nsrc;
         out[b].pad = 0;
     }
     return KXG_OK;

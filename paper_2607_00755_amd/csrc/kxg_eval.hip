@@ -670,7 +670,7 @@ template <int PER>
 struct StepIn {
     double x[PER], acc[PER], xs[PER], nx[PER];
     double lam, hi, dt, t;      // the slot's control values (stepper modes only)
-    int status;
+    int status, phase;
 };
 
 template <int PER, int TPB>
@@ -684,6 +684,7 @@ __device__ void load_step_inputs(const StepArgs &A, int b, int n, StepIn<PER> &i
         in.dt = S.dt;
         in.t = S.t;
         in.status = S.status;
+        in.phase = S.phase;
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -705,9 +706,17 @@ __device__ void load_step_inputs(const StepArgs &A, int b, int n, StepIn<PER> &i
     }
 }
 
+// Grid quantities and operator input of one distribution as the epilogue
+// holds them (element i = t + TPB q), and its loss rates R f (or null).
+template <int PER>
+struct EpiRow {
+    const double (&h)[PER], (&e)[PER], (&f)[PER];
+    const double *rate;
+};
+
 template <int PER, int TPB>
 __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)[PER],
-                            const StepIn<PER> &in, double *lds);
+                            const StepIn<PER> &in, double *lds, const EpiRow<PER> &row);
 
 // FP64 epilogue, TPB threads per distribution (a wave, or the whole 256-thread
 // workgroup), PER grid points per thread (element i = t + TPB q), App. C:
@@ -932,7 +941,8 @@ __global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
         }
     }
     if (step.mode != kStepNone) {
-        step_update<PER, TPB>(step, b, n, out, in, red);
+        const EpiRow<PER> er{hv, ev, fv, rate ? rate + (long)b * n : nullptr};
+        step_update<PER, TPB>(step, b, n, out, in, red, er);
         return;
     }
 #pragma unroll
@@ -995,6 +1005,91 @@ __device__ void write_operand(const StepArgs &A, int b, int n, const double (&nf
     }
 }
 
+// Values at element i + 1 of a distribution held as element i = t + TPB q
+// (0 beyond n): from the next lane within a wave (lane 0 of the next q for
+// the last lane), through LDS across the four waves of a workgroup.
+template <int PER, int TPB>
+__device__ void next_elems(const double (&v)[PER], double (&nx)[PER], int n)
+{
+    if constexpr (TPB == 64) {
+        const int lane = (int)threadIdx.x & 63;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const double a = __shfl(v[q], (lane + 1) & 63);
+            const double c = __shfl(v[q + 1 < PER ? q + 1 : q], 0);
+            nx[q] = lane < 63 ? a : (q + 1 < PER ? c : 0.0);
+            if (lane + 64 * q + 1 >= n) nx[q] = 0.0;
+        }
+    } else {
+        __shared__ double xch[PER * TPB];
+        __syncthreads();                       // earlier readers of xch are done
+#pragma unroll
+        for (int q = 0; q < PER; ++q) xch[threadIdx.x + TPB * q] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = threadIdx.x + TPB * q;
+            nx[q] = i + 1 < n ? xch[i + 1] : 0.0;
+        }
+    }
+}
+
+// One classical RK4 step of size du in u of the source-only regime of a
+// freeze-in slot (Sec. 4.2: elastic operator off, drift and sources only),
+// x -> xn; returns (on every thread) the step's outflow through p_min with
+// the RK4 weights of the stage states' g_0, and a non-finite flag.
+template <int PER, int TPB>
+__device__ void source_rk4(const StepArgs &A, const SlotDev &S, int n, const StepIn<PER> &in,
+                           const EpiRow<PER> &row, double u, double du, double (&xn)[PER],
+                           double (&flow_bad)[2], double *lds)
+{
+    double y[PER], nx[PER], acc[PER];
+    double o = 0.0;
+    auto rhs = [&](const double (&st)[PER], const double (&nxt)[PER], double uu, int q) {
+        const int i = epi_tl<TPB>() + TPB * q;
+        const double src = freeze_in_source(S, i, A.p[i], row.e[q], A.mass, uu);
+        return rhs_u(1, st[q], nxt[q], 0.0, A.p[i], A.dp[i], in.lam, in.hi, uu, src);
+    };
+    // stage 1 from the state and its stored neighbours
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        y[q] = in.x[q];
+        nx[q] = in.nx[q];
+    }
+    o = y[0];
+    const double cst[3] = {0.5, 0.5, 1.0}, wst[3] = {2.0, 2.0, 1.0};
+    double k[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = epi_tl<TPB>() + TPB * q;
+        k[q] = i < n ? rhs(y, nx, u, q) : 0.0;
+        acc[q] = k[q];
+    }
+    for (int st = 0; st < 3; ++st) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) y[q] = in.x[q] + cst[st] * du * k[q];
+        next_elems<PER, TPB>(y, nx, n);
+        o += wst[st] * y[0];
+        const double us = u + cst[st] * du;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = epi_tl<TPB>() + TPB * q;
+            k[q] = i < n ? rhs(y, nx, us, q) : 0.0;
+            acc[q] += wst[st] * k[q];
+        }
+    }
+    double bad[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = epi_tl<TPB>() + TPB * q;
+        xn[q] = i < n ? in.x[q] + du / 6.0 * acc[q] : 0.0;
+        if (i < n && !isfinite(xn[q])) bad[0] = 1.0;
+    }
+    grp_max<1, TPB>(bad, lds);
+    flow_bad[0] = du / 6.0 * o;                // meaningful on the thread holding i = 0
+    flow_bad[1] = bad[0];
+}
+
 // Stepper update of slot b from the operator output `out` (element
 // i = thread + 256 q), Sec. 4.2: RK4 stage, or Heun predictor
 // x* = x + dt k1, or Heun corrector x_new = x + dt (k1 + k2)/2 with the
@@ -1005,12 +1100,13 @@ __device__ void write_operand(const StepArgs &A, int b, int n, const double (&nf
 // writes the slot record.
 template <int PER, int TPB>
 __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)[PER],
-                            const StepIn<PER> &in, double *lds)
+                            const StepIn<PER> &in, double *lds, const EpiRow<PER> &er)
 {
     SlotDev &S = A.sl[b];
     const int running = in.status == 0;
     const long row = (long)b * n;
-    const double dt = in.dt, u = in.t;
+    const double u = in.t;
+    double dt = in.dt;
     double nf[PER];                            // the next operator input
     if (A.mode == kStepRK4) {
         const double lam = in.lam / in.hi;
@@ -1051,6 +1147,63 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
         return;
     }
     if (A.mode == kStepHeunPred) {
+        if (A.freeze_in && running && in.phase == 0) {
+            // Source-only regime: test Gamma_22 / H of the current state
+            // (Gamma_22 = lambda sum h f (R f) / sum h f); over eps_switch the
+            // elastic operator comes on and this attempt is the first Heun
+            // predictor, otherwise one RK4 step of drift and sources.
+            double r2[2] = {0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int i = epi_tl<TPB>() + TPB * q;
+                if (i >= n) continue;
+                r2[0] += er.h[q] * er.f[q] * er.rate[i];
+                r2[1] += er.h[q] * er.f[q];
+            }
+            grp_sum<2, TPB>(r2, lds);
+            const double g22 = r2[1] > 0.0 ? in.lam * r2[0] / r2[1] : 0.0;
+            if (g22 / (in.hi * exp(-2.0 * u)) > S.eps_switch) {
+                double mx[1] = {0.0};
+#pragma unroll
+                for (int q = 0; q < PER; ++q)
+                    if (epi_tl<TPB>() + TPB * q < n) mx[0] = fmax(mx[0], fabs(in.x[q]));
+                grp_max<1, TPB>(mx, lds);
+                if (A.adapt && u + dt > S.tend) dt = S.tend - u;
+                if (epi_tl<TPB>() == 0) {
+                    const double at = A.atol_rel * mx[0];
+                    S.phase = 1;
+                    S.u_switch = u;
+                    S.atol = at > 0.0 ? at : 1e-300;
+                    S.dt = dt;
+                }
+            } else {
+                const double du = u + S.du_src > S.tend ? S.tend - u : S.du_src;
+                double xn[PER], fb2[2];
+                source_rk4<PER, TPB>(A, S, n, in, er, u, du, xn, fb2, lds);
+                const double un = u + du;
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int i = epi_tl<TPB>() + TPB * q;
+                    nf[q] = 0.0;
+                    if (i >= n) continue;
+                    A.x[row + i] = xn[q];
+                    A.xs[row + i] = xn[q];
+                    nf[q] = g_to_f(xn[q], A.p[i], un);
+                    A.fb[row + i] = nf[q];
+                }
+                if (A.write_op) write_operand<PER, TPB>(A, b, n, nf, lds);
+                if (epi_tl<TPB>() == 0) {
+                    S.t = un;
+                    S.steps += 1;
+                    S.nsrc += 1;
+                    S.outflow += fb2[0];
+                    if (fb2[1] > 0.0) S.status = -1;
+                    else if (un >= S.tend * (1.0 - 1e-14)) S.status = 1;
+                    else if (S.maxsteps > 0 && S.steps >= S.maxsteps) S.status = 2;
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int i = epi_tl<TPB>() + TPB * q;
@@ -1063,7 +1216,8 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
                 nf[q] = A.expansion ? g_to_f(xv, A.p[i], u) : xv;
                 continue;
             }
-            const double k = rhs_u(A.expansion, xv, in.nx[q], out[q], A.p[i], A.dp[i], in.lam, in.hi, u);
+            const double src = A.freeze_in ? freeze_in_source(S, i, A.p[i], er.e[q], A.mass, u) : 0.0;
+            const double k = rhs_u(A.expansion, xv, in.nx[q], out[q], A.p[i], A.dp[i], in.lam, in.hi, u, src);
             A.acc[row + i] = k;
             const double v = xv + dt * k;
             A.xs[row + i] = v;
@@ -1073,16 +1227,19 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
         if (A.write_op) write_operand<PER, TPB>(A, b, n, nf, lds);
         return;
     }
-    // Heun corrector and control
+    // Heun corrector and control (a freeze-in slot still in the source-only
+    // regime took its step in the predictor's epilogue and is left alone)
+    const int heun = running && !(A.freeze_in && in.phase == 0);
     double xn[PER];
     double ev[2] = {0.0, 0.0};              // err, non-finite flag
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int i = epi_tl<TPB>() + TPB * q;
         xn[q] = 0.0;
-        if (i >= n || !running) continue;
+        if (i >= n || !heun) continue;
         const double xsv = in.xs[q];
-        const double k2 = rhs_u(A.expansion, xsv, in.nx[q], out[q], A.p[i], A.dp[i], in.lam, in.hi, u + dt);
+        const double src = A.freeze_in ? freeze_in_source(S, i, A.p[i], er.e[q], A.mass, u + dt) : 0.0;
+        const double k2 = rhs_u(A.expansion, xsv, in.nx[q], out[q], A.p[i], A.dp[i], in.lam, in.hi, u + dt, src);
         const double x0 = in.x[q];
         const double v = x0 + 0.5 * dt * (in.acc[q] + k2);
         xn[q] = v;
@@ -1095,7 +1252,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
     const double err = ev[0], nonfin = ev[1];
     int accept = 0, status = S.status, steps = S.steps, rej = S.rejected;
     double tnew = u, dtnew = dt, outflow = S.outflow;
-    if (running) {
+    if (heun) {
         if (nonfin > 0.0) {
             status = -1;
         } else {
@@ -1137,7 +1294,7 @@ __device__ void step_update(const StepArgs &A, int b, int n, const double (&out)
         A.fb[row + i] = nf[q];
     }
     if (A.write_op) write_operand<PER, TPB>(A, b, n, nf, lds);
-    if (epi_tl<TPB>() == 0 && running) {
+    if (epi_tl<TPB>() == 0 && heun) {
         S.t = tnew;
         S.dt = dtnew;
         S.steps = steps;
@@ -1398,6 +1555,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     }
     const Path P = path_of(k, prec, B);
     const int project = (flags & KXG_PROJECT) ? 1 : 0;
+    const bool want_rate = diag != nullptr || (step_in && step_in->freeze_in);
     if (P.stream) {
         const int ns = stream_splits(n);
         const long n2 = (long)n * n;
@@ -1428,10 +1586,11 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
 #undef KXG_ST
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
-        // the split-0 partials carry the loss term; loss rates only for diagnostics
-        if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
+        // the split-0 partials carry the loss term; loss rates only for
+        // diagnostics and the regime switch of freeze-in steppers
+        if (want_rate) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
         KXG_TRY_HIP(launch_epilogue<double>(part, nsplit, SlotCounts{}, (long)B * n, n, nullptr, nullptr,
-                                            diag ? rate : nullptr, f, k, B, project, C, diag, step, s,
+                                            want_rate ? rate : nullptr, f, k, B, project, C, diag, step, s,
                                             nullptr, 0.0, 1));
         return KXG_OK;
     }
@@ -1462,11 +1621,12 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
 #undef KXG_X3
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
-        // the loss term is folded into the operand; loss rates only for diagnostics
-        if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
+        // the loss term is folded into the operand; loss rates only for
+        // diagnostics and the regime switch
+        if (want_rate) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
         KXG_TRY_HIP(launch_epilogue<float>(part, k.maxslots16, k.nslot16, (long)bpad * g.ipad, g.ipad,
                                            f16 ? ws.fscale : nullptr, f16 ? k.d_hrow : nullptr,
-                                           diag ? rate : nullptr, f, k, B, project, C, diag, step, s,
+                                           want_rate ? rate : nullptr, f, k, B, project, C, diag, step, s,
                                            nullptr, 0.0, 1));
         return KXG_OK;
     }
@@ -1484,10 +1644,11 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
                                 g.ipad, nbt, part, s));
     profile_mark_end(s);
     KXG_TRY_HIP(hipGetLastError());
-    // the loss term is folded into the operand; loss rates only for diagnostics
-    if (diag) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
+    // the loss term is folded into the operand; loss rates only for
+    // diagnostics and the regime switch
+    if (want_rate) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
     KXG_TRY_HIP(launch_epilogue<float>(part, k.maxslots, k.nslot, (long)bpad * g.ipad, g.ipad,
-                                       nullptr, nullptr, diag ? rate : nullptr, f, k, B, project, C,
+                                       nullptr, nullptr, want_rate ? rate : nullptr, f, k, B, project, C,
                                        diag, step, s, nullptr, 0.0, 1));
     return KXG_OK;
 }

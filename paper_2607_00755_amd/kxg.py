@@ -72,20 +72,32 @@ class StepperParams(ctypes.Structure):
                 ("adapt", ctypes.c_int32), ("b_cap", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("atol_rel", ctypes.c_double),
                 ("safety", ctypes.c_double), ("fac_min", ctypes.c_double),
-                ("fac_max", ctypes.c_double), ("dt_min", ctypes.c_double)]
+                ("fac_max", ctypes.c_double), ("dt_min", ctypes.c_double),
+                ("freeze_in", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class SolveParams(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("h_i", ctypes.c_double),
                 ("dt", ctypes.c_double), ("t_end", ctypes.c_double),
-                ("max_steps", ctypes.c_int32)]
+                ("max_steps", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("src_n0", ctypes.c_double), ("src_gamma", ctypes.c_double),
+                ("src_p0", ctypes.c_double), ("src_kappa", ctypes.c_double),
+                ("src_mh", ctypes.c_double), ("src_ti", ctypes.c_double),
+                ("du_src", ctypes.c_double), ("eps_switch", ctypes.c_double)]
+
+
+# keyword names of the freeze-in fields of SolveParams (Stepper.set / set_many)
+SOURCE_KEYS = ("src_n0", "src_gamma", "src_p0", "src_kappa", "src_mh", "src_ti", "du_src",
+               "eps_switch")
 
 
 class SlotState(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double),
                 ("outflow", ctypes.c_double), ("h_i", ctypes.c_double),
                 ("steps", ctypes.c_int32), ("rejected", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("phase", ctypes.c_int32),
+                ("u_switch", ctypes.c_double), ("n_src", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -318,13 +330,24 @@ def _cuda_ready() -> bool:
         return False
 
 
+def _solve_params(lam, h_i, dt, t_end, max_steps, sources) -> SolveParams:
+    bad = set(sources) - set(SOURCE_KEYS)
+    if bad:
+        raise TypeError("unknown solve parameters: %s" % sorted(bad))
+    sp = SolveParams(float(lam), float(h_i), float(dt), float(t_end), int(max_steps), 0)
+    for k, v in sources.items():
+        setattr(sp, k, float(v))
+    return sp
+
+
 class Stepper:
     """kxg_stepper_*: on-device RK4 / adaptive Heun over many slots."""
 
     def __init__(self, kernel: Kernel, kind: int = RK4, prec: int = F64, b_cap: int = 1,
                  expansion: int = EXP_NONE, project: bool = True, adapt: bool = True,
                  rtol: float = 1e-6, atol_rel: float = 1e-12, safety: float = 0.9,
-                 fac_min: float = 0.2, fac_max: float = 5.0, dt_min: float = 1e-14):
+                 fac_min: float = 0.2, fac_max: float = 5.0, dt_min: float = 1e-14,
+                 freeze_in: bool = False):
         self._h = None
         self.kernel = kernel
         self.n = kernel.n
@@ -332,7 +355,7 @@ class Stepper:
         self.expansion = int(expansion)
         prm = StepperParams(int(kind), int(prec), int(expansion), int(bool(project)),
                             int(bool(adapt)), self.b_cap, rtol, atol_rel, safety, fac_min,
-                            fac_max, dt_min)
+                            fac_max, dt_min, int(bool(freeze_in)), 0)
         h = _vp()
         _check(lib().kxg_stepper_create(kernel.handle, ctypes.byref(prm), ctypes.byref(h)))
         self._h = h
@@ -343,23 +366,27 @@ class Stepper:
             self._h = None
 
     def set(self, slot: int, f0, lam: float, t_end: float, dt: float = 0.0, h_i: float = 0.0,
-            max_steps: int = 0, stream=None):
-        sp = SolveParams(float(lam), float(h_i), float(dt), float(t_end), int(max_steps))
+            max_steps: int = 0, stream=None, **sources):
+        """Load one slot; freeze-in keywords (SOURCE_KEYS) set the sources
+        and the source-only regime of steppers created with freeze_in."""
+        sp = _solve_params(lam, h_i, dt, t_end, max_steps, sources)
         _check(lib().kxg_stepper_set(self._h, int(slot), _dev_ptr(f0, self.n, "f0"),
                                      ctypes.byref(sp), _stream_ptr(stream)))
 
-    def set_many(self, slot0: int, f0, lam, t_end, dt=0.0, h_i=0.0, max_steps=0, stream=None):
+    def set_many(self, slot0: int, f0, lam, t_end, dt=0.0, h_i=0.0, max_steps=0, stream=None,
+                 **sources):
         """Load slots slot0 .. slot0 + len(f0) - 1 in one call (f0: device
-        [count, n] float64; the other arguments are scalars or one value per
-        slot)."""
+        [count, n] float64; the other arguments, freeze-in keywords included,
+        are scalars or one value per slot)."""
         count = f0.shape[0] if f0.dim() == 2 else 1
         per = lambda v: np.broadcast_to(np.asarray(v, dtype=np.float64), (count,))
         lam_, te_, dt_, hi_ = per(lam), per(t_end), per(dt), per(h_i)
         ms_ = np.broadcast_to(np.asarray(max_steps, dtype=np.int64), (count,))
+        src_ = {k: per(v) for k, v in sources.items()}
         arr = (SolveParams * count)()
         for j in range(count):
-            arr[j] = SolveParams(float(lam_[j]), float(hi_[j]), float(dt_[j]), float(te_[j]),
-                                 int(ms_[j]))
+            arr[j] = _solve_params(lam_[j], hi_[j], dt_[j], te_[j], ms_[j],
+                                   {k: v[j] for k, v in src_.items()})
         _check(lib().kxg_stepper_set_many(self._h, int(slot0), int(count),
                                           _dev_ptr(f0, count * self.n, "f0"), arr,
                                           _stream_ptr(stream)))
@@ -384,7 +411,8 @@ class Stepper:
         arr = (SlotState * self.b_cap)()
         _check(lib().kxg_stepper_query(self._h, arr, _stream_ptr(stream)))
         return [{"t": s.t, "dt": s.dt, "outflow": s.outflow, "h_i": s.h_i, "steps": s.steps,
-                 "rejected": s.rejected, "status": s.status} for s in arr]
+                 "rejected": s.rejected, "status": s.status, "phase": s.phase,
+                 "u_switch": s.u_switch, "n_src": s.n_src} for s in arr]
 
     def get(self, slot: int, out=None, stream=None):
         import torch

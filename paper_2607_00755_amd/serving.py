@@ -295,6 +295,12 @@ class Server:
         ok = [r for r in mine if r.status == 1]
         lat = np.array([r.latency for r in ok]) if ok else np.array([np.nan])
         span = (max(r.finished for r in ok) - min(r.arrival for r in ok)) if ok else float("nan")
+        # queue build-up: median latency of the last quarter of the arrivals
+        # over that of the first quarter (about 1 while the loop keeps up)
+        by_arr = sorted(ok, key=lambda r: r.arrival)
+        qn = len(by_arr) // 4
+        growth = (float(np.median([r.latency for r in by_arr[-qn:]])) /
+                  float(np.median([r.latency for r in by_arr[:qn]]))) if qn >= 4 else float("nan")
         return {
             "completed": len(ok),
             "truncated": sum(1 for r in mine if r.status == 2),
@@ -304,6 +310,7 @@ class Server:
             "p50_s": float(np.percentile(lat, 50)),
             "p99_s": float(np.percentile(lat, 99)),
             "solves_per_s": len(ok) / span if span and span > 0 else float("nan"),
+            "queue_growth": growth,
             "mean_steps": float(np.mean([r.steps for r in ok])) if ok else float("nan"),
             "max_steps": int(max(r.steps for r in ok)) if ok else 0,
             "mean_batch": {n: g.batch_sum / max(g.iters, 1) for n, g in self.groups.items()},

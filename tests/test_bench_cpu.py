@@ -62,12 +62,15 @@ def test_oracle_thread_control_takes_effect():
 
 
 def test_sustainable_rate_rule():
-    rows = [{"rate_req_per_s": 10.0, "solves_per_s": 9.9, "p99_s": 4.0},
-            {"rate_req_per_s": 20.0, "solves_per_s": 19.5, "p99_s": 5.0},
-            {"rate_req_per_s": 40.0, "solves_per_s": 37.0, "p99_s": 7.9},
-            {"rate_req_per_s": 60.0, "solves_per_s": 45.0, "p99_s": 20.0}]
+    rows = [{"rate_req_per_s": 10.0, "queue_growth": 1.0, "p99_s": 4.0},
+            {"rate_req_per_s": 20.0, "queue_growth": 1.1, "p99_s": 5.0},
+            {"rate_req_per_s": 40.0, "queue_growth": 1.4, "p99_s": 5.9},
+            {"rate_req_per_s": 60.0, "queue_growth": 3.0, "p99_s": 20.0}]
     assert bench.sustainable(rows)["rate_req_per_s"] == 40.0
-    rows[2]["p99_s"] = 8.1          # p99 more than twice the unloaded one
+    rows[2]["p99_s"] = 6.1          # p99 more than 1.5 x the unloaded one
+    assert bench.sustainable(rows)["rate_req_per_s"] == 20.0
+    rows[2]["p99_s"] = 5.0
+    rows[2]["queue_growth"] = 1.6   # late arrivals wait longer: a queue builds up
     assert bench.sustainable(rows)["rate_req_per_s"] == 20.0
     assert bench.sustainable([]) is None
 
