@@ -53,10 +53,12 @@ def parse():
                     help="time the oracle's 16-solve subsamples in full (minutes) instead of "
                          "extrapolating from a bounded part of each")
     ap.add_argument("--profile-run", nargs="?", const="gemm", default=None,
-                    choices=("gemm", "stream384", "x3"),
+                    choices=("gemm", "stream384", "streamx384", "x3"),
                     help="short run for profilers: 'gemm' = the timed RK4 steps, the plain "
                          "FP64 path and a 1 GiB device copy (the calibration kernel); "
                          "'stream384' = 50 plain FP64 evaluations at N = 384 and the copy; "
+                         "'streamx384' = 50 exact-form evaluations (Bose-Einstein, log "
+                         "interpolation) at N = 384 in FP64 and in FP32, and the copy; "
                          "'x3' = --steps 16-bit RK4 steps (BF16x3, then FP16x3) at N = 256, "
                          "B = 4096 and the copy")
     return ap.parse_args()
@@ -74,6 +76,9 @@ def kernel_source_sha1(sources):
 GEMM_F32_SOURCES = ("paper_2607_00755_amd/csrc/kxg_gemm_f32.hip",
                     "paper_2607_00755_amd/csrc/kxg_device.h",
                     "paper_2607_00755_amd/csrc/kxg_geom.h")
+GEMM_X3_SOURCES = ("paper_2607_00755_amd/csrc/kxg_eval.hip",
+                   "paper_2607_00755_amd/csrc/kxg_device.h",
+                   "paper_2607_00755_amd/csrc/kxg_geom.h")
 
 
 def counted_traffic(profile_md, sources):
@@ -340,6 +345,58 @@ def cpu_config_rows(full):
     return rows
 
 
+def freeze_in_workload(dev, iters=400):
+    """The two-source freeze-in evolution (Sec. 3 sources, Sec. 4.2 regimes)
+    as a batch: 256 solves on an N = 128 FP32 grid, each a seeded lambda of a
+    coupling scan with a condensate (N0 = 1, Gamma = 0.5 H_i, p0 = 0.8) and a
+    Higgs-like decay source (kappa = 1, m_h = 5 m, T_i = 2 m), starting from
+    f = 0 in the source-only regime (du = 0.01).  Times `iters` iterations
+    (one source RK4 step or one Heun attempt per slot each) and the same
+    batch on a plain expanding-run stepper (no sources, elastic operator on)
+    for the cost of the freeze-in machinery (loss rates, sources, switch)."""
+    import torch
+    from paper_2607_00755_amd import inputs, kxg
+    n, B = 128, 256
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    rng = np.random.default_rng(20261202)
+    lam = 10 ** rng.uniform(1.0, 3.0, B)
+    k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=B)
+    out = {"workload": "freeze_in_fp32_n128_b256", "iterations": iters}
+    f0 = torch.tensor(np.stack([s.f0(p) * 1e-2 for s in inputs.draw_solves(B, seed=3)]),
+                      device=dev)
+    zero = torch.zeros((B, n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+    for label, fi in (("freeze_in", True), ("plain_expanding", False)):
+        st = kxg.Stepper(k, kind=kxg.HEUN, prec=kxg.F32, b_cap=B, expansion=kxg.EXP_RADIATION,
+                         freeze_in=fi)
+        if fi:
+            st.set_many(0, zero, lam, 4.0, dt=1e-3, h_i=1.0, src_n0=1.0, src_gamma=0.5,
+                        src_p0=0.8, src_kappa=1.0, src_mh=5.0, src_ti=2.0, du_src=0.01,
+                        eps_switch=1e-2)
+        else:
+            st.set_many(0, f0, lam * 1e-2, 4.0, dt=1e-3, h_i=1.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            st.advance(8, stream=stream)         # graph capture and warm-up
+            stream.synchronize()
+            t0 = time.perf_counter()
+            st.advance(iters, stream=stream)
+            stream.synchronize()
+        el = time.perf_counter() - t0
+        q = st.query()
+        row = {"ms_per_iteration": round(1e3 * el / iters, 4),
+               "slot_iterations_per_s": round(B * iters / el, 1)}
+        if fi:
+            row["slots_switched"] = sum(1 for r in q if r["phase"] == 1)
+            row["mean_source_steps"] = round(float(np.mean([r["n_src"] for r in q])), 1)
+        out[label] = row
+        del st
+    out["freeze_in_overhead"] = round(out["freeze_in"]["ms_per_iteration"] /
+                                      out["plain_expanding"]["ms_per_iteration"], 3)
+    log("freeze-in batch: %s" % out)
+    return out
+
+
 def paper_timing_curve(dev):
     """The paper's own timing workload (Sec. 5, Fig. run_time): one full-grid
     evaluation of the contact operator for the two-bump input of
@@ -404,6 +461,26 @@ def main():
             k.eval(f, prec=kxg.F64, out=C, diagnostics=False)
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": "stream384", "evals": 50}), flush=True)
+        return
+    if args.profile_run == "streamx384":
+        # the exact-form stream (eq. app_dense_collision with Bose-Einstein
+        # factors and log interpolation, the paper's timing workload) at
+        # N = 384 in FP64 and FP32, 50 evaluations each, then the
+        # calibration copy
+        n = 384
+        p = inputs.log_grid(n, 1e-3, 1e2)
+        k = kxg.Kernel(p, precs=(kxg.F64, kxg.F32), b_cap=1, brackets=True)
+        f = torch.tensor(inputs.two_bump_benchmark(p)[None, :], device=dev)
+        C = torch.empty_like(f)
+        for prec in (kxg.F64, kxg.F32):
+            for _ in range(50):
+                k.eval(f, prec=prec, out=C, diagnostics=False, project=False, log_interp=True, eta=1)
+        torch.cuda.synchronize()
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": "streamx384", "evals": 50}), flush=True)
         return
     if args.profile_run == "x3":
         # the 16-bit workload: N = 256, B = 4096 RK4 steps in BF16x3 and FP16x3
@@ -584,7 +661,9 @@ def main():
                 "executed_mfma_frac": round(fl / (g_us * 1e-6) / 1e12 / PEAK["bf16"], 4),
                 "executed_frac_of_measured": (round(fl / (g_us * 1e-6) / 1e12 / peaks["mfma_bf16_tflops"], 4)
                                               if peaks else None),
-                "blocks": blocks16}
+                "blocks": blocks16,
+                "traffic": (counted_traffic("gemm_x3_n256_b4096.md", GEMM_X3_SOURCES)
+                            if prec == kxg.BF16X3 else None)}
             log("%s B=4096 RK4: %.3f ms/step, gemm %.1f us" % (name, 1e3 * wl, g_us))
             del st4
         # split ablations: error of 256 rows against the FP64 path, GEMM time at B = 4096
@@ -619,6 +698,7 @@ def main():
                 if key in extras:
                     extras[key]["frac_of_measured_read"] = round(extras[key]["stream_GBps"] / peaks["read_GBps"], 4)
         extras["paper_timing_workload_be_log"] = paper_timing_curve(dev)
+        extras["freeze_in_fp32_n128_b256"] = freeze_in_workload(dev)
 
     # ---------------- serving loop (continuous batching) ----------------
     serve = None
