@@ -17,6 +17,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kxg_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# another build of the same source to load instead (the sanitizer build of
+# the CPU tests); it is used as it is, never rebuilt
+LIB_OVERRIDE = os.environ.get("ORACLE_LIBRARY")
 
 GL, EXACT = 0, 1          # angular quadrature: Gauss-Legendre in mu, closed form
 LIN, LOG = 0, 1           # interpolation of f at the fourth momentum
@@ -26,23 +29,32 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
+def build(force: bool = True, sanitize: bool = False, out: Optional[str] = None) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, no FMA contraction);
+    with sanitize, into `out` with AddressSanitizer and
+    UndefinedBehaviorSanitizer (the loading process preloads libasan)."""
+    lib = out or LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
                "-shared", "-fPIC", "-o", tmp, SRC, "-lm"]
+        if sanitize:
+            cmd[1:1] = ["-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        "-fno-omit-frame-pointer"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build()
-        L = ctypes.CDLL(LIB)
+        if LIB_OVERRIDE:
+            L = ctypes.CDLL(LIB_OVERRIDE)
+        else:
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+                build()
+            L = ctypes.CDLL(LIB)
         L.or_angular_gl.restype = ctypes.c_double
         L.or_angular_exact.restype = ctypes.c_double
         L.or_weight.restype = ctypes.c_double

@@ -28,13 +28,21 @@ UNITS = {
     "kxg_gemm_f32.hip": [],
     "kxg_probe.hip": [],
     "kxg_step.hip": [],
+    "kxg_plan.cpp": [],
 }
 
 
-def _compile(unit: str) -> str:
+# host-side AddressSanitizer + UndefinedBehaviorSanitizer (the device code is
+# built as usual; each flag goes to the host pass only)
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-shared-libsan"]
+
+
+def _compile(unit: str, build_dir: str = BUILD, extra=()) -> str:
     src = os.path.join(CSRC, unit)
-    obj = os.path.join(BUILD, unit + ".o")
-    cmd = [HIPCC] + COMMON + UNITS[unit] + ["-c", src, "-o", obj]
+    obj = os.path.join(build_dir, unit + ".o")
+    cmd = [HIPCC] + COMMON + UNITS[unit] + list(extra) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     err = "\n".join(l for l in (r.stderr or "").splitlines() if noise not in l)
@@ -45,19 +53,25 @@ def _compile(unit: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, sanitize: bool = False, out_dir: str = None) -> str:
+    """Compile and link libkxg.so (in-tree, or into out_dir; with sanitize,
+    the host code carries ASan and UBSan, whose runtime the loading process
+    must preload)."""
+    build_dir = os.path.join(out_dir, "_build") if out_dir else BUILD
+    lib = os.path.join(out_dir, "libkxg.so") if out_dir else LIB
+    extra = SANITIZE if sanitize else []
+    os.makedirs(build_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=4) as ex:
-        objs = list(ex.map(_compile, sorted(UNITS)))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        objs = list(ex.map(lambda u: _compile(u, build_dir, extra), sorted(UNITS)))
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + extra + ["-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":

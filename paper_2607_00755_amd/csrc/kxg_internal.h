@@ -158,7 +158,6 @@ void free_workspace(Workspace &ws);
 hipError_t launch_moments(const kxg_kernel &k, const double *f, int B, double *out,
                           hipStream_t s);
 
-void gauss_legendre(int n, double *x, double *w);
 
 // Gain-kernel profiling (events around each launch while a profile is open).
 void profile_mark_begin(hipStream_t s);

@@ -14,7 +14,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libkxg.so")
+# the in-tree build; KXG_LIBRARY names another build of the same sources
+# (the sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("KXG_LIBRARY") or os.path.join(PKG, "libkxg.so")
 
 # status codes
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ESTEP, ENUMERIC = range(7)
