@@ -45,10 +45,13 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-check", type=int, default=32,
                     help="measured requests re-run alone and compared with their result in the mix")
-    ap.add_argument("--serve-sweep", default="40,70,100,130,160",
+    ap.add_argument("--serve-sweep", default="20,30,40,50,60,80",
                     help="comma-separated arrival rates of a saturation sweep; empty = none")
     ap.add_argument("--serve-sweep-requests", type=int, default=400,
-                    help="measured requests per sweep rate (after a fifth as many warm-up ones)")
+                    help="measured requests per sweep rate, at least (see --serve-sweep-seconds)")
+    ap.add_argument("--serve-sweep-seconds", type=float, default=10.0,
+                    help="each sweep rate also runs at least this many seconds of arrivals, "
+                         "several solve lifetimes, so that a queue can build up")
     ap.add_argument("--cpu-full", action="store_true",
                     help="time the oracle's 16-solve subsamples in full (minutes) instead of "
                          "extrapolating from a bounded part of each")
@@ -145,15 +148,15 @@ def serving_sweep(serving, args):
     (<= 2 x the p99 of the lowest rate, the nearly unloaded latency)."""
     from paper_2607_00755_amd import inputs, kxg
     rows = []
-    nr = args.serve_sweep_requests
-    nw = max(1, nr // 5)
     for rate in [float(x) for x in args.serve_sweep.split(",") if x.strip()]:
+        nr = max(args.serve_sweep_requests, int(round(args.serve_sweep_seconds * rate)))
+        nw = max(1, nr // 5)
         reqs = inputs.serving_requests(nw + nr, rate=rate)
         srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16)
         t0 = time.perf_counter()
         done = srv.run(reqs)
         st = srv.stats(done, warm=nw)
-        rows.append({"rate_req_per_s": rate, "requests": nr, "p50_s": round(st["p50_s"], 3),
+        rows.append({"rate_req_per_s": rate, "requests": nr, "warmup": nw, "p50_s": round(st["p50_s"], 3),
                      "p99_s": round(st["p99_s"], 3), "solves_per_s": round(st["solves_per_s"], 2),
                      "queue_growth": round(st["queue_growth"], 3),
                      "completed": st["completed"], "truncated": st["truncated"],
@@ -162,7 +165,8 @@ def serving_sweep(serving, args):
             (rate, st["p50_s"], st["p99_s"], st["solves_per_s"], st["queue_growth"]))
         del srv
     best = sustainable(rows)
-    return {"rates": rows, "requests_per_rate": nr, "warmup_per_rate": nw,
+    return {"rates": rows, "min_requests_per_rate": args.serve_sweep_requests,
+            "min_arrival_seconds_per_rate": args.serve_sweep_seconds,
             "max_sustainable_rate_req_per_s": None if best is None else best["rate_req_per_s"],
             "max_sustainable_solves_per_s": None if best is None else best["solves_per_s"],
             "rule": "highest rate whose late arrivals wait no longer than its early ones "
@@ -628,11 +632,11 @@ def main():
         # ---------------- 16-bit split at B = 4096: RK4 steps ----------------
         w4 = inputs.mixed_n256(4096)
         f4 = torch.tensor(w4.f0(), device=dev)
-        k4 = kxg.Kernel(p, precs=(kxg.BF16X3, kxg.F16X3), b_cap=4096)
+        k4 = kxg.Kernel(p, precs=(kxg.BF16X3, kxg.F16X3, kxg.F16X2), b_cap=4096)
         info4 = k4.stats()
         blocks16 = info4["blocks16"]
         lams4 = [s.lam for s in w4.solves]
-        for prec, name in ((kxg.BF16X3, "bf16x3"), (kxg.F16X3, "f16x3")):
+        for prec, name in ((kxg.BF16X3, "bf16x3"), (kxg.F16X3, "f16x3"), (kxg.F16X2, "f16x2")):
             st4 = kxg.Stepper(k4, kind=kxg.RK4, prec=prec, b_cap=4096)
             st4.set_many(0, f4, lam=lams4, t_end=1e30, h_i=1.0)
             torch.cuda.synchronize()       # sets on the default stream, steps on run_stream
@@ -649,9 +653,10 @@ def main():
             g_ms, g_n = kxg.profile_end()
             g_us = 1e3 * g_ms / max(g_n, 1)
             # algorithmic work per GEMM: one product over the non-zero packed
-            # entries; executed: the three split products over the kept blocks
+            # entries; executed: the split products (3, or 2 for FP16 x2) over
+            # the kept blocks
             fa = 2.0 * 4096 * info4["nnz_packed"]
-            fl = 3 * 2.0 * 4096 * 32 * 256 * blocks16
+            fl = (2 if prec == kxg.F16X2 else 3) * 2.0 * 4096 * 32 * 256 * blocks16
             extras[name + "_b4096"] = {
                 "evals_per_s": round(4 * 4096 / wl, 1), "ms_per_rk4_step": round(1e3 * wl, 3),
                 "gemm_us": round(g_us, 1),

@@ -62,7 +62,9 @@ typedef enum {
     KXG_F32 = 1,     /* FP32: stream if b_cap <= 4, else MFMA GEMM        */
     KXG_BF16X3 = 2,  /* BF16 MFMA, hi+lo split of A and of f_n f_m,
                         3 products, FP32 accumulation                     */
-    KXG_F16X3 = 3    /* FP16 MFMA, hi+lo split with power-of-two scaling  */
+    KXG_F16X3 = 3,   /* FP16 MFMA, hi+lo split with power-of-two scaling  */
+    KXG_F16X2 = 4    /* FP16 MFMA, A in one FP16 value (power-of-two row
+                        scaling), hi+lo split of f_n f_m: 2 products       */
 } kxg_prec;
 #define KXG_PREC_BIT(p) (1u << (p))
 /* Extra bit of kxg_kernel_build's prec_mask: also build the interpolation

@@ -347,7 +347,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     if (grid->quad != KXG_QUAD_GL && grid->quad != KXG_QUAD_EXACT) { set_error("kxg_kernel_build: bad quad %d", grid->quad); return KXG_EINVAL; }
     if (grid->quad == KXG_QUAD_GL && (grid->n_mu < 1 || grid->n_mu > 4096)) { set_error("kxg_kernel_build: n_mu=%d outside [1, 4096]", grid->n_mu); return KXG_EINVAL; }
     if (b_cap < 1 || b_cap > (1 << 20)) { set_error("kxg_kernel_build: b_cap=%d outside [1, 2^20]", b_cap); return KXG_EINVAL; }
-    if (prec_mask & ~(0xFu | KXG_WITH_BRACKETS | KXG_LEAN)) { set_error("kxg_kernel_build: unknown precision bits 0x%x", prec_mask); return KXG_EINVAL; }
+    if (prec_mask & ~(0x1Fu | KXG_WITH_BRACKETS | KXG_LEAN)) { set_error("kxg_kernel_build: unknown precision bits 0x%x", prec_mask); return KXG_EINVAL; }
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     kxg_kernel *k = new (std::nothrow) kxg_kernel;
@@ -364,7 +364,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     // asked for, and the dense FP32 copy only where an evaluation streams it
     const bool lean = (prec_mask & KXG_LEAN) != 0;
     const bool keep64 = !lean || (prec_mask & KXG_PREC_BIT(KXG_F64));
-    k->prec_mask = (prec_mask & 0xFu) | (keep64 ? KXG_PREC_BIT(KXG_F64) : 0u);
+    k->prec_mask = (prec_mask & 0x1Fu) | (keep64 ? KXG_PREC_BIT(KXG_F64) : 0u);
     k->p.assign(grid->p, grid->p + n);
     k->dp.resize(n);
     k->E.resize(n);
@@ -397,7 +397,8 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     const size_t n3 = (size_t)n * n * n, n2 = (size_t)n * n;
     const bool want32 = prec_mask & KXG_PREC_BIT(KXG_F32);
     const bool wantbf = prec_mask & KXG_PREC_BIT(KXG_BF16X3);
-    const bool wanth = prec_mask & KXG_PREC_BIT(KXG_F16X3);
+    // FP16 x3 and x2 share one operand (hi and lo of A; x2 reads the hi)
+    const bool wanth = prec_mask & (KXG_PREC_BIT(KXG_F16X3) | KXG_PREC_BIT(KXG_F16X2));
     kxg_status st = KXG_OK;
 #define KXG_ALLOC(ptr, cnt) \
     if (st == KXG_OK) st = dalloc(&(ptr), (cnt))
@@ -483,7 +484,8 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
                             n2 * sizeof(double) + (k->d_A32 ? jl : 0);
     const size_t packed16 = (size_t)k->ncomp16 * KXG_LDS_IBW * kBlk * 1024;   // hi + lo values
     if (wantbf) k->bytes[KXG_BF16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
-    if (wanth) k->bytes[KXG_F16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
+    if (prec_mask & KXG_PREC_BIT(KXG_F16X3)) k->bytes[KXG_F16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
+    if (prec_mask & KXG_PREC_BIT(KXG_F16X2)) k->bytes[KXG_F16X2] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
     // everything the handle holds on the device
     const size_t fbytes = (size_t)k->geo.nb * k->ws.bpad_cap * kBlk * sizeof(float);
     k->held = 5 * (size_t)n * sizeof(double) + 2 * n2 * sizeof(double) + 2 * (size_t)g.npairs * sizeof(int) +
@@ -503,7 +505,7 @@ int32_t kxg_kernel_n(const kxg_kernel *k) { return k ? k->n : 0; }
 size_t kxg_kernel_bytes(const kxg_kernel *k, int32_t prec)
 {
     if (!k) return 0;
-    if (prec >= 0 && prec < 4) return k->bytes[prec];
+    if (prec >= 0 && prec < 5) return k->bytes[prec];
     return k->held;
 }
 
@@ -551,7 +553,7 @@ kxg_status kxg_kernel_grid(const kxg_kernel *k, double *dp, double *E, double *K
 
 static kxg_status check_prec(const kxg_kernel *k, int32_t prec)
 {
-    if (prec < 0 || prec > 3) { set_error("unknown precision %d", prec); return KXG_EINVAL; }
+    if (prec < 0 || prec > 4) { set_error("unknown precision %d", prec); return KXG_EINVAL; }
     if (!(k->prec_mask & KXG_PREC_BIT(prec))) {
         set_error("precision %d was not built into this kernel handle", prec);
         return KXG_EUNSUPPORTED;
@@ -567,7 +569,7 @@ static kxg_status check_eval(const kxg_kernel *k, int32_t prec, const double *f_
     if (B < 1 || B > k->b_cap) { set_error("kxg_eval: B=%d outside [1, b_cap=%d]", B, k->b_cap); return KXG_EINVAL; }
     if (flags & ~(KXG_PROJECT | KXG_INTERP_LOG | KXG_STAT_BOSE | KXG_STAT_FERMI | KXG_SPLIT_F_ONLY | KXG_SPLIT_NONE)) { set_error("kxg_eval: unknown flags 0x%x", flags); return KXG_EINVAL; }
     if ((flags & KXG_SPLIT_F_ONLY) && (flags & KXG_SPLIT_NONE)) { set_error("kxg_eval: two split ablations together"); return KXG_EINVAL; }
-    if ((flags & (KXG_SPLIT_F_ONLY | KXG_SPLIT_NONE)) && prec != KXG_BF16X3 && prec != KXG_F16X3) { set_error("kxg_eval: split ablations apply to the 16-bit precisions only"); return KXG_EINVAL; }
+    if ((flags & (KXG_SPLIT_F_ONLY | KXG_SPLIT_NONE)) && prec != KXG_BF16X3 && prec != KXG_F16X3) { set_error("kxg_eval: split ablations apply to the three-product 16-bit precisions only"); return KXG_EINVAL; }
     if ((flags & KXG_STAT_BOSE) && (flags & KXG_STAT_FERMI)) { set_error("kxg_eval: Bose and Fermi statistics together"); return KXG_EINVAL; }
     kxg_status st = check_prec(k, prec);
     if (st != KXG_OK) return st;

@@ -39,6 +39,9 @@ inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 #define KXG_STREAM_NT 1
 #endif
 // shape of the LDS-shared 16-bit GEMM: b-blocks and i-blocks per wave
+#ifndef KXG_STREAMX_UNROLL
+#define KXG_STREAMX_UNROLL 4   // element groups in flight per thread in the exact-form stream
+#endif
 #ifndef KXG_EPI_WAVE_BCAP
 #define KXG_EPI_WAVE_BCAP 2048   // handles from this b_cap get a wave per distribution in the epilogue
 #endif
@@ -217,13 +220,14 @@ __global__ __launch_bounds__(256) void k_stream_x(const T *__restrict__ A,
 #pragma unroll
         for (int c = 0; c < NA; ++c) acc[bb][c] = (T)0;
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
-    for (; e < e_end; e += step) {
-        const vec_t a = *reinterpret_cast<const vec_t *>(row + e);
-        const double kk = Ks[k];
+    typedef uint16_t jvec_t __attribute__((ext_vector_type(VEC)));
+    // one element group (VEC weights of row k, columns m .. m + VEC - 1)
+    auto body = [&](const vec_t &a, const jvec_t &jv, int kq, int mq) {
+        const double kk = Ks[kq];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-            const int mv = m + v;
-            const int jl = jrow[e + v];
+            const int mv = mq + v;
+            const int jl = jv[v];
             if (jl == 0xFFFF) continue;
             const double kt = (kk + Ks[mv]) - ki;
             const T wr = (T)((kt - Ks[jl]) * iK[jl]);
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(256) void k_stream_x(const T *__restrict__ A,
 #pragma unroll
             for (int bb = 0; bb < BT; ++bb) {
                 const T *fb = fs + bb * n;
-                const T fn = fb[k], fm = fb[mv];
+                const T fn = fb[kq], fm = fb[mv];
                 T ft;
                 if (LOGI) {
                     const T *lb = ls + bb * n;
@@ -249,6 +253,29 @@ __global__ __launch_bounds__(256) void k_stream_x(const T *__restrict__ A,
                 }
             }
         }
+    };
+    // KXG_STREAMX_UNROLL groups of loads in flight per thread (weights and
+    // brackets), non-temporal: both tables are read once per call
+    constexpr int UN = KXG_STREAMX_UNROLL;
+    for (; e + (UN - 1) * step < e_end; e += UN * step) {
+        vec_t a[UN];
+        jvec_t jv[UN];
+        int kk[UN], mm[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            a[u] = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(row + e + (long)u * step));
+            jv[u] = __builtin_nontemporal_load(reinterpret_cast<const jvec_t *>(jrow + e + (long)u * step));
+            kk[u] = k;
+            mm[u] = m;
+            m += sm;
+            k += sk;
+            if (m >= n) { m -= n; ++k; }
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) body(a[u], jv[u], kk[u], mm[u]);
+    }
+    for (; e < e_end; e += step) {
+        body(*reinterpret_cast<const vec_t *>(row + e), *reinterpret_cast<const jvec_t *>(jrow + e), k, m);
         m += sm;
         k += sk;
         if (m >= n) { m -= n; ++k; }
@@ -1462,7 +1489,7 @@ static Path path_of(const kxg_kernel &k, int prec, int B)
         p.stream = true;
         return p;
     }
-    if (prec == KXG_BF16X3 || prec == KXG_F16X3) {
+    if (prec == KXG_BF16X3 || prec == KXG_F16X3 || prec == KXG_F16X2) {
         constexpr int TILE = 4 * KXG_LDS_BBW * 32;
         p.lds = true;
         p.bpad = div_up(B, TILE) * TILE;
@@ -1480,7 +1507,7 @@ kxg_status prep_operands(const kxg_kernel &k, const Workspace &ws, int prec, con
     const Path P = path_of(k, prec, B);
     if (P.stream) return KXG_OK;
     hipLaunchKernelGGL(k_prep, dim3(P.bpad), dim3(256), 0, s, f, B, k.n, k.geo.nb, P.bpad,
-                       prec == KXG_F16X3 ? 1 : 0, ws.fop, ws.fpar, ws.fscale);
+                       (prec == KXG_F16X3 || prec == KXG_F16X2) ? 1 : 0, ws.fop, ws.fpar, ws.fscale);
     KXG_TRY_HIP(hipGetLastError());
     return KXG_OK;
 }
@@ -1526,14 +1553,17 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         int chunk = div_up(n2, ns);
         chunk = div_up(chunk, 256 * vec) * (256 * vec);
         const int nsplit = (int)((n2 + chunk - 1) / chunk);
-        constexpr int BT = 2;
+        // distributions per pass: one for a single distribution (no idle
+        // arithmetic on an empty slot), two otherwise
+        const int BT = B == 1 ? 1 : 2;
         const dim3 grid(nsplit, n, div_up(B, BT));
         const size_t shm = 2 * n * sizeof(double) + 2 * (size_t)BT * n * (dbl ? sizeof(double) : sizeof(float));
         double *ext = static_cast<double *>(ws.part);
-#define KXG_SX(T, V, L, Q)                                                                        \
-    hipLaunchKernelGGL((k_stream_x<T, V, BT, L, Q>), grid, dim3(256), shm, s,                     \
+#define KXG_SX1(T, V, BTV, L, Q)                                                                  \
+    hipLaunchKernelGGL((k_stream_x<T, V, BTV, L, Q>), grid, dim3(256), shm, s,                    \
                        reinterpret_cast<const T *>(dbl ? (const void *)k.d_A64 : (const void *)k.d_A32), \
                        k.d_JL, f, k.d_K, k.d_invdK, n, B, chunk, ext)
+#define KXG_SX(T, V, L, Q) if (BT == 1) KXG_SX1(T, V, 1, L, Q); else KXG_SX1(T, V, 2, L, Q)
 #define KXG_SX2(T, V)                                                                             \
     if (logi && quant) KXG_SX(T, V, true, true);                                                  \
     else if (logi) KXG_SX(T, V, true, false);                                                     \
@@ -1546,6 +1576,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         }
 #undef KXG_SX2
 #undef KXG_SX
+#undef KXG_SX1
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
         KXG_TRY_HIP(launch_epilogue<double>(ext, nsplit, SlotCounts{}, 0, 0, nullptr, nullptr, rate, f, k, B,
@@ -1555,7 +1586,10 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     }
     const Path P = path_of(k, prec, B);
     const int project = (flags & KXG_PROJECT) ? 1 : 0;
-    const bool want_rate = diag != nullptr || (step_in && step_in->freeze_in);
+    // loss rates: for the diagnostics, and for the regime switch of
+    // freeze-in slots, which is tested on the predictor's input only
+    const bool want_rate = diag != nullptr ||
+                           (step_in && step_in->freeze_in && step_in->mode == kStepHeunPred);
     if (P.stream) {
         const int ns = stream_splits(n);
         const long n2 = (long)n * n;
@@ -1594,7 +1628,7 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
                                             nullptr, 0.0, 1));
         return KXG_OK;
     }
-    const bool f16 = prec == KXG_F16X3;
+    const bool f16 = prec == KXG_F16X3 || prec == KXG_F16X2;
     if (P.lds) {
         // 16-bit GEMM, the packed tensor shared through LDS
         constexpr int BBW = KXG_LDS_BBW, IBW = KXG_LDS_IBW, TILE = 4 * BBW * 32;
@@ -1606,8 +1640,10 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         hand_over(bpad, f16 ? 1 : 0);
         float *part = static_cast<float *>(ws.part);
         const dim3 grid(nbt * k.nunits16);
-        // products of the hi+lo split: 3 (production), 2 or 1 (ablations)
-        const int split = (flags & KXG_SPLIT_NONE) ? 1 : ((flags & KXG_SPLIT_F_ONLY) ? 2 : 3);
+        // products of the hi+lo split: 3 (x3), 2 (FP16 x2: A unsplit, f_n f_m
+        // split; also the F2-only ablation of x3) or 1 (ablation)
+        const int split = prec == KXG_F16X2 ? 2
+                          : ((flags & KXG_SPLIT_NONE) ? 1 : ((flags & KXG_SPLIT_F_ONLY) ? 2 : 3));
         profile_mark_begin(s);
 #define KXG_X3(F, S)                                                                              \
     hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, F, S>), grid, dim3(256), 0, s,          \

@@ -114,7 +114,7 @@ struct kxg_kernel {
     uint16_t *d_JL = nullptr;    // [n][n][n] interpolation bracket j_L (0xFFFF: cut)
     double *d_invdK = nullptr;   // [n] 1 / (K_{j+1} - K_j) (0 for the last point)
     kxg::Geometry geo;
-    size_t bytes[4] = {0, 0, 0, 0};
+    size_t bytes[5] = {0, 0, 0, 0, 0};
     size_t held = 0;             // device bytes held by the handle
     kxg::Workspace ws;
 };

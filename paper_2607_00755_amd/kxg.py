@@ -21,8 +21,8 @@ LIB_PATH = os.environ.get("KXG_LIBRARY") or os.path.join(PKG, "libkxg.so")
 # status codes
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ESTEP, ENUMERIC = range(7)
 # precisions
-F64, F32, BF16X3, F16X3 = 0, 1, 2, 3
-PREC_NAMES = {F64: "f64", F32: "f32", BF16X3: "bf16x3", F16X3: "f16x3"}
+F64, F32, BF16X3, F16X3, F16X2 = 0, 1, 2, 3, 4
+PREC_NAMES = {F64: "f64", F32: "f32", BF16X3: "bf16x3", F16X3: "f16x3", F16X2: "f16x2"}
 QUAD_GL, QUAD_EXACT = 0, 1
 PROJECT = 1
 INTERP_LOG = 2
