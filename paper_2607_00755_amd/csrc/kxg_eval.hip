@@ -33,12 +33,15 @@ typedef unsigned int u32x8 __attribute__((ext_vector_type(8)));
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
 #ifndef KXG_STREAM_UNROLL
-#define KXG_STREAM_UNROLL 8
+#define KXG_STREAM_UNROLL 16
 #endif
 #ifndef KXG_STREAM_NT
 #define KXG_STREAM_NT 1
 #endif
 // shape of the LDS-shared 16-bit GEMM: b-blocks and i-blocks per wave
+#ifndef KXG_STREAM_ROWS_TARGET
+#define KXG_STREAM_ROWS_TARGET 2048   // K splits x rows of a stream launch aimed at (more for n below it)
+#endif
 #ifndef KXG_STREAMX_UNROLL
 #define KXG_STREAMX_UNROLL 4   // element groups in flight per thread in the exact-form stream
 #endif
@@ -1408,7 +1411,7 @@ __global__ __launch_bounds__(256) void k_moments(const double *__restrict__ f, i
 int stream_splits(int n)
 {
     const long n2 = (long)n * n;
-    int s = div_up(2048, n);
+    int s = div_up(KXG_STREAM_ROWS_TARGET, n);
     const int cap = (int)(n2 / 2048);           // keep chunks >= 2048 elements
     if (s > cap) s = cap;
     if (s < 1) s = 1;
