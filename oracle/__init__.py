@@ -64,6 +64,7 @@ def lib():
         L.or_condensate_a3nu.restype = ctypes.c_double
         L.or_gamma22.restype = ctypes.c_double
         L.or_freeze_in.restype = ctypes.c_int
+        L.or_heun_comoving.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -272,6 +273,81 @@ class Operator:
     def gamma0(self, f) -> float:
         """Largest loss rate max_i sum_j R_ij f_j (the initial scattering rate)."""
         return float(np.max(self.R @ _f64(f)))
+
+
+class Comoving:
+    """The operator on a fixed comoving grid q (Sec. 4.1: p = q / a) at u = ln a,
+    exact (the tensors of the grid q / a rebuilt at every u; ntab = 0) or
+    tabulated (the tensors at ntab nodes of u in [umin, umax], mixed linearly
+    in u between the two that bracket it)."""
+
+    def __init__(self, q, mass=1.0, gdof=1.0, m2=1.0, quad=GL, nmu=18, ntab: int = 0,
+                 umin: float = 0.0, umax: float = 0.0):
+        self.q = _f64(q)
+        self.n = len(self.q)
+        self.mass, self.gdof, self.m2 = float(mass), float(gdof), float(m2)
+        self.quad, self.nmu = int(quad), int(nmu)
+        self.ntab, self.umin = int(ntab), float(umin)
+        self.du = (float(umax) - float(umin)) / (ntab - 1) if ntab > 1 else 1.0
+        n = self.n
+        if self.ntab > 0:
+            assert self.ntab >= 2 and umax > umin
+            self.tabA = np.empty((self.ntab, n, n, n))
+            self.tabR = np.empty((self.ntab, n, n))
+            for j in range(self.ntab):
+                A, R = self.tensors(self.umin + j * self.du)
+                self.tabA[j], self.tabR[j] = A, R
+        else:
+            self.tabA = self.tabR = None
+
+    def tensors(self, u: float):
+        """A, R of the physical grid q / e^u."""
+        n = self.n
+        A, R = np.empty((n, n, n)), np.empty((n, n))
+        lib().or_comoving_tensors(ctypes.c_int(n), _p(self.q), ctypes.c_double(u),
+                                  ctypes.c_double(self.mass), ctypes.c_double(self.gdof),
+                                  ctypes.c_double(self.m2), ctypes.c_int(self.quad),
+                                  ctypes.c_int(self.nmu), _p(A), _p(R))
+        return A, R
+
+    def grid(self, u: float) -> Grid:
+        """Grid quantities of the physical grid q / e^u."""
+        return Grid(self.q / np.exp(u), self.mass)
+
+    def collision(self, f, u: float, project: bool = True):
+        out = np.empty(self.n)
+        lib().or_comoving_collision(
+            ctypes.c_int(self.n), _p(self.q), ctypes.c_double(u), ctypes.c_double(self.mass),
+            ctypes.c_double(self.gdof), ctypes.c_double(self.m2), ctypes.c_int(self.quad),
+            ctypes.c_int(self.nmu), ctypes.c_int(self.ntab), ctypes.c_double(self.umin),
+            ctypes.c_double(self.du), _p(self.tabA), _p(self.tabR), _p(_f64(f)),
+            ctypes.c_int(int(project)), _p(out))
+        return out
+
+    def heun(self, x0, lam: float, Hi: float, u_end: float, dt0: float, u0: float = 0.0,
+             project: bool = True, rtol: float = 1e-6, atol: Optional[float] = None,
+             safety: float = 0.9, fmin: float = 0.2, fmax: float = 5.0,
+             max_steps: int = 10000, replay_dt=None):
+        """Adaptive (or replayed) Heun in u on the comoving grid (state f)."""
+        x = _f64(x0).copy()
+        if atol is None:
+            atol = 1e-12 * float(np.max(np.abs(x)))
+        nrep = 0 if replay_dt is None else len(replay_dt)
+        cap = max(nrep, max_steps)
+        acc_u, acc_dt = np.empty(cap), np.empty(cap)
+        rd = None if replay_dt is None else _f64(replay_dt)
+        nrej = ctypes.c_int(0)
+        nacc = lib().or_heun_comoving(
+            ctypes.c_int(self.n), _p(self.q), ctypes.c_double(self.mass),
+            ctypes.c_double(self.gdof), ctypes.c_double(self.m2), ctypes.c_int(self.quad),
+            ctypes.c_int(self.nmu), ctypes.c_int(self.ntab), ctypes.c_double(self.umin),
+            ctypes.c_double(self.du), _p(self.tabA), _p(self.tabR), _p(x),
+            ctypes.c_int(int(project)), ctypes.c_double(lam), ctypes.c_double(Hi),
+            ctypes.c_double(u0), ctypes.c_double(u_end), ctypes.c_double(dt0),
+            ctypes.c_double(rtol), ctypes.c_double(atol), ctypes.c_double(safety),
+            ctypes.c_double(fmin), ctypes.c_double(fmax), ctypes.c_int(max_steps),
+            ctypes.c_int(nrep), _p(rd), _p(acc_u), _p(acc_dt), ctypes.byref(nrej))
+        return {"x": x, "u": acc_u[:nacc], "dt": acc_dt[:nacc], "rejected": nrej.value}
 
 
 def direct(p, f, mass=1.0, gdof=1.0, m2=1.0, quad=GL, nmu=18, interp=LIN,

@@ -886,6 +886,148 @@ int or_freeze_in(int n, const double *A, const double *R, const double *p,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Comoving grid (Sec. 4.1): the distribution lives on fixed comoving      */
+/* momenta q_i (p = q / a); at scale factor a = e^u the operator is the     */
+/* one of the physical grid p_i = q_i / a with widths dp_i = dq_i / a (the  */
+/* trapezoid-in-ln rule gives exactly that), so the kernel tensors depend   */
+/* on a.  Two readings of how a time integrator obtains them:               */
+/*  - exact: the tensors of the grid q / a, rebuilt at every a;             */
+/*  - tabulated: the tensors at J nodes u_j = u_min + j du of ln a, and     */
+/*    at u in [u_j, u_j+1] the operator of the linear mix                   */
+/*    (1 - w) {A, R}(u_j) + w {A, R}(u_j+1), w = (u - u_j) / du, which is   */
+/*    (1 - w) C_j[f] + w C_j+1[f] since C is linear in A and R.             */
+/* The projection (App. C) always uses h and E of the grid q / a at u      */
+/* itself.  ntab = 0 selects the exact reading.                             */
+/* ------------------------------------------------------------------------ */
+void or_comoving_tensors(int n, const double *q, double u, double mass, double gdof,
+                         double m2, int quad, int nmu, double *A, double *R)
+{
+    double *p = malloc(sizeof(double) * n);
+    double a = exp(u);
+    for (int i = 0; i < n; ++i)
+        p[i] = q[i] / a;
+    or_kernel_build(n, p, NULL, mass, gdof, m2, quad, nmu, A, R, NULL, NULL);
+    free(p);
+}
+
+/* Raw comoving operator C_raw[f] at u (exact or tabulated, see above);   */
+/* tabA [ntab][n][n][n], tabR [ntab][n][n] hold the node tensors.          */
+static void comoving_raw(int n, const double *q, double u, double mass, double gdof,
+                         double m2, int quad, int nmu, int ntab, double umin, double du,
+                         const double *tabA, const double *tabR, const double *f,
+                         double *C, double *A, double *R, double *tmp)
+{
+    size_t n3 = (size_t)n * n * n, n2 = (size_t)n * n;
+    if (ntab <= 0) {
+        or_comoving_tensors(n, q, u, mass, gdof, m2, quad, nmu, A, R);
+        or_collision_ar(n, 1, A, R, f, NULL, NULL, C);
+        return;
+    }
+    double s = (u - umin) / du;
+    int j = (int)floor(s);
+    if (j < 0) j = 0;
+    if (j > ntab - 2) j = ntab - 2;
+    double w = s - j;
+    or_collision_ar(n, 1, tabA + (size_t)j * n3, tabR + (size_t)j * n2, f, NULL, NULL, C);
+    or_collision_ar(n, 1, tabA + (size_t)(j + 1) * n3, tabR + (size_t)(j + 1) * n2, f, NULL, NULL, tmp);
+    for (int i = 0; i < n; ++i)
+        C[i] = (1.0 - w) * C[i] + w * tmp[i];
+}
+
+/* Projected comoving operator at u: C_raw, then the projection with the  */
+/* moment weights h and energies E of the grid q / a.                       */
+void or_comoving_collision(int n, const double *q, double u, double mass, double gdof,
+                           double m2, int quad, int nmu, int ntab, double umin, double du,
+                           const double *tabA, const double *tabR, const double *f,
+                           int project, double *C)
+{
+    size_t n3 = (size_t)n * n * n;
+    double *A = ntab <= 0 ? malloc(sizeof(double) * n3) : NULL;
+    double *R = ntab <= 0 ? malloc(sizeof(double) * n * n) : NULL;
+    double *tmp = malloc(sizeof(double) * n), *raw = malloc(sizeof(double) * n);
+    double *p = malloc(sizeof(double) * n), *dp = malloc(sizeof(double) * n);
+    double *E = malloc(sizeof(double) * n), *K = malloc(sizeof(double) * n);
+    double *h = malloc(sizeof(double) * n);
+    comoving_raw(n, q, u, mass, gdof, m2, quad, nmu, ntab, umin, du, tabA, tabR, f, raw, A, R, tmp);
+    if (project) {
+        double a = exp(u);
+        for (int i = 0; i < n; ++i)
+            p[i] = q[i] / a;
+        or_grid(n, p, mass, NULL, dp, E, K, h);
+        or_project(n, h, E, f, raw, 1e-12, C, NULL);
+    } else {
+        memcpy(C, raw, sizeof(double) * n);
+    }
+    free(A); free(R); free(tmp); free(raw); free(p); free(dp); free(E); free(K); free(h);
+}
+
+/* Adaptive (or replayed) Heun in u = ln a on the comoving grid, the state */
+/* f itself (no drift term: q is fixed), dx/du = lambda C[f](u) / H(u),    */
+/* H = H_i e^{-2u}; the controller of or_heun.  Returns the accepted steps, */
+/* their (u, dt) in acc_u / acc_dt, rejections in *nrejected.               */
+int or_heun_comoving(int n, const double *q, double mass, double gdof, double m2,
+                     int quad, int nmu, int ntab, double umin, double du,
+                     const double *tabA, const double *tabR, double *x, int project,
+                     double lambda, double Hi, double u0, double u_end, double dt0,
+                     double rtol, double atol, double safety, double fmin, double fmax,
+                     int max_steps, int nreplay, const double *replay_dt, double *acc_u,
+                     double *acc_dt, int *nrejected)
+{
+    double *k1 = malloc(sizeof(double) * n), *k2 = malloc(sizeof(double) * n);
+    double *xs = malloc(sizeof(double) * n), *xn = malloc(sizeof(double) * n);
+    double u = u0, dt = dt0;
+    int acc = 0, rej = 0;
+    int limit = nreplay > 0 ? nreplay : max_steps;
+    while (acc < limit) {
+        if (nreplay > 0) {
+            dt = replay_dt[acc];
+        } else {
+            if (!(u < u_end))
+                break;
+            if (u + dt > u_end)
+                dt = u_end - u;
+        }
+        or_comoving_collision(n, q, u, mass, gdof, m2, quad, nmu, ntab, umin, du, tabA, tabR,
+                              x, project, k1);
+        double H = Hi * exp(-2.0 * u);
+        for (int i = 0; i < n; ++i) {
+            k1[i] *= lambda / H;
+            xs[i] = x[i] + dt * k1[i];
+        }
+        or_comoving_collision(n, q, u + dt, mass, gdof, m2, quad, nmu, ntab, umin, du, tabA,
+                              tabR, xs, project, k2);
+        double H2 = Hi * exp(-2.0 * (u + dt));
+        double err = 0.0;
+        for (int i = 0; i < n; ++i) {
+            k2[i] *= lambda / H2;
+            xn[i] = x[i] + 0.5 * dt * (k1[i] + k2[i]);
+            double sc = atol + rtol * (fabs(x[i]) > fabs(xn[i]) ? fabs(x[i]) : fabs(xn[i]));
+            double e = fabs(xn[i] - xs[i]) / sc;
+            if (e > err)
+                err = e;
+        }
+        if (nreplay > 0 || err <= 1.0) {
+            if (acc_u) acc_u[acc] = u;
+            if (acc_dt) acc_dt[acc] = dt;
+            u += dt;
+            memcpy(x, xn, sizeof(double) * n);
+            ++acc;
+        } else {
+            ++rej;
+        }
+        if (nreplay == 0) {
+            double fac = err > 0.0 ? safety / sqrt(err) : fmax;
+            if (fac < fmin) fac = fmin;
+            if (fac > fmax) fac = fmax;
+            dt *= fac;
+        }
+    }
+    if (nrejected) *nrejected = rej;
+    free(k1); free(k2); free(xs); free(xn);
+    return acc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Thread count of the OpenMP loops (timing of the oracle only).            */
 /* ------------------------------------------------------------------------ */
 void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

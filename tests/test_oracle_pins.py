@@ -640,3 +640,57 @@ def test_freeze_in_with_collisions_conserves_total_number():
     assert r["n_src"] > 0 and len(r["u"]) > 0 and abs(r["u"][-1] + r["dt"][-1] - 1.0) < 1e-12
     inv = np.sum(V * r["x"]) + r["outflow"] + 2 * oracle.condensate_a3nu(N0, Gam, Hi, 1.0)
     assert abs(inv - 2 * N0) < 1e-7 * 2 * N0, inv - 2 * N0
+
+
+# --------------------------------------------------------------------------
+# The comoving grid of Sec. 4.1 (q = a p fixed, the operator of the grid
+# q / a at each a): scaling limits, the tabulated reading, conservation.
+def test_comoving_operator_scaling_limits():
+    """For fixed f on the q grid the operator scales as a^-1 when the
+    particles are massless (every weight is homogeneous of degree -1 in the
+    momenta and the cut pattern is scale free) and as a^-4 when they are
+    non-relativistic (E = m, K = p^2 / 2m)."""
+    for mass, lo, hi, power in ((1e-7, 1e-2, 10.0, 1), (1.0, 1e-6, 1e-4, 4)):
+        q = inputs.log_grid(24, lo, hi)
+        f = inputs.bump_pair(q, np.sqrt(lo * hi) / 3, np.sqrt(lo * hi) * 3, 1.0, 0.5, 0.3, 0.3)
+        c = oracle.Comoving(q, mass=mass)
+        C0 = c.collision(f, 0.0, project=False)
+        for u in (0.3, 1.0):
+            Cu = c.collision(f, u, project=False)
+            assert np.max(np.abs(Cu * np.exp(power * u) - C0)) <= 1e-8 * np.max(np.abs(C0)), (mass, u)
+
+
+def test_comoving_tabulation_is_exact_at_nodes_and_first_order_between():
+    """Tabulating the tensors over u = ln a reproduces the exact operator at
+    the nodes, but between nodes converges only at first order: the grid
+    range cuts switch entries of A on and off as a changes, so A(a) jumps.
+    (This is why the evolution keeps the fixed physical grid with drift.)"""
+    q = inputs.log_grid(24, 1e-2, 10.0)
+    f = inputs.bump_pair(q, 0.2, 2.0, 1.0, 0.5, 0.3, 0.3)
+    ex = oracle.Comoving(q)
+    us = np.linspace(0.013, 0.987, 11)
+    refs = [ex.collision(f, u) for u in us]
+    errs = []
+    for J in (5, 17, 33):
+        t = oracle.Comoving(q, ntab=J, umin=0.0, umax=1.0)
+        for j in (0, J // 2, J - 1):
+            assert np.array_equal(t.collision(f, j * t.du), ex.collision(f, j * t.du))
+        errs.append(max(np.max(np.abs(t.collision(f, u) - r)) / np.max(np.abs(r))
+                        for u, r in zip(us, refs)))
+    assert errs[0] > errs[1] > errs[2] > 5e-3, errs
+
+
+def test_comoving_heun_conserves_comoving_number():
+    """a^3 sum_i h_i(a) f_i = sum_i q_i^2 dq_i f_i is constant along the
+    comoving evolution: every stage of the projected operator conserves the
+    number moment of its own grid, and h(a) = q^2 dq / a^3."""
+    q = inputs.log_grid(24, 1e-2, 10.0)
+    f0 = inputs.bump_pair(q, 0.2, 2.0, 1.0, 0.5, 0.3, 0.3)
+    c = oracle.Comoving(q)
+    g = c.grid(0.0)
+    w = g.h                     # q^2 dq at a = 1
+    Hi = oracle.Operator(q).gamma0(f0)       # time in units of the initial loss rate
+    r = c.heun(f0, 2.0, Hi, 0.2, 1e-3, max_steps=5000)
+    assert len(r["u"]) > 5 and abs(r["u"][-1] + r["dt"][-1] - 0.2) < 1e-12
+    assert abs(np.sum(w * r["x"]) / np.sum(w * f0) - 1.0) < 1e-12
+    assert np.max(np.abs(r["x"] - f0)) > 1e-3 * np.max(f0)       # it did evolve
