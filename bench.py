@@ -56,14 +56,15 @@ def parse():
                     help="time the oracle's 16-solve subsamples in full (minutes) instead of "
                          "extrapolating from a bounded part of each")
     ap.add_argument("--profile-run", nargs="?", const="gemm", default=None,
-                    choices=("gemm", "stream384", "streamx384", "x3"),
+                    choices=("gemm", "stream384", "streamx384", "x3", "serve"),
                     help="short run for profilers: 'gemm' = the timed RK4 steps, the plain "
                          "FP64 path and a 1 GiB device copy (the calibration kernel); "
                          "'stream384' = 50 plain FP64 evaluations at N = 384 and the copy; "
                          "'streamx384' = 50 exact-form evaluations (Bose-Einstein, log "
                          "interpolation) at N = 384 in FP64 and in FP32, and the copy; "
                          "'x3' = --steps 16-bit RK4 steps (BF16x3, then FP16x3) at N = 256, "
-                         "B = 4096 and the copy")
+                         "B = 4096 and the copy; 'serve' = 300 requests of the serving "
+                         "workload at 60 req/s")
     return ap.parse_args()
 
 
@@ -485,6 +486,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": "streamx384", "evals": 50}), flush=True)
+        return
+    if args.profile_run == "serve":
+        # the serving loop under a moderate load: 60 req/s, 300 requests
+        from paper_2607_00755_amd import serving
+        reqs = inputs.serving_requests(300, rate=60.0)
+        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16)
+        done = srv.run(reqs)
+        st = srv.stats(done, warm=50)
+        print(json.dumps({"profile_run": "serve", "p50_s": st["p50_s"], "p99_s": st["p99_s"],
+                          "completed": st["completed"]}), flush=True)
         return
     if args.profile_run == "x3":
         # the 16-bit workload: N = 256, B = 4096 RK4 steps in BF16x3 and FP16x3
