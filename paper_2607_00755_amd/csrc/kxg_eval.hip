@@ -27,6 +27,7 @@
 namespace kxg {
 namespace {
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x8 __attribute__((ext_vector_type(8)));
 
@@ -421,17 +422,19 @@ __global__ __launch_bounds__(256) void k_rate(RateArgs ra)
 // the workgroup stages the hi/lo fragments of its i-blocks for one
 // super-step (IBW*SS*2 KB) into one of two LDS slots, each thread carrying
 // IBW*SS/2 16-byte vectors through registers.  Two register stages (the
-// vectors in transit, f_k and f_m of the super-step) alternate without
-// copies: the global loads of super-step s+1 are in flight while the MFMAs
-// of super-step s run, and are written to the other LDS slot after them;
-// one barrier per super-step.  Every wave forms and splits its F2 operand
-// once per (b-block, dk) and feeds it to 3*IBW MFMAs.  Partials: one per K
-// split.
+// vectors in transit and f_k of the super-step) alternate without copies:
+// the global loads of super-step s+1 are in flight while the MFMAs of
+// super-step s run, and are written to the other LDS slot after them; one
+// barrier per super-step.  f_m is the same for the kBlk/SS super-steps of a
+// (kb, mb) pair: it is loaded once per pair, a pair ahead, and kept in one
+// of two wave-private LDS sets chosen by the pair's parity (registers can't
+// be chosen at run time without copies).  Every wave forms and splits its F2
+// operand once per (b-block, dk) and feeds it to 3*IBW MFMAs.  Partials:
+// one per K split.
 template <int BBW, int SS, int NQ>
 struct X3Stage {
     u32x4 gv[NQ];              // packed-tensor vectors in transit to LDS
     float fk[BBW][SS];         // f_k per b-block and dk step
-    float4 fm[BBW][2];         // f_m (the 8 values of this lane's K half)
 };
 
 template <int BBW, int IBW, int SS, bool F16, int SPLIT = 3>
@@ -444,11 +447,16 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
     typedef float fkvec __attribute__((ext_vector_type(SS)));
     constexpr int VPS = SS * 128;                  // 16-byte vectors per i-block and super-step
     constexpr int NV = IBW * VPS;                  // per super-step
-    constexpr int NQ = NV / 256;                   // per thread
+    // SPLIT < 3 never reads the lo halves of the tensor: only the hi vectors
+    // (64 of each step's 128) are loaded and staged.
+    constexpr int HALF = SPLIT == 3 ? 1 : 2;
+    constexpr int NQ = NV / HALF / 256;            // loaded vectors per thread
     constexpr int PPS = kBlk / SS;                 // super-steps per (kb, mb) pair
-    static_assert(NV % 256 == 0, "a super-step must split evenly over 256 threads");
+    static_assert(NV % (256 * HALF) == 0, "a super-step must split evenly over 256 threads");
+    static_assert(PPS >= 2, "f_m is prefetched on the second super-step of a pair");
     typedef X3Stage<BBW, SS, NQ> Stage;
     __shared__ u32x4 sA[2][NV];
+    __shared__ floatx4 sF[2][4][BBW][2][64];        // f_m: parity set, wave, b-block, half, lane
     const int L = xcd_logical(blockIdx.x, gridDim.x);
     const int bt = L % nbt, u = L / nbt;
     // work unit: group of IBW i-blocks, K slot and range of (compacted) super-steps
@@ -463,14 +471,19 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
     const float *fkb = fop + (long)(brow0 + r) * kBlk;
     const float *fmb = fop + (long)(brow0 + r) * kBlk + 8 * hb;
     // loader role: vector q = threadIdx.x + 256 c of a super-step belongs to
-    // i-block q / VPS of the group; block c of the compacted operand holds
-    // IBW * 16 * 128 vectors.  The lane offsets are 32-bit and added to a
-    // uniform base per stage (scalar base, no 64-bit address arithmetic).
-    int qoff[NQ];
+    // i-block q / VPS of the group (q / (VPS / 2) when only hi vectors are
+    // loaded: step (q / 64) of the i-block's super-step, lane q % 64); block
+    // c of the compacted operand holds IBW * 16 * 128 vectors.  The lane
+    // offsets are 32-bit and added to a uniform base per stage (scalar base,
+    // no 64-bit address arithmetic); qlds is the vector's LDS slot index.
+    int qoff[NQ], qlds[NQ];
 #pragma unroll
     for (int c = 0; c < NQ; ++c) {
         const int q = threadIdx.x + 256 * c;
-        qoff[c] = (q / VPS) * kBlk * 128 + (q % VPS);
+        const int w = HALF == 1 ? q % VPS : (q % (VPS / 2)) / 64 * 128 + q % 64;
+        const int ib = HALF == 1 ? q / VPS : q / (VPS / 2);
+        qoff[c] = ib * kBlk * 128 + w;
+        qlds[c] = ib * VPS + w;
     }
 
     floatx16 acc[BBW][IBW];
@@ -482,6 +495,32 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
             for (int e = 0; e < 16; ++e) acc[bb][ib][e] = 0.0f;
 
     Stage sa, sb;
+    // f_m of pair pr (this lane's K half of each b-block's m values)
+    auto load_fm = [&](int pr, floatx4 (&dst)[BBW][2]) {
+        const int mb = pairs[2 * pr + 1];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb) {
+            const floatx4 *src = reinterpret_cast<const floatx4 *>(fmb + mb * bstride + bb * 32 * kBlk);
+            dst[bb][0] = src[0];
+            dst[bb][1] = src[1];
+        }
+    };
+    auto put_fm = [&](int set, const floatx4 (&v)[BBW][2]) {
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) sF[set][wave][bb][j][lane] = v[bb][j];
+    };
+    // f_m of the pair after that of super-step t is due when t is the second
+    // super-step of a pair past the unit's first: loaded with t's stage,
+    // written to the LDS set of its parity after the MFMAs of t - 1 (the
+    // first super-step of t's pair, which reads the other set); the set it
+    // overwrites was last read by the pair before t's.  The first two pairs
+    // of the unit are loaded before the loop.
+    auto fm_due = [&](long t) {
+        return t % PPS == 1 && t / PPS > s0 / PPS && (t / PPS + 1) * PPS < s1;
+    };
+    floatx4 fmt[BBW][2];
     auto load_stage = [&](long s, Stage &x) {
         s = s < s1 ? s : s1 - 1;
         const long cb = s / PPS, d0 = (s % PPS) * SS;   // block, first dk step
@@ -489,23 +528,20 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
 #pragma unroll
         for (int c = 0; c < NQ; ++c) x.gv[c] = Gs[qoff[c]];
         const int pr = (int)(s / PPS);
-        const int kb = pairs[2 * pr], mb = pairs[2 * pr + 1];
+        const int kb = pairs[2 * pr];
         const int dk = (int)(s % PPS) * SS;
 #pragma unroll
         for (int bb = 0; bb < BBW; ++bb) {
             const fkvec v = *reinterpret_cast<const fkvec *>(fkb + kb * bstride + bb * 32 * kBlk + dk);
 #pragma unroll
             for (int d = 0; d < SS; ++d) x.fk[bb][d] = v[d];
-            const float4 *src = reinterpret_cast<const float4 *>(fmb + mb * bstride + bb * 32 * kBlk);
-            x.fm[bb][0] = src[0];
-            x.fm[bb][1] = src[1];
         }
     };
     auto stash = [&](int slot, const Stage &x) {
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) sA[slot][threadIdx.x + 256 * c] = x.gv[c];
+        for (int c = 0; c < NQ; ++c) sA[slot][qlds[c]] = x.gv[c];
     };
-    auto compute = [&](int slot, const Stage &x) {
+    auto compute_fm = [&](int slot, const Stage &x, const floatx4 (&fmr)[BBW][2]) {
 #pragma unroll
         for (int d = 0; d < SS; ++d) {
             opx8 Ah[IBW], Al[IBW];
@@ -521,7 +557,9 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
                 // BF16: hi is the product with its low 16 bits cleared (exact
                 // in BF16, no conversion), lo = product - hi is exact in FP32
                 // and rounded to BF16; FP16: hi rounded, lo = product - hi.
-                const float4 m0 = x.fm[bb][0], m1 = x.fm[bb][1];
+                // (FP16 results straight from fused multiply-adds take fewer
+                // instructions but ran slower: each writes half a register.)
+                const floatx4 m0 = fmr[bb][0], m1 = fmr[bb][1];
                 const floatx8 fmv = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
                 const floatx8 pv = x.fk[bb][d] * fmv;
                 opx8 ph, pl;
@@ -559,32 +597,57 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
         }
     };
 
-    // Pairs of super-steps with no exit between them (a conditional exit
-    // would let the compiler sink the prefetch below it); an odd last one is
-    // done after the loop from stage a and slot 0, which then hold it.
+    // super-step s with the f_m set of its pair
+    auto compute = [&](int slot, const Stage &x, long s) {
+        const int set = (int)((s / PPS) & 1);
+        floatx4 cur[BBW][2];
+#pragma unroll
+        for (int bb = 0; bb < BBW; ++bb)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) cur[bb][j] = sF[set][wave][bb][j][lane];
+        compute_fm(slot, x, cur);
+    };
+
+    // One super-step of the pipeline: the loads of super-step t = cs + 1 go
+    // out into stage ld, super-step cs is computed from stage cx and LDS slot
+    // cslot, then stage sx (super-step cs + 1) goes to the other slot; one
+    // barrier.
+    auto step = [&](long t, Stage &ld, int cslot, const Stage &cx, long cs, int sslot, const Stage &sx) {
+        // (f_m first: its wait before put_fm then leaves stage t's loads in flight)
+        const bool f = fm_due(t);
+        if (f) load_fm((int)(t / PPS) + 1, fmt);
+        load_stage(t, ld);
+        __builtin_amdgcn_sched_barrier(0);      // keep the prefetch ahead of the MFMAs
+        compute(cslot, cx, cs);
+        __builtin_amdgcn_sched_barrier(0);
+        stash(sslot, sx);
+        if (f) put_fm((int)((t / PPS + 1) & 1), fmt);
+        __syncthreads();
+    };
+
     if (s0 < s1) {
+        const int p0 = (int)(s0 / PPS);
         load_stage(s0, sa);
+        load_fm(p0, fmt);
+        put_fm(p0 & 1, fmt);
+        if ((long)(p0 + 1) * PPS < s1) {
+            load_fm(p0 + 1, fmt);
+            put_fm((p0 + 1) & 1, fmt);
+        }
         stash(0, sa);
     }
     __syncthreads();
     long s = s0;
-    // (the tensor pointer is not restrict-qualified: loads through it are
-    // then not moved down to their use in stash)
+    // Pairs of super-steps with no exit between them (a conditional exit
+    // would let the compiler sink the prefetch below it); an odd last one is
+    // done after the loop from stage a and slot 0, which then hold it.  (The
+    // tensor pointer is not restrict-qualified: loads through it are then not
+    // moved down to their use in stash.)
     for (; s + 1 < s1; s += 2) {
-        load_stage(s + 1, sb);
-        __builtin_amdgcn_sched_barrier(0);      // keep the prefetch ahead of the MFMAs
-        compute(0, sa);
-        __builtin_amdgcn_sched_barrier(0);
-        stash(1, sb);
-        __syncthreads();
-        load_stage(s + 2, sa);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(1, sb);
-        __builtin_amdgcn_sched_barrier(0);
-        stash(0, sa);
-        __syncthreads();
+        step(s + 1, sb, 0, sa, s, 1, sb);
+        step(s + 2, sa, 1, sb, s + 1, 0, sa);
     }
-    if (s < s1) compute(0, sa);
+    if (s < s1) compute(0, sa, s);
     float *dst = part + (long)sp * bpad * ipad;
 #pragma unroll
     for (int ib = 0; ib < IBW; ++ib) {

@@ -589,8 +589,8 @@ def test_split_ablations_lose_accuracy(dev, prec):
 
 @pytest.mark.parametrize("prec", SIXTEEN)
 def test_eval_16bit_large_batch_lds_path(dev, prec):
-    """B >= 512 takes the LDS-shared GEMM: ragged batch (600 -> 1024 rows) and
-    a ragged i-tile (n = 80: 3 blocks of 32 in tiles of 2)."""
+    """The LDS-shared GEMM at a large ragged batch (600 -> 1024 rows) and a
+    ragged i-tile (n = 80: 3 blocks of 32 in a group of 4)."""
     n = 80
     p = inputs.log_grid(n, 1e-3, 20.0)
     f0 = batch(p, 600, seed=14)
@@ -604,6 +604,26 @@ def test_eval_16bit_large_batch_lds_path(dev, prec):
     for b in (0, 31, 32, 255, 511, 512, 599):
         assert rel(C[b], oracle_C(op, f0[b:b + 1], True)[0]) <= TOL[prec], b
     assert np.array_equal(sub, C[:520])
+
+
+@pytest.mark.parametrize("prec", (kxg.F16X2, kxg.F16X3))
+@pytest.mark.parametrize("n", [48, 112, 176])
+def test_eval_16bit_lds_path_grid_sizes(dev, prec, n):
+    """The LDS-shared GEMM over grid sizes whose work units differ in length
+    (every remainder of the prefetch rotation and of the (kb, mb) pairs
+    occurs among them): sampled rows of a ragged 520-row batch against the
+    oracle."""
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    f0 = batch(p, 520, seed=21 + n)
+    k = kxg.Kernel(p, precs=(prec,), b_cap=520)
+    C, _ = k.eval(torch.tensor(f0, device=dev), prec=prec, project=True)
+    torch.cuda.synchronize()
+    C = C.cpu().numpy()
+    op = oracle.Operator(p)
+    rows = (0, 63, 64, 300, 511, 519)
+    ref = oracle_C(op, f0[list(rows)], True)
+    for j, b in enumerate(rows):
+        assert rel(C[b], ref[j]) <= TOL[prec], (n, b)
 
 
 # ---------------------------------------------------------------- exact forms
