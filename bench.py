@@ -665,7 +665,8 @@ def main():
             g_us = 1e3 * g_ms / max(g_n, 1)
             # algorithmic work per GEMM: one product over the non-zero packed
             # entries; executed: the split products (3, or 2 for FP16 x2) over
-            # the kept blocks
+            # the blocks multiplied (the group's i-blocks up to the last
+            # non-zero one of each kept pair)
             fa = 2.0 * 4096 * info4["nnz_packed"]
             fl = (2 if prec == kxg.F16X2 else 3) * 2.0 * 4096 * 32 * 256 * blocks16
             extras[name + "_b4096"] = {
@@ -677,7 +678,7 @@ def main():
                 "executed_mfma_frac": round(fl / (g_us * 1e-6) / 1e12 / PEAK["bf16"], 4),
                 "executed_frac_of_measured": (round(fl / (g_us * 1e-6) / 1e12 / peaks["mfma_bf16_tflops"], 4)
                                               if peaks else None),
-                "blocks": blocks16,
+                "blocks": blocks16, "blocks_staged": info4["staged16"],
                 "traffic": (counted_traffic("gemm_x3_n256_b4096.md", GEMM_X3_SOURCES)
                             if prec == kxg.BF16X3 else None)}
             log("%s B=4096 RK4: %.3f ms/step, gemm %.1f us" % (name, 1e3 * wl, g_us))

@@ -140,9 +140,11 @@ typedef struct {
     int64_t nonzero_blocks;   /* blocks kept in the FP32 operand (0 if no FP32) */
     int32_t gemm_units;       /* FP32 GEMM work units (K ranges) per batch tile */
     int32_t max_slots;        /* most K partials of an i-block                  */
-    int64_t blocks16;         /* (i-block, pair) blocks the 16-bit GEMM runs over:
-                                 the union of the non-zero pairs of each group of
-                                 i-blocks a workgroup covers (0 if no 16-bit) */
+    int64_t blocks16;         /* (i-block, pair) blocks the 16-bit GEMM multiplies:
+                                 the non-zero blocks of the pairs it keeps for
+                                 each group of i-blocks a workgroup covers (the
+                                 group's all-zero blocks are skipped; 0 if no
+                                 16-bit) */
     int64_t nnz_packed;       /* entries (i, k <= m) of the symmetric packing of
                                  A'[i,k,m] = A[i,k,m] - delta_ik R[i,m]
                                  (A'_ikm + A'_imk for k < m) that carry a weight
@@ -151,6 +153,10 @@ typedef struct {
                                  not move it): the contraction's own work is 2
                                  flops per entry and distribution (0 on handles
                                  without a GEMM precision) */
+    int64_t staged16;         /* (i-block, pair) blocks of the 16-bit operand:
+                                 every i-block of the group for each pair kept
+                                 (the union over the group); they are streamed
+                                 through LDS whether multiplied or not */
 } kxg_kernel_info;
 
 /* Fill *out for handle k.  Errors: KXG_EINVAL (null argument). */

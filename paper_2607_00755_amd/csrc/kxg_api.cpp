@@ -70,7 +70,7 @@ static void release(kxg_kernel *k)
     void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_R, k->d_A32,
                     k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs, k->d_JL, k->d_invdK,
                     k->d_pairs_c, k->d_cib, k->d_units, k->d_pairs16, k->d_cit16,
-                    k->d_units16};
+                    k->d_units16, k->d_act16};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     free_workspace(k->ws);
@@ -144,9 +144,10 @@ static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want32, bool want
     if (e != hipSuccess) { set_error("kxg_kernel_build: %s", hipGetErrorString(e)); return KXG_EHIP; }
     k->nnz_packed = 0;
     for (unsigned int c : nnz) k->nnz_packed += c;
-    // kept pairs of a group of i-blocks [ib0, ib0 + w)
+    // kept pairs of a group of i-blocks [ib0, ib0 + w), with the mask of
+    // the group's non-zero i-blocks in each
     auto compact = [&](int w, std::vector<int> &pairs_c, std::vector<int> &cgrp, std::vector<int> &cnt,
-                       std::vector<int> &first) {
+                       std::vector<int> &first, std::vector<int> &mask) {
         const int ng = div_up(g.nib, w);
         cnt.assign(ng, 0);
         first.assign(ng, 0);
@@ -155,20 +156,21 @@ static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want32, bool want
             int pr = 0;
             for (int kb = 0; kb < g.nb; ++kb)
                 for (int mb = kb; mb < g.nb; ++mb, ++pr) {
-                    bool any = false;
+                    int bits = 0;
                     for (int ib = q * w; ib < std::min(g.nib, (q + 1) * w); ++ib)
-                        any = any || flags[(size_t)ib * g.npairs + pr];
-                    if (!any) continue;
+                        if (flags[(size_t)ib * g.npairs + pr]) bits |= 1 << (ib - q * w);
+                    if (!bits) continue;
                     pairs_c.push_back(kb);
                     pairs_c.push_back(mb);
                     cgrp.push_back(q);
+                    mask.push_back(bits);
                     ++cnt[q];
                 }
         }
     };
     if (want32) {
-        std::vector<int> pairs_c, cib, cnt, first;
-        compact(1, pairs_c, cib, cnt, first);
+        std::vector<int> pairs_c, cib, cnt, first, mask;
+        compact(1, pairs_c, cib, cnt, first, mask);
         k->ncomp = (long)cib.size();
         const int bbw = b_cap <= 32 ? 1 : (b_cap <= 64 ? 2 : 4);
         const Units U = make_units(cnt, first, kBlk / kF32SS, div_up(b_cap, 32 * bbw), KXG_GEMM_WG_TARGET);
@@ -187,11 +189,40 @@ static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want32, bool want
     }
     if (e == hipSuccess && (wantbf || wanth)) {
         constexpr int w = KXG_LDS_IBW;
-        std::vector<int> pairs_c, cit, cnt, first;
-        compact(w, pairs_c, cit, cnt, first);
+        std::vector<int> pairs_c, cit, cnt, first, mask;
+        compact(w, pairs_c, cit, cnt, first, mask);
         k->ncomp16 = (long)cit.size();
-        const Units U = make_units(cnt, first, kBlk / KXG_LDS_SS, div_up(b_cap, 4 * KXG_LDS_BBW * 32),
-                                   KXG_LDS_WG_TARGET);
+        // The non-zero i-blocks of a kept pair are, but for a handful, the
+        // first few of its group (the kinematic cuts empty the blocks of
+        // large i first).  Each pair gets the count of i-blocks up to its
+        // last non-zero one, the GEMM multiplies only those, and the pairs of
+        // a group are reordered by that count (descending, stable) so that
+        // work units can run with a fixed count each.
+        std::vector<int> act(mask.size());
+        for (size_t c = 0; c < mask.size(); ++c) act[c] = 32 - __builtin_clz((unsigned)mask[c]);
+        k->mult16 = 0;
+        for (size_t q = 0; q < cnt.size(); ++q) {
+            const int f = first[q];
+            std::vector<int> ord(cnt[q]);
+            for (int j = 0; j < cnt[q]; ++j) ord[j] = f + j;
+            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return act[x] > act[y]; });
+            std::vector<int> pc(2 * cnt[q]), ac(cnt[q]);
+            for (int j = 0; j < cnt[q]; ++j) {
+                pc[2 * j] = pairs_c[2 * ord[j]];
+                pc[2 * j + 1] = pairs_c[2 * ord[j] + 1];
+                ac[j] = act[ord[j]];
+            }
+            std::copy(pc.begin(), pc.end(), pairs_c.begin() + 2 * f);
+            std::copy(ac.begin(), ac.end(), act.begin() + f);
+            for (int j = f; j < f + cnt[q]; ++j) k->mult16 += act[j];
+        }
+        // A unit runs with the count of its first (largest) pair; a
+        // super-step costs the staging and the F2 split (KXG_LDS_STEP_COST
+        // blocks' worth of MFMA time) plus one per block multiplied.
+        std::vector<double> wcost(act.size());
+        for (size_t c = 0; c < act.size(); ++c) wcost[c] = KXG_LDS_STEP_COST + act[c];
+        const Units U = make_units_cost(cnt, first, wcost, kBlk / KXG_LDS_SS,
+                                        div_up(b_cap, 4 * KXG_LDS_BBW * 32), KXG_LDS_WG_TARGET);
         k->nunits16 = (int)(U.units.size() / 4);
         k->maxslots16 = U.maxslots;
         std::vector<int> nslot_ib(g.nib, 0);
@@ -202,8 +233,10 @@ static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want32, bool want
         if (st == KXG_OK) st = dalloc(&k->d_pairs16, std::max<size_t>(2, pairs_c.size()));
         if (st == KXG_OK) st = dalloc(&k->d_cit16, std::max<size_t>(1, cit.size()));
         if (st == KXG_OK) st = dalloc(&k->d_units16, std::max<size_t>(4, U.units.size()));
+        if (st == KXG_OK) st = dalloc(&k->d_act16, std::max<size_t>(1, act.size()));
         if (st != KXG_OK) return st;
         e = h2d(k->d_pairs16, pairs_c);
+        if (e == hipSuccess) e = h2d(k->d_act16, act);
         if (e == hipSuccess) e = h2d(k->d_cit16, cit);
         if (e == hipSuccess) e = h2d(k->d_units16, U.units);
         k->nslot16 = pack_slot_counts(nslot_ib);
@@ -485,7 +518,8 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     const size_t packed16 = (size_t)k->ncomp16 * KXG_LDS_IBW * kBlk * 1024;   // hi + lo values
     if (wantbf) k->bytes[KXG_BF16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
     if (prec_mask & KXG_PREC_BIT(KXG_F16X3)) k->bytes[KXG_F16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
-    if (prec_mask & KXG_PREC_BIT(KXG_F16X2)) k->bytes[KXG_F16X2] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
+    // (FP16 x2 reads the hi halves only)
+    if (prec_mask & KXG_PREC_BIT(KXG_F16X2)) k->bytes[KXG_F16X2] = packed16 / 2 * sizeof(uint16_t) + n2 * sizeof(double);
     // everything the handle holds on the device
     const size_t fbytes = (size_t)k->geo.nb * k->ws.bpad_cap * kBlk * sizeof(float);
     k->held = 5 * (size_t)n * sizeof(double) + 2 * n2 * sizeof(double) + 2 * (size_t)g.npairs * sizeof(int) +
@@ -518,7 +552,8 @@ kxg_status kxg_kernel_stats(const kxg_kernel *k, kxg_kernel_info *out)
     out->nonzero_blocks = k->d_G32 ? k->ncomp : 0;
     out->gemm_units = k->nunits;
     out->max_slots = k->maxslots;
-    out->blocks16 = (k->d_Gbf || k->d_Gh) ? k->ncomp16 * KXG_LDS_IBW : 0;
+    out->blocks16 = (k->d_Gbf || k->d_Gh) ? k->mult16 : 0;
+    out->staged16 = (k->d_Gbf || k->d_Gh) ? k->ncomp16 * KXG_LDS_IBW : 0;
     out->nnz_packed = (k->d_G32 || k->d_Gbf || k->d_Gh) ? k->nnz_packed : 0;
     return KXG_OK;
 }

@@ -429,39 +429,42 @@ __global__ __launch_bounds__(256) void k_rate(RateArgs ra)
 // (kb, mb) pair: it is loaded once per pair, a pair ahead, and kept in one
 // of two wave-private LDS sets chosen by the pair's parity (registers can't
 // be chosen at run time without copies).  Every wave forms and splits its F2
-// operand once per (b-block, dk) and feeds it to 3*IBW MFMAs.  Partials:
-// one per K split.
+// operand once per (b-block, dk) and feeds it to 3*IBW MFMAs.  The kept
+// pairs of a unit all have their non-zero blocks in the group's first IBA
+// i-blocks (IBA of its first pair, the pairs of a group being ordered by
+// that count): only those are staged and multiplied, the others' partials
+// are written as zeros.  Partials: one per K split.
 template <int BBW, int SS, int NQ>
 struct X3Stage {
     u32x4 gv[NQ];              // packed-tensor vectors in transit to LDS
     float fk[BBW][SS];         // f_k per b-block and dk step
 };
 
-template <int BBW, int IBW, int SS, bool F16, int SPLIT = 3>
-__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_gemm_x3_lds(
-    const uint16_t *G, const float *__restrict__ fop, const int *__restrict__ pairs,
-    const int *__restrict__ units, int nib, int bpad, int ipad, int nbt,
-    float *__restrict__ part)
+template <int IBW, int SS, int SPLIT>
+struct X3Shape {
+    static constexpr int VPS = SS * 128;           // 16-byte vectors per i-block and super-step
+    static constexpr int NV = IBW * VPS;           // per super-step
+    // SPLIT < 3 never reads the lo halves of the tensor: only the hi vectors
+    // (64 of each step's 128) are loaded and staged.
+    static constexpr int HALF = SPLIT == 3 ? 1 : 2;
+    static constexpr int NQ = NV / HALF / 256;     // loaded vectors per thread
+    static constexpr int PPS = kBlk / SS;          // super-steps per (kb, mb) pair
+};
+
+template <int BBW, int IBW, int SS, bool F16, int SPLIT, int IBA>
+__device__ __forceinline__ void x3_run(
+    const uint16_t *G, const float *__restrict__ fop, const int *__restrict__ pairs, int it, int sp,
+    long s0, long s1, int bt, int nib, int bpad, int ipad, float *__restrict__ part,
+    u32x4 (&sA)[2][X3Shape<IBW, SS, SPLIT>::NV], floatx4 (&sF)[2][4][BBW][2][64])
 {
     typedef typename std::conditional<F16, halfx8, bf16x8>::type opx8;
     typedef float fkvec __attribute__((ext_vector_type(SS)));
-    constexpr int VPS = SS * 128;                  // 16-byte vectors per i-block and super-step
-    constexpr int NV = IBW * VPS;                  // per super-step
-    // SPLIT < 3 never reads the lo halves of the tensor: only the hi vectors
-    // (64 of each step's 128) are loaded and staged.
-    constexpr int HALF = SPLIT == 3 ? 1 : 2;
-    constexpr int NQ = NV / HALF / 256;            // loaded vectors per thread
-    constexpr int PPS = kBlk / SS;                 // super-steps per (kb, mb) pair
+    typedef X3Shape<IBW, SS, SPLIT> Sh;
+    constexpr int VPS = Sh::VPS, NV = Sh::NV, HALF = Sh::HALF, NQ = Sh::NQ, PPS = Sh::PPS;
     static_assert(NV % (256 * HALF) == 0, "a super-step must split evenly over 256 threads");
     static_assert(PPS >= 2, "f_m is prefetched on the second super-step of a pair");
+    static_assert(IBA >= 1 && IBA <= IBW, "active i-blocks");
     typedef X3Stage<BBW, SS, NQ> Stage;
-    __shared__ u32x4 sA[2][NV];
-    __shared__ floatx4 sF[2][4][BBW][2][64];        // f_m: parity set, wave, b-block, half, lane
-    const int L = xcd_logical(blockIdx.x, gridDim.x);
-    const int bt = L % nbt, u = L / nbt;
-    // work unit: group of IBW i-blocks, K slot and range of (compacted) super-steps
-    const int it = units[4 * u], sp = units[4 * u + 1];
-    const long s0 = units[4 * u + 2], s1 = units[4 * u + 3];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int r = lane & 31, hb = lane >> 5;
@@ -473,17 +476,23 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
     // loader role: vector q = threadIdx.x + 256 c of a super-step belongs to
     // i-block q / VPS of the group (q / (VPS / 2) when only hi vectors are
     // loaded: step (q / 64) of the i-block's super-step, lane q % 64); block
-    // c of the compacted operand holds IBW * 16 * 128 vectors.  The lane
-    // offsets are 32-bit and added to a uniform base per stage (scalar base,
-    // no 64-bit address arithmetic); qlds is the vector's LDS slot index.
+    // c of the compacted operand holds IBW * 16 * 128 vectors.  A wave's 64
+    // vectors are consecutive, so everything but the lane is uniform: qoff
+    // and qlds are the wave's offsets into the stage's tensor block and into
+    // an LDS slot, qact whether they belong to one of the IBA multiplied
+    // i-blocks.
+    static_assert((VPS / HALF) % 64 == 0, "a wave's vectors lie in one i-block");
+    const int wv = wave & 3;
     int qoff[NQ], qlds[NQ];
+    bool qact[NQ];
 #pragma unroll
     for (int c = 0; c < NQ; ++c) {
-        const int q = threadIdx.x + 256 * c;
-        const int w = HALF == 1 ? q % VPS : (q % (VPS / 2)) / 64 * 128 + q % 64;
-        const int ib = HALF == 1 ? q / VPS : q / (VPS / 2);
+        const int qw = wv * 64 + 256 * c;
+        const int w = HALF == 1 ? qw % VPS : (qw % (VPS / 2)) / 64 * 128;
+        const int ib = qw / (VPS / HALF);
         qoff[c] = ib * kBlk * 128 + w;
         qlds[c] = ib * VPS + w;
+        qact[c] = ib < IBA;
     }
 
     floatx16 acc[BBW][IBW];
@@ -526,7 +535,8 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
         const long cb = s / PPS, d0 = (s % PPS) * SS;   // block, first dk step
         const u32x4 *Gs = reinterpret_cast<const u32x4 *>(G) + (cb * IBW * kBlk + d0) * 128;
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) x.gv[c] = Gs[qoff[c]];
+        for (int c = 0; c < NQ; ++c)
+            if (qact[c]) x.gv[c] = Gs[qoff[c] + lane];
         const int pr = (int)(s / PPS);
         const int kb = pairs[2 * pr];
         const int dk = (int)(s % PPS) * SS;
@@ -539,14 +549,15 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
     };
     auto stash = [&](int slot, const Stage &x) {
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) sA[slot][qlds[c]] = x.gv[c];
+        for (int c = 0; c < NQ; ++c)
+            if (qact[c]) sA[slot][qlds[c] + lane] = x.gv[c];
     };
     auto compute_fm = [&](int slot, const Stage &x, const floatx4 (&fmr)[BBW][2]) {
 #pragma unroll
         for (int d = 0; d < SS; ++d) {
-            opx8 Ah[IBW], Al[IBW];
+            opx8 Ah[IBA], Al[IBA];
 #pragma unroll
-            for (int ib = 0; ib < IBW; ++ib) {
+            for (int ib = 0; ib < IBA; ++ib) {
                 Ah[ib] = __builtin_bit_cast(opx8, sA[slot][ib * VPS + d * 128 + lane]);
                 Al[ib] = __builtin_bit_cast(opx8, sA[slot][ib * VPS + d * 128 + 64 + lane]);
             }
@@ -580,7 +591,7 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
 #pragma unroll
                 for (int t = 0; t < 3; ++t)
 #pragma unroll
-                    for (int ib = 0; ib < IBW; ++ib) {
+                    for (int ib = 0; ib < IBA; ++ib) {
                         if constexpr (SPLIT == 1) {
                             if (t != 2) continue;
                         } else if constexpr (SPLIT == 2) {
@@ -661,6 +672,38 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
                 dst[(long)row * ipad + col] = acc[bb][ib][e];
             }
     }
+}
+
+// The launch: work unit u = (group of IBW i-blocks, K slot, range of
+// compacted super-steps) with its count of multiplied i-blocks, one copy of
+// the pipeline per count.
+template <int BBW, int IBW, int SS, bool F16, int SPLIT = 3>
+__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_gemm_x3_lds(
+    const uint16_t *G, const float *__restrict__ fop, const int *__restrict__ pairs,
+    const int *__restrict__ act, const int *__restrict__ units, int nib, int bpad, int ipad, int nbt,
+    float *__restrict__ part)
+{
+    static_assert(IBW == 4, "one pipeline per count of multiplied i-blocks, 1 to 4");
+    typedef X3Shape<IBW, SS, SPLIT> Sh;
+    __shared__ u32x4 sA[2][Sh::NV];
+    __shared__ floatx4 sF[2][4][BBW][2][64];        // f_m: parity set, wave, b-block, half, lane
+    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int bt = L % nbt, u = L / nbt;
+    const int it = units[4 * u], sp = units[4 * u + 1];
+    const long s0 = units[4 * u + 2], s1 = units[4 * u + 3];
+    // (the first pair of a unit has the largest count of its pairs)
+    const int na = s0 < s1 ? act[s0 / Sh::PPS] : IBW;
+#define KXG_X3_RUN(A) \
+    x3_run<BBW, IBW, SS, F16, SPLIT, A>(G, fop, pairs, it, sp, s0, s1, bt, nib, bpad, ipad, part, sA, sF)
+    if (na == 1)
+        KXG_X3_RUN(1);
+    else if (na == 2)
+        KXG_X3_RUN(2);
+    else if (na == 3)
+        KXG_X3_RUN(3);
+    else
+        KXG_X3_RUN(4);
+#undef KXG_X3_RUN
 }
 
 // Wave-wide (64-lane) butterfly reductions; every lane ends with the same
@@ -1713,8 +1756,8 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         profile_mark_begin(s);
 #define KXG_X3(F, S)                                                                              \
     hipLaunchKernelGGL((k_gemm_x3_lds<BBW, IBW, KXG_LDS_SS, F, S>), grid, dim3(256), 0, s,          \
-                       F ? k.d_Gh : k.d_Gbf, ws.fop, k.d_pairs16, k.d_units16, g.nib, bpad, g.ipad, \
-                       nbt, part)
+                       F ? k.d_Gh : k.d_Gbf, ws.fop, k.d_pairs16, k.d_act16, k.d_units16, g.nib, bpad,  \
+                       g.ipad, nbt, part)
         if (f16) {
             if (split == 3) KXG_X3(true, 3); else if (split == 2) KXG_X3(true, 2); else KXG_X3(true, 1);
         } else {

@@ -36,6 +36,9 @@ constexpr int kMaxDevices = 64;      // devices the allocation-free evaluation k
 #ifndef KXG_LDS_SS
 #define KXG_LDS_SS 2   // dk steps per LDS stage of the 16-bit GEMM
 #endif
+#ifndef KXG_LDS_STEP_COST
+#define KXG_LDS_STEP_COST 2.0   // cost of a 16-bit super-step besides its MFMAs, in blocks multiplied
+#endif
 #ifndef KXG_LDS_BBW
 #define KXG_LDS_BBW 2   // 32-row batch blocks per wave of the 16-bit GEMM
 #endif
@@ -108,6 +111,8 @@ struct kxg_kernel {
     // (union of their non-zero pairs); Gbf/Gh hold [block][i-block of the
     // group][dk][hi|lo][lane][8]
     int *d_pairs16 = nullptr, *d_cit16 = nullptr, *d_units16 = nullptr;
+    int *d_act16 = nullptr;      // [ncomp16] i-blocks [0, act) of the group hold the pair's non-zero blocks
+    long mult16 = 0;             // (i-block, pair) blocks multiplied: the sum of d_act16
     kxg::SlotCounts nslot16;
     long ncomp16 = 0;
     int nunits16 = 0, maxslots16 = 0;

@@ -82,6 +82,15 @@ void gauss_legendre(int n, double *x, double *w)
 // at most the targeted number of workgroups; the partial of unit j of a
 // group goes to K slot j.  The units depend on the handle only, so the
 // reduction order of a row does not depend on the batch.
+// units in all for one launch of at most wg_target workgroups (a second
+// round of workgroups would double the time of its CUs), and at least 4
+// super-steps a wave
+static int unit_target(long total, int nbt, int wg_target)
+{
+    const int target = std::max(1, wg_target / nbt);
+    return (int)std::max<long>(1, std::min<long>(target, total / (4 * kWaves)));
+}
+
 Units make_units(const std::vector<int> &cnt, const std::vector<int> &first, int pps,
                         int nbt, int wg_target)
 {
@@ -91,11 +100,7 @@ Units make_units(const std::vector<int> &cnt, const std::vector<int> &first, int
     for (int c : cnt) total += (long)c * pps;
     U.nslot.assign(ng, 0);
     if (total == 0) return U;
-    // units in all: one launch of at most wg_target workgroups (a second
-    // round of workgroups would double the time of its CUs), and at least
-    // 4 super-steps a wave
-    int target = std::max(1, wg_target / nbt);
-    target = (int)std::max<long>(1, std::min<long>(target, total / (4 * kWaves)));
+    const int target = unit_target(total, nbt, wg_target);
     // shared out in proportion to each group's blocks (largest remainders),
     // at least one per non-empty group
     std::vector<int> nu(ng, 0);
@@ -125,6 +130,59 @@ Units make_units(const std::vector<int> &cnt, const std::vector<int> &first, int
         U.nslot[q] = m;
         U.maxslots = std::max(U.maxslots, m);
     }
+    return U;
+}
+
+Units make_units_cost(const std::vector<int> &cnt, const std::vector<int> &first,
+                      const std::vector<double> &w, int pps, int nbt, int wg_target)
+{
+    Units U;
+    const int ng = (int)cnt.size();
+    long total = 0;
+    double wmax = 0.0;
+    int nonempty = 0;
+    for (int q = 0; q < ng; ++q) {
+        total += (long)cnt[q] * pps;
+        nonempty += cnt[q] > 0;
+        for (int b = first[q]; b < first[q] + cnt[q]; ++b) wmax = std::max(wmax, w[b]);
+    }
+    U.nslot.assign(ng, 0);
+    if (total == 0) return U;
+    const int target = std::max(unit_target(total, nbt, wg_target), nonempty);
+    // greedy cut of every group at unit cost T: a unit from super-step s runs
+    // floor(T / w) super-steps (at least one), w that of its first block
+    auto cut = [&](double T, bool emit) {
+        int units = 0;
+        for (int q = 0; q < ng; ++q) {
+            long s = (long)first[q] * pps;
+            const long e = (long)(first[q] + cnt[q]) * pps;
+            while (s < e) {
+                const long len = std::max<long>(1, (long)(T / w[s / pps]));
+                const long s1 = std::min(e, s + len);
+                if (emit) {
+                    U.units.push_back(q);
+                    U.units.push_back(U.nslot[q]++);
+                    U.units.push_back((int)s);
+                    U.units.push_back((int)s1);
+                }
+                s = s1;
+                ++units;
+            }
+        }
+        return units;
+    };
+    // the least T (to a part in 1e6) whose cut has at most target units; a
+    // whole group as one unit costs at most wmax * total
+    double lo = 0.0, hi = wmax * (double)total;
+    for (int it = 0; it < 60 && hi - lo > 1e-6 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (cut(mid, false) <= target)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    cut(hi, true);
+    for (int c : U.nslot) U.maxslots = std::max(U.maxslots, c);
     return U;
 }
 

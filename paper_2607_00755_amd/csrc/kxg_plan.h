@@ -24,4 +24,12 @@ struct Units {
 Units make_units(const std::vector<int> &cnt, const std::vector<int> &first, int pps, int nbt,
                  int wg_target);
 
+// The same where a unit's super-steps cost w[b] each, b the unit's first
+// block (w[] per kept block, non-increasing within each group): every unit
+// costs at most T, for the least T that keeps the number of units within
+// the same target (or one per non-empty group).  A group's units are cut
+// greedily in order; its last one may be short.
+Units make_units_cost(const std::vector<int> &cnt, const std::vector<int> &first,
+                      const std::vector<double> &w, int pps, int nbt, int wg_target);
+
 }  // namespace kxg
