@@ -62,7 +62,7 @@ def parse():
                          "'stream384' = 50 plain FP64 evaluations at N = 384 and the copy; "
                          "'streamx384' = 50 exact-form evaluations (Bose-Einstein, log "
                          "interpolation) at N = 384 in FP64 and in FP32, and the copy; "
-                         "'x3' = --steps 16-bit RK4 steps (BF16x3, then FP16x3) at N = 256, "
+                         "'x3' = --steps 16-bit RK4 steps (BF16x3, FP16x3, then FP16x2) at N = 256, "
                          "B = 4096 and the copy; 'serve' = 300 requests of the serving "
                          "workload at 60 req/s")
     return ap.parse_args()
@@ -82,12 +82,14 @@ GEMM_F32_SOURCES = ("paper_2607_00755_amd/csrc/kxg_gemm_f32.hip",
                     "paper_2607_00755_amd/csrc/kxg_geom.h")
 GEMM_X3_SOURCES = ("paper_2607_00755_amd/csrc/kxg_eval.hip",
                    "paper_2607_00755_amd/csrc/kxg_device.h",
-                   "paper_2607_00755_amd/csrc/kxg_geom.h")
+                   "paper_2607_00755_amd/csrc/kxg_geom.h",
+                   "paper_2607_00755_amd/csrc/kxg_plan.cpp")
 
 
-def counted_traffic(profile_md, sources):
-    """HBM bytes per launch from a committed counter summary, if it was taken
-    on the current kernel sources (sha1 recorded in the summary), else None."""
+def counted_traffic(profile_md, sources, key="traffic_bytes_per_launch"):
+    """HBM bytes per launch (field `key`) from a committed counter summary, if
+    it was taken on the current kernel sources (sha1 recorded in the
+    summary), else None."""
     try:
         text = open(os.path.join(ROOT, "profiles", profile_md)).read()
         sha = kernel_source_sha1(sources)
@@ -95,12 +97,12 @@ def counted_traffic(profile_md, sources):
         return None
     fields = {}
     for line in text.splitlines():
-        if ":" in line and line.split(":")[0].strip() in ("kernel_source_sha1", "traffic_bytes_per_launch"):
+        if ":" in line and line.split(":")[0].strip() in ("kernel_source_sha1", key):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.split()[0].strip("`")   # first token; a remark may follow
-    if fields.get("kernel_source_sha1") != sha or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_source_sha1") != sha or key not in fields:
         return None
-    return int(float(fields["traffic_bytes_per_launch"]))
+    return int(float(fields[key]))
 
 
 def serving_alone_check(serving, reqs, done, warm, count):
@@ -498,14 +500,14 @@ def main():
                           "completed": st["completed"]}), flush=True)
         return
     if args.profile_run == "x3":
-        # the 16-bit workload: N = 256, B = 4096 RK4 steps in BF16x3 and FP16x3
-        # (graph replays on a side stream), then the calibration copy
+        # the 16-bit workload: N = 256, B = 4096 RK4 steps in BF16x3, FP16x3
+        # and FP16x2 (graph replays on a side stream), then the calibration copy
         w4 = inputs.mixed_n256(4096)
         p4 = w4.grid()
         f4 = torch.tensor(w4.f0(), device=dev)
-        k4 = kxg.Kernel(p4, precs=(kxg.BF16X3, kxg.F16X3), b_cap=4096)
+        k4 = kxg.Kernel(p4, precs=(kxg.BF16X3, kxg.F16X3, kxg.F16X2), b_cap=4096)
         side = torch.cuda.Stream()
-        for prec in (kxg.BF16X3, kxg.F16X3):
+        for prec in (kxg.BF16X3, kxg.F16X3, kxg.F16X2):
             st4 = kxg.Stepper(k4, kind=kxg.RK4, prec=prec, b_cap=4096)
             st4.set_many(0, f4, lam=[s.lam for s in w4.solves], t_end=1e30, h_i=1.0)
             torch.cuda.synchronize()       # sets on the default stream, steps on side
@@ -679,8 +681,10 @@ def main():
                 "executed_frac_of_measured": (round(fl / (g_us * 1e-6) / 1e12 / peaks["mfma_bf16_tflops"], 4)
                                               if peaks else None),
                 "blocks": blocks16, "blocks_staged": info4["staged16"],
-                "traffic": (counted_traffic("gemm_x3_n256_b4096.md", GEMM_X3_SOURCES)
-                            if prec == kxg.BF16X3 else None)}
+                "traffic": counted_traffic("gemm_x3_n256_b4096.md", GEMM_X3_SOURCES,
+                                           "traffic_bytes_per_launch" + {kxg.BF16X3: "",
+                                                                         kxg.F16X3: "_f16x3",
+                                                                         kxg.F16X2: "_f16x2"}[prec])}
             log("%s B=4096 RK4: %.3f ms/step, gemm %.1f us" % (name, 1e3 * wl, g_us))
             del st4
         # split ablations: error of 256 rows against the FP64 path, GEMM time at B = 4096
