@@ -45,11 +45,11 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-check", type=int, default=32,
                     help="measured requests re-run alone and compared with their result in the mix")
-    ap.add_argument("--serve-sweep", default="30,60,90,120,150",
+    ap.add_argument("--serve-sweep", default="20,35,50,65",
                     help="comma-separated arrival rates of a saturation sweep; empty = none")
-    ap.add_argument("--serve-sweep-requests", type=int, default=400,
+    ap.add_argument("--serve-sweep-requests", type=int, default=300,
                     help="measured requests per sweep rate, at least (see --serve-sweep-seconds)")
-    ap.add_argument("--serve-sweep-seconds", type=float, default=8.0,
+    ap.add_argument("--serve-sweep-seconds", type=float, default=15.0,
                     help="each sweep rate also runs at least this many seconds of arrivals, "
                          "several solve lifetimes, so that a queue can build up")
     ap.add_argument("--cpu-full", action="store_true",
@@ -128,27 +128,26 @@ def serving_alone_check(serving, reqs, done, warm, count):
 
 def sustainable(rows):
     """The sweep row of the highest rate the loop keeps up with (rows in
-    increasing rate): no queue builds up over the run (the median latency
-    of the last quarter of the arrivals is at most 1.5 x that of the first
-    quarter) and p99 stays within 1.5 x the p99 of the lowest rate, the
-    nearly unloaded latency; None if even the lowest rate is not kept up
-    with.  The completed solves/s of a finite burst include the drain after
+    increasing rate): solves complete at least at 0.9 x the arrival rate
+    while requests arrive (keep_up >= 0.9) and no queue builds up (the
+    median latency of the last quarter of the arrivals is at most 1.5 x that
+    of the first quarter); None if even the lowest rate is not kept up with.
+    Continuous batching admits a burst into the batch rather than a queue,
+    so latency alone grows slowly past capacity: the completion rate is the
+    test.  The completed solves/s of a finite burst include the drain after
     the last arrival, so they sit below the offered rate even when the loop
     keeps up; a kept-up rate is itself the sustained throughput."""
     best = None
-    if rows:
-        p99_0 = rows[0]["p99_s"]
-        for r in rows:
-            if r["queue_growth"] <= 1.5 and r["p99_s"] <= 1.5 * p99_0:
-                best = r
+    for r in rows:
+        if r["keep_up"] >= 0.9 and r["queue_growth"] <= 1.5:
+            best = r
     return best
 
 
 def serving_sweep(serving, args):
-    """Arrival-rate sweep of the serving loop: p50/p99 latency and solves/s
-    per rate.  The largest sustainable rate is the highest one that the loop
-    still completes at (solves/s >= 0.9 x offered) without p99 running away
-    (<= 2 x the p99 of the lowest rate, the nearly unloaded latency)."""
+    """Arrival-rate sweep of the serving loop: p50/p99 latency, solves/s and
+    the completion-to-arrival rate ratio per rate; the largest sustainable
+    rate by `sustainable`."""
     from paper_2607_00755_amd import inputs, kxg
     rows = []
     for rate in [float(x) for x in args.serve_sweep.split(",") if x.strip()]:
@@ -161,20 +160,22 @@ def serving_sweep(serving, args):
         st = srv.stats(done, warm=nw)
         rows.append({"rate_req_per_s": rate, "requests": nr, "warmup": nw, "p50_s": round(st["p50_s"], 3),
                      "p99_s": round(st["p99_s"], 3), "solves_per_s": round(st["solves_per_s"], 2),
-                     "queue_growth": round(st["queue_growth"], 3),
+                     "queue_growth": round(st["queue_growth"], 3), "keep_up": round(st["keep_up"], 3),
                      "completed": st["completed"], "truncated": st["truncated"],
                      "failed": st["failed"], "wall_s": round(time.perf_counter() - t0, 1)})
-        log("serving sweep %.1f req/s: p50 %.3f s p99 %.3f s, %.2f solves/s, queue growth %.2f" %
-            (rate, st["p50_s"], st["p99_s"], st["solves_per_s"], st["queue_growth"]))
+        log("serving sweep %.1f req/s: p50 %.3f s p99 %.3f s, %.2f solves/s, queue growth %.2f, "
+            "keep-up %.2f" % (rate, st["p50_s"], st["p99_s"], st["solves_per_s"], st["queue_growth"],
+                              st["keep_up"]))
         del srv
     best = sustainable(rows)
     return {"rates": rows, "min_requests_per_rate": args.serve_sweep_requests,
             "min_arrival_seconds_per_rate": args.serve_sweep_seconds,
             "max_sustainable_rate_req_per_s": None if best is None else best["rate_req_per_s"],
             "max_sustainable_solves_per_s": None if best is None else best["solves_per_s"],
-            "rule": "highest rate whose late arrivals wait no longer than its early ones "
-                    "(median latency of the last quarter <= 1.5 x the first quarter's) with "
-                    "p99 <= 1.5 x p99 at the lowest rate"}
+            "rule": "highest rate at which solves complete at >= 0.9 x the arrival rate while "
+                    "requests arrive (from one median latency after the first arrival to the "
+                    "last) and late arrivals wait no longer than early ones (median latency of "
+                    "the last quarter <= 1.5 x the first quarter's)"}
 
 
 def packed_k(n):

@@ -301,6 +301,18 @@ class Server:
         qn = len(by_arr) // 4
         growth = (float(np.median([r.latency for r in by_arr[-qn:]])) /
                   float(np.median([r.latency for r in by_arr[:qn]]))) if qn >= 4 else float("nan")
+        # keeping up: the completion rate while requests still arrive (from
+        # one median latency after the first arrival to the last arrival)
+        # over the arrival rate; about 1 below capacity, capacity / offered
+        # rate above it, where the backlog grows until the last arrival
+        keep_up = float("nan")
+        arr = sorted(r.arrival for r in mine)
+        if len(arr) >= 8 and ok:
+            t0, ta = arr[0], arr[-1]
+            w0 = t0 + float(np.median(lat))
+            if ta - w0 > 0 and ta > t0:
+                out_rate = sum(1 for r in ok if w0 <= r.finished <= ta) / (ta - w0)
+                keep_up = out_rate / ((len(arr) - 1) / (ta - t0))
         return {
             "completed": len(ok),
             "truncated": sum(1 for r in mine if r.status == 2),
@@ -311,6 +323,7 @@ class Server:
             "p99_s": float(np.percentile(lat, 99)),
             "solves_per_s": len(ok) / span if span and span > 0 else float("nan"),
             "queue_growth": growth,
+            "keep_up": keep_up,
             "mean_steps": float(np.mean([r.steps for r in ok])) if ok else float("nan"),
             "max_steps": int(max(r.steps for r in ok)) if ok else 0,
             "mean_batch": {n: g.batch_sum / max(g.iters, 1) for n, g in self.groups.items()},

@@ -62,17 +62,41 @@ def test_oracle_thread_control_takes_effect():
 
 
 def test_sustainable_rate_rule():
-    rows = [{"rate_req_per_s": 10.0, "queue_growth": 1.0, "p99_s": 4.0},
-            {"rate_req_per_s": 20.0, "queue_growth": 1.1, "p99_s": 5.0},
-            {"rate_req_per_s": 40.0, "queue_growth": 1.4, "p99_s": 5.9},
-            {"rate_req_per_s": 60.0, "queue_growth": 3.0, "p99_s": 20.0}]
+    rows = [{"rate_req_per_s": 10.0, "queue_growth": 1.0, "keep_up": 1.0, "p99_s": 4.0},
+            {"rate_req_per_s": 20.0, "queue_growth": 1.1, "keep_up": 0.98, "p99_s": 5.0},
+            {"rate_req_per_s": 40.0, "queue_growth": 1.4, "keep_up": 0.93, "p99_s": 5.9},
+            {"rate_req_per_s": 60.0, "queue_growth": 1.2, "keep_up": 0.7, "p99_s": 8.0}]
+    # 60 req/s: completions fall behind arrivals although latency grew little
     assert bench.sustainable(rows)["rate_req_per_s"] == 40.0
-    rows[2]["p99_s"] = 6.1          # p99 more than 1.5 x the unloaded one
+    rows[2]["keep_up"] = 0.85
     assert bench.sustainable(rows)["rate_req_per_s"] == 20.0
-    rows[2]["p99_s"] = 5.0
+    rows[2]["keep_up"] = 0.95
     rows[2]["queue_growth"] = 1.6   # late arrivals wait longer: a queue builds up
     assert bench.sustainable(rows)["rate_req_per_s"] == 20.0
     assert bench.sustainable([]) is None
+
+
+def test_keep_up_ratio():
+    """stats' keep_up: completions per second while requests arrive over the
+    arrival rate, about 1 when the loop keeps up and capacity / offered rate
+    when it does not (synthetic request records, no GPU)."""
+    from types import SimpleNamespace as NS
+    from paper_2607_00755_amd import serving
+
+    def run(rate, capacity, n=400, lat=1.0):
+        done, t_free = [], 0.0
+        for j in range(n):
+            a = j / rate
+            start = max(a, t_free)              # one server of the given capacity
+            t_free = start + 1.0 / capacity
+            done.append(NS(rid=j, arrival=a, finished=start + lat, latency=start + lat - a,
+                           status=1, steps=1, solve=NS(n=64)))
+        srv = serving.Server.__new__(serving.Server)
+        srv.groups = {}
+        return srv.stats(done)["keep_up"]
+
+    assert abs(run(20.0, 50.0) - 1.0) < 0.05
+    assert abs(run(100.0, 50.0) - 0.5) < 0.05
 
 
 def test_cpu_oracle_workload_rows():
