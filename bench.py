@@ -45,11 +45,11 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-check", type=int, default=32,
                     help="measured requests re-run alone and compared with their result in the mix")
-    ap.add_argument("--serve-sweep", default="20,35,50,65",
+    ap.add_argument("--serve-sweep", default="25,50,80,110,140",
                     help="comma-separated arrival rates of a saturation sweep; empty = none")
     ap.add_argument("--serve-sweep-requests", type=int, default=300,
                     help="measured requests per sweep rate, at least (see --serve-sweep-seconds)")
-    ap.add_argument("--serve-sweep-seconds", type=float, default=15.0,
+    ap.add_argument("--serve-sweep-seconds", type=float, default=12.0,
                     help="each sweep rate also runs at least this many seconds of arrivals, "
                          "several solve lifetimes, so that a queue can build up")
     ap.add_argument("--cpu-full", action="store_true",

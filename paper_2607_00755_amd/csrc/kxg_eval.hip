@@ -909,9 +909,8 @@ __global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
         // is part of the GEMM operand) and the loss rates, when given, only
         // feed the diagnostics.
         // Slots up to nsplit (the largest count) are read for every row,
-        // unconditionally (past nsplit the last slot again); slots past the
-        // row's own count, read from the allocated workspace, are dropped in
-        // the sum.
+        // unconditionally: past the row's own count its last slot again (a
+        // cache hit, no memory traffic), dropped in the sum.
         constexpr int U = (sizeof(PT) == 4 ? KXG_EPI_U : 16) / PER > 0 ? (sizeof(PT) == 4 ? KXG_EPI_U : 16) / PER : 1;
         int ns[PER];
 #pragma unroll
@@ -934,9 +933,10 @@ __global__ __launch_bounds__(256, KXG_EPI_MINB) void k_epilogue(
             for (int q = 0; q < PER; ++q) {
                 const int i = epi_tl<TPB>() + TPB * q;
                 const PT *pp = part + (long)b * ld_b + (i < n ? i : 0);
+                const int last = ns[q] > 0 ? ns[q] - 1 : 0;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int sp = sp0 + u < nsplit ? sp0 + u : nsplit - 1;   // no branch
+                    const int sp = sp0 + u < last ? sp0 + u : last;   // no branch
                     v[q][u] = pp[(long)sp * split_stride];
                 }
             }
