@@ -80,7 +80,7 @@ def kernel_source_sha1(sources):
 GEMM_F32_SOURCES = ("paper_2607_00755_amd/csrc/kxg_gemm_f32.hip",
                     "paper_2607_00755_amd/csrc/kxg_device.h",
                     "paper_2607_00755_amd/csrc/kxg_geom.h")
-GEMM_X3_SOURCES = ("paper_2607_00755_amd/csrc/kxg_eval.hip",
+GEMM_X3_SOURCES = ("paper_2607_00755_amd/csrc/kxg_gemm16.hip",
                    "paper_2607_00755_amd/csrc/kxg_device.h",
                    "paper_2607_00755_amd/csrc/kxg_geom.h",
                    "paper_2607_00755_amd/csrc/kxg_plan.cpp")
@@ -161,6 +161,7 @@ def serving_sweep(serving, args):
         rows.append({"rate_req_per_s": rate, "requests": nr, "warmup": nw, "p50_s": round(st["p50_s"], 3),
                      "p99_s": round(st["p99_s"], 3), "solves_per_s": round(st["solves_per_s"], 2),
                      "queue_growth": round(st["queue_growth"], 3), "keep_up": round(st["keep_up"], 3),
+                     "completion_rate_per_s": round(st["keep_up"] * rate, 1),
                      "completed": st["completed"], "truncated": st["truncated"],
                      "failed": st["failed"], "wall_s": round(time.perf_counter() - t0, 1)})
         log("serving sweep %.1f req/s: p50 %.3f s p99 %.3f s, %.2f solves/s, queue growth %.2f, "
@@ -171,7 +172,7 @@ def serving_sweep(serving, args):
     return {"rates": rows, "min_requests_per_rate": args.serve_sweep_requests,
             "min_arrival_seconds_per_rate": args.serve_sweep_seconds,
             "max_sustainable_rate_req_per_s": None if best is None else best["rate_req_per_s"],
-            "max_sustainable_solves_per_s": None if best is None else best["solves_per_s"],
+            "completion_rate_at_sustainable_per_s": None if best is None else best["completion_rate_per_s"],
             "rule": "highest rate at which solves complete at >= 0.9 x the arrival rate while "
                     "requests arrive (from one median latency after the first arrival to the "
                     "last) and late arrivals wait no longer than early ones (median latency of "

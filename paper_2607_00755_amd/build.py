@@ -26,6 +26,7 @@ UNITS = {
     "kxg_build.hip": ["-ffp-contract=off"],
     "kxg_eval.hip": [],
     "kxg_gemm_f32.hip": [],
+    "kxg_gemm16.hip": [],
     "kxg_probe.hip": [],
     "kxg_step.hip": [],
     "kxg_plan.cpp": [],

@@ -145,6 +145,11 @@ hipError_t launch_read16(const void *src, long nvec, float *sink, int nwg, hipSt
 hipError_t launch_gemm_f32(int bbw, int nwg, const float *G, const float *fop, const float *fpar,
                            const int *pairs, const int *units, int bpad, int ipad, int nbt, float *part,
                            hipStream_t s);
+// 16-bit GEMM (kxg_gemm16.hip): split = 3, 2 or 1 products of the hi+lo
+// split; nwg = batch tiles x work units
+hipError_t launch_gemm16(bool f16, int split, int nwg, const uint16_t *G, const float *fop, const int *pairs,
+                         const int *act, const int *units, int nib, int bpad, int ipad, int nbt, float *part,
+                         hipStream_t s);
 
 struct StepArgs;
 // Evaluate C[f] for B rows; with `step` the epilogue applies that stepper
