@@ -16,7 +16,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x8 __attribute__((ext_vector_type(8)));
 
-// 16-bit x3 GEMM for large batches, the packed tensor shared through LDS.
+// 16-bit split GEMM, the packed tensor shared through LDS.
 // A workgroup's 4 waves work on the same K split and the same IBW i-blocks;
 // wave w takes the BBW b-blocks [w*BBW, (w+1)*BBW) of the workgroup's
 // 4*BBW*32-row batch tile.  The K range runs in super-steps of SS dk steps:
@@ -30,7 +30,7 @@ typedef unsigned int u32x8 __attribute__((ext_vector_type(8)));
 // (kb, mb) pair: it is loaded once per pair, a pair ahead, and kept in one
 // of two wave-private LDS sets chosen by the pair's parity (registers can't
 // be chosen at run time without copies).  Every wave forms and splits its F2
-// operand once per (b-block, dk) and feeds it to 3*IBW MFMAs.  The kept
+// operand once per (b-block, dk) and feeds it to SPLIT*IBA MFMAs.  The kept
 // pairs of a unit all have their non-zero blocks in the group's first IBA
 // i-blocks (IBA of its first pair, the pairs of a group being ordered by
 // that count): only those are staged and multiplied, the others' partials

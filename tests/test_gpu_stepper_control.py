@@ -174,3 +174,37 @@ def test_packed_nonzero_count_matches_oracle(dev, n):
     iu = np.triu_indices(n)
     want = int(np.count_nonzero(s[:, iu[0], iu[1]]))
     assert k.stats()["nnz_packed"] == want
+
+
+@pytest.mark.parametrize("n", [80, 256])
+def test_16bit_blocks_multiplied_match_oracle_structure(dev, n):
+    """The 16-bit GEMM multiplies, for every kept (kb, mb) pair of a group of
+    four i-blocks, the group's i-blocks up to the last one whose 32 x 16 x 16
+    block of the packed A' carries a weight; the count follows from the
+    oracle's A and R, and lies between the non-zero blocks and the staged
+    union."""
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    k = kxg.Kernel(p, precs=(kxg.F32, kxg.F16X3), b_cap=64)
+    st = k.stats()
+    op = oracle.Operator(p)
+    nzA = op.A != 0.0
+    idx = np.arange(n)
+    loss = np.zeros_like(nzA)
+    loss[idx, idx, :] = op.R != 0.0
+    s = nzA | np.transpose(nzA, (0, 2, 1)) | loss | np.transpose(loss, (0, 2, 1))
+    nb, nib = (n + 15) // 16, (n + 31) // 32
+    mult = staged = nonzero = 0
+    for g0 in range(0, nib, 4):
+        for kb in range(nb):
+            for mb in range(kb, nb):
+                flags = []
+                for ib in range(g0, min(nib, g0 + 4)):
+                    blk = s[32 * ib:32 * ib + 32, 16 * kb:16 * kb + 16, 16 * mb:16 * mb + 16]
+                    flags.append(bool(blk.any()))
+                if any(flags):
+                    mult += max(j + 1 for j, x in enumerate(flags) if x)
+                    staged += 4
+                    nonzero += sum(flags)
+    assert st["blocks16"] == mult
+    assert st["staged16"] == staged
+    assert st["nonzero_blocks"] == nonzero <= mult <= staged
