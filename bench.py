@@ -47,7 +47,7 @@ def parse():
                     help="measured requests re-run alone and compared with their result in the mix")
     ap.add_argument("--serve-sweep", default="25,50,80,110,140",
                     help="comma-separated arrival rates of a saturation sweep; empty = none")
-    ap.add_argument("--serve-sweep-requests", type=int, default=300,
+    ap.add_argument("--serve-sweep-requests", type=int, default=400,
                     help="measured requests per sweep rate, at least (see --serve-sweep-seconds)")
     ap.add_argument("--serve-sweep-seconds", type=float, default=12.0,
                     help="each sweep rate also runs at least this many seconds of arrivals, "
