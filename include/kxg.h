@@ -368,8 +368,9 @@ kxg_status kxg_stepper_release(kxg_stepper *s, int32_t slot, void *stream);
  * attempted steps, two operator calls each).  Slots that reach t_end,
  * max_steps or fail stop by themselves on the device.  On a non-default
  * stream the iterations replay HIP graphs captured on first use (eight
- * iterations per replay, then single ones for the rest; recaptured when the
- * batch bucket or the stream changes); on the default stream, or while a
+ * iterations per replay, then single ones for the rest), one pair per batch
+ * bucket of 16 slots, kept for the stepper's lifetime and captured again
+ * only when that bucket is replayed on another stream; on the default stream, or while a
  * profile is open, they are launched directly.  Same results either way.
  * Asynchronous. */
 kxg_status kxg_stepper_advance(kxg_stepper *s, int32_t n_iter, void *stream);

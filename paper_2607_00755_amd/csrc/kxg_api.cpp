@@ -90,12 +90,16 @@ struct kxg_stepper {
     Workspace ws;
     std::vector<char> used;
     int b_hi = 0;
-    // captured iterations (HIP graphs) for the current batch bucket: one,
-    // and kGraphIters in a row (fewer graph launches on long advances)
-    hipGraphExec_t gexec = nullptr;
-    hipGraphExec_t gexec_n = nullptr;
-    int g_batch = -1;
-    hipStream_t g_stream = nullptr;
+    // captured iterations (HIP graphs) per batch bucket of 16 slots: one,
+    // and kGraphIters in a row (fewer graph launches on long advances), and
+    // the stream they were captured on; a bucket is captured on its first
+    // use and kept, so that a batch moving between buckets (slots retired
+    // and refilled) replays instead of capturing again
+    struct Graphs {
+        hipGraphExec_t one = nullptr, many = nullptr;
+        hipStream_t stream = nullptr;
+    };
+    std::vector<Graphs> graphs;
     // staging of slot records for kxg_stepper_set_many: pinned host buffer,
     // its device copy, and an event that marks the end of the last copy
     SlotDev *h_init = nullptr;
@@ -716,8 +720,10 @@ kxg_status kxg_stepper_create(const kxg_kernel *k, const kxg_stepper_params *prm
 void kxg_stepper_free(kxg_stepper *s)
 {
     if (!s) return;
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-    if (s->gexec_n) (void)hipGraphExecDestroy(s->gexec_n);
+    for (kxg_stepper::Graphs &g : s->graphs) {
+        if (g.one) (void)hipGraphExecDestroy(g.one);
+        if (g.many) (void)hipGraphExecDestroy(g.many);
+    }
     if (s->init_evt) {
         (void)hipEventSynchronize(s->init_evt);
         (void)hipEventDestroy(s->init_evt);
@@ -934,8 +940,9 @@ static kxg_status enqueue_iteration(kxg_stepper *s, int B, hipStream_t st)
 }
 
 // Iterations per replay of the long graph; the remainder of an advance call
-// replays the one-iteration graph.  Both are captured over the current batch
-// bucket and re-captured when the bucket or the stream changes.
+// replays the one-iteration graph.  Both are captured per batch bucket, on
+// the bucket's first use, and again only when it is replayed on another
+// stream.
 constexpr int kGraphIters = 8;
 
 // Capture `iters` iterations of the stepper on `st` into an executable graph
@@ -962,19 +969,23 @@ static hipGraphExec_t capture_iterations(kxg_stepper *s, int batch, int iters, h
     return exec;
 }
 
-static bool ensure_graph(kxg_stepper *s, int batch, hipStream_t st)
+// The graphs of a batch bucket (batch = a multiple of 16 up to b_cap, or
+// b_cap), captured on `st` if they are not held for it yet; null if the
+// capture fails.
+static const kxg_stepper::Graphs *ensure_graph(kxg_stepper *s, int batch, hipStream_t st)
 {
-    if (s->gexec && s->g_batch == batch && s->g_stream == st) return true;
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-    if (s->gexec_n) (void)hipGraphExecDestroy(s->gexec_n);
-    s->gexec = s->gexec_n = nullptr;
-    s->g_batch = -1;
-    s->gexec = capture_iterations(s, batch, 1, st);
-    if (!s->gexec) return false;
-    s->gexec_n = capture_iterations(s, batch, kGraphIters, st);   // optional
-    s->g_batch = batch;
-    s->g_stream = st;
-    return true;
+    const size_t slot = (size_t)((batch + 15) / 16 - 1);
+    if (s->graphs.size() <= slot) s->graphs.resize(slot + 1);
+    kxg_stepper::Graphs &g = s->graphs[slot];
+    if (g.one && g.stream == st) return &g;
+    if (g.one) (void)hipGraphExecDestroy(g.one);
+    if (g.many) (void)hipGraphExecDestroy(g.many);
+    g = kxg_stepper::Graphs{};
+    g.one = capture_iterations(s, batch, 1, st);
+    if (!g.one) return nullptr;
+    g.many = capture_iterations(s, batch, kGraphIters, st);   // optional
+    g.stream = st;
+    return &g;
 }
 
 kxg_status kxg_stepper_advance(kxg_stepper *s, int32_t n_iter, void *stream)
@@ -989,13 +1000,14 @@ kxg_status kxg_stepper_advance(kxg_stepper *s, int32_t n_iter, void *stream)
     // the kernels).  Direct launches while a profile is open or on the
     // default stream.
     const int bucket = std::min(s->prm.b_cap, (B + 15) / 16 * 16);
-    if (st != nullptr && !g_prof.on && ensure_graph(s, bucket, st)) {
+    const kxg_stepper::Graphs *g = (st != nullptr && !g_prof.on) ? ensure_graph(s, bucket, st) : nullptr;
+    if (g) {
         kxg_status r = prep_operands(*s->k, s->ws, s->prm.prec, s->d_fb, bucket, st);
         if (r != KXG_OK) return r;
         int it = 0;
-        if (s->gexec_n)
-            for (; it + kGraphIters <= n_iter; it += kGraphIters) KXG_TRY_HIP(hipGraphLaunch(s->gexec_n, st));
-        for (; it < n_iter; ++it) KXG_TRY_HIP(hipGraphLaunch(s->gexec, st));
+        if (g->many)
+            for (; it + kGraphIters <= n_iter; it += kGraphIters) KXG_TRY_HIP(hipGraphLaunch(g->many, st));
+        for (; it < n_iter; ++it) KXG_TRY_HIP(hipGraphLaunch(g->one, st));
         return KXG_OK;
     }
     kxg_status r0 = prep_operands(*s->k, s->ws, s->prm.prec, s->d_fb, B, st);

@@ -547,6 +547,58 @@ def test_multi_iteration_graph_matches_eager(dev, kind, prec):
         assert [x["t"] for x in q0[:B]] == [x["t"] for x in q1[:B]]
 
 
+def test_graphs_kept_per_batch_bucket_match_eager(dev):
+    """The stepper keeps the graphs of every batch bucket (16 slots) it has
+    replayed: as slots are filled, retired and refilled, the batch moves
+    between buckets and back (16 -> 48 -> 32 -> 48 -> 16), replaying graphs
+    captured earlier. Every phase must match the same slot history launched
+    eagerly on the default stream, bit for bit."""
+    n, cap = 40, 64
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    f0 = batch(p, cap, seed=33)
+    k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=cap)
+    steppers = [kxg.Stepper(k, kind=kxg.HEUN, prec=kxg.F32, b_cap=cap,
+                            expansion=kxg.EXP_RADIATION) for _ in range(2)]
+    side = torch.cuda.Stream()
+    streams = (side, None)
+
+    def each(fn):
+        for st, s in zip(steppers, streams):
+            fn(st, s)
+            if s is not None:
+                s.synchronize()
+        torch.cuda.synchronize()
+
+    def fill(lo, hi, lam):
+        each(lambda st, s: [st.set(b, torch.tensor(f0[b], device=dev), lam=lam, t_end=1e3,
+                                   h_i=0.0, stream=s) for b in range(lo, hi)])
+
+    def drop(lo, hi):
+        each(lambda st, s: [st.release(b, stream=s) for b in range(lo, hi)])
+
+    out = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(2)]
+    used = set()
+    phases = [("fill", 0, 10, 2.0), ("fill", 10, 40, 3.0), ("drop", 20, 40, 0.0),
+              ("fill", 30, 45, 1.5), ("drop", 10, 45, 0.0)]
+    for ph, (what, lo, hi, lam) in enumerate(phases):
+        if what == "fill":
+            fill(lo, hi, lam)
+            used |= set(range(lo, hi))
+        else:
+            drop(lo, hi)
+            used -= set(range(lo, hi))
+        each(lambda st, s: st.advance(9, stream=s))
+        for b in sorted(used):
+            steppers[0].get(b, out=out[0], stream=side)
+            side.synchronize()
+            steppers[1].get(b, out=out[1])
+            torch.cuda.synchronize()
+            assert torch.equal(out[0], out[1]), (ph, b)
+        q0, q1 = steppers[0].query(stream=side), steppers[1].query()
+        assert [q0[b]["steps"] for b in sorted(used)] == [q1[b]["steps"] for b in sorted(used)]
+        assert sum(q0[b]["steps"] for b in sorted(used)) > 0
+
+
 @pytest.mark.parametrize("prec", ALL)
 def test_eval_without_diagnostics_same_C(dev, prec):
     """With no diagnostics buffer the operator output is bitwise the same."""
