@@ -54,11 +54,13 @@ typedef enum {
 
 /* Precision of the contraction sum_{n,m} A f f.  The projection, the
  * reduction of the split partials and all state updates are FP64 in every
- * case; the loss term f_i sum_j R_ij f_j is folded into the operand of the
- * GEMM paths (so it takes the contraction's precision there) and is summed
- * in FP64 on the stream paths. */
+ * case; the loss term f_i sum_j R_ij f_j is folded into the packed operand
+ * of the GEMM paths and of the FP64 stream (so it takes the contraction's
+ * precision there) and is summed in FP64 on the FP32 single-distribution
+ * and exact-form streams. */
 typedef enum {
-    KXG_F64 = 0,     /* FP64 stream over the dense kernel tensor          */
+    KXG_F64 = 0,     /* FP64 stream over the kept blocks of the packed
+                        A' (the dense tensor for the exact forms)          */
     KXG_F32 = 1,     /* FP32: stream if b_cap <= 4, else MFMA GEMM        */
     KXG_BF16X3 = 2,  /* BF16 MFMA, hi+lo split of A and of f_n f_m,
                         3 products, FP32 accumulation                     */
@@ -157,6 +159,11 @@ typedef struct {
                                  every i-block of the group for each pair kept
                                  (the union over the group); they are streamed
                                  through LDS whether multiplied or not */
+    int64_t blocks64;         /* (i-block, pair) blocks of the packed FP64
+                                 operand the plain FP64 evaluation streams (the
+                                 same blocks as the FP32 operand; each 32 rows
+                                 of 16 x 16 values, 64 KiB; 0 on handles
+                                 without FP64) */
 } kxg_kernel_info;
 
 /* Fill *out for handle k.  Errors: KXG_EINVAL (null argument). */

@@ -25,6 +25,14 @@ void set_error(const char *fmt, ...);
 
 constexpr int kMaxN = 1024;          // largest grid
 constexpr int kMaxDevices = 64;      // devices the allocation-free evaluation keeps a scratch address for
+#ifndef KXG_PSTREAM_UNROLL
+#define KXG_PSTREAM_UNROLL 8   // 16-byte loads in flight per thread in the packed FP64 stream
+#endif
+constexpr int kPStreamPairs = 128;   // kept pairs one packed-stream workgroup stages (its chunk spans at most this)
+// largest chunk of the packed FP64 stream: one round of loads per thread
+// (two values per load, 256 threads)
+constexpr int kPStreamChunk = KXG_PSTREAM_UNROLL * 512;
+static_assert(kPStreamChunk / 256 <= kPStreamPairs, "a chunk spans at most kPStreamPairs pairs");
 
 // Tuning of the GEMM launches (overridable at build time).
 #ifndef KXG_GEMM_WG_TARGET
@@ -38,6 +46,9 @@ constexpr int kMaxDevices = 64;      // devices the allocation-free evaluation k
 #endif
 #ifndef KXG_LDS_STEP_COST
 #define KXG_LDS_STEP_COST 2.0   // cost of a 16-bit super-step besides its MFMAs, in blocks multiplied
+#endif
+#ifndef KXG_PSTREAM_ROWS_TARGET
+#define KXG_PSTREAM_ROWS_TARGET 2048   // non-empty workgroups of a packed FP64 stream launch aimed at
 #endif
 #ifndef KXG_LDS_BBW
 #define KXG_LDS_BBW 2   // 32-row batch blocks per wave of the 16-bit GEMM
@@ -116,6 +127,14 @@ struct kxg_kernel {
     kxg::SlotCounts nslot16;
     long ncomp16 = 0;
     int nunits16 = 0, maxslots16 = 0;
+    // FP64 operand of the plain (stream) evaluation: the same non-zero
+    // (i-block, pair) blocks as the FP32 GEMM, row by row: row i holds the
+    // 16 x 16 blocks of its i-block's kept pairs, [pair][dk][dm]
+    double *d_P64 = nullptr;
+    int *d_pairs64 = nullptr;    // [ncomp64][2] (kb, mb), i-block by i-block, then [ncomp64] their i-blocks
+    int *d_ib64 = nullptr;       // [nib][2] first kept pair and count of each i-block
+    long ncomp64 = 0;
+    int chunk64 = 0, nsplit64 = 0;   // elements per stream workgroup, K splits (partials) per row
     uint16_t *d_JL = nullptr;    // [n][n][n] interpolation bracket j_L (0xFFFF: cut)
     double *d_invdK = nullptr;   // [n] 1 / (K_{j+1} - K_j) (0 for the last point)
     kxg::Geometry geo;
@@ -134,6 +153,7 @@ hipError_t launch_derive(kxg_kernel &k, hipStream_t s);
 hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, unsigned int *nnz,
                            hipStream_t s);
 hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s);
+hipError_t launch_pack_f64(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_pack_16(const kxg_kernel &k, int ibw, hipStream_t s);
 hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s);
 // device self-calibration (kxg_probe.hip)

@@ -65,7 +65,8 @@ class KernelInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("packed_blocks", ctypes.c_int64),
                 ("nonzero_blocks", ctypes.c_int64), ("gemm_units", ctypes.c_int32),
                 ("max_slots", ctypes.c_int32), ("blocks16", ctypes.c_int64),
-                ("nnz_packed", ctypes.c_int64), ("staged16", ctypes.c_int64)]
+                ("nnz_packed", ctypes.c_int64), ("staged16", ctypes.c_int64),
+                ("blocks64", ctypes.c_int64)]
 
 
 class StepperParams(ctypes.Structure):
@@ -259,7 +260,8 @@ class Kernel:
         return {"n": info.n, "packed_blocks": info.packed_blocks,
                 "nonzero_blocks": info.nonzero_blocks, "gemm_units": info.gemm_units,
                 "max_slots": info.max_slots, "blocks16": info.blocks16,
-                "nnz_packed": info.nnz_packed, "staged16": info.staged16}
+                "nnz_packed": info.nnz_packed, "staged16": info.staged16,
+                "blocks64": info.blocks64}
 
     def export(self):
         n = self.n

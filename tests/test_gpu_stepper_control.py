@@ -141,7 +141,11 @@ def test_lean_handle(dev):
     torch.cuda.synchronize()
     assert torch.equal(Cf, Cl)
     assert lean.bytes(-1) + 12 * n ** 3 <= full.bytes(-1)
-    assert lean.bytes(kxg.F64) == 0 and full.bytes(kxg.F64) > 8 * n ** 3
+    # FP64 evaluations read the packed kept blocks (the FP32 operand's
+    # blocks, 64 KiB each in FP64) and R
+    sf = full.stats()
+    assert sf["blocks64"] == sf["nonzero_blocks"] > 0 and lean.stats()["blocks64"] == 0
+    assert lean.bytes(kxg.F64) == 0 and full.bytes(kxg.F64) == 65536 * sf["blocks64"] + 8 * n ** 2
     with pytest.raises(kxg.KxgError) as ei:
         lean.eval(f0, prec=kxg.F64)
     assert ei.value.status == kxg.EUNSUPPORTED
