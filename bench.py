@@ -221,7 +221,8 @@ def single_paths(args, dev):
                               "bytes_per_launch": nbytes, "dense_tensor_bytes": 8 * n ** 3}
     log("plain fp64 N=384 stream: %.1f us, %.0f GB/s of packed blocks" % (us, gbps))
     del k
-    # HBM stream, N = 416 FP32 (A32 is 288 MB, also beyond the Infinity Cache)
+    # HBM stream, N = 416 FP32 (single-distribution handle: the packed kept
+    # blocks in FP32, 32 KiB each; the dense A32 would be 288 MB)
     n = 416
     p = inputs.log_grid(n, 1e-3, 20.0)
     k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=1)
@@ -236,10 +237,12 @@ def single_paths(args, dev):
     torch.cuda.synchronize()
     ms, cnt = kxg.profile_end()
     us = 1e3 * ms / max(cnt, 1)
-    gbps = 4.0 * n ** 3 / (us * 1e-6) / 1e9
+    nbytes = 32768 * k.stats()["blocks64"]
+    gbps = nbytes / (us * 1e-6) / 1e9
     out["plain_fp32_n416"] = {"stream_kernel_us": round(us, 2), "stream_GBps": round(gbps, 1),
-                              "hbm_frac": round(gbps / HBM_PEAK, 4), "bytes_per_launch": 4 * n ** 3}
-    log("plain fp32 N=416 stream: %.1f us, %.0f GB/s" % (us, gbps))
+                              "hbm_frac": round(gbps / HBM_PEAK, 4), "bytes_per_launch": nbytes,
+                              "dense_tensor_bytes": 4 * n ** 3}
+    log("plain fp32 N=416 stream: %.1f us, %.0f GB/s of packed blocks" % (us, gbps))
     del k
     # N = 32 FP64, RK4, 100 steps on a side stream (captured graph)
     w = inputs.single_fp64_n32()

@@ -55,13 +55,13 @@ typedef enum {
 /* Precision of the contraction sum_{n,m} A f f.  The projection, the
  * reduction of the split partials and all state updates are FP64 in every
  * case; the loss term f_i sum_j R_ij f_j is folded into the packed operand
- * of the GEMM paths and of the FP64 stream (so it takes the contraction's
- * precision there) and is summed in FP64 on the FP32 single-distribution
- * and exact-form streams. */
+ * of the GEMM paths and of the plain streams (so it takes the contraction's
+ * precision there) and is summed in FP64 on the exact-form streams. */
 typedef enum {
     KXG_F64 = 0,     /* FP64 stream over the kept blocks of the packed
                         A' (the dense tensor for the exact forms)          */
-    KXG_F32 = 1,     /* FP32: stream if b_cap <= 4, else MFMA GEMM        */
+    KXG_F32 = 1,     /* FP32: stream over the packed kept blocks if
+                        b_cap <= 4, else MFMA GEMM                        */
     KXG_BF16X3 = 2,  /* BF16 MFMA, hi+lo split of A and of f_n f_m,
                         3 products, FP32 accumulation                     */
     KXG_F16X3 = 3,   /* FP16 MFMA, hi+lo split with power-of-two scaling  */
@@ -76,9 +76,9 @@ typedef enum {
 /* Extra bit of kxg_kernel_build's prec_mask: a lean handle keeps only the
  * tensors its evaluations read.  The dense FP64 tensor is released after
  * the build unless KXG_F64 is in the mask (FP64 evaluations and
- * kxg_kernel_export of A then return KXG_EUNSUPPORTED); the dense FP32 copy
- * is built only for handles with b_cap <= 4 (the single-distribution
- * stream) or with the bracket table.  Meant for callers that admit work by
+ * kxg_kernel_export of A then return KXG_EUNSUPPORTED).  (On every handle
+ * the dense FP32 copy is built only with the bracket table, for the FP32
+ * exact forms.)  Meant for callers that admit work by
  * memory footprint. */
 #define KXG_LEAN (1u << 9)
 
@@ -159,11 +159,12 @@ typedef struct {
                                  every i-block of the group for each pair kept
                                  (the union over the group); they are streamed
                                  through LDS whether multiplied or not */
-    int64_t blocks64;         /* (i-block, pair) blocks of the packed FP64
-                                 operand the plain FP64 evaluation streams (the
-                                 same blocks as the FP32 operand; each 32 rows
-                                 of 16 x 16 values, 64 KiB; 0 on handles
-                                 without FP64) */
+    int64_t blocks64;         /* (i-block, pair) blocks of the packed operand
+                                 the plain evaluations stream (the same blocks
+                                 as the FP32 GEMM operand; each 32 rows of
+                                 16 x 16 values: 64 KiB in FP64, 32 KiB in
+                                 FP32 on single-distribution handles; 0 on
+                                 handles with neither) */
 } kxg_kernel_info;
 
 /* Fill *out for handle k.  Errors: KXG_EINVAL (null argument). */

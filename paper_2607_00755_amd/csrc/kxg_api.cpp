@@ -70,7 +70,7 @@ static void release(kxg_kernel *k)
     void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_R, k->d_A32,
                     k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs, k->d_JL, k->d_invdK,
                     k->d_pairs_c, k->d_cib, k->d_units, k->d_pairs16, k->d_cit16,
-                    k->d_units16, k->d_act16, k->d_P64, k->d_pairs64, k->d_ib64};
+                    k->d_units16, k->d_act16, k->d_P64, k->d_P32, k->d_pairs64, k->d_ib64};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     free_workspace(k->ws);
@@ -172,11 +172,13 @@ static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want64, bool want
                 }
         }
     };
-    if (want64) {
-        // the plain FP64 evaluation streams the kept blocks row by row; a
-        // workgroup takes chunk64 values of one row (whole steps of 512),
-        // sized so that one launch has about KXG_PSTREAM_ROWS_TARGET
-        // non-empty workgroups
+    const bool wantp32 = want32 && b_cap <= 4;
+    if (want64 || wantp32) {
+        // the plain evaluations (FP64; FP32 on single-distribution handles)
+        // stream the kept blocks row by row; a workgroup takes one chunk of
+        // one row (whole 16-byte load steps of 256 threads, at most one
+        // round of loads per thread), sized so that one launch has about
+        // KXG_PSTREAM_ROWS_TARGET non-empty workgroups
         std::vector<int> pairs_c, cib, cnt, first, mask;
         compact(1, pairs_c, cib, cnt, first, mask);
         k->ncomp64 = (long)cib.size();
@@ -184,24 +186,35 @@ static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want64, bool want
         tab.insert(tab.end(), cib.begin(), cib.end());
         std::vector<int> ibt(2 * (size_t)g.nib);
         int maxcnt = 0;
+        long total = 0;
         for (int ib = 0; ib < g.nib; ++ib) {
             ibt[2 * ib] = first[ib];
             ibt[2 * ib + 1] = cnt[ib];
             maxcnt = std::max(maxcnt, cnt[ib]);
+            total += (long)cnt[ib] * std::min(kIBlk, k->n - ib * kIBlk) * 256;
         }
-        long total = 0;
-        for (int ib = 0; ib < g.nib; ++ib) total += (long)cnt[ib] * std::min(kIBlk, k->n - ib * kIBlk) * 256;
-        long chunk = div_up(std::max<long>(1, total), KXG_PSTREAM_ROWS_TARGET);
-        chunk = std::min<long>(std::max<long>(div_up(chunk, 512) * 512, 2048), kPStreamChunk);
-        k->chunk64 = (int)chunk;
-        k->nsplit64 = std::max(1, div_up((long)maxcnt * 256, chunk));
-        st = dalloc(&k->d_P64, (size_t)std::max<long>(1, k->ncomp64) * kIBlk * 256);
+        auto split = [&](int bytes, int &chunk_out, int &nsplit_out) {
+            const long step = 256 * (16 / bytes);
+            long chunk = div_up(std::max<long>(1, total), KXG_PSTREAM_ROWS_TARGET);
+            chunk = std::min<long>(std::max<long>(div_up(chunk, step) * step, 4 * step), pstream_chunk(bytes));
+            chunk_out = (int)chunk;
+            nsplit_out = std::max(1, div_up((long)maxcnt * 256, chunk));
+        };
+        const size_t vals = (size_t)std::max<long>(1, k->ncomp64) * kIBlk * 256;
+        if (want64) {
+            split(8, k->chunk64, k->nsplit64);
+            st = dalloc(&k->d_P64, vals);
+        }
+        if (st == KXG_OK && wantp32) {
+            split(4, k->chunk32, k->nsplit32);
+            st = dalloc(&k->d_P32, vals);
+        }
         if (st == KXG_OK) st = dalloc(&k->d_pairs64, std::max<size_t>(3, tab.size()));
         if (st == KXG_OK) st = dalloc(&k->d_ib64, ibt.size());
         if (st != KXG_OK) return st;
         e = h2d(k->d_pairs64, tab);
         if (e == hipSuccess) e = h2d(k->d_ib64, ibt);
-        if (e == hipSuccess) e = launch_pack_f64(*k, s);
+        if (e == hipSuccess) e = launch_pack_rows(*k, s);
     }
     if (e == hipSuccess && want32) {
         std::vector<int> pairs_c, cib, cnt, first, mask;
@@ -479,7 +492,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     KXG_ALLOC(k->d_RT, n2);
     KXG_ALLOC(k->d_R, n2);
     KXG_ALLOC(k->d_pairs, 2 * (size_t)g.npairs);
-    if (want32 && (!lean || b_cap <= 4 || want_jl)) { KXG_ALLOC(k->d_A32, n3); }
+    if (want32 && want_jl) { KXG_ALLOC(k->d_A32, n3); }     // (the FP32 exact forms stream it)
     if (wanth) { KXG_ALLOC(k->d_hrow, (size_t)g.ipad); }
     if (want_jl) { KXG_ALLOC(k->d_JL, n3); KXG_ALLOC(k->d_invdK, (size_t)n); }
     double *d_xmu = nullptr, *d_wmu = nullptr;
@@ -548,11 +561,12 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     const size_t jl = want_jl ? n3 * sizeof(uint16_t) : 0;
     // (FP64: the packed blocks and R; the dense tensor and the brackets for
     // the exact forms)
-    const size_t packed64 = (size_t)k->ncomp64 * kIBlk * 256;
+    const size_t packed64 = k->d_P64 ? (size_t)k->ncomp64 * kIBlk * 256 : 0;
+    const size_t packed32 = k->d_P32 ? (size_t)k->ncomp64 * kIBlk * 256 : 0;
     if (keep64) k->bytes[KXG_F64] = (packed64 + n2) * sizeof(double) + (want_jl ? n3 * sizeof(double) + jl : 0);
     if (want32)
-        k->bytes[KXG_F32] = ((k->d_A32 ? n3 : 0) + (size_t)k->ncomp * kBlk * 512) * sizeof(float) +
-                            n2 * sizeof(double) + (k->d_A32 ? jl : 0);
+        k->bytes[KXG_F32] = (packed32 + (want_jl ? n3 : 0) + (size_t)k->ncomp * kBlk * 512) * sizeof(float) +
+                            n2 * sizeof(double) + (want_jl ? jl : 0);
     const size_t packed16 = (size_t)k->ncomp16 * KXG_LDS_IBW * kBlk * 1024;   // hi + lo values
     if (wantbf) k->bytes[KXG_BF16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
     if (prec_mask & KXG_PREC_BIT(KXG_F16X3)) k->bytes[KXG_F16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
@@ -564,7 +578,8 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
               (k->d_A64 ? n3 * sizeof(double) : 0) + (k->d_A32 ? n3 * sizeof(float) : 0) + jl +
               (want_jl ? (size_t)n * sizeof(double) : 0) +
               (size_t)k->ncomp * kBlk * 512 * sizeof(float) + (wantbf ? packed16 * sizeof(uint16_t) : 0) +
-              packed64 * sizeof(double) + (3 * (size_t)k->ncomp64 + 2 * (size_t)g.nib) * sizeof(int) +
+              packed64 * sizeof(double) + packed32 * sizeof(float) +
+              (k->ncomp64 || packed64 || packed32 ? (3 * (size_t)k->ncomp64 + 2 * (size_t)g.nib) * sizeof(int) : 0) +
               (wanth ? packed16 * sizeof(uint16_t) + (size_t)g.ipad * sizeof(float) : 0) +
               k->ws.part_bytes + 2 * fbytes + (size_t)k->ws.bpad_cap * sizeof(float);
     *out = k;
@@ -593,7 +608,7 @@ kxg_status kxg_kernel_stats(const kxg_kernel *k, kxg_kernel_info *out)
     out->max_slots = k->maxslots;
     out->blocks16 = (k->d_Gbf || k->d_Gh) ? k->mult16 : 0;
     out->staged16 = (k->d_Gbf || k->d_Gh) ? k->ncomp16 * KXG_LDS_IBW : 0;
-    out->blocks64 = k->d_P64 ? k->ncomp64 : 0;
+    out->blocks64 = (k->d_P64 || k->d_P32) ? k->ncomp64 : 0;
     out->nnz_packed = (k->d_G32 || k->d_Gbf || k->d_Gh) ? k->nnz_packed : 0;
     return KXG_OK;
 }

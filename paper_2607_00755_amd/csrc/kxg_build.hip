@@ -287,15 +287,16 @@ __global__ void k_pack_f32(int n, long ncomp, const int *__restrict__ pairs_c,
     }
 }
 
-// FP64 operand of the plain evaluation over the kept blocks, row by row:
-// row i of i-block ib = i / 32 starts at (first_ib * 32 + (i % 32) cnt_ib)
-// blocks of 256 values and holds the blocks of the i-block's kept pairs in
-// order, each [dk][dm] (m fastest).  Work item = (kept block c, row of the
-// i-block, value).
-__global__ void k_pack_f64(int n, long ncomp, const int *__restrict__ pairs,
-                           const int *__restrict__ ib64, const int *__restrict__ cib,
-                           const double *__restrict__ A, const double *__restrict__ RT,
-                           double *__restrict__ P)
+// Operand of the plain evaluation over the kept blocks (FP64 or FP32), row
+// by row: row i of i-block ib = i / 32 starts at (first_ib * 32 + (i % 32)
+// cnt_ib) blocks of 256 values and holds the blocks of the i-block's kept
+// pairs in order, each [dk][dm] (m fastest).  Work item = (kept block c, row
+// of the i-block, value).
+template <typename T>
+__global__ void k_pack_rows(int n, long ncomp, const int *__restrict__ pairs,
+                            const int *__restrict__ ib64, const int *__restrict__ cib,
+                            const double *__restrict__ A, const double *__restrict__ RT,
+                            T *__restrict__ P)
 {
     const long total = ncomp * kIBlk * 256;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -307,7 +308,7 @@ __global__ void k_pack_f64(int n, long ncomp, const int *__restrict__ pairs,
         const int ib = cib[c];
         const int first = ib64[2 * ib], cnt = ib64[2 * ib + 1];
         const long dst = ((long)first * kIBlk + (long)r * cnt + (c - first)) * 256 + w;
-        P[dst] = packed_value(A, RT, n, ib * kIBlk + r, pairs[2 * c], pairs[2 * c + 1], w / kBlk, w % kBlk);
+        P[dst] = (T)packed_value(A, RT, n, ib * kIBlk + r, pairs[2 * c], pairs[2 * c + 1], w / kBlk, w % kBlk);
     }
 }
 
@@ -464,12 +465,15 @@ hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_pack_f64(const kxg_kernel &k, hipStream_t s)
+hipError_t launch_pack_rows(const kxg_kernel &k, hipStream_t s)
 {
     const long tot = k.ncomp64 * kIBlk * 256;
-    if (tot > 0)
-        hipLaunchKernelGGL(k_pack_f64, dim3(grid_for(tot)), dim3(256), 0, s, k.n, k.ncomp64,
+    if (tot > 0 && k.d_P64)
+        hipLaunchKernelGGL(k_pack_rows<double>, dim3(grid_for(tot)), dim3(256), 0, s, k.n, k.ncomp64,
                            k.d_pairs64, k.d_ib64, k.d_pairs64 + 2 * k.ncomp64, k.d_A64, k.d_RT, k.d_P64);
+    if (tot > 0 && k.d_P32)
+        hipLaunchKernelGGL(k_pack_rows<float>, dim3(grid_for(tot)), dim3(256), 0, s, k.n, k.ncomp64,
+                           k.d_pairs64, k.d_ib64, k.d_pairs64 + 2 * k.ncomp64, k.d_A64, k.d_RT, k.d_P32);
     return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@
 #include "kxg_internal.h"
 #include "kxg_step.h"
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 
@@ -29,12 +30,6 @@ namespace {
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
-#ifndef KXG_STREAM_UNROLL
-#define KXG_STREAM_UNROLL 16
-#endif
-#ifndef KXG_STREAM_NT
-#define KXG_STREAM_NT 1
-#endif
 // shape of the LDS-shared 16-bit GEMM: b-blocks and i-blocks per wave
 #ifndef KXG_STREAM_ROWS_TARGET
 #define KXG_STREAM_ROWS_TARGET 2048   // K splits x rows of a stream launch aimed at (more for n below it)
@@ -53,145 +48,31 @@ inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 #endif
 
 // ---------------------------------------------------------------------------
-// Stream gain over the dense tensor (FP32 single-distribution handles):
-// grid (split, i, group of BT distributions).  Each workgroup
-// reads a contiguous chunk of row i of the dense tensor once and forms
-// sum A[i][k][m] f_k f_m for its BT distributions, f taken from LDS; the
-// (k, m) position of each element is tracked incrementally.  With R given
-// (row order), the split-0 workgroups also subtract the loss
-// f_i sum_m R_im f_m (FP64), so the partials sum to gain - loss.
-template <typename T, int VEC, int BT>
-__global__ __launch_bounds__(256) void k_stream(const T *__restrict__ A,
-                                                const double *__restrict__ f, int n, int B,
-                                                int chunk, double *__restrict__ part,
-                                                const double *__restrict__ R)
-{
-    extern __shared__ double smem_d[];
-    T *fs = reinterpret_cast<T *>(smem_d);
-    __shared__ double red[4][BT];
-    __shared__ double redl[4][BT];
-    const int split = blockIdx.x, i = blockIdx.y, b0 = blockIdx.z * BT;
-    const bool loss = R && split == 0;
-    double lsum[BT];
-#pragma unroll
-    for (int bb = 0; bb < BT; ++bb) lsum[bb] = 0.0;
-    if (loss) {
-        for (int m = threadIdx.x; m < n; m += 256) {
-            const double r = R[(long)i * n + m];
-#pragma unroll
-            for (int bb = 0; bb < BT; ++bb)
-                if (b0 + bb < B) lsum[bb] += r * f[(long)(b0 + bb) * n + m];
-        }
-    }
-    for (int q = threadIdx.x; q < BT * n; q += 256) {
-        const int bb = q / n, m = q - bb * n;
-        fs[q] = (b0 + bb < B) ? (T)f[(long)(b0 + bb) * n + m] : (T)0;
-    }
-    __syncthreads();
-    const long n2 = (long)n * n;
-    const T *row = A + (long)i * n2;
-    const long e_beg = (long)split * chunk;
-    const long e_end = e_beg + chunk < n2 ? e_beg + chunk : n2;
-    long e = e_beg + (long)threadIdx.x * VEC;
-    int k = (int)(e / n), m = (int)(e - (long)k * n);
-    constexpr int step = 256 * VEC;
-    const int sk = step / n, sm = step - (step / n) * n;
-    T acc[BT];
-#pragma unroll
-    for (int bb = 0; bb < BT; ++bb) acc[bb] = (T)0;
-    typedef T vec_t __attribute__((ext_vector_type(VEC)));
-    // KXG_STREAM_UNROLL loads in flight per thread; A is read once per call,
-    // so the loads are marked non-temporal
-    constexpr int UN = KXG_STREAM_UNROLL;
-    for (; e + (UN - 1) * step < e_end; e += UN * step) {
-        vec_t a[UN];
-        int kk[UN], mm[UN];
-#pragma unroll
-        for (int u = 0; u < UN; ++u) {
-#if KXG_STREAM_NT
-            a[u] = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(row + e + (long)u * step));
-#else
-            a[u] = *reinterpret_cast<const vec_t *>(row + e + (long)u * step);
-#endif
-            kk[u] = k;
-            mm[u] = m;
-            m += sm;
-            k += sk;
-            if (m >= n) { m -= n; ++k; }
-        }
-#pragma unroll
-        for (int u = 0; u < UN; ++u) {
-#pragma unroll
-            for (int bb = 0; bb < BT; ++bb) {
-                const T *fb = fs + bb * n;
-                T s = (T)0;
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) s += a[u][v] * fb[mm[u] + v];
-                acc[bb] += fb[kk[u]] * s;
-            }
-        }
-    }
-    for (; e < e_end; e += step) {
-        const vec_t a = *reinterpret_cast<const vec_t *>(row + e);
-#pragma unroll
-        for (int bb = 0; bb < BT; ++bb) {
-            const T *fb = fs + bb * n;
-            T s = (T)0;
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) s += a[v] * fb[m + v];
-            acc[bb] += fb[k] * s;
-        }
-        m += sm;
-        k += sk;
-        if (m >= n) { m -= n; ++k; }
-    }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int bb = 0; bb < BT; ++bb) {
-        double v = (double)acc[bb];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) red[wave][bb] = v;
-        if (loss) {
-            double l = lsum[bb];
-            for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
-            if (lane == 0) redl[wave][bb] = l;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < BT && b0 + (int)threadIdx.x < B) {
-        const int bb = threadIdx.x;
-        double v = ((red[0][bb] + red[1][bb]) + red[2][bb]) + red[3][bb];
-        if (loss) {
-            const double rate = ((redl[0][bb] + redl[1][bb]) + redl[2][bb]) + redl[3][bb];
-            v -= f[(long)(b0 + bb) * n + i] * rate;
-        }
-        part[((long)split * B + b0 + bb) * n + i] = v;
-    }
-}
-
-// Plain FP64 evaluation over the packed operand: grid (split, i, group of
-// BT distributions).  Row i holds, for each kept (kb, mb) pair of its
-// i-block, the 16 x 16 block of A'[i,k,m] + A'[i,m,k] (A' = A with the loss
-// folded in, kb < mb) or of A'[i,k,m] (kb = mb), [dk][dm]; each workgroup
-// reads `chunk` consecutive values of the row once (16-byte non-temporal
-// loads, two values of one block row each) and forms sum P f_k f_m for its
-// BT distributions, f zero-padded to whole blocks in LDS.  The (kb, mb) of
-// the pairs its chunk spans are staged in LDS.  Split s of a row shorter
-// than s * chunk writes a zero partial, so every row has `gridDim.x`
-// partials (gain minus loss) in split order.
-template <int BT>
-__global__ __launch_bounds__(256) void k_stream_p(const double *__restrict__ P,
+// Plain evaluation over the packed operand (FP64, or FP32 on
+// single-distribution handles): grid (split, i, group of BT distributions).
+// Row i holds, for each kept (kb, mb) pair of its i-block, the 16 x 16 block
+// of A'[i,k,m] + A'[i,m,k] (A' = A with the loss folded in, kb < mb) or of
+// A'[i,k,m] (kb = mb), [dk][dm]; each workgroup reads `chunk` consecutive
+// values of the row once (16-byte non-temporal loads of VEC values of one
+// block row) and forms sum P f_k f_m for its BT distributions, f zero-padded
+// to whole blocks in LDS; per-thread sums in T, the workgroup's reduction
+// in FP64.  The (kb, mb) of the pairs its chunk spans are staged in LDS.
+// Split s of a row shorter than s * chunk writes a zero partial, so every
+// row has `gridDim.x` partials (gain minus loss) in split order.
+template <typename T, int BT>
+__global__ __launch_bounds__(256) void k_stream_p(const T *__restrict__ P,
                                                   const int *__restrict__ pairs,
                                                   const int *__restrict__ ib64,
                                                   const double *__restrict__ f, int n, int nbf, int B,
                                                   int chunk, double *__restrict__ part)
 {
     extern __shared__ double smem_d[];
-    double *fs = smem_d;                            // [BT][nbf]
+    T *fs = reinterpret_cast<T *>(smem_d);          // [BT][nbf]
     __shared__ int2 spair[kPStreamPairs];           // (16 kb, 16 mb)
     __shared__ double red[4][BT];
-    typedef double d2 __attribute__((ext_vector_type(2)));
-    constexpr int UN = KXG_PSTREAM_UNROLL, STEP = 512;
+    constexpr int VEC = 16 / sizeof(T);
+    typedef T vt __attribute__((ext_vector_type(VEC)));
+    constexpr int UN = KXG_PSTREAM_UNROLL, STEP = 256 * VEC;
     const int split = blockIdx.x, i = blockIdx.y, b0 = blockIdx.z * BT;
     const int ib = i / kIBlk;
     const int first = ib64[2 * ib], cnt = ib64[2 * ib + 1];
@@ -203,32 +84,31 @@ __global__ __launch_bounds__(256) void k_stream_p(const double *__restrict__ P,
         return;
     }
     const long e_end = e_beg + chunk < len ? e_beg + chunk : len;
-    const double *row = P + ((long)first * kIBlk + (long)(i % kIBlk) * cnt) * 256;
+    const T *row = P + ((long)first * kIBlk + (long)(i % kIBlk) * cnt) * 256;
     // the first UN loads of every thread go out before f and the pair
     // table are staged, so that their latencies overlap (a chunk is one
     // such round unless the host chose a longer one)
-    auto load_round = [&](long e, d2 (&a)[UN]) {
+    auto load_round = [&](long e, vt (&a)[UN]) {
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
             const long eu = e + (long)u * STEP;
-            a[u] = eu < e_end ? __builtin_nontemporal_load(reinterpret_cast<const d2 *>(row + eu))
-                              : d2{0.0, 0.0};
+            a[u] = eu < e_end ? __builtin_nontemporal_load(reinterpret_cast<const vt *>(row + eu)) : vt{};
         }
     };
-    long e = e_beg + 2 * (long)threadIdx.x;
-    d2 a[UN];
+    long e = e_beg + VEC * (long)threadIdx.x;
+    vt a[UN];
     load_round(e, a);
     const int c0 = (int)(e_beg >> 8), nc = (int)((e_end - 1) >> 8) - c0 + 1;
     for (int q = threadIdx.x; q < BT * nbf; q += 256) {
         const int bb = q / nbf, m = q - bb * nbf;
-        fs[q] = (b0 + bb < B && m < n) ? f[(long)(b0 + bb) * n + m] : 0.0;
+        fs[q] = (b0 + bb < B && m < n) ? (T)f[(long)(b0 + bb) * n + m] : (T)0;
     }
     for (int c = threadIdx.x; c < nc; c += 256)
         spair[c] = make_int2(pairs[2 * (first + c0 + c)] * kBlk, pairs[2 * (first + c0 + c) + 1] * kBlk);
     __syncthreads();
-    double acc[BT];
+    T acc[BT];
 #pragma unroll
-    for (int bb = 0; bb < BT; ++bb) acc[bb] = 0.0;
+    for (int bb = 0; bb < BT; ++bb) acc[bb] = (T)0;
     while (e < e_end) {
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
@@ -239,8 +119,10 @@ __global__ __launch_bounds__(256) void k_stream_p(const double *__restrict__ P,
                 const int kk = pr.x + (w >> 4), mm = pr.y + (w & 15);
 #pragma unroll
                 for (int bb = 0; bb < BT; ++bb) {
-                    const double *fb = fs + bb * nbf;
-                    const double sv = a[u].x * fb[mm] + a[u].y * fb[mm + 1];
+                    const T *fb = fs + bb * nbf;
+                    T sv = (T)0;
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) sv += a[u][v] * fb[mm + v];
                     acc[bb] += fb[kk] * sv;
                 }
             }
@@ -251,7 +133,7 @@ __global__ __launch_bounds__(256) void k_stream_p(const double *__restrict__ P,
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int bb = 0; bb < BT; ++bb) {
-        double v = acc[bb];
+        double v = (double)acc[bb];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
         if (lane == 0) red[wave][bb] = v;
     }
@@ -1383,8 +1265,8 @@ kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws)
     // rows of the GEMM operands: a multiple of both batch tilings
     constexpr int tile16 = 4 * KXG_LDS_BBW * 32;
     const int bpad = div_up(div_up(b_cap, 128) * 128, tile16) * tile16;
-    size_t need = (size_t)std::max(stream_splits(n), k.nsplit64) * b_cap * n * sizeof(double);
-    if (k.d_JL) need = (size_t)stream_splits(n) * b_cap * 4 * n * sizeof(double);
+    size_t need = (size_t)std::max({stream_splits(n), k.nsplit64, k.nsplit32}) * b_cap * n * sizeof(double);
+    if (k.d_JL) need = std::max(need, (size_t)stream_splits(n) * b_cap * 4 * n * sizeof(double));
     const size_t slots = (size_t)std::max(k.d_G32 ? k.maxslots : 0, (k.d_Gbf || k.d_Gh) ? k.maxslots16 : 0);
     need = std::max(need, slots * bpad * k.geo.ipad * sizeof(float));
     need += (size_t)b_cap * n * sizeof(double);      // loss rates
@@ -1422,7 +1304,7 @@ struct Path {
 static Path path_of(const kxg_kernel &k, int prec, int B)
 {
     Path p{false, false, 0};
-    if (prec == KXG_F64 || (prec == KXG_F32 && B <= 4 && k.b_cap <= 4 && k.d_A32)) {
+    if (prec == KXG_F64 || (prec == KXG_F32 && B <= 4 && k.b_cap <= 4 && k.d_P32)) {
         p.stream = true;
         return p;
     }
@@ -1527,59 +1409,31 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
     // freeze-in slots, which is tested on the predictor's input only
     const bool want_rate = diag != nullptr ||
                            (step_in && step_in->freeze_in && step_in->mode == kStepHeunPred);
-    if (P.stream && prec == KXG_F64) {
-        // plain FP64 evaluation over the packed kept blocks, the loss folded
-        // in; loss rates only for diagnostics and the regime switch
-        if (!k.d_P64) {
-            set_error("kxg_eval: FP64 operand not built");
+    if (P.stream) {
+        // plain evaluation over the packed kept blocks (FP64; FP32 on
+        // single-distribution handles), the loss folded in; loss rates only
+        // for diagnostics and the regime switch of freeze-in steppers
+        const bool dbl = prec == KXG_F64;
+        if (dbl ? !k.d_P64 : !k.d_P32) {
+            set_error("kxg_eval: packed stream operand not built");
             return KXG_EUNSUPPORTED;
         }
         const int BT = B == 1 ? 1 : (B == 2 ? 2 : 4);
         const int nbf = k.geo.nb * kBlk;
-        const dim3 grid(k.nsplit64, n, div_up(B, BT));
-        const size_t shm = (size_t)BT * nbf * sizeof(double);
+        const int nsplit = dbl ? k.nsplit64 : k.nsplit32;
+        const dim3 grid(nsplit, n, div_up(B, BT));
+        const size_t shm = (size_t)BT * nbf * (dbl ? sizeof(double) : sizeof(float));
         double *part = static_cast<double *>(ws.part);
         profile_mark_begin(s);
-#define KXG_SP(BTV) \
-    hipLaunchKernelGGL((k_stream_p<BTV>), grid, dim3(256), shm, s, k.d_P64, k.d_pairs64, k.d_ib64, f, n, nbf, B, \
-                       k.chunk64, part)
-        if (BT == 1) KXG_SP(1); else if (BT == 2) KXG_SP(2); else KXG_SP(4);
+#define KXG_SP(T, P, CH, BTV) \
+    hipLaunchKernelGGL((k_stream_p<T, BTV>), grid, dim3(256), shm, s, P, k.d_pairs64, k.d_ib64, f, n, nbf, B, CH, part)
+#define KXG_SP2(T, P, CH) \
+    if (BT == 1) KXG_SP(T, P, CH, 1); else if (BT == 2) KXG_SP(T, P, CH, 2); else KXG_SP(T, P, CH, 4)
+        if (dbl) { KXG_SP2(double, k.d_P64, k.chunk64); } else { KXG_SP2(float, k.d_P32, k.chunk32); }
+#undef KXG_SP2
 #undef KXG_SP
         profile_mark_end(s);
         KXG_TRY_HIP(hipGetLastError());
-        if (want_rate) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
-        KXG_TRY_HIP(launch_epilogue<double>(part, k.nsplit64, SlotCounts{}, (long)B * n, n, nullptr, nullptr,
-                                            want_rate ? rate : nullptr, f, k, B, project, C, diag, step, s,
-                                            nullptr, 0.0, 1));
-        return KXG_OK;
-    }
-    if (P.stream) {
-        // FP32 single-distribution handles: the dense FP32 copy of A (FP64
-        // always has the packed operand, above)
-        const int ns = stream_splits(n);
-        const long n2 = (long)n * n;
-        const int vec = (n % 4 == 0) ? 4 : ((n % 2 == 0) ? 2 : 1);
-        int chunk = div_up(n2, ns);
-        chunk = div_up(chunk, 256 * vec) * (256 * vec);
-        const int nsplit = (int)((n2 + chunk - 1) / chunk);
-        // distributions per pass: one for a single distribution (no idle
-        // lanes of work), four otherwise
-        const int BT = B == 1 ? 1 : (B == 2 ? 2 : 4);
-        const dim3 grid(nsplit, n, div_up(B, BT));
-        const size_t shm = (size_t)BT * n * sizeof(float);
-        double *part = static_cast<double *>(ws.part);
-        profile_mark_begin(s);
-#define KXG_ST(T, V, BTV) \
-    hipLaunchKernelGGL((k_stream<T, V, BTV>), grid, dim3(256), shm, s, k.d_A32, f, n, B, chunk, part, k.d_R)
-#define KXG_ST2(T, V) \
-    if (BT == 1) KXG_ST(T, V, 1); else if (BT == 2) KXG_ST(T, V, 2); else KXG_ST(T, V, 4)
-        if (vec == 4) { KXG_ST2(float, 4); } else if (vec == 2) { KXG_ST2(float, 2); } else { KXG_ST2(float, 1); }
-#undef KXG_ST2
-#undef KXG_ST
-        profile_mark_end(s);
-        KXG_TRY_HIP(hipGetLastError());
-        // the split-0 partials carry the loss term; loss rates only for
-        // diagnostics and the regime switch of freeze-in steppers
         if (want_rate) KXG_TRY_HIP(launch_rate(k, f, B, rate, s));
         KXG_TRY_HIP(launch_epilogue<double>(part, nsplit, SlotCounts{}, (long)B * n, n, nullptr, nullptr,
                                             want_rate ? rate : nullptr, f, k, B, project, C, diag, step, s,
@@ -1692,7 +1546,7 @@ static size_t call_workspace(const kxg_kernel &k, int prec, int B, uint32_t flag
     if (exact) {
         part = (size_t)stream_splits(n) * B * 4 * n * sizeof(double);
     } else if (P.stream) {
-        part = (size_t)std::max(stream_splits(n), k.nsplit64) * B * n * sizeof(double);
+        part = (size_t)std::max({stream_splits(n), k.nsplit64, k.nsplit32}) * B * n * sizeof(double);
     } else {
         bpad = P.bpad;
         const int slots = P.lds ? k.maxslots16 : k.maxslots;

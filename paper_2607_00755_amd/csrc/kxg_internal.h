@@ -29,10 +29,10 @@ constexpr int kMaxDevices = 64;      // devices the allocation-free evaluation k
 #define KXG_PSTREAM_UNROLL 8   // 16-byte loads in flight per thread in the packed FP64 stream
 #endif
 constexpr int kPStreamPairs = 128;   // kept pairs one packed-stream workgroup stages (its chunk spans at most this)
-// largest chunk of the packed FP64 stream: one round of loads per thread
-// (two values per load, 256 threads)
-constexpr int kPStreamChunk = KXG_PSTREAM_UNROLL * 512;
-static_assert(kPStreamChunk / 256 <= kPStreamPairs, "a chunk spans at most kPStreamPairs pairs");
+// largest chunk of the packed stream of element size `bytes`: one round of
+// 16-byte loads per thread (256 threads)
+constexpr int pstream_chunk(int bytes) { return KXG_PSTREAM_UNROLL * 256 * (16 / bytes); }
+static_assert(pstream_chunk(4) / 256 <= kPStreamPairs, "a chunk spans at most kPStreamPairs pairs");
 
 // Tuning of the GEMM launches (overridable at build time).
 #ifndef KXG_GEMM_WG_TARGET
@@ -127,14 +127,17 @@ struct kxg_kernel {
     kxg::SlotCounts nslot16;
     long ncomp16 = 0;
     int nunits16 = 0, maxslots16 = 0;
-    // FP64 operand of the plain (stream) evaluation: the same non-zero
+    // Operands of the plain (stream) evaluations: the same non-zero
     // (i-block, pair) blocks as the FP32 GEMM, row by row: row i holds the
-    // 16 x 16 blocks of its i-block's kept pairs, [pair][dk][dm]
+    // 16 x 16 blocks of its i-block's kept pairs, [pair][dk][dm]; FP64 for
+    // FP64 evaluations, FP32 for the single-distribution FP32 handles
     double *d_P64 = nullptr;
+    float *d_P32 = nullptr;
     int *d_pairs64 = nullptr;    // [ncomp64][2] (kb, mb), i-block by i-block, then [ncomp64] their i-blocks
     int *d_ib64 = nullptr;       // [nib][2] first kept pair and count of each i-block
     long ncomp64 = 0;
-    int chunk64 = 0, nsplit64 = 0;   // elements per stream workgroup, K splits (partials) per row
+    int chunk64 = 0, nsplit64 = 0;   // FP64: values per stream workgroup, K splits (partials) per row
+    int chunk32 = 0, nsplit32 = 0;   // FP32: the same
     uint16_t *d_JL = nullptr;    // [n][n][n] interpolation bracket j_L (0xFFFF: cut)
     double *d_invdK = nullptr;   // [n] 1 / (K_{j+1} - K_j) (0 for the last point)
     kxg::Geometry geo;
@@ -153,7 +156,7 @@ hipError_t launch_derive(kxg_kernel &k, hipStream_t s);
 hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, unsigned int *nnz,
                            hipStream_t s);
 hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s);
-hipError_t launch_pack_f64(const kxg_kernel &k, hipStream_t s);
+hipError_t launch_pack_rows(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_pack_16(const kxg_kernel &k, int ibw, hipStream_t s);
 hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s);
 // device self-calibration (kxg_probe.hip)

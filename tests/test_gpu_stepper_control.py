@@ -129,8 +129,10 @@ def test_set_many_equals_single_sets(dev, kind, prec):
 
 
 def test_lean_handle(dev):
-    """A lean FP32 GEMM handle drops the dense FP64 and FP32 tensors, gives
-    bit-identical batched results and refuses FP64 evaluation and export."""
+    """A lean FP32 GEMM handle drops the dense FP64 tensor and the packed
+    FP64 operand (neither handle holds the dense FP32 copy, which only the
+    exact forms read), gives bit-identical batched results and refuses FP64
+    evaluation and export."""
     n = 96
     p = inputs.log_grid(n, 1e-3, 20.0)
     f0 = torch.tensor(np.stack([s.f0(p) for s in inputs.draw_solves(70, seed=43)]), device=dev)
@@ -140,7 +142,7 @@ def test_lean_handle(dev):
     Cl, _ = lean.eval(f0, prec=kxg.F32)
     torch.cuda.synchronize()
     assert torch.equal(Cf, Cl)
-    assert lean.bytes(-1) + 12 * n ** 3 <= full.bytes(-1)
+    assert lean.bytes(-1) + 8 * n ** 3 + 65536 * full.stats()["blocks64"] <= full.bytes(-1)
     # FP64 evaluations read the packed kept blocks (the FP32 operand's
     # blocks, 64 KiB each in FP64) and R
     sf = full.stats()
