@@ -430,7 +430,11 @@ def paper_timing_curve(dev):
         f = torch.tensor(inputs.two_bump_benchmark(q)[None, :], device=dev)
         C = torch.empty_like(f)
         d = torch.empty((1, kxg.NDIAG), dtype=torch.float64, device=dev)
-        row = {"n": n, "build_ms": round(build_ms, 2)}
+        # bytes one FP64 (FP32) evaluation streams: the weights and brackets
+        # of the blocks that hold a weight, in both (kb, mb) orders
+        nbx = k.stats()["blocks_exact"]
+        row = {"n": n, "build_ms": round(build_ms, 2), "stream_bytes_f64": nbx * (65536 + 16384),
+               "stream_bytes_f32": nbx * (32768 + 16384), "dense_bytes_f64": 10 * n ** 3}
         for prec in (kxg.F64, kxg.F32):
             for _ in range(3):
                 k.eval(f, prec=prec, project=False, log_interp=True, eta=1, out=C, diag=d)

@@ -59,7 +59,8 @@ typedef enum {
  * precision there) and is summed in FP64 on the exact-form streams. */
 typedef enum {
     KXG_F64 = 0,     /* FP64 stream over the kept blocks of the packed
-                        A' (the dense tensor for the exact forms)          */
+                        A' (the exact forms: A and its brackets on the
+                        kept blocks, both orders)                          */
     KXG_F32 = 1,     /* FP32: stream over the packed kept blocks if
                         b_cap <= 4, else MFMA GEMM                        */
     KXG_BF16X3 = 2,  /* BF16 MFMA, hi+lo split of A and of f_n f_m,
@@ -69,17 +70,17 @@ typedef enum {
                         scaling), hi+lo split of f_n f_m: 2 products       */
 } kxg_prec;
 #define KXG_PREC_BIT(p) (1u << (p))
-/* Extra bit of kxg_kernel_build's prec_mask: also build the interpolation
- * bracket table j_L[i][n][m] (2 bytes per entry) that the exact-form
- * evaluations (KXG_INTERP_LOG, KXG_STAT_BOSE, KXG_STAT_FERMI) stream. */
+/* Extra bit of kxg_kernel_build's prec_mask: also build the operands the
+ * exact-form evaluations (KXG_INTERP_LOG, KXG_STAT_BOSE, KXG_STAT_FERMI)
+ * stream: the weights A[i,n,m] (FP64 and/or FP32, as the handle's
+ * precisions ask) and the interpolation brackets j_L (2 bytes each) on the
+ * blocks that hold a weight. */
 #define KXG_WITH_BRACKETS (1u << 8)
 /* Extra bit of kxg_kernel_build's prec_mask: a lean handle keeps only the
  * tensors its evaluations read.  The dense FP64 tensor is released after
  * the build unless KXG_F64 is in the mask (FP64 evaluations and
- * kxg_kernel_export of A then return KXG_EUNSUPPORTED).  (On every handle
- * the dense FP32 copy is built only with the bracket table, for the FP32
- * exact forms.)  Meant for callers that admit work by
- * memory footprint. */
+ * kxg_kernel_export of A then return KXG_EUNSUPPORTED).  Meant for callers
+ * that admit work by memory footprint. */
 #define KXG_LEAN (1u << 9)
 
 /* Angular integral of the reduced kernel (App. B). */
@@ -165,6 +166,12 @@ typedef struct {
                                  16 x 16 values: 64 KiB in FP64, 32 KiB in
                                  FP32 on single-distribution handles; 0 on
                                  handles with neither) */
+    int64_t blocks_exact;     /* (i-block, kb, mb) blocks, both (kb, mb) orders,
+                                 the exact-form evaluations stream: those of
+                                 every pair with a structural weight; each 32
+                                 rows of 16 x 16 weights and brackets (64 KiB
+                                 of FP64 or 32 KiB of FP32 weights, 16 KiB of
+                                 brackets; 0 on handles without brackets) */
 } kxg_kernel_info;
 
 /* Fill *out for handle k.  Errors: KXG_EINVAL (null argument). */

@@ -67,8 +67,9 @@ static kxg_status dalloc(T **ptr, size_t count)
 static void release(kxg_kernel *k)
 {
     if (!k) return;
-    void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_R, k->d_A32,
-                    k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs, k->d_JL, k->d_invdK,
+    void *ptrs[] = {k->d_p, k->d_dp, k->d_E, k->d_K, k->d_h, k->d_A64, k->d_RT, k->d_R,
+                    k->d_G32, k->d_Gbf, k->d_Gh, k->d_hrow, k->d_pairs, k->d_invdK,
+                    k->d_AX64, k->d_AX32, k->d_JX, k->d_xpairs, k->d_xib,
                     k->d_pairs_c, k->d_cib, k->d_units, k->d_pairs16, k->d_cit16,
                     k->d_units16, k->d_act16, k->d_P64, k->d_P32, k->d_pairs64, k->d_ib64};
     for (void *q : ptrs)
@@ -125,7 +126,7 @@ static SlotCounts pack_slot_counts(const std::vector<int> &per_ib)
 }
 
 static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want64, bool want32, bool wantbf, bool wanth,
-                                hipStream_t s)
+                                bool wantx64, bool wantx32, hipStream_t s)
 {
     const Geometry &g = k->geo;
     const size_t nflags = (size_t)g.nib * g.npairs;
@@ -215,6 +216,60 @@ static kxg_status build_compact(kxg_kernel *k, int b_cap, bool want64, bool want
         e = h2d(k->d_pairs64, tab);
         if (e == hipSuccess) e = h2d(k->d_ib64, ibt);
         if (e == hipSuccess) e = launch_pack_rows(*k, s);
+    }
+    if (e == hipSuccess && (wantx64 || wantx32)) {
+        // the exact forms stream A and the brackets over the blocks, in both
+        // (kb, mb) orders, of every pair with a structural weight in the
+        // i-block (a superset of the non-zero entries of A); a workgroup takes
+        // whole load steps of one row, sized like the plain streams
+        std::vector<int> xp, xc, xib(2 * (size_t)g.nib);
+        int maxcnt = 0;
+        long total = 0;
+        for (int ib = 0; ib < g.nib; ++ib) {
+            xib[2 * ib] = (int)xc.size();
+            int pr = 0;
+            for (int kb = 0; kb < g.nb; ++kb)
+                for (int mb = kb; mb < g.nb; ++mb, ++pr) {
+                    if (!nnz[(size_t)ib * g.npairs + pr]) continue;
+                    xp.push_back(kb);
+                    xp.push_back(mb);
+                    xc.push_back(ib);
+                    if (kb != mb) {
+                        xp.push_back(mb);
+                        xp.push_back(kb);
+                        xc.push_back(ib);
+                    }
+                }
+            xib[2 * ib + 1] = (int)xc.size() - xib[2 * ib];
+            maxcnt = std::max(maxcnt, xib[2 * ib + 1]);
+            total += (long)xib[2 * ib + 1] * std::min(kIBlk, k->n - ib * kIBlk) * 256;
+        }
+        k->nx = (long)xc.size();
+        auto split = [&](int bytes, int &chunk_out, int &nsplit_out) {
+            const long step = 256 * (16 / bytes);
+            long chunk = div_up(std::max<long>(1, total), KXG_PSTREAM_ROWS_TARGET);
+            chunk = std::max<long>(div_up(chunk, step) * step, 4 * step);
+            chunk = std::min<long>(chunk, (long)kPStreamPairs / 2 * 256);   // (a multiple of both steps)
+            chunk_out = (int)chunk;
+            nsplit_out = std::max(1, div_up((long)maxcnt * 256, chunk));
+        };
+        xp.insert(xp.end(), xc.begin(), xc.end());
+        const size_t vals = (size_t)std::max<long>(1, k->nx) * kIBlk * 256;
+        if (wantx64) {
+            split(8, k->chunkx64, k->nsplitx64);
+            st = dalloc(&k->d_AX64, vals);
+        }
+        if (st == KXG_OK && wantx32) {
+            split(4, k->chunkx32, k->nsplitx32);
+            st = dalloc(&k->d_AX32, vals);
+        }
+        if (st == KXG_OK) st = dalloc(&k->d_JX, vals);
+        if (st == KXG_OK) st = dalloc(&k->d_xpairs, std::max<size_t>(3, xp.size()));
+        if (st == KXG_OK) st = dalloc(&k->d_xib, xib.size());
+        if (st != KXG_OK) return st;
+        e = h2d(k->d_xpairs, xp);
+        if (e == hipSuccess) e = h2d(k->d_xib, xib);
+        if (e == hipSuccess) e = launch_pack_exact(*k, s);
     }
     if (e == hipSuccess && want32) {
         std::vector<int> pairs_c, cib, cnt, first, mask;
@@ -492,9 +547,8 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     KXG_ALLOC(k->d_RT, n2);
     KXG_ALLOC(k->d_R, n2);
     KXG_ALLOC(k->d_pairs, 2 * (size_t)g.npairs);
-    if (want32 && want_jl) { KXG_ALLOC(k->d_A32, n3); }     // (the FP32 exact forms stream it)
     if (wanth) { KXG_ALLOC(k->d_hrow, (size_t)g.ipad); }
-    if (want_jl) { KXG_ALLOC(k->d_JL, n3); KXG_ALLOC(k->d_invdK, (size_t)n); }
+    if (want_jl) { KXG_ALLOC(k->d_invdK, (size_t)n); }
     double *d_xmu = nullptr, *d_wmu = nullptr;
     if (k->nmu > 0) { KXG_ALLOC(d_xmu, (size_t)k->nmu); KXG_ALLOC(d_wmu, (size_t)k->nmu); }
 #undef KXG_ALLOC
@@ -538,7 +592,6 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     if (e == hipSuccess) e = launch_build_A(*k, d_xmu, d_wmu, s);
     if (e == hipSuccess) e = launch_build_R(*k, s);
     if (e == hipSuccess) e = launch_derive(*k, s);
-    if (e == hipSuccess && want_jl) e = launch_brackets(*k, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (d_xmu) (void)hipFree(d_xmu);
     if (d_wmu) (void)hipFree(d_wmu);
@@ -548,7 +601,7 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
         return KXG_EHIP;
     }
     if (keep64 || want32 || wantbf || wanth) {
-        st = build_compact(k, b_cap, keep64, want32, wantbf, wanth, s);
+        st = build_compact(k, b_cap, keep64, want32, wantbf, wanth, want_jl && keep64, want_jl && want32, s);
         if (st != KXG_OK) { release(k); return st; }
     }
     if (!keep64) {
@@ -558,15 +611,17 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     st = alloc_workspace(*k, b_cap, k->ws);
     if (st != KXG_OK) { release(k); return st; }
     // tensors an evaluation at each precision reads
-    const size_t jl = want_jl ? n3 * sizeof(uint16_t) : 0;
-    // (FP64: the packed blocks and R; the dense tensor and the brackets for
-    // the exact forms)
+    // (plain evaluations: the packed kept blocks and R; the exact forms: A
+    // and the brackets over their blocks)
     const size_t packed64 = k->d_P64 ? (size_t)k->ncomp64 * kIBlk * 256 : 0;
     const size_t packed32 = k->d_P32 ? (size_t)k->ncomp64 * kIBlk * 256 : 0;
-    if (keep64) k->bytes[KXG_F64] = (packed64 + n2) * sizeof(double) + (want_jl ? n3 * sizeof(double) + jl : 0);
+    const size_t xvals = (size_t)k->nx * kIBlk * 256;
+    const size_t jl = k->d_JX ? xvals * sizeof(uint16_t) : 0;
+    const size_t ax64 = k->d_AX64 ? xvals * sizeof(double) : 0, ax32 = k->d_AX32 ? xvals * sizeof(float) : 0;
+    if (keep64) k->bytes[KXG_F64] = (packed64 + n2) * sizeof(double) + (ax64 ? ax64 + jl : 0);
     if (want32)
-        k->bytes[KXG_F32] = (packed32 + (want_jl ? n3 : 0) + (size_t)k->ncomp * kBlk * 512) * sizeof(float) +
-                            n2 * sizeof(double) + (want_jl ? jl : 0);
+        k->bytes[KXG_F32] = (packed32 + (size_t)k->ncomp * kBlk * 512) * sizeof(float) + n2 * sizeof(double) +
+                            (ax32 ? ax32 + jl : 0);
     const size_t packed16 = (size_t)k->ncomp16 * KXG_LDS_IBW * kBlk * 1024;   // hi + lo values
     if (wantbf) k->bytes[KXG_BF16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
     if (prec_mask & KXG_PREC_BIT(KXG_F16X3)) k->bytes[KXG_F16X3] = packed16 * sizeof(uint16_t) + n2 * sizeof(double);
@@ -575,7 +630,8 @@ kxg_status kxg_kernel_build(const kxg_grid *grid, uint32_t prec_mask, int32_t b_
     // everything the handle holds on the device
     const size_t fbytes = (size_t)k->geo.nb * k->ws.bpad_cap * kBlk * sizeof(float);
     k->held = 5 * (size_t)n * sizeof(double) + 2 * n2 * sizeof(double) + 2 * (size_t)g.npairs * sizeof(int) +
-              (k->d_A64 ? n3 * sizeof(double) : 0) + (k->d_A32 ? n3 * sizeof(float) : 0) + jl +
+              (k->d_A64 ? n3 * sizeof(double) : 0) + ax64 + ax32 + jl +
+              (k->d_xpairs ? (3 * (size_t)k->nx + 2 * (size_t)g.nib) * sizeof(int) : 0) +
               (want_jl ? (size_t)n * sizeof(double) : 0) +
               (size_t)k->ncomp * kBlk * 512 * sizeof(float) + (wantbf ? packed16 * sizeof(uint16_t) : 0) +
               packed64 * sizeof(double) + packed32 * sizeof(float) +
@@ -609,6 +665,7 @@ kxg_status kxg_kernel_stats(const kxg_kernel *k, kxg_kernel_info *out)
     out->blocks16 = (k->d_Gbf || k->d_Gh) ? k->mult16 : 0;
     out->staged16 = (k->d_Gbf || k->d_Gh) ? k->ncomp16 * KXG_LDS_IBW : 0;
     out->blocks64 = (k->d_P64 || k->d_P32) ? k->ncomp64 : 0;
+    out->blocks_exact = k->d_JX ? k->nx : 0;
     out->nnz_packed = (k->d_G32 || k->d_Gbf || k->d_Gh) ? k->nnz_packed : 0;
     return KXG_OK;
 }
@@ -664,9 +721,10 @@ static kxg_status check_eval(const kxg_kernel *k, int32_t prec, const double *f_
     kxg_status st = check_prec(k, prec);
     if (st != KXG_OK) return st;
     if (flags & (KXG_INTERP_LOG | KXG_STAT_BOSE | KXG_STAT_FERMI)) {
-        if (!k->d_JL) { set_error("kxg_eval: exact-form evaluation needs a handle built with KXG_WITH_BRACKETS"); return KXG_EUNSUPPORTED; }
+        if (!k->d_JX) { set_error("kxg_eval: exact-form evaluation needs a handle built with KXG_WITH_BRACKETS"); return KXG_EUNSUPPORTED; }
         if (prec != KXG_F64 && prec != KXG_F32) { set_error("kxg_eval: exact-form evaluation runs in FP64 or FP32 only"); return KXG_EUNSUPPORTED; }
-        if (prec == KXG_F32 && !k->d_A32) { set_error("kxg_eval: FP32 tensor not built"); return KXG_EUNSUPPORTED; }
+        if (prec == KXG_F32 && !k->d_AX32) { set_error("kxg_eval: FP32 exact-form operand not built"); return KXG_EUNSUPPORTED; }
+        if (prec == KXG_F64 && !k->d_AX64) { set_error("kxg_eval: FP64 exact-form operand not built"); return KXG_EUNSUPPORTED; }
     }
     return KXG_OK;
 }

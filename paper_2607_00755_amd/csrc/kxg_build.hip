@@ -159,39 +159,22 @@ __global__ __launch_bounds__(256) void k_build_R(int n, const double *__restrict
     }
 }
 
-// Interpolation bracket per (i, n, m) for the exact-form evaluations: the
-// largest j <= N-2 with K_j <= K~ (eq. app_interp_weights; the same K~
-// expression and comparisons as the weight kernel), 0xFFFF where the entry
-// is cut.  Bisection over the grid.
-__global__ __launch_bounds__(256) void k_brackets(int n, const double *__restrict__ K,
-                                                  uint16_t *__restrict__ JL)
+// Interpolation bracket of entry (i, k, m) for the exact-form evaluations
+// (eq. app_interp_weights): the largest j <= N-2 with K_j <= K~ for
+// K~ = K_k + K_m - K_i (the same K~ expression and comparisons as the weight
+// kernel), 0xFFFF where the entry is cut (K~ outside the grid) or an index
+// lies past the grid (padding).  Bisection over the grid.
+__device__ uint16_t bracket_of(int n, const double *__restrict__ K, int i, int k, int m)
 {
-    const long total = (long)n * n * n;
-    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (long)gridDim.x * blockDim.x) {
-        const int m = (int)(idx % n);
-        const long r = idx / n;
-        const int a = (int)(r % n);
-        const int i = (int)(r / n);
-        const double kt = (K[a] + K[m]) - K[i];
-        uint16_t out = 0xFFFF;
-        if (kt >= K[0] && kt <= K[n - 1]) {
-            int lo = 0, hi = n - 2;                 // invariant: K[lo] <= kt
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (K[mid] <= kt) lo = mid; else hi = mid - 1;
-            }
-            out = (uint16_t)lo;
-        }
-        JL[idx] = out;
+    if (i >= n || k >= n || m >= n) return 0xFFFF;
+    const double kt = (K[k] + K[m]) - K[i];
+    if (!(kt >= K[0] && kt <= K[n - 1])) return 0xFFFF;
+    int lo = 0, hi = n - 2;                 // invariant: K[lo] <= kt
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (K[mid] <= kt) lo = mid; else hi = mid - 1;
     }
-}
-
-__global__ void k_to_f32(long count, const double *__restrict__ src, float *__restrict__ dst)
-{
-    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
-         idx += (long)gridDim.x * blockDim.x)
-        dst[idx] = (float)src[idx];
+    return (uint16_t)lo;
 }
 
 // Value of the block-packed operand for output row i and pair (kb <= mb),
@@ -309,6 +292,34 @@ __global__ void k_pack_rows(int n, long ncomp, const int *__restrict__ pairs,
         const int first = ib64[2 * ib], cnt = ib64[2 * ib + 1];
         const long dst = ((long)first * kIBlk + (long)r * cnt + (c - first)) * 256 + w;
         P[dst] = (T)packed_value(A, RT, n, ib * kIBlk + r, pairs[2 * c], pairs[2 * c + 1], w / kBlk, w % kBlk);
+    }
+}
+
+// Operands of the exact forms over the ordered kept blocks, row by row:
+// row i of i-block ib starts at (first_ib * 32 + (i % 32) cnt_ib) blocks of
+// 256 values and holds A[i,k,m] (as is: no symmetrisation, no loss) of its
+// i-block's blocks (kb, mb) in order, each [dk][dm], and (if JX is given)
+// the brackets j_L of the same entries.  Work item = (block c, row, value).
+template <typename T>
+__global__ void k_pack_exact(int n, long nx, const int *__restrict__ xpairs, const int *__restrict__ xib,
+                             const int *__restrict__ cib, const double *__restrict__ A,
+                             const double *__restrict__ K, T *__restrict__ AX, uint16_t *__restrict__ JX)
+{
+    const long total = nx * kIBlk * 256;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        const int w = (int)(idx % 256);
+        const long t = idx / 256;
+        const int r = (int)(t % kIBlk);
+        const long c = t / kIBlk;
+        const int ib = cib[c];
+        const int first = xib[2 * ib], cnt = xib[2 * ib + 1];
+        const long dst = ((long)first * kIBlk + (long)r * cnt + (c - first)) * 256 + w;
+        const int i = ib * kIBlk + r;
+        const int k = xpairs[2 * c] * kBlk + w / kBlk, m = xpairs[2 * c + 1] * kBlk + w % kBlk;
+        const bool in = i < n && k < n && m < n;
+        AX[dst] = in ? (T)A[((long)i * n + k) * n + m] : (T)0;
+        if (JX) JX[dst] = bracket_of(n, K, i, k, m);
     }
 }
 
@@ -440,10 +451,17 @@ hipError_t launch_build_R(const kxg_kernel &k, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s)
+hipError_t launch_pack_exact(const kxg_kernel &k, hipStream_t s)
 {
-    const long total = (long)k.n * k.n * k.n;
-    hipLaunchKernelGGL(k_brackets, dim3(grid_for(total)), dim3(256), 0, s, k.n, k.d_K, k.d_JL);
+    const long tot = k.nx * kIBlk * 256;
+    if (tot <= 0) return hipSuccess;
+    const int *cib = k.d_xpairs + 2 * k.nx;
+    if (k.d_AX64)
+        hipLaunchKernelGGL(k_pack_exact<double>, dim3(grid_for(tot)), dim3(256), 0, s, k.n, k.nx, k.d_xpairs,
+                           k.d_xib, cib, k.d_A64, k.d_K, k.d_AX64, k.d_JX);
+    if (k.d_AX32)
+        hipLaunchKernelGGL(k_pack_exact<float>, dim3(grid_for(tot)), dim3(256), 0, s, k.n, k.nx, k.d_xpairs,
+                           k.d_xib, cib, k.d_A64, k.d_K, k.d_AX32, k.d_AX64 ? nullptr : k.d_JX);
     return hipGetLastError();
 }
 
@@ -493,11 +511,6 @@ hipError_t launch_pack_16(const kxg_kernel &k, int ibw, hipStream_t s)
 hipError_t launch_derive(kxg_kernel &k, hipStream_t s)
 {
     const Geometry &g = k.geo;
-    const long dense = (long)k.n * k.n * k.n;
-    if (k.d_A32) {
-        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(dense)), dim3(256), 0, s, dense, k.d_A64,
-                           k.d_A32);
-    }
     if (k.d_hrow)
         hipLaunchKernelGGL(k_row_scale, dim3(g.ipad), dim3(256), 0, s, k.n, g.ipad, k.d_A64,
                            k.d_RT, k.d_hrow);

@@ -30,10 +30,6 @@ namespace {
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
-// shape of the LDS-shared 16-bit GEMM: b-blocks and i-blocks per wave
-#ifndef KXG_STREAM_ROWS_TARGET
-#define KXG_STREAM_ROWS_TARGET 2048   // K splits x rows of a stream launch aimed at (more for n below it)
-#endif
 #ifndef KXG_STREAMX_UNROLL
 #define KXG_STREAMX_UNROLL 4   // element groups in flight per thread in the exact-form stream
 #endif
@@ -173,52 +169,66 @@ __device__ inline float exp_interp(float x, const float *) { return expf(x); }
 
 // ---------------------------------------------------------------------------
 // Exact-form stream (eq. app_dense_collision with the statistical factor of
-// eq. Lambda_quantum): one pass over the dense weights and the bracket table;
+// eq. Lambda_quantum): one pass over the weights A[i,n,m] and the bracket
+// table of the blocks that hold a weight (row i: its i-block's (kb, mb)
+// blocks in both orders, [dk][dm]; the pairs' (kb, mb) staged in LDS);
 // per (i, n, m) the fourth-momentum value f~ is interpolated with the
 // energy-linear weights omega_R = (K~ - K_jL) / (K_jL+1 - K_jL), linearly in
 // f or (LOGI) in ln max(f, 1e-300), and four sums are accumulated per
 // distribution: gain = sum W f_n f_m, S0 = sum W f~, S1 = sum W f~ (f_n + f_m),
 // T1 = sum W f~ f_n f_m (the last two only with quantum statistics).  The
 // epilogue forms C = (1 + eta f_i)(gain + eta T1) - f_i (S0 + eta S1 + eta^2 T1).
-template <typename T, int VEC, int BT, bool LOGI, bool QUANT>
+// Grid (split, i, group of BT distributions); split s of a row shorter than
+// s * chunk writes zero partials.
+template <typename T, int BT, bool LOGI, bool QUANT>
 __global__ __launch_bounds__(256) void k_stream_x(const T *__restrict__ A,
                                                   const uint16_t *__restrict__ JL,
+                                                  const int *__restrict__ xpairs,
+                                                  const int *__restrict__ xib,
                                                   const double *__restrict__ f,
                                                   const double *__restrict__ K,
-                                                  const double *__restrict__ invdK, int n, int B,
+                                                  const double *__restrict__ invdK, int n, int nbf, int B,
                                                   int chunk, double *__restrict__ part)
 {
-    constexpr int NA = QUANT ? 4 : 2;
+    constexpr int NA = QUANT ? 4 : 2, VEC = 2;
     extern __shared__ double smem_d[];
-    double *Ks = smem_d;                       // [n]
-    double *iK = Ks + n;                       // [n]
-    T *fs = reinterpret_cast<T *>(iK + n);     // [BT][n]
-    T *ls = fs + BT * n;                       // [BT][n] ln max(f, floor) (LOGI)
+    double *Ks = smem_d;                       // [nbf]
+    double *iK = Ks + nbf;                     // [nbf]
+    T *fs = reinterpret_cast<T *>(iK + nbf);   // [BT][nbf]
+    T *ls = fs + BT * nbf;                     // [BT][nbf] ln max(f, floor) (LOGI)
     __shared__ double red[4][BT][NA];
     __shared__ T t32[32];                      // 2^(j/32) for the FP64 exponential
+    __shared__ int2 spair[kPStreamPairs];      // (16 kb, 16 mb)
     const int split = blockIdx.x, i = blockIdx.y, b0 = blockIdx.z * BT;
-    for (int q = threadIdx.x; q < n; q += 256) {
-        Ks[q] = K[q];
-        iK[q] = invdK[q];
+    const int ib = i / kIBlk;
+    const int first = xib[2 * ib], cnt = xib[2 * ib + 1];
+    const long len = (long)cnt * 256;
+    const long e_beg = (long)split * chunk;
+    if (e_beg >= len) {
+        if ((int)threadIdx.x < BT * 4 && b0 + (int)threadIdx.x / 4 < B)
+            part[(((long)split * B + b0 + threadIdx.x / 4) * 4 + threadIdx.x % 4) * n + i] = 0.0;
+        return;
+    }
+    const long e_end = e_beg + chunk < len ? e_beg + chunk : len;
+    const int c0 = (int)(e_beg >> 8), nc = (int)((e_end - 1) >> 8) - c0 + 1;
+    for (int q = threadIdx.x; q < nbf; q += 256) {
+        Ks[q] = q < n ? K[q] : 0.0;
+        iK[q] = q < n ? invdK[q] : 0.0;
     }
     if (LOGI && sizeof(T) == 8 && threadIdx.x < 32) t32[threadIdx.x] = (T)exp2((double)threadIdx.x / 32.0);
-    for (int q = threadIdx.x; q < BT * n; q += 256) {
-        const int bb = q / n, m = q - bb * n;
-        const double v = (b0 + bb < B) ? f[(long)(b0 + bb) * n + m] : 0.0;
+    for (int q = threadIdx.x; q < BT * nbf; q += 256) {
+        const int bb = q / nbf, m = q - bb * nbf;
+        const double v = (b0 + bb < B && m < n) ? f[(long)(b0 + bb) * n + m] : 0.0;
         fs[q] = (T)v;
         if (LOGI) ls[q] = (T)log(v > 1e-300 ? v : 1e-300);
     }
+    for (int c = threadIdx.x; c < nc; c += 256)
+        spair[c] = make_int2(xpairs[2 * (first + c0 + c)] * kBlk, xpairs[2 * (first + c0 + c) + 1] * kBlk);
     __syncthreads();
-    const long n2 = (long)n * n;
-    const T *row = A + (long)i * n2;
-    const uint16_t *jrow = JL + (long)i * n2;
+    const long roff = ((long)first * kIBlk + (long)(i % kIBlk) * cnt) * 256;
+    const T *row = A + roff;
+    const uint16_t *jrow = JL + roff;
     const double ki = Ks[i];
-    const long e_beg = (long)split * chunk;
-    const long e_end = e_beg + chunk < n2 ? e_beg + chunk : n2;
-    long e = e_beg + (long)threadIdx.x * VEC;
-    int k = (int)(e / n), m = (int)(e - (long)k * n);
-    constexpr int step = 256 * VEC;
-    const int sk = step / n, sm = step - (step / n) * n;
     T acc[BT][NA];
 #pragma unroll
     for (int bb = 0; bb < BT; ++bb)
@@ -226,7 +236,7 @@ __global__ __launch_bounds__(256) void k_stream_x(const T *__restrict__ A,
         for (int c = 0; c < NA; ++c) acc[bb][c] = (T)0;
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
     typedef uint16_t jvec_t __attribute__((ext_vector_type(VEC)));
-    // one element group (VEC weights of row k, columns m .. m + VEC - 1)
+    // one element group (VEC weights of block row k, columns m .. m + VEC - 1)
     auto body = [&](const vec_t &a, const jvec_t &jv, int kq, int mq) {
         const double kk = Ks[kq];
 #pragma unroll
@@ -240,11 +250,11 @@ __global__ __launch_bounds__(256) void k_stream_x(const T *__restrict__ A,
             const T w = a[v];
 #pragma unroll
             for (int bb = 0; bb < BT; ++bb) {
-                const T *fb = fs + bb * n;
+                const T *fb = fs + bb * nbf;
                 const T fn = fb[kq], fm = fb[mv];
                 T ft;
                 if (LOGI) {
-                    const T *lb = ls + bb * n;
+                    const T *lb = ls + bb * nbf;
                     ft = exp_interp(wl * lb[jl] + wr * lb[jl + 1], t32);
                 } else {
                     ft = wl * fb[jl] + wr * fb[jl + 1];
@@ -261,29 +271,25 @@ __global__ __launch_bounds__(256) void k_stream_x(const T *__restrict__ A,
     };
     // KXG_STREAMX_UNROLL groups of loads in flight per thread (weights and
     // brackets), non-temporal: both tables are read once per call
-    constexpr int UN = KXG_STREAMX_UNROLL;
-    for (; e + (UN - 1) * step < e_end; e += UN * step) {
+    constexpr int UN = KXG_STREAMX_UNROLL, STEP = 256 * VEC;
+    for (long e = e_beg + (long)threadIdx.x * VEC; e < e_end; e += (long)UN * STEP) {
         vec_t a[UN];
         jvec_t jv[UN];
-        int kk[UN], mm[UN];
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
-            a[u] = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(row + e + (long)u * step));
-            jv[u] = __builtin_nontemporal_load(reinterpret_cast<const jvec_t *>(jrow + e + (long)u * step));
-            kk[u] = k;
-            mm[u] = m;
-            m += sm;
-            k += sk;
-            if (m >= n) { m -= n; ++k; }
+            const long eu = e + (long)u * STEP;
+            const bool in = eu < e_end;
+            a[u] = in ? __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(row + eu)) : vec_t{};
+            jv[u] = in ? __builtin_nontemporal_load(reinterpret_cast<const jvec_t *>(jrow + eu))
+                       : jvec_t{0xFFFF, 0xFFFF};
         }
 #pragma unroll
-        for (int u = 0; u < UN; ++u) body(a[u], jv[u], kk[u], mm[u]);
-    }
-    for (; e < e_end; e += step) {
-        body(*reinterpret_cast<const vec_t *>(row + e), *reinterpret_cast<const jvec_t *>(jrow + e), k, m);
-        m += sm;
-        k += sk;
-        if (m >= n) { m -= n; ++k; }
+        for (int u = 0; u < UN; ++u) {
+            const long eu = e + (long)u * STEP;
+            const int w = (int)(eu & 255);
+            const int2 pr = spair[eu < e_end ? (int)(eu >> 8) - c0 : 0];
+            body(a[u], jv[u], pr.x + (w >> 4), pr.y + (w & 15));
+        }
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -1224,16 +1230,6 @@ __global__ __launch_bounds__(256) void k_moments(const double *__restrict__ f, i
     }
 }
 
-int stream_splits(int n)
-{
-    const long n2 = (long)n * n;
-    int s = div_up(KXG_STREAM_ROWS_TARGET, n);
-    const int cap = (int)(n2 / 2048);           // keep chunks >= 2048 elements
-    if (s > cap) s = cap;
-    if (s < 1) s = 1;
-    return s;
-}
-
 // 32-row batch blocks per wave of the FP32 GEMM for a call of B rows: the
 // width that minimises width x (workgroups per CU), the MFMA time of the
 // busiest CU.  On a tie a narrower tile wins while the launch stays within
@@ -1265,8 +1261,8 @@ kxg_status alloc_workspace(const kxg_kernel &k, int b_cap, Workspace &ws)
     // rows of the GEMM operands: a multiple of both batch tilings
     constexpr int tile16 = 4 * KXG_LDS_BBW * 32;
     const int bpad = div_up(div_up(b_cap, 128) * 128, tile16) * tile16;
-    size_t need = (size_t)std::max({stream_splits(n), k.nsplit64, k.nsplit32}) * b_cap * n * sizeof(double);
-    if (k.d_JL) need = std::max(need, (size_t)stream_splits(n) * b_cap * 4 * n * sizeof(double));
+    size_t need = (size_t)std::max({1, k.nsplit64, k.nsplit32}) * b_cap * n * sizeof(double);
+    if (k.d_JX) need = std::max(need, (size_t)std::max(k.nsplitx64, k.nsplitx32) * b_cap * 4 * n * sizeof(double));
     const size_t slots = (size_t)std::max(k.d_G32 ? k.maxslots : 0, (k.d_Gbf || k.d_Gh) ? k.maxslots16 : 0);
     need = std::max(need, slots * bpad * k.geo.ipad * sizeof(float));
     need += (size_t)b_cap * n * sizeof(double);      // loss rates
@@ -1365,34 +1361,26 @@ kxg_status eval_impl(const kxg_kernel &k, const Workspace &ws, int prec, const d
         const bool logi = (flags & KXG_INTERP_LOG) != 0;
         const bool quant = (flags & (KXG_STAT_BOSE | KXG_STAT_FERMI)) != 0;
         const double eta = (flags & KXG_STAT_BOSE) ? 1.0 : ((flags & KXG_STAT_FERMI) ? -1.0 : 0.0);
-        const int ns = stream_splits(n);
-        const long n2 = (long)n * n;
         const bool dbl = prec == KXG_F64;
-        const int vec = (n % 2 == 0) ? 2 : 1;
-        int chunk = div_up(n2, ns);
-        chunk = div_up(chunk, 256 * vec) * (256 * vec);
-        const int nsplit = (int)((n2 + chunk - 1) / chunk);
+        const int nsplit = dbl ? k.nsplitx64 : k.nsplitx32;
+        const int chunk = dbl ? k.chunkx64 : k.chunkx32;
+        const int nbf = k.geo.nb * kBlk;
         // distributions per pass: one for a single distribution (no idle
         // arithmetic on an empty slot), two otherwise
         const int BT = B == 1 ? 1 : 2;
         const dim3 grid(nsplit, n, div_up(B, BT));
-        const size_t shm = 2 * n * sizeof(double) + 2 * (size_t)BT * n * (dbl ? sizeof(double) : sizeof(float));
+        const size_t shm = 2 * nbf * sizeof(double) + 2 * (size_t)BT * nbf * (dbl ? sizeof(double) : sizeof(float));
         double *ext = static_cast<double *>(ws.part);
-#define KXG_SX1(T, V, BTV, L, Q)                                                                  \
-    hipLaunchKernelGGL((k_stream_x<T, V, BTV, L, Q>), grid, dim3(256), shm, s,                    \
-                       reinterpret_cast<const T *>(dbl ? (const void *)k.d_A64 : (const void *)k.d_A32), \
-                       k.d_JL, f, k.d_K, k.d_invdK, n, B, chunk, ext)
-#define KXG_SX(T, V, L, Q) if (BT == 1) KXG_SX1(T, V, 1, L, Q); else KXG_SX1(T, V, 2, L, Q)
-#define KXG_SX2(T, V)                                                                             \
-    if (logi && quant) KXG_SX(T, V, true, true);                                                  \
-    else if (logi) KXG_SX(T, V, true, false);                                                     \
-    else KXG_SX(T, V, false, true)
+#define KXG_SX1(T, AX, BTV, L, Q)                                                                    \
+    hipLaunchKernelGGL((k_stream_x<T, BTV, L, Q>), grid, dim3(256), shm, s, AX, k.d_JX, k.d_xpairs, k.d_xib, f, \
+                       k.d_K, k.d_invdK, n, nbf, B, chunk, ext)
+#define KXG_SX(T, AX, L, Q) if (BT == 1) KXG_SX1(T, AX, 1, L, Q); else KXG_SX1(T, AX, 2, L, Q)
+#define KXG_SX2(T, AX)                                                                              \
+    if (logi && quant) KXG_SX(T, AX, true, true);                                                   \
+    else if (logi) KXG_SX(T, AX, true, false);                                                      \
+    else KXG_SX(T, AX, false, true)
         profile_mark_begin(s);
-        if (dbl) {
-            if (vec == 2) { KXG_SX2(double, 2); } else { KXG_SX2(double, 1); }
-        } else {
-            if (vec == 2) { KXG_SX2(float, 2); } else { KXG_SX2(float, 1); }
-        }
+        if (dbl) { KXG_SX2(double, k.d_AX64); } else { KXG_SX2(float, k.d_AX32); }
 #undef KXG_SX2
 #undef KXG_SX
 #undef KXG_SX1
@@ -1544,9 +1532,9 @@ static size_t call_workspace(const kxg_kernel &k, int prec, int B, uint32_t flag
     size_t part;
     int bpad = 0;
     if (exact) {
-        part = (size_t)stream_splits(n) * B * 4 * n * sizeof(double);
+        part = (size_t)std::max(k.nsplitx64, k.nsplitx32) * B * 4 * n * sizeof(double);
     } else if (P.stream) {
-        part = (size_t)std::max({stream_splits(n), k.nsplit64, k.nsplit32}) * B * n * sizeof(double);
+        part = (size_t)std::max({1, k.nsplit64, k.nsplit32}) * B * n * sizeof(double);
     } else {
         bpad = P.bpad;
         const int slots = P.lds ? k.maxslots16 : k.maxslots;

@@ -102,7 +102,6 @@ struct kxg_kernel {
     double *d_A64 = nullptr;     // [n][n][n] FP64 master, m fastest
     double *d_RT = nullptr;      // [n][n] R transposed: RT[j][i] = R[i][j]
     double *d_R = nullptr;       // [n][n] R in row order
-    float *d_A32 = nullptr;      // [n][n][n] FP32 copy (single-f stream)
     float *d_G32 = nullptr;      // packed GEMM operand, FP32
     uint16_t *d_Gbf = nullptr;   // packed GEMM operand, BF16 hi/lo
     uint16_t *d_Gh = nullptr;    // packed GEMM operand, FP16 hi/lo (row-scaled)
@@ -138,7 +137,18 @@ struct kxg_kernel {
     long ncomp64 = 0;
     int chunk64 = 0, nsplit64 = 0;   // FP64: values per stream workgroup, K splits (partials) per row
     int chunk32 = 0, nsplit32 = 0;   // FP32: the same
-    uint16_t *d_JL = nullptr;    // [n][n][n] interpolation bracket j_L (0xFFFF: cut)
+    // Operands of the exact forms (handles built with brackets): A[i,k,m]
+    // itself (not symmetrised, no loss) and the interpolation bracket j_L
+    // (0xFFFF: cut) on the (i-block, kb, mb) blocks, in both orders, of the
+    // pairs with a structural weight, row by row like P64 ([block][dk][dm]);
+    // A in FP64 and/or FP32
+    double *d_AX64 = nullptr;
+    float *d_AX32 = nullptr;
+    uint16_t *d_JX = nullptr;
+    int *d_xpairs = nullptr;     // [nx][2] (kb, mb) of the ordered blocks, i-block by i-block, then [nx] their i-blocks
+    int *d_xib = nullptr;        // [nib][2] first block and count of each i-block
+    long nx = 0;
+    int chunkx64 = 0, nsplitx64 = 0, chunkx32 = 0, nsplitx32 = 0;
     double *d_invdK = nullptr;   // [n] 1 / (K_{j+1} - K_j) (0 for the last point)
     kxg::Geometry geo;
     size_t bytes[5] = {0, 0, 0, 0, 0};
@@ -158,7 +168,7 @@ hipError_t launch_block_nz(const kxg_kernel &k, unsigned char *flags, unsigned i
 hipError_t launch_pack_f32(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_pack_rows(const kxg_kernel &k, hipStream_t s);
 hipError_t launch_pack_16(const kxg_kernel &k, int ibw, hipStream_t s);
-hipError_t launch_brackets(const kxg_kernel &k, hipStream_t s);
+hipError_t launch_pack_exact(const kxg_kernel &k, hipStream_t s);
 // device self-calibration (kxg_probe.hip)
 hipError_t launch_peak_mfma(int bf16, int nwg, int iters, float *sink, hipStream_t s);
 hipError_t launch_copy16(const void *src, void *dst, long nvec, hipStream_t s);

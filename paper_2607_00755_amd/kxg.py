@@ -66,7 +66,7 @@ class KernelInfo(ctypes.Structure):
                 ("nonzero_blocks", ctypes.c_int64), ("gemm_units", ctypes.c_int32),
                 ("max_slots", ctypes.c_int32), ("blocks16", ctypes.c_int64),
                 ("nnz_packed", ctypes.c_int64), ("staged16", ctypes.c_int64),
-                ("blocks64", ctypes.c_int64)]
+                ("blocks64", ctypes.c_int64), ("blocks_exact", ctypes.c_int64)]
 
 
 class StepperParams(ctypes.Structure):
@@ -261,7 +261,7 @@ class Kernel:
                 "nonzero_blocks": info.nonzero_blocks, "gemm_units": info.gemm_units,
                 "max_slots": info.max_slots, "blocks16": info.blocks16,
                 "nnz_packed": info.nnz_packed, "staged16": info.staged16,
-                "blocks64": info.blocks64}
+                "blocks64": info.blocks64, "blocks_exact": info.blocks_exact}
 
     def export(self):
         n = self.n
