@@ -182,6 +182,43 @@ def test_packed_nonzero_count_matches_oracle(dev, n):
     assert k.stats()["nnz_packed"] == want
 
 
+@pytest.mark.parametrize("n", [48, 100])
+def test_stream_blocks_match_oracle_structure(dev, n):
+    """The exact forms stream, per i-block, the (kb, mb) blocks of every pair
+    whose packed 32 x 16 x 16 block carries a weight by structure (A in
+    either order, or R on the diagonal), in both orders (one for kb = mb);
+    the plain streams the same non-zero blocks as the FP32 GEMM.  Both counts
+    follow from the oracle's A and R (n = 100: ragged last blocks)."""
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    k = kxg.Kernel(p, precs=(kxg.F64, kxg.F32), b_cap=1, brackets=True)
+    st = k.stats()
+    op = oracle.Operator(p)
+    nzA = op.A != 0.0
+    idx = np.arange(n)
+    loss = np.zeros_like(nzA)
+    loss[idx, idx, :] = op.R != 0.0
+    s = nzA | np.transpose(nzA, (0, 2, 1)) | loss | np.transpose(loss, (0, 2, 1))
+    nb, nib = (n + 15) // 16, (n + 31) // 32
+    exact = 0
+    for ib in range(nib):
+        for kb in range(nb):
+            for mb in range(kb, nb):
+                blk = s[ib * 32:(ib + 1) * 32, kb * 16:(kb + 1) * 16, mb * 16:(mb + 1) * 16]
+                if blk.any():
+                    exact += 1 if kb == mb else 2
+    assert st["blocks_exact"] == exact
+    assert st["blocks64"] == st["nonzero_blocks"] > 0
+    # every weight of A lies in a streamed block: the exact form over the
+    # kept blocks equals the oracle's direct evaluation (the parity tests'
+    # bound), here for one distribution with log interpolation
+    f = inputs.draw_solves(1, seed=8)[0].f0(p)
+    C, _ = k.eval(torch.tensor(f[None, :], device=dev), prec=kxg.F64, project=False,
+                  log_interp=True, eta=1)
+    ref = oracle.direct(p, f, interp=oracle.LOG, eta=1)[0]
+    got = C.cpu().numpy()[0]
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("n", [80, 256])
 def test_16bit_blocks_multiplied_match_oracle_structure(dev, n):
     """The 16-bit GEMM multiplies, for every kept (kb, mb) pair of a group of
