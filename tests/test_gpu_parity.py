@@ -154,6 +154,21 @@ def test_eval_f32(dev, B, cap):
     assert rel(C.cpu().numpy(), oracle_C(op, f0, True)) <= TOL[kxg.F32]
 
 
+@pytest.mark.parametrize("n", [37, 100])
+@pytest.mark.parametrize("B", [1, 3])
+def test_eval_f32_single_ragged(dev, n, B):
+    """FP32 single-distribution handles stream the packed kept blocks in
+    FP32; grids whose last i-block and last 16-blocks are partial."""
+    p = inputs.log_grid(n, 1e-3, 20.0)
+    f0 = batch(p, B, seed=13)
+    k = kxg.Kernel(p, precs=(kxg.F32,), b_cap=4)
+    op = oracle.Operator(p)
+    for project in (False, True):
+        C, _ = k.eval(torch.tensor(f0, device=dev), prec=kxg.F32, project=project)
+        torch.cuda.synchronize()
+        assert rel(C.cpu().numpy(), oracle_C(op, f0, project)) <= TOL[kxg.F32]
+
+
 @pytest.mark.parametrize("prec", SIXTEEN)
 @pytest.mark.parametrize("B,n", [(3, 40), (40, 64), (130, 100)])
 def test_eval_16bit(dev, prec, B, n):
