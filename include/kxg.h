@@ -206,9 +206,10 @@ kxg_status kxg_kernel_grid(const kxg_kernel *k, double *dp, double *E,
  * linear-interpolation form gain - f R f (any precision).  With them it is
  * eq. app_dense_collision with the statistical factor of eq. Lambda_quantum
  * (eta = +1, -1, or 0 for the dilute limit) and f at the fourth momentum
- * interpolated linearly or in log f; this exact form streams A and the
- * bracket table once per group of distributions (precisions KXG_F64 and
- * KXG_F32 only; the handle must be built with KXG_WITH_BRACKETS).
+ * interpolated linearly or in log f; this exact form streams A and its
+ * interpolation brackets (on the blocks that hold a weight) once per group
+ * of distributions (precisions KXG_F64 and KXG_F32 only; the handle must be
+ * built with KXG_WITH_BRACKETS).
  *  f_dev   device [B][n] FP64 input distributions
  *  C_dev   device [B][n] FP64 output (raw or projected)
  *  diag_dev device [B][KXG_NDIAG] FP64 or NULL:
@@ -224,8 +225,8 @@ kxg_status kxg_kernel_grid(const kxg_kernel *k, double *dp, double *E,
  * KXG_SPLIT_F_ONLY / KXG_SPLIT_NONE drop products of the hi+lo split of the
  * 16-bit contraction (accuracy ablations; 16-bit precisions only).
  * Errors: KXG_EINVAL (bad flags, both statistics, both ablations, an
- * ablation at FP64/FP32), KXG_EUNSUPPORTED (precision or bracket table not
- * built, exact form at 16-bit), KXG_EHIP. */
+ * ablation at FP64/FP32), KXG_EUNSUPPORTED (precision or exact-form operands
+ * not built, exact form at 16-bit), KXG_EHIP. */
 kxg_status kxg_eval(const kxg_kernel *k, int32_t prec, const double *f_dev,
                     int32_t B, double *C_dev, uint32_t flags, double *diag_dev,
                     void *stream);
