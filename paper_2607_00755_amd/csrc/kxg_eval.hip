@@ -30,6 +30,9 @@ namespace {
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
+#ifndef KXG_STREAMX_VEC32
+#define KXG_STREAMX_VEC32 2   // FP32 weights per load in the exact-form stream (2 or 4)
+#endif
 #ifndef KXG_STREAMX_UNROLL
 #define KXG_STREAMX_UNROLL 4   // element groups in flight per thread in the exact-form stream
 #endif
@@ -190,7 +193,9 @@ __global__ __launch_bounds__(256) void k_stream_x(const T *__restrict__ A,
                                                   const double *__restrict__ invdK, int n, int nbf, int B,
                                                   int chunk, double *__restrict__ part)
 {
-    constexpr int NA = QUANT ? 4 : 2, VEC = 2;
+    // 16-byte weight loads in FP32 (four values), 16 in FP64 (two); the
+    // brackets of the same values alongside
+    constexpr int NA = QUANT ? 4 : 2, VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : KXG_STREAMX_VEC32;
     extern __shared__ double smem_d[];
     double *Ks = smem_d;                       // [nbf]
     double *iK = Ks + nbf;                     // [nbf]
@@ -281,7 +286,7 @@ __global__ __launch_bounds__(256) void k_stream_x(const T *__restrict__ A,
             const bool in = eu < e_end;
             a[u] = in ? __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(row + eu)) : vec_t{};
             jv[u] = in ? __builtin_nontemporal_load(reinterpret_cast<const jvec_t *>(jrow + eu))
-                       : jvec_t{0xFFFF, 0xFFFF};
+                       : jvec_t(0xFFFF);
         }
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
