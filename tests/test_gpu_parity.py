@@ -182,7 +182,9 @@ def test_eval_16bit(dev, prec, B, n):
 
 
 def test_eval_full_size_batched_f32_sampled(dev):
-    """N=256, B=512 FP32 GEMM (the batched workload) on sampled rows."""
+    """N=256, B=512 FP32 GEMM (the batched workload) on sampled rows; the
+    plain FP64 stream over the packed blocks (the single-distribution path)
+    on the same rows, one by one and as a group of four."""
     w = inputs.batched_fp32_n256()
     p = w.grid()
     f0 = w.f0()
@@ -190,13 +192,21 @@ def test_eval_full_size_batched_f32_sampled(dev):
     f = torch.tensor(f0, device=dev)
     C, _ = k.eval(f, prec=kxg.F32, project=True)
     C16, _ = k.eval(f, prec=kxg.BF16X3, project=True)
+    rows = (0, 1, 127, 128, 300, 511)
+    C64 = [k.eval(f[b:b + 1].contiguous(), prec=kxg.F64, project=True)[0] for b in rows]
+    C64g, _ = k.eval(f[list(rows[:4])].contiguous(), prec=kxg.F64, project=True)
     torch.cuda.synchronize()
     C, C16 = C.cpu().numpy(), C16.cpu().numpy()
+    C64 = [c.cpu().numpy()[0] for c in C64]
+    C64g = C64g.cpu().numpy()
     op = oracle.Operator(p)
-    for b in (0, 1, 127, 128, 300, 511):
+    for j, b in enumerate(rows):
         ref = oracle_C(op, f0[b:b + 1], True)[0]
         assert rel(C[b], ref) <= TOL[kxg.F32], b
         assert rel(C16[b], ref) <= TOL[kxg.BF16X3], b
+        assert rel(C64[j], ref) <= TOL[kxg.F64], b
+        if j < 4:
+            assert np.array_equal(C64g[j], C64[j]), b
 
 
 def test_batch_invariance_bitwise(dev):
