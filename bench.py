@@ -116,7 +116,7 @@ def serving_alone_check(serving, reqs, done, warm, count):
     worst, same_steps = 0.0, True
     for rid in sample:
         one = reqs[rid]
-        alone = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16, keep_results=True)
+        alone = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=64, keep_results=True)
         solo = alone.run([inputs.Solve(one.lam, one.p_low, one.p_high, one.ratio, n=one.n,
                                        t_end=one.t_end, arrival=0.0)])[0]
         a, b = solo.result, mixed[rid].result
@@ -154,7 +154,7 @@ def serving_sweep(serving, args):
         nr = max(args.serve_sweep_requests, int(round(args.serve_sweep_seconds * rate)))
         nw = max(1, nr // 5)
         reqs = inputs.serving_requests(nw + nr, rate=rate)
-        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16)
+        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=64)
         t0 = time.perf_counter()
         done = srv.run(reqs)
         st = srv.stats(done, warm=nw)
@@ -504,7 +504,7 @@ def main():
         # the serving loop under a moderate load: 60 req/s, 300 requests
         from paper_2607_00755_amd import serving
         reqs = inputs.serving_requests(300, rate=60.0)
-        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16)
+        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=64)
         done = srv.run(reqs)
         st = srv.stats(done, warm=50)
         print(json.dumps({"profile_run": "serve", "p50_s": st["p50_s"], "p99_s": st["p99_s"],
@@ -740,7 +740,7 @@ def main():
     if args.serve_requests > 0:
         from paper_2607_00755_amd import serving
         reqs = inputs.serving_requests(args.serve_warm + args.serve_requests, rate=args.serve_rate)
-        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=16, keep_results=args.serve_check > 0)
+        srv = serving.Server(prec=kxg.F32, b_cap=512, iters_per_tick=64, keep_results=args.serve_check > 0)
         t0 = time.perf_counter()
         done = srv.run(reqs)
         el = time.perf_counter() - t0

@@ -80,7 +80,7 @@ class Server:
     """Continuous-batching loop over libkxg steppers, one group per grid size."""
 
     def __init__(self, prec: int = kxg.F32, b_cap: int = 128, budget_bytes: int = 8 << 30,
-                 iters_per_tick: int = 16, pmin: float = inputs.SERVING_PMIN,
+                 iters_per_tick: int = 64, pmin: float = inputs.SERVING_PMIN,
                  pmax: float = inputs.SERVING_PMAX, rtol: float = 1e-6,
                  keep_results: bool = False, max_steps: int = 200000):
         import torch
